@@ -1,0 +1,497 @@
+/*
+ * rpr_oracle.c -- plain, slow FP64 CPU oracle for ray-parameterized
+ * reverberation propagation (Schissler & Manocha, arXiv 1803.00430).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * includes this file; it exists so that tests, the smoke check and the CPU
+ * baseline of the benchmark can compare the HIP path against an independent,
+ * obviously-correct implementation.  It shares no code, header, table or
+ * constant generator with the HIP path.
+ *
+ * What it computes (paper Section 4.2 and Section 5 "Sound Propagation"):
+ * stochastic rays leave each source with unit energy per frequency band split
+ * over the traced rays, bounce off a triangle scene with per-band absorption
+ * and scattering, and are scored at a transparent listener sphere into a
+ * low-rate impulse response: per time bin, per band, per real spherical
+ * harmonic (SH) coefficient of the arrival direction (Section 4.2, the IR as
+ * an intensity histogram I(t) plus SH coefficients X_lm(t)).  Readings of the
+ * paper where it is silent are listed at each function.
+ *
+ * Everything is FP64 and brute force: every segment is tested against every
+ * triangle (Moller-Trumbore), SH are evaluated through associated Legendre
+ * functions in spherical coordinates, and histogram updates are OpenMP atomics.
+ *
+ * The random stream is Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11),
+ * written here from its published definition; the HIP path has its own copy.
+ * Counter (ray, pair, reflection order, 0), key (seed low, seed high).
+ */
+#define _GNU_SOURCE
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_BANDS 8
+#define ORC_FNV_BASIS 2166136261u
+#define ORC_FNV_PRIME 16777619u
+#define ORC_HASH_ESCAPE 0xFFFFFFFFu
+
+typedef struct {
+    int64_t n_rays_total; /* energy normalisation: each ray starts with 1/n_rays_total per band */
+    int64_t ray_begin;    /* absolute ray ids [ray_begin, ray_end) are traced for every source */
+    int64_t ray_end;
+    int32_t max_bounces;  /* K: segments of reflection order 0..K are traced */
+    int32_t sh_order;     /* n in 0..3, (n+1)^2 coefficients */
+    int32_t n_bins;       /* T */
+    int32_t pair_base;    /* RNG counter word 1 = pair_base + source index */
+    double bin_width_s;   /* dt */
+    double speed_of_sound;
+    uint64_t seed;
+} OrcTraceParams;
+
+typedef struct {
+    int64_t n_segments;        /* closest-hit queries, including the escaping one */
+    int64_t n_finite_segments; /* segments that ended on a surface */
+    int64_t n_escaped;
+    int64_t n_rays;
+    double seg_len_sum;        /* sum of finite segment lengths */
+    double e_emitted;          /* energy emitted per band = n_rays / n_rays_total */
+    int32_t first_arrival_bin; /* INT32_MAX if no deposit */
+    int32_t first_late_bin;    /* first bin reached by an order >= 3 segment */
+    double e_class[3][ORC_MAX_BANDS]; /* time-integrated intensity: direct / early / late */
+    double e_escaped[ORC_MAX_BANDS];
+    double e_alive_at_stop[ORC_MAX_BANDS];
+    double e_alive_at_bounce_cap[ORC_MAX_BANDS];
+    double e_absorbed[ORC_MAX_BANDS];
+} OrcIrStats;
+
+/* ------------------------------------------------------------------ RNG */
+
+/* Philox4x32-10: ten rounds of the Philox S-box
+ *   (c0,c1,c2,c3) -> (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0))
+ * with the Weyl key schedule k += (W0, W1) between rounds. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1) from the top 23 bits of a 32-bit word: the odd multiples
+ * of 2^-24.  Exactly representable in FP32 and FP64, so both sides start every
+ * decision from the same number. */
+double orc_uniform(uint32_t x)
+{
+    return ((double)(x >> 9) * 2.0 + 1.0) * (1.0 / 16777216.0);
+}
+
+static void draw(uint64_t seed, uint32_t ray, uint32_t pair, uint32_t order, double u[4])
+{
+    uint32_t ctr[4] = {ray, pair, order, 0u};
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    for (int i = 0; i < 4; ++i) u[i] = orc_uniform(x[i]);
+}
+
+/* ------------------------------------------------------------------ SH */
+
+/* Real orthonormal SH (Section 2, "Spherical Harmonics") of order <= n at the
+ * unit direction v, index k = l(l+1)+m.  Reading of the sign convention: the
+ * Condon-Shortley phase is included in P_l^m, which is the convention under
+ * which the dominant-direction formula of Section 4.1 ("Input
+ * Spatialization") returns the arrival direction from the first-order
+ * coefficients.  Y_l0 = K_l^0 P_l^0(cos t); Y_lm = sqrt2 K_l^m cos(m p) P_l^m
+ * (m > 0); Y_l,-m = sqrt2 K_l^m sin(m p) P_l^m (m > 0), where
+ * K_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!). */
+void orc_sh_eval(int n, const double v[3], double *out)
+{
+    double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double ct = v[2] / r;
+    if (ct > 1.0) ct = 1.0;
+    if (ct < -1.0) ct = -1.0;
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double phi = atan2(v[1], v[0]);
+    double P[4][4]; /* P[l][m], m <= l */
+    memset(P, 0, sizeof(P));
+    /* P_m^m = (-1)^m (2m-1)!! sin^m(t);  P_{m+1}^m = (2m+1) cos(t) P_m^m;
+     * P_l^m = ((2l-1) cos(t) P_{l-1}^m - (l+m-1) P_{l-2}^m) / (l-m). */
+    for (int m = 0; m <= n; ++m) {
+        double pmm = 1.0;
+        for (int i = 1; i <= m; ++i) pmm *= -(2.0 * i - 1.0) * st;
+        P[m][m] = pmm;
+        if (m + 1 <= n) P[m + 1][m] = (2.0 * m + 1.0) * ct * pmm;
+        for (int l = m + 2; l <= n; ++l)
+            P[l][m] = ((2.0 * l - 1.0) * ct * P[l - 1][m] - (l + m - 1.0) * P[l - 2][m]) / (double)(l - m);
+    }
+    for (int l = 0; l <= n; ++l) {
+        for (int m = -l; m <= l; ++m) {
+            int am = m < 0 ? -m : m;
+            double fr = 1.0; /* (l-|m|)! / (l+|m|)! */
+            for (int i = l - am + 1; i <= l + am; ++i) fr /= (double)i;
+            double K = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * fr);
+            double y;
+            if (m == 0) y = K * P[l][0];
+            else if (m > 0) y = sqrt(2.0) * K * cos(m * phi) * P[l][m];
+            else y = sqrt(2.0) * K * sin(am * phi) * P[l][am];
+            out[l * (l + 1) + m] = y;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ geometry */
+
+static void sub3(const double a[3], const double b[3], double o[3]) { o[0] = a[0] - b[0]; o[1] = a[1] - b[1]; o[2] = a[2] - b[2]; }
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void cross3(const double a[3], const double b[3], double o[3])
+{
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Moller-Trumbore ray/triangle test; returns t (> 0) or INFINITY. */
+static double tri_hit(const double *verts, const int32_t *tri, const double o[3], const double d[3])
+{
+    const double *v0 = verts + 3 * (int64_t)tri[0];
+    const double *v1 = verts + 3 * (int64_t)tri[1];
+    const double *v2 = verts + 3 * (int64_t)tri[2];
+    double e1[3], e2[3], p[3], s[3], q[3];
+    sub3(v1, v0, e1);
+    sub3(v2, v0, e2);
+    cross3(d, e2, p);
+    double det = dot3(e1, p);
+    if (det == 0.0) return INFINITY;
+    double inv = 1.0 / det;
+    sub3(o, v0, s);
+    double u = dot3(s, p) * inv;
+    if (u < 0.0 || u > 1.0) return INFINITY;
+    cross3(s, e1, q);
+    double v = dot3(d, q) * inv;
+    if (v < 0.0 || u + v > 1.0) return INFINITY;
+    double t = dot3(e2, q) * inv;
+    return t > 0.0 ? t : INFINITY;
+}
+
+/* Closest hit over all triangles except `exclude`: smallest t > 0, ties to
+ * the lower triangle index.  Returns the triangle index or -1. */
+static int64_t closest_hit(const double *verts, const int32_t *tris, int64_t n_tris,
+                           const double o[3], const double d[3], int64_t exclude, double *t_out)
+{
+    double best = INFINITY;
+    int64_t best_i = -1;
+    for (int64_t i = 0; i < n_tris; ++i) {
+        if (i == exclude) continue;
+        double t = tri_hit(verts, tris + 3 * i, o, d);
+        if (t < best) {
+            best = t;
+            best_i = i;
+        }
+    }
+    *t_out = best;
+    return best_i;
+}
+
+void orc_closest_hit_batch(const double *verts, const int32_t *tris, int64_t n_tris,
+                           const double *orig, const double *dir, int64_t n_rays,
+                           double *t_out, int64_t *tri_out)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t r = 0; r < n_rays; ++r)
+        tri_out[r] = closest_hit(verts, tris, n_tris, orig + 3 * r, dir + 3 * r, -1, t_out + r);
+}
+
+/* Orthonormal basis (b1, b2, n) for a unit normal n, from Duff et al.,
+ * "Building an Orthonormal Basis, Revisited" (JCGT 2017). */
+static void onb(const double n[3], double b1[3], double b2[3])
+{
+    double sg = n[2] >= 0.0 ? 1.0 : -1.0;
+    double a = -1.0 / (sg + n[2]);
+    double b = n[0] * n[1] * a;
+    b1[0] = 1.0 + sg * n[0] * n[0] * a; b1[1] = sg * b; b1[2] = -sg * n[0];
+    b2[0] = b; b2[1] = sg + n[1] * n[1] * a; b2[2] = -n[1];
+}
+
+/* Emission direction, uniform on the sphere (omnidirectional source). */
+void orc_emission_dir(const double u[4], double d[3])
+{
+    double z = 1.0 - 2.0 * u[0];
+    double phi = 2.0 * M_PI * u[1];
+    double rxy = sqrt(fmax(0.0, 1.0 - z * z));
+    d[0] = rxy * cos(phi);
+    d[1] = rxy * sin(phi);
+    d[2] = z;
+}
+
+/* Lambert (cosine-lobe) direction about the unit normal nf. */
+void orc_diffuse_dir(const double nf[3], const double u[4], double d[3])
+{
+    double b1[3], b2[3];
+    onb(nf, b1, b2);
+    double rr = sqrt(u[2]);
+    double lx = rr * cos(2.0 * M_PI * u[1]);
+    double ly = rr * sin(2.0 * M_PI * u[1]);
+    double lz = sqrt(fmax(0.0, 1.0 - u[2]));
+    for (int i = 0; i < 3; ++i) d[i] = lx * b1[i] + ly * b2[i] + lz * nf[i];
+}
+
+/* Batch samplers over the ray streams, for the direction-moment checks:
+ * out[i] = the emission direction of ray i (counter (i, pair, 0, 0)), or the
+ * diffuse direction about nf drawn from counter (i, pair, order, 0). */
+void orc_emission_batch(uint64_t seed, uint32_t pair, int64_t n, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double u[4];
+        draw(seed, (uint32_t)i, pair, 0u, u);
+        orc_emission_dir(u, out + 3 * i);
+    }
+}
+
+void orc_diffuse_batch(uint64_t seed, uint32_t pair, uint32_t order, const double nf[3], int64_t n,
+                       double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double u[4];
+        draw(seed, (uint32_t)i, pair, order, u);
+        orc_diffuse_dir(nf, u, out + 3 * i);
+    }
+}
+
+static uint32_t fnv(uint32_t h, uint32_t w) { return (h ^ w) * ORC_FNV_PRIME; }
+
+/* ------------------------------------------------------------------ trace */
+
+static void atomic_min_i32(int32_t *p, int32_t v)
+{
+#pragma omp critical(orc_min)
+    {
+        if (v < *p) *p = v;
+    }
+}
+
+/* Score one segment [o, o + t_hit d) at the listener sphere (centre pl,
+ * radius r) with the track-length estimator: the part of the segment inside
+ * the sphere, in propagation time, is split exactly over the histogram bins
+ * it overlaps; each bin receives E_b * Y_k(-d) * (overlap in s) / V_sphere.
+ * The arrival direction is -d (the notation table defines the direction as
+ * pointing back toward the source along the path).  Orders 0, 1-2 and >= 3
+ * are the direct, early and late classes (Section 5: the first two
+ * reflection orders are early, higher orders feed the late IR). */
+static void deposit(const double o[3], const double d[3], double t_hit, double L, int order,
+                    const double *E, int nb, const double pl[3], double r, const OrcTraceParams *p,
+                    double *hist, double *hist_late, OrcIrStats *st)
+{
+    double oc[3], w[3];
+    sub3(o, pl, oc);
+    double bq = dot3(d, oc);
+    for (int i = 0; i < 3; ++i) w[i] = oc[i] - bq * d[i];
+    double disc = r * r - dot3(w, w);
+    if (!(disc > 0.0)) return;
+    double sq = sqrt(disc);
+    double ta = fmax(-bq - sq, 0.0);
+    double tb = fmin(-bq + sq, t_hit);
+    if (!(tb > ta)) return;
+    const double c = p->speed_of_sound, dt = p->bin_width_s;
+    const int T = p->n_bins;
+    const int nc = (p->sh_order + 1) * (p->sh_order + 1);
+    double tau_a = (L + ta) / c, tau_b = (L + tb) / c;
+    double vs = 4.0 / 3.0 * M_PI * r * r * r;
+    double md[3] = {-d[0], -d[1], -d[2]};
+    double Y[16];
+    orc_sh_eval(p->sh_order, md, Y);
+    int cls = order == 0 ? 0 : (order <= 2 ? 1 : 2);
+    int64_t m0 = (int64_t)floor(tau_a / dt);
+    for (int64_t m = m0; m < T; ++m) {
+        double lo = fmax(tau_a, (double)m * dt);
+        double hi = fmin(tau_b, (double)(m + 1) * dt);
+        if (lo >= tau_b) break;
+        double dtau = hi - lo;
+        if (!(dtau > 0.0)) continue;
+        double wgt = dtau / vs;
+        for (int b = 0; b < nb; ++b) {
+            double e = E[b] * wgt;
+            for (int k = 0; k < nc; ++k) {
+#pragma omp atomic
+                hist[(m * nb + b) * nc + k] += e * Y[k];
+            }
+            if (order >= 3 && hist_late) {
+#pragma omp atomic
+                hist_late[m * nb + b] += e;
+            }
+#pragma omp atomic
+            st->e_class[cls][b] += e;
+        }
+        if ((int32_t)m < st->first_arrival_bin) atomic_min_i32(&st->first_arrival_bin, (int32_t)m);
+        if (order >= 3 && (int32_t)m < st->first_late_bin) atomic_min_i32(&st->first_late_bin, (int32_t)m);
+    }
+}
+
+/* Trace rays [ray_begin, ray_end) of every source.
+ *   verts [V][3], tris [T][3], tri_mat [T] (NULL = material 0)
+ *   absorption, scattering [M][nb], p_diffuse [M] (probability of a diffuse
+ *     bounce; the caller passes mean_b scattering rounded to FP32, the
+ *     precision in which the HIP path takes the same decision)
+ *   srcs [n_src][3], listener[4] = centre xyz, radius
+ *   hist      [n_src][T][nb][(n+1)^2]  zeroed and filled
+ *   hist_late [n_src][T][nb] or NULL    (orders >= 3 only)
+ *   stats     [n_src]
+ *   ray_hash  [n_src][ray_end-ray_begin] or NULL: FNV-1a over the sequence of
+ *     hit triangle ids and bounce kinds, for finding rays whose discrete path
+ *     differs between implementations.
+ * Returns 0, or -1 on invalid arguments. */
+int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                 const int32_t *tri_mat, const double *absorption, const double *scattering,
+                 const double *p_diffuse, int32_t n_materials, int32_t nb, const double *srcs,
+                 int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
+                 double *hist_late, OrcIrStats *stats, uint32_t *ray_hash)
+{
+    if (nb < 1 || nb > ORC_MAX_BANDS || p->sh_order < 0 || p->sh_order > 3 || p->n_bins < 1 ||
+        !(p->bin_width_s > 0) || !(listener[3] > 0) || p->ray_end < p->ray_begin ||
+        p->n_rays_total < 1 || n_src < 0 || n_materials < 1)
+        return -1;
+    for (int64_t i = 0; i < 3 * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return -1;
+    const int T = p->n_bins;
+    const int nc = (p->sh_order + 1) * (p->sh_order + 1);
+    const int64_t R = p->ray_end - p->ray_begin;
+    memset(hist, 0, sizeof(double) * (size_t)n_src * T * nb * nc);
+    if (hist_late) memset(hist_late, 0, sizeof(double) * (size_t)n_src * T * nb);
+    for (int s = 0; s < n_src; ++s) {
+        memset(&stats[s], 0, sizeof(OrcIrStats));
+        stats[s].first_arrival_bin = INT32_MAX;
+        stats[s].first_late_bin = INT32_MAX;
+    }
+    const double c = p->speed_of_sound;
+    const double window = (double)T * p->bin_width_s;
+    const double e0 = 1.0 / (double)p->n_rays_total;
+
+#pragma omp parallel for schedule(dynamic, 16) collapse(2)
+    for (int s = 0; s < n_src; ++s) {
+        for (int64_t ri = 0; ri < R; ++ri) {
+            OrcIrStats *st = &stats[s];
+            double *H = hist + (size_t)s * T * nb * nc;
+            double *HL = hist_late ? hist_late + (size_t)s * T * nb : NULL;
+            const uint32_t ray = (uint32_t)(p->ray_begin + ri);
+            const uint32_t pair = (uint32_t)(p->pair_base + s);
+            double u[4], o[3], d[3], E[ORC_MAX_BANDS];
+            draw(p->seed, ray, pair, 0u, u);
+            orc_emission_dir(u, d);
+            for (int i = 0; i < 3; ++i) o[i] = srcs[3 * s + i];
+            for (int b = 0; b < nb; ++b) E[b] = e0;
+            double L = 0.0;
+            int k = 0;
+            int64_t last = -1;
+            uint32_t h = ORC_FNV_BASIS;
+            int64_t nseg = 0, nfin = 0, nesc = 0;
+            double seglen = 0.0, absorbed[ORC_MAX_BANDS] = {0};
+            for (;;) {
+                double t_hit;
+                int64_t tri = closest_hit(verts, tris, n_tris, o, d, last, &t_hit);
+                deposit(o, d, t_hit, L, k, E, nb, listener, listener[3], p, H, HL, st);
+                ++nseg;
+                if (tri < 0) {
+                    ++nesc;
+                    h = fnv(h, ORC_HASH_ESCAPE);
+                    for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+                        st->e_escaped[b] += E[b];
+                    }
+                    break;
+                }
+                L += t_hit;
+                ++nfin;
+                seglen += t_hit;
+                h = fnv(h, (uint32_t)tri);
+                if (L / c >= window || k == p->max_bounces) {
+                    for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+                        st->e_alive_at_stop[b] += E[b];
+                        if (k == p->max_bounces && !(L / c >= window)) {
+#pragma omp atomic
+                            st->e_alive_at_bounce_cap[b] += E[b];
+                        }
+                    }
+                    break;
+                }
+                ++k;
+                double x[3];
+                for (int i = 0; i < 3; ++i) x[i] = o[i] + t_hit * d[i];
+                const int32_t *tv = tris + 3 * tri;
+                double e1[3], e2[3], nrm[3], nf[3];
+                sub3(verts + 3 * (int64_t)tv[1], verts + 3 * (int64_t)tv[0], e1);
+                sub3(verts + 3 * (int64_t)tv[2], verts + 3 * (int64_t)tv[0], e2);
+                cross3(e1, e2, nrm);
+                double nl = sqrt(dot3(nrm, nrm));
+                for (int i = 0; i < 3; ++i) nrm[i] /= nl;
+                double sgn = dot3(d, nrm) > 0.0 ? -1.0 : 1.0; /* face the incoming ray */
+                for (int i = 0; i < 3; ++i) nf[i] = sgn * nrm[i];
+                int mat = tri_mat ? tri_mat[tri] : 0;
+                const double *al = absorption + (int64_t)mat * nb;
+                const double *sc = scattering + (int64_t)mat * nb;
+                double pd = p_diffuse[mat];
+                draw(p->seed, ray, pair, (uint32_t)k, u);
+                for (int b = 0; b < nb; ++b) absorbed[b] += al[b] * E[b];
+                if (u[0] < pd) {
+                    for (int b = 0; b < nb; ++b) E[b] *= (1.0 - al[b]) * sc[b] / pd;
+                    orc_diffuse_dir(nf, u, d);
+                    h = fnv(h, 1u);
+                } else {
+                    for (int b = 0; b < nb; ++b) E[b] *= (1.0 - al[b]) * (1.0 - sc[b]) / (1.0 - pd);
+                    double dn = dot3(d, nf);
+                    for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
+                    h = fnv(h, 0u);
+                }
+                for (int i = 0; i < 3; ++i) o[i] = x[i];
+                last = tri;
+            }
+#pragma omp atomic
+            st->n_segments += nseg;
+#pragma omp atomic
+            st->n_finite_segments += nfin;
+#pragma omp atomic
+            st->n_escaped += nesc;
+#pragma omp atomic
+            st->n_rays += 1;
+#pragma omp atomic
+            st->seg_len_sum += seglen;
+#pragma omp atomic
+            st->e_emitted += e0;
+            for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+                st->e_absorbed[b] += absorbed[b];
+            }
+            if (ray_hash) ray_hash[(int64_t)s * R + ri] = h;
+        }
+    }
+    return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

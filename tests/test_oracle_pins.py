@@ -1,0 +1,420 @@
+"""Pins of the CPU FP64 oracle against facts fixed outside it: published
+known-answer vectors, a library routine, closed forms of room acoustics and
+invariants of the estimator.  All CPU-only."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import rpr_scenes as R
+
+C_SOUND = 343.0
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ Philox
+
+def test_philox_known_answers(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) if l.strip() and l[0] != "#"]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert orc.philox(v[0:4], v[4:6]) == v[6:10]
+
+
+@pytest.mark.skipif(shutil.which("hipcc") is None, reason="hipcc not available to build the rocRAND host check")
+def test_philox_matches_rocrand(orc, tmp_path):
+    exe = tmp_path / "rr"
+    subprocess.check_call(["hipcc", "-O1", "-o", str(exe), os.path.join(GOLDEN, "rocrand_philox.cpp")])
+    cases = [(0, 0, 0, 0), (0x299f31d0a4093822, 7, 5, 3), (12345, 4095, 0, 50), (2**63 + 17, 2**31 - 1, 255, 200),
+             (1000 + 77, 65535, 77, 1), (1, 1, 1, 1)]
+    args = [str(x) for c in cases for x in c]
+    out = subprocess.check_output([str(exe)] + args, text=True).split("\n")
+    for c, line in zip(cases, out):
+        seed, i, j, k = c
+        ref = [int(x, 16) for x in line.split()]
+        assert orc.philox([i, j, k, 0], [seed & 0xFFFFFFFF, seed >> 32]) == ref, c
+
+
+def test_uniform_is_exact_odd_multiple(orc):
+    assert orc.uniform(0) == 2.0**-24
+    assert orc.uniform(0xFFFFFFFF) == 1.0 - 2.0**-24
+    for x in (1, 511, 512, 0x80000000, 0x12345678):
+        u = orc.uniform(x)
+        k = u * 2**24
+        assert k == int(k) and int(k) % 2 == 1 and 0 < u < 1
+        assert np.float32(u) == u
+
+
+# ------------------------------------------------------------------ directions
+
+def test_emission_moments(orc):
+    d = orc.emission_batch(5, 0, 1_000_000)
+    n = len(d)
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-12)
+    tol = 5 * math.sqrt(1.0 / 3.0) / math.sqrt(n)
+    assert np.all(np.abs(d.mean(0)) < tol)
+    M = d.T @ d / n
+    assert np.all(np.abs(M - np.eye(3) / 3) < 5 * math.sqrt(4 / 45.0) / math.sqrt(n) + 1e-12)
+
+
+def test_cosine_lobe_moments(orc):
+    nf = np.array([0.3, -0.5, 0.8])
+    nf /= np.linalg.norm(nf)
+    d = orc.diffuse_batch(9, 2, 3, nf, 1_000_000)
+    n = len(d)
+    c = d @ nf
+    assert c.min() > 0
+    # Lambert lobe: E[cos] = 2/3, E[cos^2] = 1/2, tangential mean 0
+    assert abs(c.mean() - 2 / 3) < 5 * math.sqrt(1 / 2 - 4 / 9) / math.sqrt(n)
+    assert abs((c * c).mean() - 0.5) < 5 * math.sqrt(1 / 3 - 1 / 4) / math.sqrt(n)
+    tang = d - np.outer(c, nf)
+    assert np.all(np.abs(tang.mean(0)) < 5 * math.sqrt(0.25) / math.sqrt(n))
+
+
+# ------------------------------------------------------------------ SH
+
+def _real_sh_from_scipy(order, dirs):
+    """Real SH with the Condon-Shortley phase from scipy's complex SH:
+    Y_l0 = Y_l^0, Y_lm = sqrt2 Re Y_l^m, Y_l,-m = sqrt2 Im Y_l^m (m > 0)."""
+    from scipy.special import sph_harm_y
+    theta = np.arccos(np.clip(dirs[:, 2], -1, 1))
+    phi = np.arctan2(dirs[:, 1], dirs[:, 0])
+    out = np.zeros((len(dirs), (order + 1) ** 2))
+    for l in range(order + 1):
+        for m in range(-l, l + 1):
+            y = sph_harm_y(l, abs(m), theta, phi)
+            if m == 0:
+                v = y.real
+            elif m > 0:
+                v = math.sqrt(2) * y.real
+            else:
+                v = math.sqrt(2) * y.imag
+            out[:, l * (l + 1) + m] = v
+    return out
+
+
+def test_sh_matches_scipy(orc):
+    g = R.rng(4)
+    d = g.normal(size=(200, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.vstack([d, [[0, 0, 1], [0, 0, -1], [1, 0, 0], [0, 1, 0]]])
+    assert np.allclose(orc.sh_eval(3, d), _real_sh_from_scipy(3, d), atol=1e-13)
+
+
+def test_sh_orthonormal_by_quadrature(orc):
+    # Gauss-Legendre in cos(theta) x trapezoid in phi integrates degree <= 2n exactly
+    x, w = np.polynomial.legendre.leggauss(8)
+    nphi = 16
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    st = np.sqrt(1 - x * x)
+    dirs = np.array([[s * math.cos(p), s * math.sin(p), z] for z, s in zip(x, st) for p in phi])
+    wts = np.array([wi * 2 * np.pi / nphi for wi in w for _ in phi])
+    Y = orc.sh_eval(3, dirs)
+    G = (Y * wts[:, None]).T @ Y
+    assert np.abs(G - np.eye(16)).max() < 1e-12
+
+
+def test_sh_addition_theorem(orc):
+    g = R.rng(5)
+    d = g.normal(size=(50, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = orc.sh_eval(3, d)
+    for l in range(4):
+        s = (Y[:, l * l:(l + 1) ** 2] ** 2).sum(1)
+        assert np.allclose(s, (2 * l + 1) / (4 * math.pi), atol=1e-13)
+
+
+def test_sh_dominant_direction_convention(orc):
+    # Section 4.1 ("Input Spatialization"): the direction is recovered as
+    # normalize(-X_{1,1}, -X_{1,-1}, X_{1,0}); index k = l(l+1)+m.
+    g = R.rng(6)
+    for _ in range(20):
+        x = g.normal(size=3)
+        x /= np.linalg.norm(x)
+        Y = orc.sh_eval(1, x)[0]
+        v = np.array([-Y[3], -Y[1], Y[2]])
+        assert np.allclose(v / np.linalg.norm(v), x, atol=1e-13)
+
+
+# ------------------------------------------------------------------ geometry
+
+def test_closest_hit_matches_slab_distances(orc):
+    dims = np.array([10.0, 7.0, 3.0])
+    verts, tris, _ = R.shoebox(dims, edge=1.3)  # tessellated walls: many coplanar triangles
+    g = R.rng(7)
+    o = g.uniform(0.05, 0.95, (3000, 3)) * dims
+    d = g.normal(size=(3000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t, tri = orc.closest_hit(verts, tris, o, d)
+    with np.errstate(divide="ignore"):
+        tx = np.where(d > 0, (dims - o) / d, np.where(d < 0, -o / d, np.inf))
+    ref = tx.min(1)
+    assert np.all(tri >= 0)
+    assert np.allclose(t, ref, rtol=1e-12, atol=1e-12)
+    # the triangle hit lies on the wall of the minimising axis
+    ax = tx.argmin(1)
+    v = verts.astype(np.float64)[tris[tri]]
+    wall = np.where(d[np.arange(len(d)), ax] > 0, dims[ax], 0.0)
+    assert np.allclose(v[np.arange(len(d)), :, ax], wall[:, None], atol=1e-5)
+
+
+# ------------------------------------------------------------------ closed forms
+
+def _inv_rho2_ball(d, r):
+    """Mean of 1/rho^2 over a ball of radius r whose centre is at distance d > r."""
+    return 3.0 / (4 * r**3 * d) * (2 * d * r - (d * d - r * r) * math.log((d + r) / (d - r)))
+
+
+def _direct_energy(d, r, c=C_SOUND):
+    """Time-integrated intensity of unit-energy omnidirectional emission, as
+    seen by the track-length estimator of a sphere at distance d:
+    E = (1/(4 pi c)) <1/rho^2>_ball."""
+    return _inv_rho2_ball(d, r) / (4 * math.pi * c)
+
+
+def _direct_bins(d, r, T, dt, c=C_SOUND):
+    """Per-bin version: the ball's volume element at range rho is the shell
+    cap area pi rho (r^2 - (rho-d)^2) / d, so bin m receives
+    (1/(4 pi c V)) * integral over its range interval of that area / rho^2."""
+    V = 4 / 3 * math.pi * r**3
+
+    def F(rho):
+        return (math.pi / d) * ((r * r - d * d) * math.log(rho) + 2 * d * rho - rho * rho / 2)
+
+    out = np.zeros(T)
+    for m in range(T):
+        a = max(m * dt * c, d - r)
+        b = min((m + 1) * dt * c, d + r)
+        if b > a:
+            out[m] = (F(b) - F(a)) / (4 * math.pi * c * V)
+    return out
+
+
+def _batched(orc, scene, nb_total, n_batches, **kw):
+    """Run the oracle over `n_batches` disjoint ray ranges that together cover
+    nb_total rays (all normalised by nb_total); returns the list of results."""
+    per = nb_total // n_batches
+    return [orc.trace_ir(scene, scene["sources"], scene["listener"], scene["radius"], n_rays_total=nb_total,
+                         ray_begin=i * per, ray_end=(i + 1) * per, **kw) for i in range(n_batches)]
+
+
+def _mean_se(x):
+    x = np.asarray(x, np.float64)
+    n = len(x)
+    return x.sum(0), x.std(0, ddof=1) * math.sqrt(n)
+
+
+@pytest.mark.slow
+def test_direct_sound_closed_form(orc):
+    c = R.tiny_config()
+    d = float(np.linalg.norm(c["sources"][0] - c["listener"]))
+    T, dt = 40, 1e-3
+    runs = _batched(orc, c, 2**22, 32, max_bounces=0, sh_order=0, n_bins=T, bin_width_s=dt, seed=11)
+    e, se = _mean_se([r["stats"][0]["e_class"][0][0] for r in runs])
+    ref = _direct_energy(d, c["radius"])
+    assert abs(e - ref) < 5 * se, (e, ref, se)
+    assert abs(ref - 6.834e-6) < 2e-9
+    I = [math.sqrt(4 * math.pi) * r["hist"][0, :, 0, 0] for r in runs]
+    Im, Ise = _mean_se(I)
+    ref_bins = _direct_bins(d, c["radius"], T, dt)
+    nz = ref_bins > 0
+    assert np.array_equal(Im > 0, nz)  # bins 15..18 and nothing else
+    assert np.all(np.abs(Im - ref_bins)[nz] < 5 * Ise[nz] + 1e-15)
+    # every band carries the same order-0 energy
+    for r in runs:
+        ec = r["stats"][0]["e_class"][0]
+        assert np.all(ec == ec[0])
+
+
+def _images_order_1_2(src, dims):
+    """Image sources of a shoebox of reflection order 1 and 2 (6 + 18)."""
+    per_axis = []
+    for a in range(3):
+        s, L = src[a], dims[a]
+        per_axis.append([(s, 0), (-s, 1), (2 * L - s, 1), (2 * L + s, 2), (s - 2 * L, 2)])
+    out = []
+    for xa in per_axis[0]:
+        for ya in per_axis[1]:
+            for za in per_axis[2]:
+                o = xa[1] + ya[1] + za[1]
+                if 1 <= o <= 2:
+                    out.append((np.array([xa[0], ya[0], za[0]]), o))
+    return out
+
+
+@pytest.mark.slow
+def test_specular_shoebox_matches_image_sources(orc):
+    c = R.tiny_config()
+    sc = dict(c, scattering=np.zeros((1, 4), np.float32))
+    dims = np.array([10.0, 7.0, 3.0])
+    imgs = _images_order_1_2(c["sources"][0].astype(np.float64), dims)
+    assert len(imgs) == 24 and sum(o == 1 for _, o in imgs) == 6
+    runs = _batched(orc, sc, 2**22, 32, max_bounces=2, sh_order=1, n_bins=200, bin_width_s=1e-3, seed=12)
+    alpha = c["absorption"][0].astype(np.float64)
+    lp = c["listener"].astype(np.float64)
+    for b in range(4):
+        e, se = _mean_se([r["stats"][0]["e_class"][1][b] for r in runs])
+        ref = sum((1 - alpha[b]) ** o * _direct_energy(float(np.linalg.norm(p - lp)), c["radius"]) for p, o in imgs)
+        assert abs(e - ref) < 5 * se, (b, e, ref, se)
+    # bands differ only by (1-alpha_b)^o: first-order only run gives exact ratios
+    r1 = orc.trace_ir(sc, c["sources"], lp, c["radius"], n_rays_total=65536, max_bounces=1, sh_order=0,
+                      n_bins=200, bin_width_s=1e-3, seed=13)
+    ec = r1["stats"][0]["e_class"][1]
+    assert np.allclose(ec / ec[0], (1 - alpha) / (1 - alpha[0]), rtol=1e-12)
+
+
+def test_zero_absorption_conserves_energy(orc):
+    c = R.tiny_config()
+    sc = dict(c, absorption=np.zeros((1, 4), np.float32), scattering=np.full((1, 4), 0.5, np.float32))
+    T = 2000
+    r = orc.trace_ir(sc, c["sources"], c["listener"], c["radius"], n_rays_total=16384, max_bounces=100000,
+                     sh_order=0, n_bins=T, bin_width_s=1e-3, seed=14)
+    st = r["stats"][0]
+    assert st["n_escaped"] == 0 and np.all(st["e_escaped"] == 0)
+    assert np.all(st["e_absorbed"] == 0)
+    assert np.allclose(st["e_alive_at_stop"], 1.0, rtol=1e-12)
+    H = r["hist"][0]
+    assert np.all(H[:, 1:, :] == H[:, :1, :])  # all bands identical
+    I = math.sqrt(4 * math.pi) * H[:, 0, 0]
+    late = I[300:].mean()
+    assert abs(late / (1e-3 / 210.0) - 1) < 0.03, late
+
+
+def test_energy_budget_open_box(orc):
+    verts, tris, tm = R.merge(R.box_surfaces((0, 0, 0), (10, 7, 3), faces=("x0", "x1", "y0", "y1", "z0")), [0] * 5)
+    sc = dict(verts=verts, tris=tris, tri_mat=tm, absorption=np.array([[0.05, 0.2, 0.5, 0.9]], np.float32),
+              scattering=np.full((1, 4), 0.3, np.float32))
+    r = orc.trace_ir(sc, np.array([[2, 2, 1.5]]), np.array([7, 5, 1.5]), 0.5, n_rays_total=8192,
+                     max_bounces=30, sh_order=0, n_bins=300, bin_width_s=1e-3, seed=15)
+    st = r["stats"][0]
+    assert st["n_escaped"] > 0
+    tot = st["e_absorbed"] + st["e_escaped"] + st["e_alive_at_stop"]
+    assert np.allclose(tot, 1.0, atol=1e-12)
+
+
+@pytest.mark.slow
+def test_mean_free_path_is_4V_over_S(orc):
+    c = R.tiny_config()
+    sc = dict(c, absorption=np.full((1, 1), 0.01, np.float32), scattering=np.ones((1, 1), np.float32))
+    r = orc.trace_ir(sc, c["sources"], c["listener"], c["radius"], n_rays_total=4096, max_bounces=2000,
+                     sh_order=0, n_bins=30000, bin_width_s=1e-3, seed=16)
+    st = r["stats"][0]
+    mfp = st["seg_len_sum"] / st["n_finite_segments"]
+    assert abs(mfp / (4 * 210.0 / 242.0) - 1) < 0.01, mfp
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("alpha,K,T", [(0.02, 1000, 9000), (0.1, 400, 2000), (0.3, 200, 700)])
+def test_rt60_between_eyring_and_sabine(orc, alpha, K, T):
+    c = R.tiny_config()
+    sc = dict(c, absorption=np.full((1, 1), alpha, np.float32), scattering=np.ones((1, 1), np.float32))
+    r = orc.trace_ir(sc, c["sources"], c["listener"], c["radius"], n_rays_total=8192, max_bounces=K,
+                     sh_order=0, n_bins=T, bin_width_s=1e-3, seed=17)
+    p = orc.estimate_reverb(r["hist"][0], r["hist_late"][0], r["stats"][0], 1e-3)
+    V, S = 210.0, 242.0
+    k = 24 * math.log(10) / C_SOUND
+    sabine = k * V / (S * alpha)
+    eyring = k * V / (-S * math.log(1 - alpha))
+    assert p["rt60_range"][0] == 0
+    assert 0.98 * eyring <= p["rt60"][0] <= 1.02 * sabine, (p["rt60"][0], eyring, sabine)
+
+
+def test_class_energies_sum_to_histogram(orc):
+    c = R.tiny_config()
+    r = orc.trace_ir(c, c["sources"], c["listener"], c["radius"], n_rays_total=4096, max_bounces=50,
+                     sh_order=2, n_bins=2000, bin_width_s=1e-3, seed=0)
+    st = r["stats"][0]
+    I = math.sqrt(4 * math.pi) * r["hist"][0][:, :, 0]
+    assert np.allclose(I.sum(0), st["e_class"].sum(0), rtol=1e-12)
+    assert np.allclose(r["hist_late"][0].sum(0), st["e_class"][2], rtol=1e-12)
+    assert st["n_segments"] == st["n_finite_segments"] + st["n_escaped"]
+    assert st["n_rays"] == 4096
+
+
+# ------------------------------------------------------------------ estimator
+
+def _exp_ir(rt, T, dt, onset=0, floor_db=None):
+    m = np.arange(T)
+    I = 10 ** (-6 * (m - onset) * dt / rt)
+    I[m < onset] = 0
+    if floor_db is not None:
+        I[I < 10 ** (floor_db / 10)] = 0
+    return I
+
+
+def test_rt60_exact_on_pure_exponential(orc):
+    for rt in (0.3, 0.8, 1.7):
+        I = _exp_ir(rt, 4000, 1e-3, floor_db=-100)
+        est, rng_, st = orc.rt60_schroeder(I, 1e-3)
+        assert st == 0 and rng_ == 0
+        assert abs(est / rt - 1) < 1e-6
+
+
+def test_rt60_range_fallback(orc):
+    dt = 1e-3
+    # 0.12 dB/ms decay then silence; the last W = T/20 = 100 bins before the
+    # final nonzero bin may not take part in reaching a range's bottom level.
+    # Cut at -45 dB: the backward integral 100 bins before the end is ~-33 dB,
+    # so T30 (-35) is out of reach and T20 is used.
+    I = _exp_ir(0.5, 2000, dt, floor_db=-45)
+    est, rng_, st = orc.rt60_schroeder(I, dt)
+    assert rng_ == 1 and st == 0
+    assert abs(est / 0.5 - 1) < 0.02
+    I = _exp_ir(0.5, 2000, dt, floor_db=-35)
+    assert orc.rt60_schroeder(I, dt)[1] == 2
+    I = _exp_ir(0.5, 2000, dt, floor_db=-25)
+    assert orc.rt60_schroeder(I, dt)[1] == 3
+    I = _exp_ir(0.5, 2000, dt, floor_db=-12)
+    assert orc.rt60_schroeder(I, dt)[2] == orc.ST_NO_RANGE
+    assert orc.rt60_schroeder(np.zeros(100), dt)[2] == orc.ST_NO_ENERGY
+
+
+def test_rt60_tail_compensation(orc):
+    dt = 1e-3
+    rt = 2.0
+    I = _exp_ir(rt, 1000, dt)  # cut by the 1 s window at -30 dB
+    est, rng_, st = orc.rt60_schroeder(I, dt)
+    assert st & orc.ST_TAIL_COMPENSATED
+    assert abs(est / rt - 1) < 0.01
+    # without compensation the truncated Schroeder curve is visibly biased
+    est0, _, _ = orc.rt60_schroeder(I, dt, tail_iters=0)
+    assert abs(est0 / rt - 1) > 0.03
+
+
+def test_estimator_closed_forms(orc):
+    dt = 1e-3
+    T, B = 1500, 2
+    x = np.array([0.2, -0.7, 0.4])
+    x /= np.linalg.norm(x)
+    Y = orc.sh_eval(3, x)[0]
+    I = np.stack([_exp_ir(0.6, T, dt, onset=40), _exp_ir(0.9, T, dt, onset=40)], 1)
+    H = I[:, :, None] * Y[None, None, :] / math.sqrt(4 * math.pi) / Y[0]
+    stats = dict(e_class=np.array([[1e-5, 2e-5], [3e-5, 4e-5], [5e-5, 6e-5]]),
+                 e_alive_at_bounce_cap=np.zeros(2), e_emitted=1.0, first_late_bin=57, first_arrival_bin=40,
+                 seg_len_sum=123.0, n_finite_segments=40)
+    p = orc.estimate_reverb(H, None, stats, dt)
+    assert np.allclose(p["rt60"], [0.6, 0.9], rtol=1e-5)
+    assert np.allclose(p["g_reverb"], np.sqrt(stats["e_class"][2] * 6 * math.log(10) / p["rt60"]), rtol=1e-12)
+    assert np.allclose(p["dir_loudness"], np.tile(Y, (B, 1)), atol=1e-12)  # single arrival direction
+    assert p["predelay_s"] == 57 * dt and p["first_arrival_s"] == 40 * dt
+    assert p["mean_free_path_m"] == 123.0 / 40
+    stats["e_alive_at_bounce_cap"] = np.array([2e-3, 0.0])
+    p = orc.estimate_reverb(H, None, stats, dt)
+    assert p["status"][0] & orc.ST_TRUNCATED_BY_BOUNCES and not p["status"][1] & orc.ST_TRUNCATED_BY_BOUNCES
+
+
+def test_hash_and_subset_additivity(orc):
+    """Ray ranges partition the estimate: tracing [0,a) and [a,N) separately
+    sums to the full trace, and per-ray path hashes are reproducible."""
+    c = R.tiny_config()
+    kw = dict(n_rays_total=512, max_bounces=20, sh_order=2, n_bins=500, bin_width_s=1e-3, seed=0)
+    full = orc.trace_ir(c, c["sources"], c["listener"], 0.5, want_hash=True, **kw)
+    a = orc.trace_ir(c, c["sources"], c["listener"], 0.5, ray_begin=0, ray_end=200, want_hash=True, **kw)
+    b = orc.trace_ir(c, c["sources"], c["listener"], 0.5, ray_begin=200, ray_end=512, want_hash=True, **kw)
+    assert np.allclose(a["hist"] + b["hist"], full["hist"], rtol=1e-12, atol=1e-20)
+    assert np.array_equal(np.concatenate([a["ray_hash"][0], b["ray_hash"][0]]), full["ray_hash"][0])
+    assert len(np.unique(full["ray_hash"][0])) > 500
