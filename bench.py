@@ -1,0 +1,173 @@
+"""Benchmark: ray-bounces/s of the full propagation path on one MI355X.
+
+Workload (the procedural city): 99,996 triangles, 8 sources x 32,768 rays,
+up to 100 bounces, 4 bands, SH order 3, 3000 bins of 1 ms, FP32.  One step is
+one pass of the hot path over that input: the scene's linear BVH is rebuilt
+(scene_create), every source is traced (trace_ir) and the reverb parameters
+of the 8 IRs are estimated (estimate_reverb).  `value` is ray-bounces
+(closest-hit queries) per second of the whole step.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=2048, help="rays per source in the oracle sample")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(msg, quiet=False):
+    if not quiet:
+        print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not supported",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = R.city_config()
+    S = len(cfg["sources"])
+    N, K, T, n, dt = cfg["n_rays"], cfg["max_bounces"], cfg["n_bins"], cfg["sh_order"], cfg["bin_width_s"]
+    B = cfg["absorption"].shape[1]
+    log(f"city: {len(cfg['tris'])} triangles, {S} sources x {N} rays, K={K}, T={T}, n={n}", a.quiet)
+
+    # inputs resident in HBM before anything is timed
+    verts = torch.as_tensor(cfg["verts"], device=dev)
+    tris = torch.as_tensor(cfg["tris"], device=dev)
+    tmat = torch.as_tensor(cfg["tri_mat"], device=dev)
+    absb = torch.as_tensor(cfg["absorption"], device=dev)
+    scat = torch.as_tensor(cfg["scattering"], device=dev)
+    hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
+    params = P.alloc_params(S, device=dev)
+    prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+    stream = torch.cuda.current_stream()
+
+    # one counting pass (untimed): nodes and triangles fetched per ray-bounce
+    scene = P.Scene(verts, tris, tmat, absb, scat, device=dev)
+    info = scene.info()
+    cprm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"],
+                          flags=P.TRACE_COUNT_VISITS)
+    P.trace_ir(scene, cfg["sources"], cfg["listener"], cfg["radius"], cprm, hist, late, stats)
+    torch.cuda.synchronize()
+    st = P.stats_host(stats)
+    segs = int(st["n_segments"].sum())
+    vn = float(st["n_node_visits"].sum()) / segs
+    vt = float(st["n_tri_tests"].sum()) / segs
+    bytes_per_seg = 64.0 * vn + 48.0 * vt
+    scene.close()
+    log(f"BVH depth {info['max_depth']}; {segs} segments/step; {vn:.1f} nodes + {vt:.1f} triangles per segment",
+        a.quiet)
+
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    t_build, t_trace, t_est = [], [], []
+
+    def step(record):
+        e0 = time.perf_counter()
+        sc = P.Scene(verts, tris, tmat, absb, scat, device=dev)  # synchronises after the build
+        b_ms = (time.perf_counter() - e0) * 1e3
+        ev[1].record(stream)
+        P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
+        ev[2].record(stream)
+        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+        ev[3].record(stream)
+        if record:
+            torch.cuda.synchronize()
+            t_build.append(b_ms)
+            t_trace.append(ev[1].elapsed_time(ev[2]))
+            t_est.append(ev[2].elapsed_time(ev[3]))
+        return sc
+
+    for _ in range(a.warmup):
+        step(False).close()
+    torch.cuda.synchronize()
+    # timed region: exactly `steps` steps, synchronised on both sides
+    scenes = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        scenes.append(step(False))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for s_ in scenes:
+        s_.close()
+    # per-phase timing in a separate pass (phases synchronised one by one)
+    for _ in range(min(a.steps, 10)):
+        step(True).close()
+
+    st = P.stats_host(stats)
+    segs = int(st["n_segments"].sum())
+    ms_step = wall * 1e3 / a.steps
+    value = segs * a.steps / wall
+    trace_ms = float(np.mean(t_trace))
+    achieved = segs * bytes_per_seg / (trace_ms * 1e-3) / 1e9
+    pg = P.params_host(params)
+
+    out = {
+        "metric": "ray-bounces/s", "value": value, "unit": "ray-bounces/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "city: procedural city of 99,996 triangles (extruded boxes, tessellated), "
+                               "8 sources x 32,768 rays, 100 bounces, 4 bands, SH order 3, 3000 x 1 ms bins; "
+                               "step = BVH build + trace + estimate",
+                   "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
+                   "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_trace", "bytes_per_ray_bounce": bytes_per_seg,
+                     "node_visits_per_ray_bounce": vn, "tri_tests_per_ray_bounce": vt,
+                     "kernel_ms": trace_ms},
+        "breakdown_ms": {"build": float(np.mean(t_build)), "trace": trace_ms, "estimate": float(np.mean(t_est))},
+        "trace_ray_bounces_per_s": segs / (trace_ms * 1e-3),
+        "irs_per_s": S / (ms_step * 1e-3),
+        "segments_per_step": segs,
+        "rt60_s_source0": [float(x) for x in pg["rt60"][0][:B]],
+    }
+    if not a.no_cpu_baseline:
+        import oracle
+        R_s = a.cpu_rays
+        c0 = time.perf_counter()
+        o = oracle.trace_ir(cfg, cfg["sources"], cfg["listener"], cfg["radius"], n_rays_total=N, ray_begin=0,
+                            ray_end=R_s, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+        c_wall = time.perf_counter() - c0
+        osegs = sum(x["n_segments"] for x in o["stats"])
+        out["cpu_baseline"] = {"value": osegs / c_wall, "unit": "ray-bounces/s", "cores": oracle.num_threads(),
+                               "kind": "oracle",
+                               "sample": f"city, rays 0..{R_s - 1} of each of the 8 sources ({osegs} ray-bounces, "
+                                         f"{c_wall:.1f} s), FP64 brute force"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

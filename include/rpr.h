@@ -1,0 +1,224 @@
+/*
+ * rpr.h -- C ABI of librpr.so: ray-parameterized reverberation propagation on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Schissler & Manocha, "Interactive Sound Rendering on Mobile Devices
+ * using Ray-Parameterized Reverberation Filters" (arXiv 1803.00430).  Rays
+ * leave each sound source carrying energy in N frequency bands, reflect
+ * specularly or diffusely off a triangle scene under per-band absorption and
+ * scattering (Section 5, "Sound Propagation"), and are scored at a listener
+ * sphere into a low-rate impulse response: an intensity histogram per band
+ * together with the real spherical-harmonic (SH) coefficients of the arrival
+ * direction per time sample (Section 4.2, first paragraph).  Reverb
+ * parameters -- RT60 per band, direct/early/late energies, reverb gain
+ * (Eq. 5-8), predelay, mean free path and the energy-weighted directivity of
+ * Eq. 1 -- are then estimated from that histogram (Section 4.2).
+ *
+ * Conventions for every entry point
+ *  - Return value: RPR_OK (0) or a negative RPR_E* code; last_error() then
+ *    holds a message for the calling thread.  Argument errors are detected
+ *    before anything is launched or written.
+ *  - "device" pointers are HIP device memory owned by the caller; "host"
+ *    pointers are read before the call returns.  The library never frees a
+ *    caller buffer.  Objects created by the library (RprScene, RprBatch,
+ *    RprModel) are owned by the library until the matching destroy call.
+ *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the legacy
+ *    default stream) and is complete when that stream is synchronised,
+ *    unless the entry point says it synchronises.
+ *  - Calls that use the same RprScene or RprBatch must be ordered on one
+ *    stream: each object owns a small workspace (queue counter, pair table)
+ *    that concurrent calls would share.
+ *  - A device fault is reported as RPR_EDEVICE by the call that observes it.
+ */
+#ifndef RPR_H
+#define RPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RPR_OK 0
+#define RPR_EINVAL (-1)       /* invalid argument */
+#define RPR_ENOMEM (-2)       /* device allocation failed */
+#define RPR_EDEVICE (-3)      /* HIP runtime error or device fault */
+#define RPR_EUNSUPPORTED (-4) /* valid but outside what this build supports */
+
+#define RPR_MAX_BANDS 8
+#define RPR_MAX_SH_ORDER 3
+#define RPR_MAX_COEFFS 16
+
+/* Per-band estimation status bits (RprReverbParams.status). */
+#define RPR_ST_OK 0
+#define RPR_ST_NO_ENERGY 1            /* the band's histogram is all zero */
+#define RPR_ST_BAD_FIT 2              /* least-squares slope >= 0 */
+#define RPR_ST_NO_RANGE 4             /* no decay range (T30/T20/T10/EDT) reachable */
+#define RPR_ST_TRUNCATED_BY_BOUNCES 8 /* > 1e-3 of the emitted energy was alive at the bounce limit */
+#define RPR_ST_TAIL_COMPENSATED 16    /* the window cut the decay; the missing tail was added */
+
+typedef struct RprScene RprScene;
+
+typedef struct {
+    float pos[3]; /* metres */
+} RprSource;
+
+typedef struct {
+    float pos[3];
+    float radius; /* metres, > 0 */
+} RprListener;
+
+/* Parameters of one trace.  Every source traces the absolute ray ids
+ * [ray_begin, ray_end); each ray starts with energy 1/n_rays_total in every
+ * band, so disjoint ray ranges of the same n_rays_total add up.  The random
+ * numbers of ray i of pair j at reflection order k are Philox4x32-10 of the
+ * counter (i, j, k, 0) under the key (seed mod 2^32, seed >> 32), with
+ * j = pair_base + source index. */
+typedef struct {
+    int64_t n_rays_total;
+    int64_t ray_begin;
+    int64_t ray_end;
+    int32_t max_bounces;  /* K >= 0: segments of reflection order 0..K are traced */
+    int32_t sh_order;     /* 0..3: (sh_order+1)^2 SH coefficients */
+    int32_t n_bins;       /* T >= 1 histogram bins */
+    int32_t pair_base;
+    float bin_width_s;    /* > 0 */
+    float speed_of_sound; /* > 0, m/s */
+    uint64_t seed;
+    int32_t flags;        /* RPR_TRACE_* bits */
+    int32_t reserved;     /* 0 */
+} RprTraceParams;
+
+/* RprTraceParams.flags: count BVH nodes visited and triangles tested into
+ * RprIrStats.n_node_visits / n_tri_tests (a separate, slower kernel variant;
+ * the counts size the traversal's memory traffic). */
+#define RPR_TRACE_COUNT_VISITS 1
+
+/* Per-IR trace statistics (device, written by trace_ir). */
+typedef struct {
+    int64_t n_segments;        /* closest-hit queries (ray-bounces), escaping ones included */
+    int64_t n_finite_segments; /* segments that ended on a surface */
+    int64_t n_escaped;
+    int64_t n_rays;
+    double seg_len_sum;        /* metres, over finite segments */
+    double e_emitted;          /* n_rays / n_rays_total */
+    int32_t first_arrival_bin; /* first bin with any deposit, INT32_MAX if none */
+    int32_t first_late_bin;    /* first bin reached by an order >= 3 segment, INT32_MAX if none */
+    double e_class[3][RPR_MAX_BANDS]; /* deposited intensity of orders 0 / 1-2 / >=3 */
+    double e_escaped[RPR_MAX_BANDS];
+    double e_alive_at_stop[RPR_MAX_BANDS];       /* energy of rays stopped by K or the window */
+    double e_alive_at_bounce_cap[RPR_MAX_BANDS]; /* ... of those, stopped by K alone */
+    double e_absorbed[RPR_MAX_BANDS];            /* sum over bounces of alpha_b * E_b */
+    int64_t n_node_visits; /* internal BVH nodes fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
+    int64_t n_tri_tests;   /* triangle records fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
+} RprIrStats;
+
+typedef struct {
+    int64_t n_tris;
+    int64_t n_nodes;      /* internal BVH nodes (n_tris - 1) */
+    int32_t max_depth;    /* deepest leaf, in edges from the root */
+    int32_t n_bands;
+    int32_t n_materials;
+    int32_t n_degenerate; /* zero-area triangles (kept; never hit) */
+    float bounds_lo[3];
+    float bounds_hi[3];
+} RprSceneInfo;
+
+/* Build a scene and its BVH (linear BVH: Morton codes of triangle centroids,
+ * radix sort, hierarchy from longest common key prefixes, bottom-up bounds).
+ *   verts        device [n_verts][3] f32, metres
+ *   tris         device [n_tris][3] i32 vertex indices
+ *   tri_material device [n_tris] i32 in [0, n_materials), or NULL = material 0
+ *   absorption   device [n_materials][n_bands] f32 in [0, 1]
+ *   scattering   device [n_materials][n_bands] f32 in [0, 1]
+ *   n_bands      1..8 (Section 5 uses 4 bands)
+ * The scene copies what it needs; the inputs may be freed afterwards.
+ * Synchronises hip_stream (the build reads back validation flags and the tree
+ * depth).  Errors: RPR_EINVAL for out-of-range indices or materials,
+ * non-finite vertices, coefficients outside [0, 1]; RPR_EUNSUPPORTED if the
+ * tree is deeper than the traversal stack (64). */
+int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                 const int32_t* tri_material, const float* absorption, const float* scattering,
+                 int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out);
+int scene_destroy(RprScene* scene);
+int scene_info(const RprScene* scene, RprSceneInfo* out /* host */);
+
+/* Stochastic ray tracing from each source to the listener sphere (Section 5,
+ * "Sound Propagation", traced forward from the sources; Section 4.2, the
+ * low-rate IR).  The sphere is transparent; every segment of reflection
+ * order k deposits, into each bin m it overlaps in propagation time, the
+ * track-length estimate E_b * Y_c(-d) * overlap_s / V_sphere (d = propagation
+ * direction, so -d points back along the path as in the notation table).
+ *   srcs      host [n_src]
+ *   lst       host, one listener
+ *   p         host
+ *   hist      device [n_src][n_bins][n_bands][(sh_order+1)^2] f32, overwritten
+ *   hist_late device [n_src][n_bins][n_bands] f32 (orders >= 3 only), or NULL
+ *   stats     device [n_src], overwritten
+ *   ray_hash  device [n_src][ray_end - ray_begin] u32, or NULL: FNV-1a of the
+ *             ray's sequence of hit triangle ids and bounce kinds.
+ * Rays are traced by persistent workgroups that refill lanes from a global
+ * queue; the scene's workspace makes calls on one scene stream-ordered. */
+int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+             const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+             uint32_t* ray_hash, void* hip_stream);
+
+typedef struct {
+    int32_t rt60_source; /* 0: all orders (default); 1: orders >= 3 only (hist_late) */
+    int32_t tail_iters;  /* refits with the missing tail added when the window cut the decay (3) */
+} RprEstimateParams;
+
+typedef struct {
+    float rt60[RPR_MAX_BANDS];       /* seconds; 0 if status has NO_ENERGY/BAD_FIT/NO_RANGE */
+    int32_t rt60_range[RPR_MAX_BANDS]; /* 0 T30, 1 T20, 2 T10, 3 EDT, -1 none */
+    int32_t status[RPR_MAX_BANDS];   /* RPR_ST_* bits */
+    float e_direct[RPR_MAX_BANDS];
+    float e_early[RPR_MAX_BANDS];
+    float e_late[RPR_MAX_BANDS];
+    float g_reverb[RPR_MAX_BANDS];   /* Eq. 5 with Eq. 8: sqrt(e_late * 6 ln 10 / rt60) */
+    float predelay_s;                /* first late (order >= 3) bin * bin width; -1 if none */
+    float first_arrival_s;           /* first bin with any energy * bin width; -1 if none */
+    float mean_free_path_m;          /* seg_len_sum / n_finite_segments */
+    float reserved;
+    float dir_loudness[RPR_MAX_BANDS][RPR_MAX_COEFFS]; /* Eq. 1 */
+} RprReverbParams;
+
+/* Reverb parameters of n_ir histograms (Section 4.2): per band, the intensity
+ * I[m] = sqrt(4 pi) hist[m][b][0] (or hist_late) is integrated backwards
+ * (Schroeder), converted to dB and fitted by least squares on the first
+ * reachable range of T30, T20, T10, EDT; RT60 = -60 / slope.  FP64
+ * internally.
+ *   hist      device [n_ir][n_bins][n_bands][(sh_order+1)^2] f32
+ *   hist_late device [n_ir][n_bins][n_bands] f32, or NULL (then rt60_source must be 0)
+ *   stats     device [n_ir]
+ *   ep        host, or NULL for {0, 3}
+ *   out       device [n_ir] */
+int estimate_reverb(const float* hist, const float* hist_late, const RprIrStats* stats, int32_t n_ir,
+                    int32_t n_bins, int32_t n_bands, int32_t sh_order, float bin_width_s,
+                    const RprEstimateParams* ep, RprReverbParams* out, void* hip_stream);
+
+/* Closest hit of arbitrary rays against the scene's BVH, with the same
+ * traversal and triangle test as trace_ir (no triangle excluded).
+ *   orig, dir device [n][3] f32;  t_out device [n] f32 (INFINITY on a miss);
+ *   tri_out device [n] i32 (original triangle index, -1 on a miss). */
+int scene_closest_hit(const RprScene* scene, const float* orig, const float* dir, int64_t n,
+                      float* t_out, int32_t* tri_out, void* hip_stream);
+
+/* Device implementations of the shared primitives, exposed for unit checks.
+ * debug_philox: in device [n][6] u32 = ctr0..3, key0..1; out device [n][4].
+ * debug_sh_eval: dirs device [n][3] f32 (unit), out device [n][16] f32 (the
+ * first (order+1)^2 entries written, real SH with the Condon-Shortley phase,
+ * index l(l+1)+m). */
+int debug_philox(const uint32_t* in, int64_t n, uint32_t* out, void* hip_stream);
+int debug_sh_eval(const float* dirs, int64_t n, int32_t order, float* out, void* hip_stream);
+
+/* Thread-local message describing the last non-zero status. */
+const char* last_error(void);
+/* Library version string. */
+const char* rpr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPR_H */

@@ -1,0 +1,287 @@
+"""Python binding of librpr.so: ray-parameterized reverberation propagation
+(arXiv 1803.00430) on MI355X.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch provides device memory and streams; tensors are passed to the C ABI
+(include/rpr.h) as raw pointers.  Importing this module does not need a GPU;
+calling into the library does, and fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpr.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "rpr.h")
+
+RPR_OK = 0
+MAX_BANDS = 8
+MAX_COEFFS = 16
+INT32_MAX = 2**31 - 1
+
+ST_OK = 0
+ST_NO_ENERGY = 1
+ST_BAD_FIT = 2
+ST_NO_RANGE = 4
+ST_TRUNCATED_BY_BOUNCES = 8
+ST_TAIL_COMPENSATED = 16
+
+
+class RprError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rpr error {code}: {msg}")
+        self.code = code
+
+
+class Source(C.Structure):
+    _fields_ = [("pos", C.c_float * 3)]
+
+
+class Listener(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("radius", C.c_float)]
+
+
+class TraceParams(C.Structure):
+    _fields_ = [("n_rays_total", C.c_int64), ("ray_begin", C.c_int64), ("ray_end", C.c_int64),
+                ("max_bounces", C.c_int32), ("sh_order", C.c_int32), ("n_bins", C.c_int32),
+                ("pair_base", C.c_int32), ("bin_width_s", C.c_float), ("speed_of_sound", C.c_float),
+                ("seed", C.c_uint64), ("flags", C.c_int32), ("reserved", C.c_int32)]
+
+
+TRACE_COUNT_VISITS = 1
+
+
+class EstimateParams(C.Structure):
+    _fields_ = [("rt60_source", C.c_int32), ("tail_iters", C.c_int32)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("max_depth", C.c_int32),
+                ("n_bands", C.c_int32), ("n_materials", C.c_int32), ("n_degenerate", C.c_int32),
+                ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3)]
+
+
+# Host views of the device structs (same layout as include/rpr.h).
+IR_STATS_DTYPE = np.dtype([
+    ("n_segments", "<i8"), ("n_finite_segments", "<i8"), ("n_escaped", "<i8"), ("n_rays", "<i8"),
+    ("seg_len_sum", "<f8"), ("e_emitted", "<f8"), ("first_arrival_bin", "<i4"), ("first_late_bin", "<i4"),
+    ("e_class", "<f8", (3, MAX_BANDS)), ("e_escaped", "<f8", (MAX_BANDS,)),
+    ("e_alive_at_stop", "<f8", (MAX_BANDS,)), ("e_alive_at_bounce_cap", "<f8", (MAX_BANDS,)),
+    ("e_absorbed", "<f8", (MAX_BANDS,)), ("n_node_visits", "<i8"), ("n_tri_tests", "<i8"),
+])
+REVERB_PARAMS_DTYPE = np.dtype([
+    ("rt60", "<f4", (MAX_BANDS,)), ("rt60_range", "<i4", (MAX_BANDS,)), ("status", "<i4", (MAX_BANDS,)),
+    ("e_direct", "<f4", (MAX_BANDS,)), ("e_early", "<f4", (MAX_BANDS,)), ("e_late", "<f4", (MAX_BANDS,)),
+    ("g_reverb", "<f4", (MAX_BANDS,)), ("predelay_s", "<f4"), ("first_arrival_s", "<f4"),
+    ("mean_free_path_m", "<f4"), ("reserved", "<f4"), ("dir_loudness", "<f4", (MAX_BANDS, MAX_COEFFS)),
+])
+assert IR_STATS_DTYPE.itemsize == 520 and REVERB_PARAMS_DTYPE.itemsize == 752
+
+_vp = C.c_void_p
+_i64 = C.c_int64
+_i32 = C.c_int32
+
+# name -> (restype, argtypes); every entry point of include/rpr.h
+SIGNATURES = {
+    "scene_create": (C.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "scene_destroy": (C.c_int, [_vp]),
+    "scene_info": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
+    "trace_ir": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp, _vp,
+                           _vp, _vp, _vp]),
+    "estimate_reverb": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, C.c_float, C.POINTER(EstimateParams),
+                                  _vp, _vp]),
+    "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "debug_philox": (C.c_int, [_vp, _i64, _vp, _vp]),
+    "debug_sh_eval": (C.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    "last_error": (C.c_char_p, []),
+    "rpr_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librpr.so (built in-tree by paper_1803_00430_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1803_00430_amd.build`"
+                               " (there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RPR_OK:
+        raise RprError(rc, lib().last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(x, device):
+    import torch
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.float32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, np.float32), device=device)
+
+
+def _dev_i32(x, device):
+    import torch
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=torch.int32).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x, np.int32), device=device)
+
+
+class Scene:
+    """A triangle scene with per-band materials and its BVH on the GPU."""
+
+    def __init__(self, verts, tris, tri_mat, absorption, scattering, device="cuda", stream=None):
+        import torch
+        self.device = torch.device(device)
+        v = _dev_f32(verts, self.device).reshape(-1, 3)
+        t = _dev_i32(tris, self.device).reshape(-1, 3)
+        m = None if tri_mat is None else _dev_i32(tri_mat, self.device).reshape(-1)
+        a = _dev_f32(absorption, self.device)
+        s = _dev_f32(scattering, self.device)
+        if a.dim() != 2 or a.shape != s.shape:
+            raise ValueError("absorption and scattering must both be [materials, bands]")
+        self.n_materials, self.n_bands = int(a.shape[0]), int(a.shape[1])
+        h = C.c_void_p()
+        _check(lib().scene_create(_ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(m), _ptr(a), _ptr(s),
+                                  self.n_materials, self.n_bands, _stream(stream), C.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_dict(cls, d, **kw):
+        return cls(d["verts"], d["tris"], d.get("tri_mat"), d["absorption"], d["scattering"], **kw)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("scene is closed")
+        return self._h
+
+    def info(self) -> dict:
+        si = SceneInfo()
+        _check(lib().scene_info(self.handle, C.byref(si)))
+        return dict(n_tris=si.n_tris, n_nodes=si.n_nodes, max_depth=si.max_depth, n_bands=si.n_bands,
+                    n_materials=si.n_materials, n_degenerate=si.n_degenerate,
+                    bounds_lo=list(si.bounds_lo), bounds_hi=list(si.bounds_hi))
+
+    def closest_hit(self, orig, dirs, stream=None):
+        import torch
+        o = _dev_f32(orig, self.device).reshape(-1, 3)
+        d = _dev_f32(dirs, self.device).reshape(-1, 3)
+        n = o.shape[0]
+        t = torch.empty(n, dtype=torch.float32, device=self.device)
+        tri = torch.empty(n, dtype=torch.int32, device=self.device)
+        _check(lib().scene_closest_hit(self.handle, _ptr(o), _ptr(d), n, _ptr(t), _ptr(tri), _stream(stream)))
+        return t, tri
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace_params(*, n_rays_total, max_bounces, sh_order, n_bins, bin_width_s, seed, ray_begin=0, ray_end=None,
+                 pair_base=0, speed_of_sound=343.0, flags=0) -> TraceParams:
+    return TraceParams(int(n_rays_total), int(ray_begin), int(n_rays_total if ray_end is None else ray_end),
+                       int(max_bounces), int(sh_order), int(n_bins), int(pair_base), float(bin_width_s),
+                       float(speed_of_sound), int(seed), int(flags), 0)
+
+
+def alloc_trace_outputs(n_src, n_bins, n_bands, sh_order, n_rays=0, device="cuda", late=True, want_hash=False):
+    import torch
+    nc = (sh_order + 1) ** 2
+    hist = torch.empty((n_src, n_bins, n_bands, nc), dtype=torch.float32, device=device)
+    hist_late = torch.empty((n_src, n_bins, n_bands), dtype=torch.float32, device=device) if late else None
+    stats = torch.empty((n_src, IR_STATS_DTYPE.itemsize), dtype=torch.uint8, device=device)
+    ray_hash = torch.empty((n_src, n_rays), dtype=torch.int32, device=device) if want_hash else None
+    return hist, hist_late, stats, ray_hash
+
+
+def trace_ir(scene: Scene, sources, listener, radius, params: TraceParams, hist, hist_late, stats, ray_hash=None,
+             stream=None):
+    """Enqueue trace_ir on `stream` into caller-allocated tensors."""
+    srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float32)
+    n = len(srcs)
+    src_arr = (Source * max(n, 1))()
+    for i in range(n):
+        src_arr[i].pos[:] = [float(x) for x in srcs[i]]
+    lp = np.asarray(listener, np.float32)
+    lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
+    _check(lib().trace_ir(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist), _ptr(hist_late),
+                          _ptr(stats), _ptr(ray_hash), _stream(stream)))
+
+
+def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width_s, out, rt60_source=0,
+                    tail_iters=3, stream=None):
+    """Enqueue estimate_reverb; `out` is a uint8 tensor [n_ir, 752]."""
+    n_ir = int(stats.shape[0])
+    ep = EstimateParams(int(rt60_source), int(tail_iters))
+    _check(lib().estimate_reverb(_ptr(hist), _ptr(hist_late), _ptr(stats), n_ir, int(n_bins), int(n_bands),
+                                 int(sh_order), float(bin_width_s), C.byref(ep), _ptr(out), _stream(stream)))
+
+
+def alloc_params(n_ir, device="cuda"):
+    import torch
+    return torch.empty((n_ir, REVERB_PARAMS_DTYPE.itemsize), dtype=torch.uint8, device=device)
+
+
+def stats_host(stats) -> np.ndarray:
+    """Device stats tensor -> numpy structured array (IR_STATS_DTYPE)."""
+    return stats.cpu().numpy().view(IR_STATS_DTYPE).reshape(-1)
+
+
+def params_host(params) -> np.ndarray:
+    return params.cpu().numpy().view(REVERB_PARAMS_DTYPE).reshape(-1)
+
+
+def debug_philox(ctr_key, stream=None):
+    """ctr_key: uint32-valued [n, 6] (ctr0..3, key0..1) -> [n, 4] device outputs."""
+    import torch
+    a = np.ascontiguousarray(ctr_key, np.uint32).view(np.int32)
+    t = torch.as_tensor(a, device="cuda")
+    out = torch.empty((a.shape[0], 4), dtype=torch.int32, device="cuda")
+    _check(lib().debug_philox(_ptr(t), a.shape[0], _ptr(out), _stream(stream)))
+    return out
+
+
+def debug_sh_eval(dirs, order, stream=None):
+    import torch
+    d = _dev_f32(dirs, "cuda").reshape(-1, 3)
+    out = torch.empty((d.shape[0], MAX_COEFFS), dtype=torch.float32, device="cuda")
+    _check(lib().debug_sh_eval(_ptr(d), d.shape[0], int(order), _ptr(out), _stream(stream)))
+    return out
+
+
+def header_functions(path: str = HEADER) -> list[str]:
+    """Names of the functions declared in include/rpr.h."""
+    import re
+    src = open(path).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))

@@ -1,0 +1,665 @@
+// Scene creation: material table, triangle records and a linear BVH.
+//
+// Linear BVH (Karras, HPG 2012): 30-bit Morton codes of the triangle
+// centroids in the scene's centroid bounds, a stable least-significant-digit
+// radix sort of (code, triangle) pairs, internal nodes from the longest common
+// prefixes of neighbouring codes (ties broken by the sorted index), and
+// bottom-up bounds where the second child to finish builds its parent.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rpr_device.hpp"
+#include "rpr_internal.hpp"
+
+namespace rpr {
+namespace {
+
+constexpr int kBuildBlock = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kBuildBlock * kSortItems;
+
+// Validation flags, set by the prep kernel and read back by scene_create.
+enum : uint32_t {
+    kBadIndex = 1u,
+    kBadVertex = 2u,
+    kBadMaterial = 4u,
+    kBadCoeff = 8u,
+    kBadTree = 16u,  // internal consistency check of the build failed
+};
+
+struct BuildFlags {
+    uint32_t flags;
+    int32_t max_depth;
+    uint32_t n_degenerate;
+    uint32_t pad;
+    // centroid bounds as order-preserving integer keys of the floats
+    int32_t clo[3], chi[3];
+    int32_t blo[3], bhi[3];  // triangle bounds (all vertices)
+};
+
+__device__ __forceinline__ int32_t ordered(float f)
+{
+    const int32_t i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7FFFFFFF;
+}
+__host__ __device__ inline float unordered(int32_t i)
+{
+    const int32_t j = i >= 0 ? i : i ^ 0x7FFFFFFF;
+    float f;
+    std::memcpy(&f, &j, 4);
+    return f;
+}
+
+__global__ void k_init_flags(BuildFlags* f)
+{
+    if (threadIdx.x == 0) {
+        f->flags = 0;
+        f->max_depth = 0;
+        f->n_degenerate = 0;
+        for (int a = 0; a < 3; ++a) {
+            f->clo[a] = ordered(__builtin_inff());
+            f->chi[a] = ordered(-__builtin_inff());
+            f->blo[a] = ordered(__builtin_inff());
+            f->bhi[a] = ordered(-__builtin_inff());
+        }
+    }
+}
+
+// Material record per material (see kMat* offsets): p_d = mean_b s_b computed
+// in FP64 and rounded to FP32, and the per-band weights applied on a diffuse
+// or specular bounce.
+__global__ void k_materials(const float* __restrict__ absorption, const float* __restrict__ scattering, int nm,
+                            int nb, float* __restrict__ mats, BuildFlags* f)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nm) return;
+    double ssum = 0.0;
+    bool bad = false;
+    for (int b = 0; b < nb; ++b) {
+        const float a = absorption[m * nb + b], s = scattering[m * nb + b];
+        if (!(a >= 0.0f && a <= 1.0f) || !(s >= 0.0f && s <= 1.0f)) bad = true;
+        ssum += (double)s;
+    }
+    if (bad) atomicOr(&f->flags, (uint32_t)kBadCoeff);
+    const float pd = (float)(ssum / (double)nb);
+    float* r = mats + (int64_t)m * kMatStride;
+    for (int i = 0; i < kMatStride; ++i) r[i] = 0.0f;
+    r[kMatPd] = pd;
+    for (int b = 0; b < nb; ++b) {
+        const double a = absorption[m * nb + b], s = scattering[m * nb + b];
+        r[kMatAlpha + b] = (float)a;
+        r[kMatWd + b] = pd > 0.0f ? (float)((1.0 - a) * s / (double)pd) : 0.0f;
+        r[kMatWs + b] = pd < 1.0f ? (float)((1.0 - a) * (1.0 - s) / (1.0 - (double)pd)) : 0.0f;
+    }
+}
+
+// Triangle bounds, centroids and validation; reduces the centroid bounds.
+__global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
+                       const int32_t* __restrict__ tri_mat, int nm, float4* __restrict__ cent,
+                       BuildFlags* f)
+{
+    __shared__ int32_t s_lo[3][kBuildBlock / kWave], s_hi[3][kBuildBlock / kWave];
+    __shared__ int32_t s_blo[3][kBuildBlock / kWave], s_bhi[3][kBuildBlock / kWave];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float c[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float cm[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    if (t < nt) {
+        uint32_t flags = 0;
+        int32_t idx[3];
+        for (int k = 0; k < 3; ++k) {
+            idx[k] = tris[3 * t + k];
+            if (idx[k] < 0 || idx[k] >= nv) {
+                flags |= kBadIndex;
+                idx[k] = 0;
+            }
+        }
+        if (tri_mat) {
+            const int32_t m = tri_mat[t];
+            if (m < 0 || m >= nm) flags |= kBadMaterial;
+        }
+        float v[3][3];
+        for (int k = 0; k < 3; ++k)
+            for (int a = 0; a < 3; ++a) {
+                v[k][a] = nv > 0 ? verts[3 * (int64_t)idx[k] + a] : 0.0f;
+                if (!isfinite(v[k][a])) flags |= kBadVertex;
+            }
+        const float e1x = v[1][0] - v[0][0], e1y = v[1][1] - v[0][1], e1z = v[1][2] - v[0][2];
+        const float e2x = v[2][0] - v[0][0], e2y = v[2][1] - v[0][1], e2z = v[2][2] - v[0][2];
+        const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+        if (nx == 0.0f && ny == 0.0f && nz == 0.0f) atomicAdd(&f->n_degenerate, 1u);
+        if (flags) atomicOr(&f->flags, flags);
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
+            hi[a] = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
+            c[a] = cm[a] = 0.5f * (lo[a] + hi[a]);
+        }
+        cent[t] = make_float4(c[0], c[1], c[2], 0.0f);
+    }
+    // wave then block reduction of the bounds
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) {
+            c[a] = fminf(c[a], __shfl_xor(c[a], o));
+            cm[a] = fmaxf(cm[a], __shfl_xor(cm[a], o));
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
+        }
+        if (lane == 0) {
+            s_lo[a][w] = ordered(c[a]);
+            s_hi[a][w] = ordered(cm[a]);
+            s_blo[a][w] = ordered(lo[a]);
+            s_bhi[a][w] = ordered(hi[a]);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        const int a = threadIdx.x;
+        int32_t l = s_lo[a][0], h = s_hi[a][0], bl = s_blo[a][0], bh = s_bhi[a][0];
+        for (int i = 1; i < kBuildBlock / kWave; ++i) {
+            l = min(l, s_lo[a][i]);
+            h = max(h, s_hi[a][i]);
+            bl = min(bl, s_blo[a][i]);
+            bh = max(bh, s_bhi[a][i]);
+        }
+        atomicMin(&f->clo[a], l);
+        atomicMax(&f->chi[a], h);
+        atomicMin(&f->blo[a], bl);
+        atomicMax(&f->bhi[a], bh);
+    }
+}
+
+// Spread the low 10 bits of v to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(const float4* __restrict__ cent, int64_t nt, const BuildFlags* f,
+                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const float4 c = cent[t];
+    const float cc[3] = {c.x, c.y, c.z};
+    uint32_t code = 0;
+    for (int a = 0; a < 3; ++a) {
+        const float lo = unordered(f->clo[a]), hi = unordered(f->chi[a]);
+        const float ext = hi - lo;
+        float u = ext > 0.0f ? (cc[a] - lo) / ext : 0.5f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const uint32_t q = min((uint32_t)(u * 1024.0f), 1023u);
+        code |= spread3(q) << (2 - a);
+    }
+    keys[t] = code;
+    vals[t] = (uint32_t)t;
+}
+
+// ---------------------------------------------------------------- radix sort
+// Per-tile digit counts, stored digit-major: counts[d * n_tiles + tile].
+__global__ void __launch_bounds__(kBuildBlock) k_radix_count(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                             uint32_t* __restrict__ counts, int n_tiles)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + r * kBuildBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of the digit-major counts in one workgroup of 1024 threads.
+__global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* __restrict__ counts, int64_t len)
+{
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t b = t * per, e = min(len, b + per);
+    uint32_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[t] = s;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const uint32_t v = t >= o ? part[t - o] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t c = counts[i];
+        counts[i] = run;
+        run += c;
+    }
+}
+
+// Stable scatter: each tile is processed in rounds of 256 keys; within a
+// round, lanes of a wave with equal digits are matched by eight ballots and
+// ranked by position, and waves are ordered through per-digit counters.
+__global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
+                                                               const uint32_t* __restrict__ vals_in, int64_t n,
+                                                               int shift, const uint32_t* __restrict__ offsets,
+                                                               int n_tiles, uint32_t* __restrict__ keys_out,
+                                                               uint32_t* __restrict__ vals_out, BuildFlags* bad)
+{
+    constexpr int W = kBuildBlock / kWave;
+    __shared__ uint32_t g_off[256];
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcnt[W][256];
+    __shared__ uint32_t woff[W][256];
+    const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
+    g_off[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+    run[tid] = 0;
+    for (int i = 0; i < W; ++i) wcnt[i][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + r * kBuildBlock + tid;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t val = valid ? vals_in[i] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            const uint64_t b = __ballot((d >> bit) & 1u);
+            peers &= ((d >> bit) & 1u) ? b : ~b;
+        }
+        const uint32_t rank = __popcll(peers & lanemask_lt(lane));
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        {
+            uint32_t s = run[tid];
+            for (int k = 0; k < W; ++k) {
+                woff[k][tid] = s;
+                s += wcnt[k][tid];
+                wcnt[k][tid] = 0;
+            }
+            run[tid] = s;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = g_off[d] + woff[w][d] + rank;
+            if (pos < (uint64_t)n) {
+                keys_out[pos] = key;
+                vals_out[pos] = val;
+            } else {
+                atomicOr(&bad->flags, (uint32_t)kBadTree);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- hierarchy
+__device__ __forceinline__ int delta(const uint32_t* __restrict__ k, int n, int i, int j)
+{
+    if (j < 0 || j >= n) return -1;
+    const uint32_t a = k[i], b = k[j];
+    if (a != b) return __clz(a ^ b);
+    return 32 + __clz((uint32_t)(i ^ j));
+}
+
+// Internal node i covers a key range [min(i,j), max(i,j)] grown from i in the
+// direction of the neighbour with the longer common prefix; it splits where
+// the common prefix of the range ends.  parent[] indexes internal nodes
+// 0..n-2 then leaves n-1..2n-2.
+__global__ void k_karras(const uint32_t* __restrict__ keys, int n, int2* __restrict__ child,
+                         int32_t* __restrict__ parent, BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
+    const int dmin = delta(keys, n, i, i - d);
+    int lmax = 2;
+    while (delta(keys, n, i, i + lmax * d) > dmin) lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (delta(keys, n, i, i + (l + t) * d) > dmin) l += t;
+    const int j = i + l * d;
+    const int dnode = delta(keys, n, i, j);
+    int s = 0;
+    int t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (delta(keys, n, i, i + (s + t) * d) > dnode) s += t;
+    } while (t > 1);
+    const int g = i + s * d + min(d, 0);
+    const int lo = min(i, j), hi = max(i, j);
+    if (g < 0 || g + 1 > n - 1 || lo < 0 || hi > n - 1) {
+        // cannot happen for a correct split search; keep every index in range
+        atomicOr(&f->flags, (uint32_t)kBadTree);
+        child[i] = make_int2(leaf_link(0), leaf_link(0));
+        return;
+    }
+    const int c0 = (lo == g) ? leaf_link(g) : g;
+    const int c1 = (hi == g + 1) ? leaf_link(g + 1) : g + 1;
+    child[i] = make_int2(c0, c1);
+    parent[is_leaf(c0) ? (n - 1) + leaf_index(c0) : c0] = i;
+    parent[is_leaf(c1) ? (n - 1) + leaf_index(c1) : c1] = i;
+}
+
+// Sorted triangle records and leaf bounds (box[n-1+i]).
+__global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris,
+                              const int32_t* __restrict__ tri_mat, const uint32_t* __restrict__ order, int n,
+                              float4* __restrict__ recs, float4* __restrict__ box, uint32_t* __restrict__ seen,
+                              BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t t = order[i];
+    if (t >= (uint32_t)n) {
+        atomicOr(&f->flags, (uint32_t)kBadTree);
+        t = 0;
+    } else if (atomicAdd(&seen[t], 1u) != 0u) {
+        atomicOr(&f->flags, (uint32_t)kBadTree);  // not a permutation
+    }
+    float v[3][3];
+    for (int k = 0; k < 3; ++k) {
+        int32_t vi = tris[3 * (int64_t)t + k];
+        if (vi < 0 || vi >= nv) vi = 0;  // flagged by k_prep; the scene is rejected after the build
+        for (int a = 0; a < 3; ++a) v[k][a] = verts[3 * (int64_t)vi + a];
+    }
+    const int32_t m = tri_mat ? tri_mat[t] : 0;
+    recs[3 * (int64_t)i + 0] = make_float4(v[0][0], v[0][1], v[0][2], __uint_as_float(t));
+    recs[3 * (int64_t)i + 1] =
+        make_float4(v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2], __int_as_float(m));
+    recs[3 * (int64_t)i + 2] = make_float4(v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2], 0.0f);
+    float lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
+        hi[a] = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
+    }
+    const int64_t b = (int64_t)(n - 1) + i;
+    box[2 * b + 0] = make_float4(lo[0], lo[1], lo[2], 0.0f);
+    box[2 * b + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
+}
+
+// Bottom-up bounds: every leaf walks towards the root; at each internal node
+// the first arrival stops and the second (which then sees both children's
+// bounds) computes the union and continues.
+__global__ void k_refit(int n, const int2* __restrict__ child, const int32_t* __restrict__ parent,
+                        uint32_t* __restrict__ arrivals, float4* __restrict__ box)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int node = parent[(n - 1) + i];
+    // a tree of depth > kMaxStack is rejected anyway; the bound only keeps a
+    // malformed parent chain from looping
+    for (int guard = 0; node >= 0 && guard < 4 * kMaxStack; ++guard) {
+        const uint32_t prev =
+            __hip_atomic_fetch_add(&arrivals[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == 0) return;
+        const int2 c = child[node];
+        const int64_t a = is_leaf(c.x) ? (int64_t)(n - 1) + leaf_index(c.x) : c.x;
+        const int64_t b = is_leaf(c.y) ? (int64_t)(n - 1) + leaf_index(c.y) : c.y;
+        const float4 alo = box[2 * a], ahi = box[2 * a + 1], blo = box[2 * b], bhi = box[2 * b + 1];
+        box[2 * (int64_t)node + 0] =
+            make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
+        box[2 * (int64_t)node + 1] =
+            make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
+        __atomic_thread_fence(__ATOMIC_RELEASE);
+        if (node == 0) return;
+        node = parent[node];
+    }
+}
+
+// Structure check: every link in range, and every node except the root
+// referenced by exactly one parent (refs indexes internal nodes then leaves).
+__global__ void k_check_links(int n, const int2* __restrict__ child, uint32_t* __restrict__ refs, BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int2 c = child[i];
+    const int32_t l[2] = {c.x, c.y};
+    for (int k = 0; k < 2; ++k) {
+        const int64_t idx = is_leaf(l[k]) ? (int64_t)(n - 1) + leaf_index(l[k]) : l[k];
+        const bool ok = is_leaf(l[k]) ? (leaf_index(l[k]) < n) : (l[k] > 0 && l[k] < n - 1);
+        if (!ok) atomicOr(&f->flags, (uint32_t)kBadTree);
+        else atomicAdd(&refs[idx], 1u);
+    }
+}
+
+__global__ void k_check_refs(int n, const uint32_t* __restrict__ refs, BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 2 * n - 1) return;
+    const uint32_t want = i == 0 ? 0u : 1u;
+    if (refs[i] != want) atomicOr(&f->flags, (uint32_t)kBadTree);
+}
+
+// Traversal nodes: both children's boxes and links in 64 bytes.
+__global__ void k_pack(int n, const int2* __restrict__ child, const float4* __restrict__ box,
+                       float4* __restrict__ nodes)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int2 c = child[i];
+    const int64_t a = is_leaf(c.x) ? (int64_t)(n - 1) + leaf_index(c.x) : c.x;
+    const int64_t b = is_leaf(c.y) ? (int64_t)(n - 1) + leaf_index(c.y) : c.y;
+    const float4 alo = box[2 * a], ahi = box[2 * a + 1], blo = box[2 * b], bhi = box[2 * b + 1];
+    nodes[4 * (int64_t)i + 0] = make_float4(alo.x, alo.y, alo.z, ahi.x);
+    nodes[4 * (int64_t)i + 1] = make_float4(ahi.y, ahi.z, blo.x, blo.y);
+    nodes[4 * (int64_t)i + 2] = make_float4(blo.z, bhi.x, bhi.y, bhi.z);
+    nodes[4 * (int64_t)i + 3] = make_float4(__int_as_float(c.x), __int_as_float(c.y), 0.0f, 0.0f);
+}
+
+// Depth of every leaf (edges to the root); the maximum sizes the traversal stack.
+__global__ void k_depth(int n, const int32_t* __restrict__ parent, BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int d = 0;
+    int node = parent[(n - 1) + i];
+    while (node >= 0 && d <= 4 * kMaxStack) {
+        ++d;
+        node = node == 0 ? -1 : parent[node];
+    }
+    atomicMax(&f->max_depth, d);
+}
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n)
+    {
+        return hipMalloc(&p, sizeof(T) * (n ? n : 1));
+    }
+};
+
+inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+}  // namespace rpr
+
+using namespace rpr;
+
+extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                            const int32_t* tri_material, const float* absorption, const float* scattering,
+                            int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out)
+{
+    if (!out) return set_error(RPR_EINVAL, "scene_create: out is null");
+    *out = nullptr;
+    if (n_bands < 1 || n_bands > RPR_MAX_BANDS)
+        return set_error(RPR_EINVAL, "scene_create: n_bands=%d not in 1..%d", n_bands, RPR_MAX_BANDS);
+    if (n_materials < 1) return set_error(RPR_EINVAL, "scene_create: n_materials=%d < 1", n_materials);
+    if (n_tris < 0 || n_verts < 0) return set_error(RPR_EINVAL, "scene_create: negative size");
+    if (n_tris > (int64_t)1 << 30) return set_error(RPR_EUNSUPPORTED, "scene_create: n_tris=%lld too large", (long long)n_tris);
+    if (n_tris > 0 && (!verts || !tris || n_verts < 1))
+        return set_error(RPR_EINVAL, "scene_create: null geometry with n_tris=%lld", (long long)n_tris);
+    if (!absorption || !scattering) return set_error(RPR_EINVAL, "scene_create: null material arrays");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int n = (int)n_tris;
+
+    RprScene* sc = new RprScene();
+    auto fail = [&](int code) {
+        if (sc->nodes) (void)hipFree(sc->nodes);
+        if (sc->tris) (void)hipFree(sc->tris);
+        if (sc->mats) (void)hipFree(sc->mats);
+        workspace_free(sc->ws);
+        delete sc;
+        return code;
+    };
+    {
+        hipError_t e = hipGetDevice(&sc->device);
+        if (e != hipSuccess) return fail(set_error(RPR_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+    }
+    sc->n_tris = n_tris;
+    sc->n_bands = n_bands;
+    sc->n_materials = n_materials;
+
+#define TRY(expr)                                                                                 \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(set_error(e_ == hipErrorOutOfMemory ? RPR_ENOMEM : RPR_EDEVICE,           \
+                                  "scene_create: %s: %s", #expr, hipGetErrorString(e_)));         \
+    } while (0)
+
+    DevBuf<BuildFlags> flags;
+    TRY(flags.alloc(1));
+    TRY(hipMalloc(&sc->mats, sizeof(float) * kMatStride * n_materials));
+    TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
+    TRY(hipMalloc(&sc->nodes, sizeof(float4) * 4 * (size_t)(n > 1 ? n - 1 : 1)));
+    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
+    hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
+                       n_materials, n_bands, sc->mats, flags.p);
+    TRY(hipGetLastError());
+
+    if (n > 0) {
+        const int n_tiles = (int)blocks(n, kSortTile);
+        DevBuf<float4> cent, box;
+        DevBuf<uint32_t> k0, v0, k1, v1, counts, arrivals, seen, refs;
+        DevBuf<int2> child;
+        DevBuf<int32_t> parent;
+        TRY(cent.alloc(n));
+        TRY(k0.alloc(n));
+        TRY(v0.alloc(n));
+        TRY(k1.alloc(n));
+        TRY(v1.alloc(n));
+        TRY(counts.alloc((size_t)256 * n_tiles));
+        TRY(box.alloc(2 * (size_t)(2 * n - 1)));
+        TRY(child.alloc(n > 1 ? n - 1 : 1));
+        TRY(parent.alloc(2 * (size_t)n - 1));
+        TRY(arrivals.alloc(n > 1 ? n - 1 : 1));
+        TRY(seen.alloc(n));
+        TRY(refs.alloc(2 * (size_t)n - 1));
+        TRY(hipMemsetAsync(seen.p, 0, sizeof(uint32_t) * n, st));
+        TRY(hipMemsetAsync(refs.p, 0, sizeof(uint32_t) * (2 * (size_t)n - 1), st));
+        hipLaunchKernelGGL(k_prep, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts, n_verts, tris,
+                           n_tris, tri_material, n_materials, cent.p, flags.p);
+        hipLaunchKernelGGL(k_morton, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent.p, n_tris,
+                           flags.p, k0.p, v0.p);
+        uint32_t *ki = k0.p, *vi = v0.p, *ko = k1.p, *vo = v1.p;
+        for (int shift = 0; shift < 32; shift += 8) {
+            hipLaunchKernelGGL(k_radix_count, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n_tris, shift, counts.p,
+                               n_tiles);
+            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, counts.p, (int64_t)256 * n_tiles);
+            hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, vi, n_tris, shift,
+                               counts.p, n_tiles, ko, vo, flags.p);
+            std::swap(ki, ko);
+            std::swap(vi, vo);
+        }
+        // after four passes the sorted keys/ids are back in (k0, v0)
+        TRY(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), st));
+        TRY(hipMemsetAsync(arrivals.p, 0, sizeof(uint32_t) * (n > 1 ? n - 1 : 1), st));
+        hipLaunchKernelGGL(k_tri_records, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts,
+                           n_verts, tris, tri_material, vi, n, sc->tris, box.p, seen.p, flags.p);
+        if (n > 1) {
+            hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, ki, n,
+                               child.p, parent.p, flags.p);
+            hipLaunchKernelGGL(k_check_links, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
+                               child.p, refs.p, flags.p);
+            hipLaunchKernelGGL(k_check_refs, dim3(blocks(2 * (int64_t)n - 1, kBuildBlock)), dim3(kBuildBlock), 0,
+                               st, n, refs.p, flags.p);
+            hipLaunchKernelGGL(k_refit, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
+                               parent.p, arrivals.p, box.p);
+            hipLaunchKernelGGL(k_pack, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
+                               box.p, sc->nodes);
+            hipLaunchKernelGGL(k_depth, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,
+                               flags.p);
+        }
+        TRY(hipGetLastError());
+        BuildFlags hf;
+        TRY(hipMemcpyAsync(&hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, st));
+        TRY(hipStreamSynchronize(st));
+        if (hf.flags & kBadIndex) return fail(set_error(RPR_EINVAL, "scene_create: vertex index out of range"));
+        if (hf.flags & kBadVertex) return fail(set_error(RPR_EINVAL, "scene_create: non-finite vertex"));
+        if (hf.flags & kBadMaterial) return fail(set_error(RPR_EINVAL, "scene_create: material index out of range"));
+        if (hf.flags & kBadCoeff)
+            return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
+        if (hf.flags & kBadTree) return fail(set_error(RPR_EDEVICE, "scene_create: BVH consistency check failed"));
+        sc->max_depth = hf.max_depth;
+        sc->n_degenerate = (int32_t)hf.n_degenerate;
+        for (int a = 0; a < 3; ++a) {
+            sc->lo[a] = unordered(hf.blo[a]);
+            sc->hi[a] = unordered(hf.bhi[a]);
+        }
+        if (sc->max_depth > kMaxStack)
+            return fail(set_error(RPR_EUNSUPPORTED, "scene_create: BVH depth %d exceeds the traversal stack %d",
+                                  sc->max_depth, kMaxStack));
+    } else {
+        BuildFlags hf;
+        TRY(hipMemcpyAsync(&hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, st));
+        TRY(hipStreamSynchronize(st));
+        if (hf.flags & kBadCoeff)
+            return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
+    }
+#undef TRY
+    sc->view.nodes = sc->nodes;
+    sc->view.tris = sc->tris;
+    sc->view.mats = sc->mats;
+    sc->view.root = n == 1 ? leaf_link(0) : 0;
+    sc->view.n_tris = n;
+    sc->view.n_bands = n_bands;
+    *out = sc;
+    return RPR_OK;
+}
+
+extern "C" int scene_destroy(RprScene* scene)
+{
+    if (!scene) return RPR_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    if (dev != scene->device) (void)hipSetDevice(scene->device);
+    (void)hipFree(scene->nodes);
+    (void)hipFree(scene->tris);
+    (void)hipFree(scene->mats);
+    workspace_free(scene->ws);
+    if (dev >= 0 && dev != scene->device) (void)hipSetDevice(dev);
+    delete scene;
+    return RPR_OK;
+}
+
+extern "C" int scene_info(const RprScene* scene, RprSceneInfo* out)
+{
+    if (!scene || !out) return set_error(RPR_EINVAL, "scene_info: null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n_tris = scene->n_tris;
+    out->n_nodes = scene->n_tris > 1 ? scene->n_tris - 1 : 0;
+    out->max_depth = scene->max_depth;
+    out->n_bands = scene->n_bands;
+    out->n_materials = scene->n_materials;
+    out->n_degenerate = scene->n_degenerate;
+    for (int a = 0; a < 3; ++a) {
+        out->bounds_lo[a] = scene->lo[a];
+        out->bounds_hi[a] = scene->hi[a];
+    }
+    return RPR_OK;
+}

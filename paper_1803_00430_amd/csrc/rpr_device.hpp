@@ -1,0 +1,224 @@
+// Device-side primitives of the trace: the counter-based random stream, real
+// spherical harmonics, the orthonormal basis of a normal, and the ray/box and
+// ray/triangle tests of the BVH traversal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "rpr_internal.hpp"
+
+namespace rpr {
+
+// ---------------------------------------------------------------- random stream
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
+// multiplies whose halves are xored with the other two words and the key;
+// the key advances by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a = c.x, b = c.z;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, a), lo_a = 0xD2511F53u * a;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, b), lo_b = 0xCD9E8D57u * b;
+        c = make_uint4(hi_b ^ c.y ^ k0, lo_b, hi_a ^ c.w ^ k1, lo_a);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Odd multiple of 2^-24 in (0, 1) from the top 23 bits: exact in FP32.
+__device__ __forceinline__ float u01(uint32_t x)
+{
+    return (float)((x >> 9) * 2u + 1u) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------- real SH
+// Real orthonormal spherical harmonics with the Condon-Shortley phase as
+// polynomials in the unit vector (x, y, z), coefficient index l(l+1)+m, l <= 3.
+__device__ __forceinline__ float sh_coeff(int k, float x, float y, float z)
+{
+    switch (k) {
+    case 0: return 0.28209479177387814f;
+    case 1: return -0.4886025119029199f * y;
+    case 2: return 0.4886025119029199f * z;
+    case 3: return -0.4886025119029199f * x;
+    case 4: return 1.0925484305920792f * x * y;
+    case 5: return -1.0925484305920792f * y * z;
+    case 6: return 0.31539156525252005f * (3.0f * z * z - 1.0f);
+    case 7: return -1.0925484305920792f * x * z;
+    case 8: return 0.5462742152960396f * (x * x - y * y);
+    case 9: return -0.5900435899266435f * y * (3.0f * x * x - y * y);
+    case 10: return 2.890611442640554f * x * y * z;
+    case 11: return -0.4570457994644658f * y * (5.0f * z * z - 1.0f);
+    case 12: return 0.3731763325901154f * z * (5.0f * z * z - 3.0f);
+    case 13: return -0.4570457994644658f * x * (5.0f * z * z - 1.0f);
+    case 14: return 1.445305721320277f * z * (x * x - y * y);
+    case 15: return -0.5900435899266435f * x * (x * x - 3.0f * y * y);
+    default: return 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------- directions
+// Uniform direction on the sphere from two uniforms.
+__device__ __forceinline__ void sphere_dir(float u0, float u1, float& x, float& y, float& z)
+{
+    z = 1.0f - 2.0f * u0;                       // exact
+    const float rxy = 2.0f * sqrtf(u0 * (1.0f - u0)); // sqrt(1 - z^2) without cancellation
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    x = rxy * c;
+    y = rxy * s;
+}
+
+// Cosine-weighted direction about the unit normal n, through the branchless
+// orthonormal basis of Duff et al. (JCGT 2017).
+__device__ __forceinline__ void lambert_dir(float nx, float ny, float nz, float u1, float u2, float& dx,
+                                            float& dy, float& dz)
+{
+    const float sg = nz >= 0.0f ? 1.0f : -1.0f;
+    const float a = -1.0f / (sg + nz);
+    const float b = nx * ny * a;
+    const float b1x = 1.0f + sg * nx * nx * a, b1y = sg * b, b1z = -sg * nx;
+    const float b2x = b, b2y = sg + ny * ny * a, b2z = -ny;
+    const float rr = sqrtf(u2);
+    float s, c;
+    sincospif(2.0f * u1, &s, &c);
+    const float lx = rr * c, ly = rr * s, lz = sqrtf(1.0f - u2);
+    dx = lx * b1x + ly * b2x + lz * nx;
+    dy = lx * b1y + ly * b2y + lz * ny;
+    dz = lx * b1z + ly * b2z + lz * nz;
+}
+
+// ---------------------------------------------------------------- intersection
+// Slab test of one box against [0, tmax]; tmax is widened by a few ulps so
+// that flat boxes (axis-aligned walls) are not lost to rounding.
+__device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz,
+                                     float ox, float oy, float oz, float ix, float iy, float iz, float tmax,
+                                     float& tnear)
+{
+    const float t0x = (lox - ox) * ix, t1x = (hix - ox) * ix;
+    const float t0y = (loy - oy) * iy, t1y = (hiy - oy) * iy;
+    const float t0z = (loz - oz) * iz, t1z = (hiz - oz) * iz;
+    const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
+    const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tnear = tn;
+    return tn <= tf * 1.00000048f;
+}
+
+// Moller-Trumbore against a precomputed (v0, e1, e2) record; the barycentric
+// bounds are widened by 1e-6 so that rays through a shared edge hit one of
+// its two triangles.  Returns t > 0 or +inf.
+__device__ __forceinline__ float tri_test(const float4 a, const float4 b, const float4 c, float ox, float oy,
+                                          float oz, float dx, float dy, float dz)
+{
+    const float e1x = b.x, e1y = b.y, e1z = b.z;
+    const float e2x = c.x, e2y = c.y, e2z = c.z;
+    const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
+    const float det = e1x * px + e1y * py + e1z * pz;
+    const float inv = 1.0f / det;
+    const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
+    const float u = (sx * px + sy * py + sz * pz) * inv;
+    const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
+    const float v = (dx * qx + dy * qy + dz * qz) * inv;
+    const float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    const float eps = 1e-6f;
+    const bool ok = det != 0.0f && u >= -eps && v >= -eps && u + v <= 1.0f + eps && t > 0.0f;
+    return ok ? t : __builtin_inff();
+}
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    const float m = 1e-30f;
+    return 1.0f / (fabsf(d) > m ? d : (d >= 0.0f ? m : -m));
+}
+
+// Closest hit with a per-lane stack in LDS (stack[slot * 64 + lane]).  The
+// leaf `exclude` (sorted index) is skipped: the triangle the ray just left.
+// Ties in t go to the lower original triangle index.  Returns the sorted leaf
+// index of the hit or -1, with t in `t_hit`.
+template <int STACK, bool COUNT = false>
+__device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float oy, float oz, float dx, float dy,
+                                           float dz, int exclude, int32_t* __restrict__ stack, int lane,
+                                           float& t_hit, uint32_t& hit_id, uint32_t* n_nodes = nullptr,
+                                           uint32_t* n_tris = nullptr)
+{
+    float tb = __builtin_inff();
+    int best = -1;
+    uint32_t best_id = 0xFFFFFFFFu;
+    if (sc.n_tris <= 0) {
+        t_hit = tb;
+        hit_id = best_id;
+        return -1;
+    }
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    int sp = 0;
+    int32_t node = sc.root;
+    for (;;) {
+        if (!is_leaf(node)) {
+            const float4* n = sc.nodes + 4 * (int64_t)node;
+            const float4 a = n[0], b = n[1], c = n[2], l = n[3];
+            if (COUNT) ++*n_nodes;
+            float t0, t1;
+            const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, ox, oy, oz, ix, iy, iz, tb, t0);
+            const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, ox, oy, oz, ix, iy, iz, tb, t1);
+            const int32_t l0 = __float_as_int(l.x), l1 = __float_as_int(l.y);
+            if (h0 && h1) {
+                const bool first0 = t0 <= t1;
+                const int32_t nearl = first0 ? l0 : l1, farl = first0 ? l1 : l0;
+                // The stack is at least as deep as the tree (checked when the
+                // scene is built); a full stack would drop the far child
+                // rather than write out of bounds.
+                if (sp < STACK) stack[sp++ * kWave + lane] = farl;
+                node = nearl;
+                continue;
+            }
+            if (h0 || h1) {
+                node = h0 ? l0 : l1;
+                continue;
+            }
+        } else {
+            const int li = leaf_index(node);
+            if (li != exclude) {
+                const float4* t = sc.tris + 3 * (int64_t)li;
+                const float4 a = t[0], b = t[1], c = t[2];
+                if (COUNT) ++*n_tris;
+                const float th = tri_test(a, b, c, ox, oy, oz, dx, dy, dz);
+                const uint32_t id = __float_as_uint(a.w);
+                if (th < tb || (th == tb && id < best_id)) {
+                    tb = th;
+                    best = li;
+                    best_id = id;
+                }
+            }
+        }
+        if (sp == 0) break;
+        node = stack[--sp * kWave + lane];
+    }
+    t_hit = tb;
+    hit_id = best_id;
+    return best;
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (lane == 0) ? 0ull : (~0ull >> (64 - lane)); }
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t fnv1a(uint32_t h, uint32_t w) { return (h ^ w) * 16777619u; }
+
+}  // namespace rpr

@@ -1,0 +1,116 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/rpr.h"
+
+namespace rpr {
+
+// Thread-local error message; set_error returns the code for `return set_error(...)`.
+int set_error(int code, const char* fmt, ...);
+
+#define RPR_HIP_TRY(expr)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            return ::rpr::set_error(e_ == hipErrorOutOfMemory ? RPR_ENOMEM : RPR_EDEVICE,  \
+                                    "%s: %s (%s:%d)", #expr, hipGetErrorString(e_),        \
+                                    __FILE__, __LINE__);                                   \
+        }                                                                                  \
+    } while (0)
+
+constexpr int kWave = 64;
+constexpr int kMaxStack = 64;       // traversal stack entries per lane (>= max tree depth)
+constexpr int kMatStride = 32;      // floats per material record
+// Material record: [0] p_diffuse, [1 + b] alpha_b, [9 + b] diffuse weight
+// (1-alpha_b) s_b / p_d, [17 + b] specular weight (1-alpha_b)(1-s_b)/(1-p_d).
+constexpr int kMatPd = 0, kMatAlpha = 1, kMatWd = 9, kMatWs = 17;
+
+// Node links: >= 0 internal node index, < 0 leaf = ~sorted triangle index.
+__host__ __device__ inline bool is_leaf(int32_t link) { return link < 0; }
+__host__ __device__ inline int32_t leaf_index(int32_t link) { return ~link; }
+__host__ __device__ inline int32_t leaf_link(int32_t i) { return ~i; }
+
+// One scene's BVH as consumed by the traversal kernels.
+//   nodes: 4 float4 per internal node:
+//     n0 = (c0.lo.x, c0.lo.y, c0.lo.z, c0.hi.x)
+//     n1 = (c0.hi.y, c0.hi.z, c1.lo.x, c1.lo.y)
+//     n2 = (c1.lo.z, c1.hi.x, c1.hi.y, c1.hi.z)
+//     n3 = (link0, link1, 0, 0) as int bits
+//   tris: 3 float4 per triangle in Morton (leaf) order:
+//     (v0.xyz, original index bits), (e1.xyz, material bits), (e2.xyz, 0)
+struct SceneView {
+    const float4* nodes;
+    const float4* tris;
+    const float* mats;
+    int32_t root;  // link of the root (leaf link when n_tris == 1; 0 when empty and n_tris == 0)
+    int32_t n_tris;
+    int32_t n_bands;
+    int32_t pad;
+};
+
+// Per source-listener pair, as read by the trace kernel.
+struct PairDesc {
+    SceneView scene;
+    float src[3];
+    float lst[3];
+    float radius;
+    float inv_vs;       // 1 / sphere volume
+    float c;            // speed of sound
+    float dt;           // bin width
+    float l_window;     // path length at which the histogram window ends: c * T * dt
+    float e0;           // 1 / n_rays_total
+    int32_t n_bins;
+    int32_t max_bounces;
+    int32_t sh_order;
+    int32_t n_coeffs;
+    uint32_t key0, key1;
+    uint32_t pair_id;   // RNG counter word 1
+    int32_t flags;      // RPR_TRACE_* bits
+    int64_t ray_begin;  // absolute id of the pair's first ray
+    int64_t n_rays;     // rays of this pair in the launch
+    int64_t queue_begin;// first global queue slot of this pair
+    float* hist;        // [T][B][NC]
+    float* hist_late;   // [T][B] or null
+    RprIrStats* stats;
+    uint32_t* ray_hash; // [n_rays] or null
+};
+
+struct Workspace {
+    void* dev = nullptr;      // queue counter (+ padding) followed by the pair table
+    size_t bytes = 0;
+    void* host_pin = nullptr; // pinned staging for the pair table
+    size_t host_bytes = 0;
+};
+
+}  // namespace rpr
+
+struct RprScene {
+    int device = 0;
+    int64_t n_tris = 0;
+    int32_t n_bands = 0;
+    int32_t n_materials = 0;
+    int32_t max_depth = 0;
+    int32_t n_degenerate = 0;
+    float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    float4* nodes = nullptr;
+    float4* tris = nullptr;
+    float* mats = nullptr;
+    rpr::SceneView view{};
+    rpr::Workspace ws;
+};
+
+namespace rpr {
+// Ensure the workspace holds `pairs` pair descriptors; returns RPR_OK or an error.
+int workspace_reserve(Workspace& ws, size_t pairs);
+void workspace_free(Workspace& ws);
+// Launch the persistent trace over `n_pairs` descriptors already in device memory.
+int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
+                 int nb, int max_depth, bool count_visits, int grid_override, hipStream_t stream);
+int device_cu_count();
+}  // namespace rpr

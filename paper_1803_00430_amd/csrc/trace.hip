@@ -1,0 +1,671 @@
+// Persistent stochastic ray tracing from sources to a listener sphere.
+//
+// One wave per workgroup.  Each lane owns one ray at a time; lanes whose ray
+// has terminated are refilled from a global queue of (pair, ray) slots with
+// one atomic per wave, so waves stay full while ray lifetimes differ (an
+// escape after one segment vs. a hundred bounces).  Closest hits use the
+// scene's linear BVH with a per-lane node stack in LDS.  Listener-sphere
+// deposits are gathered over the wave and issued as coalesced atomics: for
+// each depositing lane, the 64 lanes cover the band x SH-coefficient row of a
+// histogram bin (4 bands x 16 coefficients at SH order 3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "rpr_device.hpp"
+#include "rpr_internal.hpp"
+
+namespace rpr {
+namespace {
+
+constexpr int kSetupChunk = 64;
+
+// Per-lane statistics of the rays one lane traced for pair `p`.
+template <int NB>
+struct LaneAcc {
+    int p;
+    uint32_t seg, fin, esc, rays, nodes, tris;
+    double len;
+    float esc_e[NB], alive[NB], cap[NB], absb[NB];
+};
+
+template <int NB>
+__device__ __forceinline__ void lane_acc_zero(LaneAcc<NB>& a)
+{
+    a.p = -1;
+    a.seg = a.fin = a.esc = a.rays = a.nodes = a.tris = 0;
+    a.len = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) a.esc_e[b] = a.alive[b] = a.cap[b] = a.absb[b] = 0.0f;
+}
+
+// Segmented wave reduction of every lane's accumulators by pair, one set of
+// global atomics per distinct pair.
+template <int NB, bool COUNT>
+__device__ __forceinline__ void lane_acc_flush(LaneAcc<NB>& a, const PairDesc* __restrict__ pairs, int lane)
+{
+    uint64_t rem = __ballot(a.p >= 0);
+    while (rem) {
+        const int l0 = __ffsll((unsigned long long)rem) - 1;
+        const int q = __builtin_amdgcn_readfirstlane(__shfl(a.p, l0));
+        const bool in = a.p == q;
+        const uint64_t m = __ballot(in);
+        RprIrStats* S = pairs[q].stats;
+        const int nb = pairs[q].scene.n_bands;
+        const float e0 = pairs[q].e0;
+        const uint32_t seg = wave_sum_u32(in ? a.seg : 0u);
+        const uint32_t fin = wave_sum_u32(in ? a.fin : 0u);
+        const uint32_t esc = wave_sum_u32(in ? a.esc : 0u);
+        const uint32_t rays = wave_sum_u32(in ? a.rays : 0u);
+        const double len = wave_sum(in ? a.len : 0.0);
+        if (lane == 0) {
+            atomicAdd((unsigned long long*)&S->n_segments, (unsigned long long)seg);
+            atomicAdd((unsigned long long*)&S->n_finite_segments, (unsigned long long)fin);
+            atomicAdd((unsigned long long*)&S->n_escaped, (unsigned long long)esc);
+            atomicAdd((unsigned long long*)&S->n_rays, (unsigned long long)rays);
+            unsafeAtomicAdd(&S->seg_len_sum, len);
+            unsafeAtomicAdd(&S->e_emitted, (double)rays * (double)e0);
+        }
+        if (COUNT) {
+            const double nn = wave_sum(in ? (double)a.nodes : 0.0);
+            const double nt = wave_sum(in ? (double)a.tris : 0.0);
+            if (lane == 0) {
+                atomicAdd((unsigned long long*)&S->n_node_visits, (unsigned long long)nn);
+                atomicAdd((unsigned long long*)&S->n_tri_tests, (unsigned long long)nt);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if (b >= nb) break;
+            const double ve = wave_sum(in ? (double)a.esc_e[b] : 0.0);
+            const double va = wave_sum(in ? (double)a.alive[b] : 0.0);
+            const double vc = wave_sum(in ? (double)a.cap[b] : 0.0);
+            const double vb = wave_sum(in ? (double)a.absb[b] : 0.0);
+            if (lane == 0) {
+                unsafeAtomicAdd(&S->e_escaped[b], ve);
+                unsafeAtomicAdd(&S->e_alive_at_stop[b], va);
+                unsafeAtomicAdd(&S->e_alive_at_bounce_cap[b], vc);
+                unsafeAtomicAdd(&S->e_absorbed[b], vb);
+            }
+        }
+        rem &= ~m;
+    }
+    lane_acc_zero(a);
+}
+
+// Deposited class energies of pair `p` (wave-uniform), held by lane
+// cls * NB + b, plus the first arrival bins.
+struct DepAcc {
+    int p;
+    double e;
+    int fa, fl;
+};
+
+template <int NB>
+__device__ __forceinline__ void dep_acc_flush(DepAcc& d, const PairDesc* __restrict__ pairs, int lane)
+{
+    if (d.p >= 0) {
+        RprIrStats* S = pairs[d.p].stats;
+        const int nb = pairs[d.p].scene.n_bands;
+        if (lane < 3 * NB && (lane % NB) < nb && d.e != 0.0) unsafeAtomicAdd(&S->e_class[lane / NB][lane % NB], d.e);
+        if (lane == 0) {
+            if (d.fa != INT_MAX) atomicMin(&S->first_arrival_bin, d.fa);
+            if (d.fl != INT_MAX) atomicMin(&S->first_late_bin, d.fl);
+        }
+    }
+    d.p = -1;
+    d.e = 0.0;
+    d.fa = d.fl = INT_MAX;
+}
+
+__device__ __forceinline__ int find_pair(const PairDesc* __restrict__ pairs, int n_pairs, long long r)
+{
+    int lo = 0, hi = n_pairs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pairs[mid].queue_begin <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int NB, int STACK, bool COUNT>
+__global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pairs, int n_pairs,
+                                                 unsigned long long* __restrict__ queue, long long total)
+{
+    __shared__ int32_t stk[STACK * kWave];
+    const int lane = threadIdx.x;
+    const uint64_t lt = lanemask_lt(lane);
+
+    bool alive = false;
+    int p = -1;
+    uint32_t ray = 0;
+    long long rl = 0;
+    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f, L = 0.f;
+    int k = 0, last = -1;
+    uint32_t h = 0;
+    float E[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) E[b] = 0.f;
+    SceneView sc{};
+    LaneAcc<NB> acc;
+    lane_acc_zero(acc);
+    DepAcc dep{-1, 0.0, INT_MAX, INT_MAX};
+    bool exhausted = false;
+
+    for (;;) {
+        // ------------------------------------------------ refill dead lanes
+        if (!exhausted) {
+            const uint64_t dead = __ballot(!alive);
+            if (dead) {
+                const int nd = __popcll(dead);
+                const int leader = __ffsll((unsigned long long)dead) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(queue, (unsigned long long)nd);
+                base = __shfl(base, leader);
+                if (base + (unsigned long long)nd >= (unsigned long long)total) exhausted = true;
+                int np = -1;
+                long long r = -1;
+                if (!alive) {
+                    r = (long long)(base + (unsigned long long)__popcll(dead & lt));
+                    if (r < total) np = find_pair(pairs, n_pairs, r);
+                }
+                if (__ballot(np >= 0 && acc.p >= 0 && acc.p != np)) lane_acc_flush<NB, COUNT>(acc, pairs, lane);
+                if (np >= 0) {
+                    const PairDesc& P = pairs[np];
+                    p = np;
+                    rl = r - P.queue_begin;
+                    ray = (uint32_t)(P.ray_begin + rl);
+                    const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, 0u, 0u), P.key0, P.key1);
+                    sphere_dir(u01(x.x), u01(x.y), dx, dy, dz);
+                    ox = P.src[0];
+                    oy = P.src[1];
+                    oz = P.src[2];
+                    L = 0.f;
+                    k = 0;
+                    last = -1;
+                    h = 2166136261u;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) E[b] = P.e0;
+                    sc = P.scene;
+                    alive = true;
+                }
+            }
+        }
+        if (__ballot(alive) == 0) break;
+
+        // ------------------------------------------------ closest hit
+        float t_hit = __builtin_inff();
+        uint32_t hit_id = 0xFFFFFFFFu;
+        int hit = -1;
+        if (alive)
+            hit = closest_hit<STACK, COUNT>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, t_hit, hit_id, &acc.nodes,
+                                            &acc.tris);
+
+        // ------------------------------------------------ listener sphere
+        bool has_dep = false;
+        float tau_a = 0.f, tau_b = 0.f;
+        if (alive) {
+            const PairDesc& P = pairs[p];
+            const float cx = ox - P.lst[0], cy = oy - P.lst[1], cz = oz - P.lst[2];
+            const float bq = dx * cx + dy * cy + dz * cz;
+            const float wx = cx - bq * dx, wy = cy - bq * dy, wz = cz - bq * dz;
+            const float disc = P.radius * P.radius - (wx * wx + wy * wy + wz * wz);
+            if (disc > 0.f) {
+                const float sq = sqrtf(disc);
+                const float ta = fmaxf(-bq - sq, 0.f);
+                const float tb = fminf(-bq + sq, t_hit);
+                if (tb > ta) {
+                    tau_a = (L + ta) / P.c;
+                    tau_b = (L + tb) / P.c;
+                    has_dep = tau_a < (float)P.n_bins * P.dt;
+                }
+            }
+        }
+
+        // ------------------------------------------------ wave-aggregated deposits
+        uint64_t dm = __ballot(has_dep);
+        while (dm) {
+            const int src = __ffsll((unsigned long long)dm) - 1;
+            dm &= dm - 1;
+            const int q = __builtin_amdgcn_readfirstlane(__shfl(p, src));
+            const float ta = __shfl(tau_a, src), tb = __shfl(tau_b, src);
+            const float ax = -__shfl(dx, src), ay = -__shfl(dy, src), az = -__shfl(dz, src);
+            const int kk = __shfl(k, src);
+            float Eb[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) Eb[b] = __shfl(E[b], src);
+            const PairDesc& P = pairs[q];
+            const int T = P.n_bins, nc = P.n_coeffs, nb = P.scene.n_bands;
+            const float dt = P.dt, inv_vs = P.inv_vs;
+            float* __restrict__ hist = P.hist;
+            float* __restrict__ hlate = P.hist_late;
+            const int nbc = nb * nc;
+            int m0 = (int)floorf(ta / dt);
+            m0 = m0 < 0 ? 0 : m0;
+            float sum_dtau = 0.f;
+            int first_m = INT_MAX;
+            for (int base = 0; base < nbc; base += kWave) {
+                const int j = base + lane;
+                const bool act = j < nbc;
+                const int b = act ? j / nc : 0, ci = act ? j % nc : 0;
+                float eb = 0.f;
+#pragma unroll
+                for (int bb = 0; bb < NB; ++bb) eb = (bb == b) ? Eb[bb] : eb;
+                const float val = eb * sh_coeff(ci, ax, ay, az) * inv_vs;
+                const bool late = act && kk >= 3 && ci == 0 && hlate != nullptr;
+                for (int m = m0; m < T; ++m) {
+                    const float lo = fmaxf(ta, (float)m * dt);
+                    const float hi = fminf(tb, (float)(m + 1) * dt);
+                    if (lo >= tb) break;
+                    const float dtau = hi - lo;
+                    if (dtau > 0.f) {
+                        if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * dtau);
+                        if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * dtau * inv_vs);
+                        if (base == 0) {
+                            sum_dtau += dtau;
+                            first_m = min(first_m, m);
+                        }
+                    }
+                }
+            }
+            if (q != dep.p) {
+                dep_acc_flush<NB>(dep, pairs, lane);
+                dep.p = q;
+            }
+            const int cls = kk == 0 ? 0 : (kk <= 2 ? 1 : 2);
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                if (lane == cls * NB + b) dep.e += (double)(Eb[b] * sum_dtau * inv_vs);
+            if (first_m != INT_MAX) {
+                dep.fa = min(dep.fa, first_m);
+                if (kk >= 3) dep.fl = min(dep.fl, first_m);
+            }
+        }
+
+        // ------------------------------------------------ bounce or terminate
+        if (alive) {
+            const PairDesc& P = pairs[p];
+            if (acc.p < 0) acc.p = p;
+            ++acc.seg;
+            bool term = false;
+            if (hit < 0) {
+                ++acc.esc;
+                h = fnv1a(h, 0xFFFFFFFFu);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc.esc_e[b] += E[b];
+                term = true;
+            } else {
+                L += t_hit;
+                ++acc.fin;
+                acc.len += (double)t_hit;
+                h = fnv1a(h, hit_id);
+                const bool win = L >= P.l_window;
+                if (win || k == P.max_bounces) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        acc.alive[b] += E[b];
+                        if (!win) acc.cap[b] += E[b];
+                    }
+                    term = true;
+                } else {
+                    ++k;
+                    ox += t_hit * dx;
+                    oy += t_hit * dy;
+                    oz += t_hit * dz;
+                    const float4* tr = sc.tris + 3 * (int64_t)hit;
+                    const float4 e1 = tr[1], e2 = tr[2];
+                    float nx = e1.y * e2.z - e1.z * e2.y, ny = e1.z * e2.x - e1.x * e2.z,
+                          nz = e1.x * e2.y - e1.y * e2.x;
+                    const float inl = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+                    nx *= inl;
+                    ny *= inl;
+                    nz *= inl;
+                    if (dx * nx + dy * ny + dz * nz > 0.f) {
+                        nx = -nx;
+                        ny = -ny;
+                        nz = -nz;
+                    }
+                    const float* __restrict__ mr = sc.mats + (int64_t)__float_as_int(e1.w) * kMatStride;
+                    const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, (uint32_t)k, 0u), P.key0, P.key1);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc.absb[b] += mr[kMatAlpha + b] * E[b];
+                    if (u01(x.x) < mr[kMatPd]) {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) E[b] *= mr[kMatWd + b];
+                        lambert_dir(nx, ny, nz, u01(x.y), u01(x.z), dx, dy, dz);
+                        h = fnv1a(h, 1u);
+                    } else {
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) E[b] *= mr[kMatWs + b];
+                        const float dn = 2.0f * (dx * nx + dy * ny + dz * nz);
+                        dx -= dn * nx;
+                        dy -= dn * ny;
+                        dz -= dn * nz;
+                        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                        dx *= il;
+                        dy *= il;
+                        dz *= il;
+                        h = fnv1a(h, 0u);
+                    }
+                    last = hit;
+                }
+            }
+            if (term) {
+                ++acc.rays;
+                if (P.ray_hash) P.ray_hash[rl] = h;
+                alive = false;
+            }
+        }
+    }
+    lane_acc_flush<NB, COUNT>(acc, pairs, lane);
+    dep_acc_flush<NB>(dep, pairs, lane);
+}
+
+// ---------------------------------------------------------------- setup kernels
+struct SetupArgs {
+    PairDesc base;
+    int s0, ns;
+    long long rays_per_src;
+    long long hist_stride, late_stride;
+    float src[kSetupChunk][3];
+    unsigned long long* queue;
+};
+
+__global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
+{
+    const int i = threadIdx.x;
+    if (i == 0 && a.s0 == 0) *a.queue = 0ull;
+    if (i >= a.ns) return;
+    const int s = a.s0 + i;
+    PairDesc d = a.base;
+    d.src[0] = a.src[i][0];
+    d.src[1] = a.src[i][1];
+    d.src[2] = a.src[i][2];
+    d.pair_id = a.base.pair_id + (uint32_t)s;
+    d.queue_begin = (long long)s * a.rays_per_src;
+    d.hist = a.base.hist + (size_t)s * a.hist_stride;
+    d.hist_late = a.base.hist_late ? a.base.hist_late + (size_t)s * a.late_stride : nullptr;
+    d.stats = a.base.stats + s;
+    d.ray_hash = a.base.ray_hash ? a.base.ray_hash + (size_t)s * a.rays_per_src : nullptr;
+    out[s] = d;
+    RprIrStats* S = d.stats;
+    S->n_segments = S->n_finite_segments = S->n_escaped = S->n_rays = 0;
+    S->seg_len_sum = 0.0;
+    S->e_emitted = 0.0;
+    S->first_arrival_bin = INT_MAX;
+    S->first_late_bin = INT_MAX;
+    S->n_node_visits = S->n_tri_tests = 0;
+    for (int b = 0; b < RPR_MAX_BANDS; ++b) {
+        S->e_class[0][b] = S->e_class[1][b] = S->e_class[2][b] = 0.0;
+        S->e_escaped[b] = S->e_alive_at_stop[b] = S->e_alive_at_bounce_cap[b] = S->e_absorbed[b] = 0.0;
+    }
+}
+
+__global__ void k_fill(float* __restrict__ p, size_t n, float v)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+__global__ void __launch_bounds__(kWave) k_closest(SceneView sc, const float* __restrict__ orig,
+                                                   const float* __restrict__ dir, long long n,
+                                                   float* __restrict__ t_out, int32_t* __restrict__ tri_out)
+{
+    __shared__ int32_t stk[kMaxStack * kWave];
+    const long long i = (long long)blockIdx.x * kWave + threadIdx.x;
+    if (i >= n) return;
+    float t;
+    uint32_t id;
+    const int hit = closest_hit<kMaxStack>(sc, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
+                                           dir[3 * i + 1], dir[3 * i + 2], -1, stk, threadIdx.x, t, id);
+    t_out[i] = t;
+    tri_out[i] = hit >= 0 ? (int32_t)id : -1;
+}
+
+__global__ void k_debug_philox(const uint32_t* __restrict__ in, long long n, uint32_t* __restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t* c = in + 6 * i;
+    const uint4 r = philox4x32_10(make_uint4(c[0], c[1], c[2], c[3]), c[4], c[5]);
+    out[4 * i + 0] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+__global__ void k_debug_sh(const float* __restrict__ dirs, long long n, int order, float* __restrict__ out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float x = dirs[3 * i], y = dirs[3 * i + 1], z = dirs[3 * i + 2];
+    const int nc = (order + 1) * (order + 1);
+    for (int c = 0; c < RPR_MAX_COEFFS; ++c) out[RPR_MAX_COEFFS * i + c] = c < nc ? sh_coeff(c, x, y, z) : 0.0f;
+}
+
+// ---------------------------------------------------------------- launch helpers
+using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long);
+
+template <int NB, int STACK, bool COUNT>
+TraceFn trace_fn()
+{
+    return k_trace<NB, STACK, COUNT>;
+}
+
+struct Variant {
+    TraceFn fn;
+    int blocks_per_cu;
+};
+
+std::mutex g_mu;
+Variant g_var[2][2][2];  // [bands 4/8][stack 32/64][count visits]
+bool g_var_init = false;
+int g_cus = 0;
+
+int ensure_variants()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_var_init) return RPR_OK;
+    int dev = 0;
+    RPR_HIP_TRY(hipGetDevice(&dev));
+    RPR_HIP_TRY(hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev));
+    TraceFn fns[2][2][2] = {{{trace_fn<4, 32, false>(), trace_fn<4, 32, true>()},
+                             {trace_fn<4, 64, false>(), trace_fn<4, 64, true>()}},
+                            {{trace_fn<8, 32, false>(), trace_fn<8, 32, true>()},
+                             {trace_fn<8, 64, false>(), trace_fn<8, 64, true>()}}};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+            for (int c = 0; c < 2; ++c) {
+                int nb = 0;
+                RPR_HIP_TRY(
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fns[a][b][c], kWave, 0));
+                g_var[a][b][c] = Variant{fns[a][b][c], nb > 0 ? nb : 1};
+            }
+    g_var_init = true;
+    return RPR_OK;
+}
+
+}  // namespace
+
+int device_cu_count()
+{
+    if (ensure_variants() != RPR_OK) return 0;
+    return g_cus;
+}
+
+int workspace_reserve(Workspace& ws, size_t pairs)
+{
+    const size_t need = 256 + sizeof(PairDesc) * (pairs ? pairs : 1);
+    if (ws.bytes >= need) return RPR_OK;
+    if (ws.dev) {
+        RPR_HIP_TRY(hipDeviceSynchronize());
+        (void)hipFree(ws.dev);
+        ws.dev = nullptr;
+        ws.bytes = 0;
+    }
+    const size_t bytes = std::max(need, (size_t)4096);
+    RPR_HIP_TRY(hipMalloc(&ws.dev, bytes));
+    ws.bytes = bytes;
+    return RPR_OK;
+}
+
+void workspace_free(Workspace& ws)
+{
+    if (ws.dev) (void)hipFree(ws.dev);
+    if (ws.host_pin) (void)hipHostFree(ws.host_pin);
+    ws = Workspace{};
+}
+
+int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,
+                 int max_depth, bool count_visits, int grid_override, hipStream_t stream)
+{
+    if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
+    int rc = ensure_variants();
+    if (rc != RPR_OK) return rc;
+    const Variant& v = g_var[nb <= 4 ? 0 : 1][max_depth <= 32 ? 0 : 1][count_visits ? 1 : 0];
+    long long grid = grid_override > 0 ? grid_override : (long long)g_cus * v.blocks_per_cu;
+    const long long need = (total_rays + kWave - 1) / kWave;
+    grid = std::max(1ll, std::min(grid, need));
+    hipLaunchKernelGGL(v.fn, dim3((unsigned)grid), dim3(kWave), 0, stream, d_pairs, n_pairs, d_queue,
+                       (long long)total_rays);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+}  // namespace rpr
+
+using namespace rpr;
+
+extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                        const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                        uint32_t* ray_hash, void* hip_stream)
+{
+    if (!scene || !p || !lst || (n_src > 0 && (!srcs || !hist || !stats)))
+        return set_error(RPR_EINVAL, "trace_ir: null argument");
+    if (n_src < 0) return set_error(RPR_EINVAL, "trace_ir: n_src=%d < 0", n_src);
+    if (p->sh_order < 0 || p->sh_order > RPR_MAX_SH_ORDER)
+        return set_error(RPR_EINVAL, "trace_ir: sh_order=%d not in 0..3", p->sh_order);
+    if (p->n_bins < 1) return set_error(RPR_EINVAL, "trace_ir: n_bins=%d < 1", p->n_bins);
+    if (!(p->bin_width_s > 0.f) || !std::isfinite(p->bin_width_s))
+        return set_error(RPR_EINVAL, "trace_ir: bin_width_s must be > 0");
+    if (!(p->speed_of_sound > 0.f) || !std::isfinite(p->speed_of_sound))
+        return set_error(RPR_EINVAL, "trace_ir: speed_of_sound must be > 0");
+    if (p->max_bounces < 0) return set_error(RPR_EINVAL, "trace_ir: max_bounces < 0");
+    if (p->n_rays_total < 1) return set_error(RPR_EINVAL, "trace_ir: n_rays_total < 1");
+    if (p->ray_begin < 0 || p->ray_end < p->ray_begin || p->ray_end > ((int64_t)1 << 32))
+        return set_error(RPR_EINVAL, "trace_ir: bad ray range [%lld, %lld)", (long long)p->ray_begin,
+                         (long long)p->ray_end);
+    if (!(lst->radius > 0.f) || !std::isfinite(lst->radius))
+        return set_error(RPR_EINVAL, "trace_ir: listener radius must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(lst->pos[a])) return set_error(RPR_EINVAL, "trace_ir: non-finite listener position");
+    for (int s = 0; s < n_src; ++s)
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(srcs[s].pos[a])) return set_error(RPR_EINVAL, "trace_ir: non-finite source %d", s);
+    if (n_src == 0) return RPR_OK;
+    const double window = (double)p->n_bins * (double)p->bin_width_s;
+    if ((double)p->max_bounces > 1e7) return set_error(RPR_EINVAL, "trace_ir: max_bounces too large");
+    (void)window;
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    RprScene* sc = const_cast<RprScene*>(scene);
+    int rc = workspace_reserve(sc->ws, (size_t)n_src);
+    if (rc != RPR_OK) return rc;
+    unsigned long long* d_queue = (unsigned long long*)sc->ws.dev;
+    PairDesc* d_pairs = (PairDesc*)((char*)sc->ws.dev + 256);
+
+    const int nb = scene->n_bands;
+    const int nc = (p->sh_order + 1) * (p->sh_order + 1);
+    const long long R = p->ray_end - p->ray_begin;
+    const size_t hist_stride = (size_t)p->n_bins * nb * nc;
+    const size_t late_stride = (size_t)p->n_bins * nb;
+
+    SetupArgs a;
+    std::memset(&a, 0, sizeof(a));
+    PairDesc& d = a.base;
+    d.scene = scene->view;
+    d.lst[0] = lst->pos[0];
+    d.lst[1] = lst->pos[1];
+    d.lst[2] = lst->pos[2];
+    d.radius = lst->radius;
+    d.inv_vs = (float)(1.0 / (4.0 / 3.0 * M_PI * (double)lst->radius * lst->radius * lst->radius));
+    d.c = p->speed_of_sound;
+    d.dt = p->bin_width_s;
+    d.l_window = (float)((double)p->speed_of_sound * (double)p->n_bins * (double)p->bin_width_s);
+    d.e0 = (float)(1.0 / (double)p->n_rays_total);
+    d.n_bins = p->n_bins;
+    d.max_bounces = p->max_bounces;
+    d.sh_order = p->sh_order;
+    d.n_coeffs = nc;
+    d.key0 = (uint32_t)(p->seed & 0xFFFFFFFFull);
+    d.key1 = (uint32_t)(p->seed >> 32);
+    d.pair_id = (uint32_t)p->pair_base;
+    d.flags = p->flags;
+    d.ray_begin = p->ray_begin;
+    d.n_rays = R;
+    d.hist = hist;
+    d.hist_late = hist_late;
+    d.stats = stats;
+    d.ray_hash = ray_hash;
+    a.rays_per_src = R;
+    a.hist_stride = (long long)hist_stride;
+    a.late_stride = (long long)late_stride;
+    a.queue = d_queue;
+    for (int s0 = 0; s0 < n_src; s0 += kSetupChunk) {
+        a.s0 = s0;
+        a.ns = std::min(kSetupChunk, n_src - s0);
+        for (int i = 0; i < a.ns; ++i)
+            for (int c = 0; c < 3; ++c) a.src[i][c] = srcs[s0 + i].pos[c];
+        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupChunk), 0, st, a, d_pairs);
+    }
+    const size_t nh = hist_stride * n_src;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nh + 255) / 256, 16384)), dim3(256), 0, st, hist, nh,
+                       0.0f);
+    if (hist_late) {
+        const size_t nl = late_stride * n_src;
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nl + 255) / 256, 16384)), dim3(256), 0, st,
+                           hist_late, nl, 0.0f);
+    }
+    RPR_HIP_TRY(hipGetLastError());
+    return launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->max_depth,
+                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0, 0, st);
+}
+
+extern "C" int scene_closest_hit(const RprScene* scene, const float* orig, const float* dir, int64_t n,
+                                 float* t_out, int32_t* tri_out, void* hip_stream)
+{
+    if (!scene || n < 0 || (n > 0 && (!orig || !dir || !t_out || !tri_out)))
+        return set_error(RPR_EINVAL, "scene_closest_hit: bad argument");
+    if (n == 0) return RPR_OK;
+    hipLaunchKernelGGL(k_closest, dim3((unsigned)((n + kWave - 1) / kWave)), dim3(kWave), 0,
+                       (hipStream_t)hip_stream, scene->view, orig, dir, (long long)n, t_out, tri_out);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+extern "C" int debug_philox(const uint32_t* in, int64_t n, uint32_t* out, void* hip_stream)
+{
+    if (n < 0 || (n > 0 && (!in || !out))) return set_error(RPR_EINVAL, "debug_philox: bad argument");
+    if (n == 0) return RPR_OK;
+    hipLaunchKernelGGL(k_debug_philox, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream, in,
+                       (long long)n, out);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+extern "C" int debug_sh_eval(const float* dirs, int64_t n, int32_t order, float* out, void* hip_stream)
+{
+    if (n < 0 || order < 0 || order > RPR_MAX_SH_ORDER || (n > 0 && (!dirs || !out)))
+        return set_error(RPR_EINVAL, "debug_sh_eval: bad argument");
+    if (n == 0) return RPR_OK;
+    hipLaunchKernelGGL(k_debug_sh, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)hip_stream, dirs,
+                       (long long)n, order, out);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}

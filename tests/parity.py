@@ -1,0 +1,113 @@
+"""Helpers shared by the GPU parity tests: run the HIP path and the oracle on
+the same seeded inputs and compare them ray for ray."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+import paper_1803_00430_amd as P
+
+HIST_TOL = 1e-4   # relative, per bin-band-coefficient row sum (and per cell, scaled by that row)
+RT60_TOL = 0.01   # relative
+
+
+def gpu_trace(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray_end=None, max_bounces,
+              sh_order, n_bins, bin_width_s, seed, pair_base=0, want_hash=True):
+    import torch
+    if ray_end is None:
+        ray_end = n_rays_total
+    srcs = np.atleast_2d(np.asarray(sources, np.float32))
+    nb = scene.n_bands
+    hist, late, stats, rh = P.alloc_trace_outputs(len(srcs), n_bins, nb, sh_order, ray_end - ray_begin,
+                                                  want_hash=want_hash)
+    prm = P.trace_params(n_rays_total=n_rays_total, ray_begin=ray_begin, ray_end=ray_end,
+                         max_bounces=max_bounces, sh_order=sh_order, n_bins=n_bins, bin_width_s=bin_width_s,
+                         seed=seed, pair_base=pair_base)
+    P.trace_ir(scene, srcs, listener, radius, prm, hist, late, stats, rh)
+    torch.cuda.synchronize()
+    return dict(hist=hist.double().cpu().numpy(), hist_late=late.double().cpu().numpy(),
+                stats=P.stats_host(stats), ray_hash=None if rh is None else rh.cpu().numpy().view(np.uint32),
+                _dev=(hist, late, stats))
+
+
+def orc_trace(sd, sources, listener, radius, **kw):
+    return oracle.trace_ir(sd, sources, listener, radius, want_hash=True, **kw)
+
+
+def _stats_vec(st, nb):
+    """Comparable stats of one IR as floats (GPU structured row or oracle dict)."""
+    if isinstance(st, dict):
+        g = lambda k: st[k]
+    else:
+        g = lambda k: st[k]
+    return dict(
+        n_segments=float(g("n_segments")), n_finite_segments=float(g("n_finite_segments")),
+        n_escaped=float(g("n_escaped")), n_rays=float(g("n_rays")), seg_len_sum=float(g("seg_len_sum")),
+        e_emitted=float(g("e_emitted")),
+        e_class=np.asarray(g("e_class"))[:, :nb].astype(np.float64),
+        e_escaped=np.asarray(g("e_escaped"))[:nb].astype(np.float64),
+        e_alive_at_stop=np.asarray(g("e_alive_at_stop"))[:nb].astype(np.float64),
+        e_alive_at_bounce_cap=np.asarray(g("e_alive_at_bounce_cap"))[:nb].astype(np.float64),
+        e_absorbed=np.asarray(g("e_absorbed"))[:nb].astype(np.float64),
+        first_arrival_bin=int(g("first_arrival_bin")), first_late_bin=int(g("first_late_bin")),
+    )
+
+
+def traced_pair(scene, sd, sources, listener, radius, **kw):
+    """Trace on both sides; rays whose discrete path (hit triangles and bounce
+    kinds) differs between FP32 and FP64 are traced again one by one on both
+    sides and removed from both results.  Returns (gpu, oracle, divergent)."""
+    g = gpu_trace(scene, sources, listener, radius, **kw)
+    okw = {k: v for k, v in kw.items() if k != "want_hash"}
+    o = orc_trace(sd, sources, listener, radius, **okw)
+    srcs = np.atleast_2d(np.asarray(sources, np.float32))
+    nb = scene.n_bands
+    gs = [_stats_vec(g["stats"][s], nb) for s in range(len(srcs))]
+    os_ = [_stats_vec(o["stats"][s], nb) for s in range(len(srcs))]
+    div = np.argwhere(g["ray_hash"] != o["ray_hash"])
+    rb = kw.get("ray_begin", 0)
+    for (s, i) in div:
+        one = dict(kw, ray_begin=rb + int(i), ray_end=rb + int(i) + 1, pair_base=kw.get("pair_base", 0) + int(s))
+        g1 = gpu_trace(scene, srcs[s:s + 1], listener, radius, **one)
+        o1 = orc_trace(sd, srcs[s:s + 1], listener, radius, **{k: v for k, v in one.items() if k != "want_hash"})
+        g["hist"][s] -= g1["hist"][0]
+        g["hist_late"][s] -= g1["hist_late"][0]
+        o["hist"][s] -= o1["hist"][0]
+        o["hist_late"][s] -= o1["hist_late"][0]
+        for side, one_res, lst_ in ((gs, g1["stats"][0], None), (os_, o1["stats"][0], None)):
+            v1 = _stats_vec(one_res, nb)
+            for key in ("n_segments", "n_finite_segments", "n_escaped", "n_rays", "seg_len_sum", "e_emitted",
+                        "e_class", "e_escaped", "e_alive_at_stop", "e_alive_at_bounce_cap", "e_absorbed"):
+                side[s][key] = side[s][key] - v1[key]
+    g["cmp_stats"] = gs
+    o["cmp_stats"] = os_
+    return g, o, div
+
+
+def assert_hist_close(Hg, Ho, tol=HIST_TOL, what="hist"):
+    """Row sums over bins agree within tol of sum|H_oracle|, and every cell
+    within tol of that same absolute row sum."""
+    Hg = np.asarray(Hg, np.float64)
+    Ho = np.asarray(Ho, np.float64)
+    assert Hg.shape == Ho.shape
+    row_abs = np.abs(Ho).sum(axis=0)
+    floor = 1e-30
+    dr = np.abs(Hg.sum(0) - Ho.sum(0))
+    assert np.all(dr <= tol * row_abs + floor), f"{what}: row-sum error {np.max(dr / (row_abs + floor)):.3e}"
+    dc = np.abs(Hg - Ho)
+    assert np.all(dc <= tol * row_abs[None] + floor), \
+        f"{what}: cell error {np.max(dc / (row_abs[None] + floor)):.3e}"
+
+
+def assert_stats_close(sg, so, rel=1e-5):
+    for k in ("n_segments", "n_finite_segments", "n_escaped", "n_rays"):
+        assert abs(sg[k] - so[k]) <= max(1.0, 1e-5 * so[k]), (k, sg[k], so[k])
+    for k in ("seg_len_sum", "e_emitted"):
+        assert abs(sg[k] - so[k]) <= rel * abs(so[k]) + 1e-12, (k, sg[k], so[k])
+    for k in ("e_escaped", "e_alive_at_stop", "e_alive_at_bounce_cap", "e_absorbed"):
+        scale = max(np.abs(so[k]).max(), so["e_emitted"] * 1e-9)
+        assert np.all(np.abs(sg[k] - so[k]) <= 1e-4 * scale + 1e-15), (k, sg[k], so[k])
+    scale = np.abs(so["e_class"]).max(axis=0) + 1e-30
+    assert np.all(np.abs(sg["e_class"] - so["e_class"]) <= HIST_TOL * scale[None]), (sg["e_class"], so["e_class"])

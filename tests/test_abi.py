@@ -1,0 +1,73 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/rpr.h declares, and the binding's struct layouts match the header's
+(checked by compiling the header with gcc).  No GPU calls."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1803_00430_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_header_function():
+    names = P.header_functions()
+    assert {"scene_create", "scene_destroy", "trace_ir", "estimate_reverb", "last_error"} <= set(names)
+    L = P.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(P.SIGNATURES) == set(names)
+    assert L.rpr_version().startswith(b"rpr")
+
+
+def test_invalid_arguments_fail_before_any_launch():
+    L = P.lib()
+    out = C.c_void_p()
+    # n_bands out of range: rejected on the host, nothing launched
+    rc = L.scene_create(None, 0, None, 0, None, None, None, 1, 9, None, C.byref(out))
+    assert rc == -1 and out.value is None
+    assert b"n_bands" in L.last_error()
+    assert L.trace_ir(None, None, 0, None, None, None, None, None, None, None) == -1
+    ep = P.EstimateParams(0, 3)
+    assert L.estimate_reverb(None, None, None, 1, 10, 4, 4, 1e-3, C.byref(ep), None, None) == -1
+    assert L.estimate_reverb(None, None, None, 0, 10, 4, 2, 1e-3, C.byref(ep), None, None) == 0  # empty: no-op
+
+
+def test_struct_layouts_match_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "rpr.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("RprIrStats %zu\nRprReverbParams %zu\nRprTraceParams %zu\nRprSceneInfo %zu\n",
+         sizeof(RprIrStats), sizeof(RprReverbParams), sizeof(RprTraceParams), sizeof(RprSceneInfo));
+  P(RprIrStats, seg_len_sum); P(RprIrStats, first_arrival_bin); P(RprIrStats, e_class);
+  P(RprIrStats, e_escaped); P(RprIrStats, e_absorbed); P(RprIrStats, n_tri_tests);
+  P(RprReverbParams, g_reverb); P(RprReverbParams, predelay_s); P(RprReverbParams, dir_loudness);
+  P(RprTraceParams, bin_width_s); P(RprTraceParams, seed);
+  return 0;
+}''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    assert int(got["RprIrStats"]) == P.IR_STATS_DTYPE.itemsize
+    assert int(got["RprReverbParams"]) == P.REVERB_PARAMS_DTYPE.itemsize
+    assert int(got["RprTraceParams"]) == C.sizeof(P.TraceParams)
+    assert int(got["RprSceneInfo"]) == C.sizeof(P.SceneInfo)
+    for name in ("seg_len_sum", "first_arrival_bin", "e_class", "e_escaped", "e_absorbed", "n_tri_tests"):
+        assert int(got[f"RprIrStats.{name}"]) == P.IR_STATS_DTYPE.fields[name][1], name
+    for name in ("g_reverb", "predelay_s", "dir_loudness"):
+        assert int(got[f"RprReverbParams.{name}"]) == P.REVERB_PARAMS_DTYPE.fields[name][1], name
+    assert int(got["RprTraceParams.bin_width_s"]) == P.TraceParams.bin_width_s.offset
+    assert int(got["RprTraceParams.seed"]) == P.TraceParams.seed.offset
+
+
+def test_binding_has_no_cpu_path():
+    # the binding module must not import the oracle
+    src = open(os.path.join(ROOT, "paper_1803_00430_amd", "__init__.py")).read()
+    assert "oracle" not in src.replace("no fallback", "")

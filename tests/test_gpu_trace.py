@@ -1,0 +1,249 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances: histograms within 1e-4 relative per bin-band-coefficient row sum
+(cells within 1e-4 of that row's absolute sum), RT60 within 1%, after removing
+the rays whose discrete path differs between FP32 and FP64 (fewer than 1e-3 of
+the rays).  Integer outputs (Philox words) bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1803_00430_amd as P
+import rpr_scenes as R
+from parity import RT60_TOL, assert_hist_close, assert_stats_close, gpu_trace, orc_trace, traced_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return torch
+
+
+def test_philox_bit_exact(torch_cuda):
+    g = R.rng(1)
+    n = 4096
+    ck = g.integers(0, 2**32, size=(n, 6), dtype=np.uint64).astype(np.uint32)
+    ck[:10] = 0
+    ck[10:20] = 0xFFFFFFFF
+    out = P.debug_philox(ck).cpu().numpy().view(np.uint32)
+    for i in list(range(0, n, 7)) + [0, 10, 15]:
+        assert list(out[i]) == oracle.philox(ck[i, :4], ck[i, 4:]), i
+
+
+def test_sh_matches_oracle(torch_cuda):
+    g = R.rng(2)
+    d = g.normal(size=(2000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    d = np.vstack([d, np.eye(3), -np.eye(3)]).astype(np.float32)
+    for order in (0, 1, 2, 3):
+        got = P.debug_sh_eval(d, order).cpu().numpy()
+        ref = oracle.sh_eval(order, d.astype(np.float64))
+        nc = (order + 1) ** 2
+        assert np.abs(got[:, :nc] - ref).max() < 2e-6
+        assert np.all(got[:, nc:] == 0)
+
+
+def _cluttered_room(seed, n_boxes=40, edge=0.7):
+    g = R.rng(seed)
+    dims = np.array([12.0, 9.0, 4.0])
+    parts = R.box_surfaces((0, 0, 0), dims, edge)
+    mats = [int(g.integers(3)) for _ in parts]
+    for _ in range(n_boxes):
+        sz = g.uniform(0.2, 1.5, 3)
+        lo = g.uniform(0, 1, 3) * (dims - sz)
+        for f in R.box_surfaces(lo, lo + sz, edge):
+            parts.append(f)
+            mats.append(int(g.integers(3)))
+    verts, tris, tm = R.merge(parts, mats)
+    return dict(verts=verts, tris=tris, tri_mat=tm,
+                absorption=g.uniform(0.05, 0.6, (3, 4)).astype(np.float32),
+                scattering=g.uniform(0.1, 0.9, (3, 4)).astype(np.float32), dims=dims)
+
+
+def _soup(seed, n):
+    g = R.rng(seed)
+    c = g.uniform(-20, 20, (n, 3))
+    v = c[:, None, :] + g.normal(scale=1.5, size=(n, 3, 3))
+    verts = v.reshape(-1, 3).astype(np.float32)
+    tris = np.arange(3 * n, dtype=np.int32).reshape(n, 3)
+    return dict(verts=verts, tris=tris, tri_mat=np.zeros(n, np.int32),
+                absorption=np.full((1, 4), 0.2, np.float32), scattering=np.full((1, 4), 0.5, np.float32))
+
+
+@pytest.mark.parametrize("kind", ["room", "soup"])
+def test_bvh_closest_hit_equals_brute_force(torch_cuda, kind):
+    sd = _cluttered_room(3) if kind == "room" else _soup(4, 6000)
+    sc = P.Scene.from_dict(sd)
+    info = sc.info()
+    assert info["n_tris"] == len(sd["tris"]) and 0 < info["max_depth"] <= 64
+    lo, hi = (np.zeros(3), sd["dims"]) if kind == "room" else (np.full(3, -25.0), np.full(3, 25.0))
+    o, d = R.random_rays(5, 20000, lo + 0.01, hi - 0.01)
+    t, tri = sc.closest_hit(o, d)
+    t = t.cpu().numpy()
+    tri = tri.cpu().numpy()
+    tr, trir = oracle.closest_hit(sd["verts"], sd["tris"], o.astype(np.float64), d.astype(np.float64))
+    hit = trir >= 0
+    assert np.array_equal(tri >= 0, hit) or np.mean((tri >= 0) != hit) < 1e-3
+    both = hit & (tri >= 0)
+    rel = np.abs(t[both] - tr[both]) / np.maximum(tr[both], 1e-3)
+    assert np.quantile(rel, 0.999) < 1e-4
+    # the same triangle, except where several triangles are hit at (nearly) the same t
+    same = tri[both] == trir[both]
+    assert same.mean() > 0.995
+
+
+def _tiny_kw(c, **over):
+    kw = dict(n_rays_total=c["n_rays"], max_bounces=c["max_bounces"], sh_order=c["sh_order"],
+              n_bins=c["n_bins"], bin_width_s=c["bin_width_s"], seed=c["seed"])
+    kw.update(over)
+    return kw
+
+
+def test_tiny_config_parity(torch_cuda):
+    """The tiny shoebox at its full configuration (4096 rays, 50 bounces, 2000
+    bins of 1 ms, SH order 2, 4 bands, Philox seed 0)."""
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    kw = _tiny_kw(c)
+    g, o, div = traced_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
+    assert len(div) < 1e-3 * c["n_rays"] + 1
+    assert_hist_close(g["hist"][0], o["hist"][0])
+    assert_hist_close(g["hist_late"][0], o["hist_late"][0], what="hist_late")
+    assert_stats_close(g["cmp_stats"][0], o["cmp_stats"][0])
+    # RT60 parity, each side estimating from its own histogram
+    out = P.alloc_params(1)
+    hist, late, stats = g["_dev"]
+    P.estimate_reverb(hist, late, stats, c["n_bins"], 4, c["sh_order"], c["bin_width_s"], out)
+    pg = P.params_host(out)[0]
+    po = oracle.estimate_reverb(o["hist"][0], o["hist_late"][0], o["stats"][0], c["bin_width_s"])
+    assert np.all(np.abs(pg["rt60"][:4] - po["rt60"]) <= RT60_TOL * po["rt60"])
+    assert np.array_equal(pg["rt60_range"][:4], po["rt60_range"])
+
+
+def test_ragged_multisource_parity(torch_cuda):
+    """Cluttered tessellated room (thousands of triangles, 3 materials), three
+    sources, a ray count that is not a multiple of the wave size, SH order 3,
+    a window that ends before the bounce limit."""
+    sd = _cluttered_room(7, n_boxes=25, edge=1.1)
+    sc = P.Scene.from_dict(sd)
+    srcs = np.array([[1.0, 1.0, 1.2], [6.0, 4.5, 2.0], [10.5, 8.0, 3.1]], np.float32)
+    lst = np.array([5.0, 5.0, 1.6], np.float32)
+    kw = dict(n_rays_total=1000, max_bounces=300, sh_order=3, n_bins=700, bin_width_s=1e-3, seed=77,
+              pair_base=5)
+    g, o, div = traced_pair(sc, sd, srcs, lst, 0.6, **kw)
+    assert len(div) < 1e-3 * 3000 + 1, len(div)
+    for s in range(3):
+        assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
+        assert_stats_close(g["cmp_stats"][s], o["cmp_stats"][s])
+
+
+def test_ray_subset_matches_full_range(torch_cuda):
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    kw = _tiny_kw(c, max_bounces=20)
+    full = gpu_trace(sc, c["sources"], c["listener"], c["radius"], **kw)
+    a = gpu_trace(sc, c["sources"], c["listener"], c["radius"], ray_begin=0, ray_end=1000, **kw)
+    b = gpu_trace(sc, c["sources"], c["listener"], c["radius"], ray_begin=1000, ray_end=4096, **kw)
+    assert np.array_equal(np.concatenate([a["ray_hash"][0], b["ray_hash"][0]]), full["ray_hash"][0])
+    assert_hist_close(a["hist"][0] + b["hist"][0], full["hist"][0], tol=1e-6)
+
+
+def test_estimate_parity_on_identical_input(torch_cuda):
+    """Both estimators on the same (GPU-made) histogram: FP64 on both sides."""
+    import torch
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    for K, n_bins, a in ((50, 2000, None), (400, 1500, 0.05), (200, 800, 0.02)):
+        sd = dict(c) if a is None else dict(c, absorption=np.full((1, 4), a, np.float32))
+        s2 = sc if a is None else P.Scene.from_dict(sd)
+        g = gpu_trace(s2, c["sources"], c["listener"], c["radius"], **_tiny_kw(c, max_bounces=K, n_bins=n_bins))
+        hist, late, stats = g["_dev"]
+        for src in (0, 1):
+            out = P.alloc_params(1)
+            P.estimate_reverb(hist, late, stats, n_bins, 4, c["sh_order"], c["bin_width_s"], out, rt60_source=src)
+            pg = P.params_host(out)[0]
+            st = g["stats"][0]
+            sdict = {k: st[k] for k in st.dtype.names}
+            po = oracle.estimate_reverb(g["hist"][0], g["hist_late"][0], sdict, c["bin_width_s"], rt60_source=src)
+            assert np.allclose(pg["rt60"][:4], po["rt60"], rtol=1e-6)
+            assert np.array_equal(pg["rt60_range"][:4], po["rt60_range"])
+            assert np.array_equal(pg["status"][:4], po["status"])
+            assert np.allclose(pg["g_reverb"][:4], po["g_reverb"], rtol=1e-6)
+            assert np.allclose(pg["dir_loudness"][:4, :9], po["dir_loudness"], rtol=1e-5, atol=1e-7)
+            assert pg["predelay_s"] == np.float32(po["predelay_s"])
+            assert abs(pg["mean_free_path_m"] - po["mean_free_path_m"]) <= 1e-6 * po["mean_free_path_m"]
+
+
+def test_zero_absorption_invariants(torch_cuda):
+    c = R.tiny_config()
+    sd = dict(c, absorption=np.zeros((1, 4), np.float32))
+    sc = P.Scene.from_dict(sd)
+    g = gpu_trace(sc, c["sources"], c["listener"], c["radius"], **_tiny_kw(c, max_bounces=300))
+    st = g["stats"][0]
+    assert st["n_escaped"] == 0 and np.all(st["e_escaped"][:4] == 0)
+    assert np.all(st["e_absorbed"][:4] == 0)
+    assert np.allclose(st["e_alive_at_stop"][:4], 1.0, rtol=1e-5)
+    H = g["hist"][0]
+    assert np.all(H[:, 1:, :] == H[:, :1, :])
+
+
+def test_edge_cases(torch_cuda):
+    import torch
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    # empty ray range: zero histogram and zero counts
+    g = gpu_trace(sc, c["sources"], c["listener"], c["radius"], **_tiny_kw(c, ray_begin=5, ray_end=5))
+    assert not g["hist"].any() and g["stats"][0]["n_segments"] == 0
+    assert g["stats"][0]["first_arrival_bin"] == P.INT32_MAX
+    # K = 0, SH order 0: direct sound only, all bands equal
+    g = gpu_trace(sc, c["sources"], c["listener"], c["radius"], **_tiny_kw(c, max_bounces=0, sh_order=0))
+    st = g["stats"][0]
+    assert st["n_segments"] == 4096 and np.all(st["e_class"][1:, :4] == 0)
+    # no sources: a no-op
+    hist, late, stats, _ = P.alloc_trace_outputs(1, 10, 4, 0)
+    P.trace_ir(sc, np.zeros((0, 3), np.float32), c["listener"], 0.5,
+               P.trace_params(n_rays_total=4, max_bounces=1, sh_order=0, n_bins=10, bin_width_s=1e-3, seed=0),
+               hist, late, stats)
+    # invalid arguments are rejected before anything runs
+    with pytest.raises(P.RprError):
+        P.trace_ir(sc, c["sources"], c["listener"], 0.5,
+                   P.trace_params(n_rays_total=4, max_bounces=1, sh_order=4, n_bins=10, bin_width_s=1e-3, seed=0),
+                   hist, late, stats)
+    with pytest.raises(P.RprError):
+        P.trace_ir(sc, c["sources"], c["listener"], -1.0,
+                   P.trace_params(n_rays_total=4, max_bounces=1, sh_order=0, n_bins=10, bin_width_s=1e-3, seed=0),
+                   hist, late, stats)
+
+
+def test_degenerate_scenes(torch_cuda):
+    # a single triangle (the root is a leaf) and an empty scene (free field)
+    one = dict(verts=np.array([[0, -5, -5], [0, 5, -5], [0, 0, 5]], np.float32), tris=np.array([[0, 1, 2]], np.int32),
+               tri_mat=None, absorption=np.full((1, 4), 0.3, np.float32), scattering=np.zeros((1, 4), np.float32))
+    kw = dict(n_rays_total=2048, max_bounces=3, sh_order=1, n_bins=100, bin_width_s=1e-3, seed=3)
+    for sd in (one, dict(one, verts=np.zeros((0, 3), np.float32), tris=np.zeros((0, 3), np.int32))):
+        sc = P.Scene.from_dict(sd)
+        srcs = np.array([[2.0, 0.0, 0.0]], np.float32)
+        lst = np.array([4.0, 1.0, 0.0], np.float32)
+        g, o, div = traced_pair(sc, dict(sd, tri_mat=np.zeros(len(sd["tris"]), np.int32)), srcs, lst, 0.5, **kw)
+        assert len(div) <= 2
+        assert_hist_close(g["hist"][0], o["hist"][0])
+        assert_stats_close(g["cmp_stats"][0], o["cmp_stats"][0])
+
+
+def test_invalid_scene_rejected(torch_cuda):
+    c = R.tiny_config()
+    bad = dict(c, tris=np.where(c["tris"] == 3, 99, c["tris"]).astype(np.int32))
+    with pytest.raises(P.RprError):
+        P.Scene.from_dict(bad)
+    with pytest.raises(P.RprError):
+        P.Scene.from_dict(dict(c, absorption=np.full((1, 4), 1.5, np.float32)))
+    v = c["verts"].copy()
+    v[2, 1] = np.nan
+    with pytest.raises(P.RprError):
+        P.Scene.from_dict(dict(c, verts=v))
