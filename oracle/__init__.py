@@ -88,6 +88,10 @@ def lib():
                                    C.POINTER(C.c_uint32)]
         L.orc_trace_ir.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
+        L.orc_trace_path.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp, dp,
+                                     C.c_int32, dp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_double,
+                                     C.c_int32, dp, dp, dp, C.POINTER(C.c_int64)]
+        L.orc_trace_path.restype = C.c_int
         _lib = L
     return _lib
 
@@ -224,6 +228,23 @@ def trace_ir(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray
         raise ValueError("oracle trace_ir: invalid arguments")
     return dict(hist=hist, hist_late=hist_late, stats=[stats_to_dict(stats[s], B) for s in range(S)],
                 ray_hash=rh)
+
+
+def trace_path(scene, source, *, seed, ray, pair, max_bounces, window_len, max_seg=4096):
+    """Segments of one ray: dict(orig [n,3], dir [n,3], t [n], tri [n]) (diagnostics)."""
+    verts = np.ascontiguousarray(scene["verts"], np.float64)
+    tris = np.ascontiguousarray(scene["tris"], np.int32)
+    tm = np.ascontiguousarray(scene["tri_mat"], np.int32)
+    ab = np.ascontiguousarray(scene["absorption"], np.float64)
+    sc = np.ascontiguousarray(scene["scattering"], np.float64)
+    pdf = np.ascontiguousarray(p_diffuse(scene["scattering"]))
+    src = np.ascontiguousarray(source, np.float64)
+    o = np.zeros((max_seg, 3)); d = np.zeros((max_seg, 3)); t = np.zeros(max_seg); tri = np.zeros(max_seg, np.int64)
+    n = lib().orc_trace_path(_dp(verts), len(tris), tris.ctypes.data_as(C.POINTER(C.c_int32)),
+                             tm.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), _dp(pdf), ab.shape[1],
+                             _dp(src), seed, ray, pair, max_bounces, window_len, max_seg, _dp(o), _dp(d), _dp(t),
+                             tri.ctypes.data_as(C.POINTER(C.c_int64)))
+    return dict(orig=o[:n], dir=d[:n], t=t[:n], tri=tri[:n])
 
 
 # ----------------------------------------------------------------- estimation

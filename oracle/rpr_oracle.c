@@ -487,6 +487,64 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
     return 0;
 }
 
+/* Path of one ray for diagnostics: per segment k (up to max_seg), the
+ * segment's origin, direction, hit distance (INFINITY on escape) and hit
+ * triangle (-1 on escape).  Returns the number of segments written. */
+int orc_trace_path(const double *verts, int64_t n_tris, const int32_t *tris, const int32_t *tri_mat,
+                   const double *absorption, const double *scattering, const double *p_diffuse, int32_t nb,
+                   const double src[3], uint64_t seed, uint32_t ray, uint32_t pair, int32_t max_bounces,
+                   double window_len, int32_t max_seg, double *orig, double *dir, double *t_out, int64_t *tri_out)
+{
+    (void)absorption;
+    (void)scattering;
+    (void)nb;
+    double u[4], o[3], d[3];
+    draw(seed, ray, pair, 0u, u);
+    orc_emission_dir(u, d);
+    for (int i = 0; i < 3; ++i) o[i] = src[i];
+    double L = 0.0;
+    int k = 0;
+    int64_t last = -1;
+    int n = 0;
+    while (n < max_seg) {
+        double t_hit;
+        int64_t tri = closest_hit(verts, tris, n_tris, o, d, last, &t_hit);
+        for (int i = 0; i < 3; ++i) {
+            orig[3 * n + i] = o[i];
+            dir[3 * n + i] = d[i];
+        }
+        t_out[n] = t_hit;
+        tri_out[n] = tri;
+        ++n;
+        if (tri < 0) break;
+        L += t_hit;
+        if (L >= window_len || k == max_bounces) break;
+        ++k;
+        double x[3];
+        for (int i = 0; i < 3; ++i) x[i] = o[i] + t_hit * d[i];
+        const int32_t *tv = tris + 3 * tri;
+        double e1[3], e2[3], nrm[3], nf[3];
+        sub3(verts + 3 * (int64_t)tv[1], verts + 3 * (int64_t)tv[0], e1);
+        sub3(verts + 3 * (int64_t)tv[2], verts + 3 * (int64_t)tv[0], e2);
+        cross3(e1, e2, nrm);
+        double nl = sqrt(dot3(nrm, nrm));
+        for (int i = 0; i < 3; ++i) nrm[i] /= nl;
+        double sgn = dot3(d, nrm) > 0.0 ? -1.0 : 1.0;
+        for (int i = 0; i < 3; ++i) nf[i] = sgn * nrm[i];
+        int mat = tri_mat ? tri_mat[tri] : 0;
+        draw(seed, ray, pair, (uint32_t)k, u);
+        if (u[0] < p_diffuse[mat]) {
+            orc_diffuse_dir(nf, u, d);
+        } else {
+            double dn = dot3(d, nf);
+            for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
+        }
+        for (int i = 0; i < 3; ++i) o[i] = x[i];
+        last = tri;
+    }
+    return n;
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -53,16 +53,44 @@ __device__ __forceinline__ double I_fit(const EstArgs& a, const float* H, const 
     return 3.5449077018110318 * (double)H[((size_t)m * a.nb + b) * a.nc];  // sqrt(4 pi) * H_00
 }
 
+// Backward integral S[m] = C + sum_{j=m..m_last} I[j], evaluated chunk by
+// chunk from the end (inclusive suffix sums within a chunk of 64 bins plus a
+// running carry).  Every use of S -- its value at 0 and at the range-test bin,
+// and the decay curve -- comes from this one evaluation order, so y[0] is
+// exactly 0 dB and a threshold decision never depends on two differently
+// rounded sums of the same quantity.
+template <class F>
+__device__ __forceinline__ double schroeder_scan(const EstArgs& a, const float* H, const float* HL, int b,
+                                                 int m_last, double C, int lane, F&& visit)
+{
+    double carry = C;
+    const int n_chunks = (m_last + kWave) / kWave;
+    for (int ch = n_chunks - 1; ch >= 0; --ch) {
+        const int m = ch * kWave + lane;
+        double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const double t = __shfl_down(v, o, kWave);
+            if (lane + o < kWave) v += t;
+        }
+        const double S = carry + v;
+        carry += __shfl(v, 0, kWave);
+        if (m <= m_last) visit(m, S);
+    }
+    return carry;  // S[0]
+}
+
 __device__ Fit fit_once(const EstArgs& a, const float* H, const float* HL, int b, int m_last, int W, double C,
-                        double tot, int lane)
+                        int lane)
 {
     Fit f{0.0, -1, RPR_ST_NO_RANGE};
     const int top = m_last - W;
     if (top < 0) return f;
-    double st = 0.0;
-    for (int m = top + lane; m <= m_last; m += kWave) st += I_fit(a, H, HL, m, b);
-    const double S_top = C + wsum(st);
-    const double S0 = C + tot;
+    double s_top_lane = 0.0;
+    const double S0 = schroeder_scan(a, H, HL, b, m_last, C, lane, [&](int m, double S) {
+        if (m == top) s_top_lane = S;
+    });
+    const double S_top = wsum(s_top_lane);  // exactly one lane holds it
     const double y_top = 10.0 * log10(S_top / S0);
     const double his[4] = {-5.0, -5.0, -5.0, 0.0};
     const double los[4] = {-35.0, -25.0, -15.0, -10.0};
@@ -70,31 +98,17 @@ __device__ Fit fit_once(const EstArgs& a, const float* H, const float* HL, int b
         const double hi = his[r], lo = los[r];
         if (!(y_top <= lo)) continue;
         double n = 0, s_t = 0, s_y = 0, s_tt = 0, s_ty = 0;
-        double carry = C;
-        const int n_chunks = (m_last + kWave) / kWave;
-        for (int ch = n_chunks - 1; ch >= 0; --ch) {
-            const int m = ch * kWave + lane;
-            double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
-            // inclusive suffix sum within the chunk
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const double t = __shfl_down(v, o, kWave);
-                if (lane + o < kWave) v += t;
+        schroeder_scan(a, H, HL, b, m_last, C, lane, [&](int m, double S) {
+            const double y = 10.0 * log10(S / S0);
+            if (y <= hi && y >= lo) {
+                const double t = (double)m * a.dt;
+                n += 1.0;
+                s_t += t;
+                s_y += y;
+                s_tt += t * t;
+                s_ty += t * y;
             }
-            const double S = carry + v;
-            carry += __shfl(v, 0, kWave);
-            if (m <= m_last) {
-                const double y = 10.0 * log10(S / S0);
-                if (y <= hi && y >= lo) {
-                    const double t = (double)m * a.dt;
-                    n += 1.0;
-                    s_t += t;
-                    s_y += y;
-                    s_tt += t * t;
-                    s_ty += t * y;
-                }
-            }
-        }
+        });
         n = wsum(n);
         s_t = wsum(s_t);
         s_y = wsum(s_y);
@@ -123,14 +137,13 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
     // pass 1: last nonzero bin of the fitted intensity, its total, and the
     // per-coefficient sums of Eq. 1
     int m_last = -1;
-    double tot_fit = 0.0, tot_all = 0.0;
+    double tot_all = 0.0;
     double dsum[RPR_MAX_COEFFS];
 #pragma unroll
     for (int c = 0; c < RPR_MAX_COEFFS; ++c) dsum[c] = 0.0;
     for (int m = lane; m < T; m += kWave) {
         const double v = I_fit(a, H, HL, m, b);
         if (v > 0.0) m_last = m;
-        tot_fit += v;
         const float* row = H + ((size_t)m * nb + b) * nc;
         tot_all += 3.5449077018110318 * (double)row[0];
 #pragma unroll
@@ -145,11 +158,7 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
     const int W = T / 20 > 1 ? T / 20 : 1;
     Fit f{0.0, -1, RPR_ST_NO_ENERGY};
     if (m_last >= 0) {
-        // the fit sums run over [0, m_last] only
-        double t2 = 0.0;
-        for (int m = lane; m <= m_last; m += kWave) t2 += I_fit(a, H, HL, m, b);
-        tot_fit = wsum(t2);
-        f = fit_once(a, H, HL, b, m_last, W, 0.0, tot_fit, lane);
+        f = fit_once(a, H, HL, b, m_last, W, 0.0, lane);
         if (f.status == RPR_ST_OK && m_last >= T - W) {
             double ts = 0.0;
             for (int m = m_last - W + 1 + lane; m <= m_last; m += kWave) ts += I_fit(a, H, HL, m, b);
@@ -157,7 +166,7 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
             for (int it = 0; it < a.tail_iters; ++it) {
                 const double tau = f.rt / (6.0 * 2.302585092994046);
                 const double C = tail * exp(-(double)(W + 1) * a.dt / (2.0 * tau)) * tau / a.dt;
-                const Fit g = fit_once(a, H, HL, b, m_last, W, C, tot_fit, lane);
+                const Fit g = fit_once(a, H, HL, b, m_last, W, C, lane);
                 if (g.status != RPR_ST_OK) break;
                 f = Fit{g.rt, g.range, RPR_ST_OK | RPR_ST_TAIL_COMPENSATED};
             }

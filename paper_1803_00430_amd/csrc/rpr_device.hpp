@@ -187,7 +187,8 @@ __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float 
                 if (COUNT) ++*n_tris;
                 const float th = tri_test(a, b, c, ox, oy, oz, dx, dy, dz);
                 const uint32_t id = __float_as_uint(a.w);
-                if (th < tb || (th == tb && id < best_id)) {
+                // a miss is +inf and must never win the tie-break against "no hit yet"
+                if (th < tb || (th == tb && th < __builtin_inff() && id < best_id)) {
                     tb = th;
                     best = li;
                     best_id = id;
