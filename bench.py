@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=2048, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device-to-device three times "
+                         "(a known-size reference for the HBM byte counters)")
     return ap.parse_args()
 
 
@@ -85,9 +88,10 @@ def main():
     segs = int(st["n_segments"].sum())
     vn = float(st["n_node_visits"].sum()) / segs
     vt = float(st["n_tri_tests"].sum()) / segs
-    bytes_per_seg = 64.0 * vn + 48.0 * vt
+    bytes_per_seg = 128.0 * vn + 48.0 * vt  # 4-wide node = 128 B, triangle record = 48 B
     scene.close()
-    log(f"BVH depth {info['max_depth']}; {segs} segments/step; {vn:.1f} nodes + {vt:.1f} triangles per segment",
+    log(f"BVH depth {info['max_depth']}, stack {info['stack_need']}; {segs} segments/step; "
+        f"{vn:.1f} nodes + {vt:.1f} triangles per segment",
         a.quiet)
 
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -166,6 +170,14 @@ def main():
                                "kind": "oracle",
                                "sample": f"city, rays 0..{R_s - 1} of each of the 8 sources ({osegs} ray-bounces, "
                                          f"{c_wall:.1f} s), FP64 brute force"}
+    if a.calib_copy_mib > 0:
+        n = a.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)  # an elementwise kernel: reads and writes `n` floats
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 4 * n
     print(json.dumps(out), flush=True)
 
 

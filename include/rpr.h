@@ -86,7 +86,8 @@ typedef struct {
     float speed_of_sound; /* > 0, m/s */
     uint64_t seed;
     int32_t flags;        /* RPR_TRACE_* bits */
-    int32_t reserved;     /* 0 */
+    int32_t waves_per_cu; /* launch width of the persistent trace: resident waves per compute unit
+                             (0 = the library's default); results do not depend on it */
 } RprTraceParams;
 
 /* RprTraceParams.flags: count BVH nodes visited and triangles tested into
@@ -115,17 +116,20 @@ typedef struct {
 
 typedef struct {
     int64_t n_tris;
-    int64_t n_nodes;      /* internal BVH nodes (n_tris - 1) */
-    int32_t max_depth;    /* deepest leaf, in edges from the root */
+    int64_t n_nodes;      /* 4-wide BVH nodes */
+    int32_t max_depth;    /* deepest leaf of the binary tree, in edges from the root */
     int32_t n_bands;
     int32_t n_materials;
     int32_t n_degenerate; /* zero-area triangles (kept; never hit) */
     float bounds_lo[3];
     float bounds_hi[3];
+    int32_t stack_need;   /* traversal stack entries the deepest path can need (<= 64) */
+    int32_t reserved;
 } RprSceneInfo;
 
 /* Build a scene and its BVH (linear BVH: Morton codes of triangle centroids,
- * radix sort, hierarchy from longest common key prefixes, bottom-up bounds).
+ * radix sort, hierarchy from longest common key prefixes, bottom-up bounds,
+ * collapsed into 4-wide nodes for traversal).
  *   verts        device [n_verts][3] f32, metres
  *   tris         device [n_tris][3] i32 vertex indices
  *   tri_material device [n_tris] i32 in [0, n_materials), or NULL = material 0
@@ -135,8 +139,8 @@ typedef struct {
  * The scene copies what it needs; the inputs may be freed afterwards.
  * Synchronises hip_stream (the build reads back validation flags and the tree
  * depth).  Errors: RPR_EINVAL for out-of-range indices or materials,
- * non-finite vertices, coefficients outside [0, 1]; RPR_EUNSUPPORTED if the
- * tree is deeper than the traversal stack (64). */
+ * non-finite vertices, coefficients outside [0, 1]; RPR_EUNSUPPORTED if a
+ * path of the tree could need more than the traversal stack (64 entries). */
 int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                  const int32_t* tri_material, const float* absorption, const float* scattering,
                  int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out);

@@ -265,7 +265,8 @@ def _fit(I, dt, C0, m_last, W):
     ranges T30, T20, T10, EDT whose bottom level is reached at some
     m <= m_last - W is fitted by ordinary least squares over the points with
     lo <= y <= hi (at least 3).  Returns (rt60, range index, status)."""
-    S = C0 + np.cumsum(I[: m_last + 1][::-1])[::-1]
+    Sb = np.cumsum(I[: m_last + 1][::-1])[::-1]
+    S = C0 + Sb
     y = 10.0 * np.log10(S / S[0])
     t = np.arange(m_last + 1) * dt
     top = m_last - W

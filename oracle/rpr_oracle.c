@@ -38,6 +38,10 @@
 #define ORC_FNV_BASIS 2166136261u
 #define ORC_FNV_PRIME 16777619u
 #define ORC_HASH_ESCAPE 0xFFFFFFFFu
+/* Reading (self-intersection; the paper does not discuss it): a reflected
+ * segment starts 1 mm off the surface along the normal that faces the
+ * incoming ray, and the triangle just hit is excluded from the next query. */
+#define ORC_SURFACE_OFFSET 1e-3
 
 typedef struct {
     int64_t n_rays_total; /* energy normalisation: each ray starts with 1/n_rays_total per band */
@@ -462,7 +466,7 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
                     for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
                     h = fnv(h, 0u);
                 }
-                for (int i = 0; i < 3; ++i) o[i] = x[i];
+                for (int i = 0; i < 3; ++i) o[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
                 last = tri;
             }
 #pragma omp atomic
@@ -539,7 +543,7 @@ int orc_trace_path(const double *verts, int64_t n_tris, const int32_t *tris, con
             double dn = dot3(d, nf);
             for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
         }
-        for (int i = 0; i < 3; ++i) o[i] = x[i];
+        for (int i = 0; i < 3; ++i) o[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
         last = tri;
     }
     return n;

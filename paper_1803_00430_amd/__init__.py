@@ -48,7 +48,7 @@ class TraceParams(C.Structure):
     _fields_ = [("n_rays_total", C.c_int64), ("ray_begin", C.c_int64), ("ray_end", C.c_int64),
                 ("max_bounces", C.c_int32), ("sh_order", C.c_int32), ("n_bins", C.c_int32),
                 ("pair_base", C.c_int32), ("bin_width_s", C.c_float), ("speed_of_sound", C.c_float),
-                ("seed", C.c_uint64), ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("seed", C.c_uint64), ("flags", C.c_int32), ("waves_per_cu", C.c_int32)]
 
 
 TRACE_COUNT_VISITS = 1
@@ -61,7 +61,8 @@ class EstimateParams(C.Structure):
 class SceneInfo(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("max_depth", C.c_int32),
                 ("n_bands", C.c_int32), ("n_materials", C.c_int32), ("n_degenerate", C.c_int32),
-                ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3)]
+                ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3), ("stack_need", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 # Host views of the device structs (same layout as include/rpr.h).
@@ -182,7 +183,7 @@ class Scene:
         _check(lib().scene_info(self.handle, C.byref(si)))
         return dict(n_tris=si.n_tris, n_nodes=si.n_nodes, max_depth=si.max_depth, n_bands=si.n_bands,
                     n_materials=si.n_materials, n_degenerate=si.n_degenerate,
-                    bounds_lo=list(si.bounds_lo), bounds_hi=list(si.bounds_hi))
+                    bounds_lo=list(si.bounds_lo), bounds_hi=list(si.bounds_hi), stack_need=si.stack_need)
 
     def closest_hit(self, orig, dirs, stream=None):
         import torch
@@ -207,10 +208,10 @@ class Scene:
 
 
 def trace_params(*, n_rays_total, max_bounces, sh_order, n_bins, bin_width_s, seed, ray_begin=0, ray_end=None,
-                 pair_base=0, speed_of_sound=343.0, flags=0) -> TraceParams:
+                 pair_base=0, speed_of_sound=343.0, flags=0, waves_per_cu=0) -> TraceParams:
     return TraceParams(int(n_rays_total), int(ray_begin), int(n_rays_total if ray_end is None else ray_end),
                        int(max_bounces), int(sh_order), int(n_bins), int(pair_base), float(bin_width_s),
-                       float(speed_of_sound), int(seed), int(flags), 0)
+                       float(speed_of_sound), int(seed), int(flags), int(waves_per_cu))
 
 
 def alloc_trace_outputs(n_src, n_bins, n_bands, sh_order, n_rays=0, device="cuda", late=True, want_hash=False):

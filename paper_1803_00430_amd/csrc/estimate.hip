@@ -53,44 +53,74 @@ __device__ __forceinline__ double I_fit(const EstArgs& a, const float* H, const 
     return 3.5449077018110318 * (double)H[((size_t)m * a.nb + b) * a.nc];  // sqrt(4 pi) * H_00
 }
 
-// Backward integral S[m] = C + sum_{j=m..m_last} I[j], evaluated chunk by
-// chunk from the end (inclusive suffix sums within a chunk of 64 bins plus a
-// running carry).  Every use of S -- its value at 0 and at the range-test bin,
-// and the decay curve -- comes from this one evaluation order, so y[0] is
-// exactly 0 dB and a threshold decision never depends on two differently
-// rounded sums of the same quantity.
-template <class F>
-__device__ __forceinline__ double schroeder_scan(const EstArgs& a, const float* H, const float* HL, int b,
-                                                 int m_last, double C, int lane, F&& visit)
-{
-    double carry = C;
-    const int n_chunks = (m_last + kWave) / kWave;
-    for (int ch = n_chunks - 1; ch >= 0; --ch) {
-        const int m = ch * kWave + lane;
-        double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const double t = __shfl_down(v, o, kWave);
-            if (lane + o < kWave) v += t;
-        }
-        const double S = carry + v;
-        carry += __shfl(v, 0, kWave);
-        if (m <= m_last) visit(m, S);
-    }
-    return carry;  // S[0]
-}
+// Backward integral without the tail constant, Sb[m] = sum_{j=m..m_last} I[j],
+// evaluated chunk by chunk from the end (inclusive suffix sums within a chunk
+// of 64 bins plus a running carry); S[m] = C + Sb[m].  Every use of S -- its
+// value at 0 and at the range-test bin, and the decay curve -- is formed the
+// same way from the same Sb, so y[0] is exactly 0 dB and no threshold
+// decision depends on two differently rounded sums of one quantity.  With
+// LDS, Sb is computed once and kept (T <= kLdsBins); otherwise it is
+// recomputed by every pass.
+constexpr int kLdsBins = 8192;
 
-__device__ Fit fit_once(const EstArgs& a, const float* H, const float* HL, int b, int m_last, int W, double C,
-                        int lane)
+template <bool LDS>
+struct SbSource {
+    const EstArgs& a;
+    const float* H;
+    const float* HL;
+    int b, m_last, lane;
+    double* sS;  // LDS copy when LDS
+
+    template <class F>
+    __device__ __forceinline__ double scan(F&& visit) const
+    {
+        double carry = 0.0;
+        const int n_chunks = (m_last + kWave) / kWave;
+        for (int ch = n_chunks - 1; ch >= 0; --ch) {
+            const int m = ch * kWave + lane;
+            double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const double t = __shfl_down(v, o, kWave);
+                if (lane + o < kWave) v += t;
+            }
+            const double Sb = carry + v;
+            carry += __shfl(v, 0, kWave);
+            if (m <= m_last) visit(m, Sb);
+        }
+        return carry;
+    }
+
+    __device__ __forceinline__ void prepare()
+    {
+        if (LDS) scan([&](int m, double Sb) { sS[m] = Sb; });
+        __syncthreads();
+    }
+
+    // visit(m, Sb[m]) for m in [0, m_last]; returns Sb[0]
+    template <class F>
+    __device__ __forceinline__ double each(F&& visit) const
+    {
+        if (LDS) {
+            for (int m = lane; m <= m_last; m += kWave) visit(m, sS[m]);
+            return sS[0];
+        }
+        return scan(visit);
+    }
+};
+
+template <bool LDS>
+__device__ Fit fit_once(const SbSource<LDS>& src, double dt, int m_last, int W, double C, int lane)
 {
     Fit f{0.0, -1, RPR_ST_NO_RANGE};
     const int top = m_last - W;
     if (top < 0) return f;
-    double s_top_lane = 0.0;
-    const double S0 = schroeder_scan(a, H, HL, b, m_last, C, lane, [&](int m, double S) {
-        if (m == top) s_top_lane = S;
+    double sb_top_lane = 0.0;
+    const double Sb0 = src.each([&](int m, double Sb) {
+        if (m == top) sb_top_lane = Sb;
     });
-    const double S_top = wsum(s_top_lane);  // exactly one lane holds it
+    const double S0 = C + Sb0;
+    const double S_top = C + wsum(sb_top_lane);  // exactly one lane holds Sb[top]
     const double y_top = 10.0 * log10(S_top / S0);
     const double his[4] = {-5.0, -5.0, -5.0, 0.0};
     const double los[4] = {-35.0, -25.0, -15.0, -10.0};
@@ -98,10 +128,10 @@ __device__ Fit fit_once(const EstArgs& a, const float* H, const float* HL, int b
         const double hi = his[r], lo = los[r];
         if (!(y_top <= lo)) continue;
         double n = 0, s_t = 0, s_y = 0, s_tt = 0, s_ty = 0;
-        schroeder_scan(a, H, HL, b, m_last, C, lane, [&](int m, double S) {
-            const double y = 10.0 * log10(S / S0);
+        src.each([&](int m, double Sb) {
+            const double y = 10.0 * log10((C + Sb) / S0);
             if (y <= hi && y >= lo) {
-                const double t = (double)m * a.dt;
+                const double t = (double)m * dt;
                 n += 1.0;
                 s_t += t;
                 s_y += y;
@@ -124,8 +154,10 @@ __device__ Fit fit_once(const EstArgs& a, const float* H, const float* HL, int b
     return f;
 }
 
+template <bool LDS>
 __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
 {
+    extern __shared__ double sS[];
     const int ir = blockIdx.x / a.nb, b = blockIdx.x % a.nb;
     const int lane = threadIdx.x;
     const int T = a.T, nb = a.nb, nc = a.nc;
@@ -157,8 +189,10 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
 
     const int W = T / 20 > 1 ? T / 20 : 1;
     Fit f{0.0, -1, RPR_ST_NO_ENERGY};
+    SbSource<LDS> src{a, H, HL, b, m_last, lane, sS};
+    if (m_last >= 0) src.prepare();
     if (m_last >= 0) {
-        f = fit_once(a, H, HL, b, m_last, W, 0.0, lane);
+        f = fit_once(src, a.dt, m_last, W, 0.0, lane);
         if (f.status == RPR_ST_OK && m_last >= T - W) {
             double ts = 0.0;
             for (int m = m_last - W + 1 + lane; m <= m_last; m += kWave) ts += I_fit(a, H, HL, m, b);
@@ -166,7 +200,7 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
             for (int it = 0; it < a.tail_iters; ++it) {
                 const double tau = f.rt / (6.0 * 2.302585092994046);
                 const double C = tail * exp(-(double)(W + 1) * a.dt / (2.0 * tau)) * tau / a.dt;
-                const Fit g = fit_once(a, H, HL, b, m_last, W, C, lane);
+                const Fit g = fit_once(src, a.dt, m_last, W, C, lane);
                 if (g.status != RPR_ST_OK) break;
                 f = Fit{g.rt, g.range, RPR_ST_OK | RPR_ST_TAIL_COMPENSATED};
             }
@@ -234,7 +268,11 @@ extern "C" int estimate_reverb(const float* hist, const float* hist_late, const 
               e.rt60_source, e.tail_iters, out};
     const long long grid = (long long)n_ir * n_bands;
     if (grid > 0x7FFFFFFF) return set_error(RPR_EUNSUPPORTED, "estimate_reverb: too many IRs");
-    hipLaunchKernelGGL(k_estimate, dim3((unsigned)grid), dim3(kWave), 0, (hipStream_t)hip_stream, a);
+    if (n_bins <= kLdsBins)
+        hipLaunchKernelGGL(k_estimate<true>, dim3((unsigned)grid), dim3(kWave), sizeof(double) * n_bins,
+                           (hipStream_t)hip_stream, a);
+    else
+        hipLaunchKernelGGL(k_estimate<false>, dim3((unsigned)grid), dim3(kWave), 0, (hipStream_t)hip_stream, a);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }

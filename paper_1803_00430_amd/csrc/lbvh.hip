@@ -9,6 +9,8 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "rpr_device.hpp"
@@ -33,6 +35,8 @@ enum : uint32_t {
 struct BuildFlags {
     uint32_t flags;
     int32_t max_depth;
+    int32_t max_stack;  // most stack entries any root-to-leaf path of the 4-wide tree can push
+    uint32_t n_nodes4;  // 4-wide nodes
     uint32_t n_degenerate;
     uint32_t pad;
     // centroid bounds as order-preserving integer keys of the floats
@@ -58,6 +62,8 @@ __global__ void k_init_flags(BuildFlags* f)
     if (threadIdx.x == 0) {
         f->flags = 0;
         f->max_depth = 0;
+        f->max_stack = 0;
+        f->n_nodes4 = 0;
         f->n_degenerate = 0;
         for (int a = 0; a < 3; ++a) {
             f->clo[a] = ordered(__builtin_inff());
@@ -387,32 +393,35 @@ __global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const
     box[2 * b + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
 }
 
-// Bottom-up bounds: every leaf walks towards the root; at each internal node
-// the first arrival stops and the second (which then sees both children's
-// bounds) computes the union and continues.
-__global__ void k_refit(int n, const int2* __restrict__ child, const int32_t* __restrict__ parent,
-                        uint32_t* __restrict__ arrivals, float4* __restrict__ box)
+// Bottom-up bounds without ordering: internal boxes are kept as
+// order-preserving integer keys and widened with atomic min/max.  Each leaf
+// walks towards the root and stops at the first ancestor that none of its six
+// bounds widened: that ancestor already holds bounds at least as wide, set by
+// a leaf that is itself still propagating them upwards.  No fences are needed
+// because min and max commute.
+__global__ void k_box_init(int64_t n6, int32_t* __restrict__ ibox)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n6) return;
+    ibox[i] = (i % 6) < 3 ? ordered(__builtin_inff()) : ordered(-__builtin_inff());
+}
+
+__global__ void k_refit(int n, const int32_t* __restrict__ parent, const float4* __restrict__ box,
+                        int32_t* __restrict__ ibox)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int node = parent[(n - 1) + i];
-    // a tree of depth > kMaxStack is rejected anyway; the bound only keeps a
-    // malformed parent chain from looping
+    const int64_t lb = (int64_t)(n - 1) + i;
+    const float4 lo = box[2 * lb], hi = box[2 * lb + 1];
+    const int32_t v[6] = {ordered(lo.x), ordered(lo.y), ordered(lo.z), ordered(hi.x), ordered(hi.y), ordered(hi.z)};
+    int node = parent[lb];
     for (int guard = 0; node >= 0 && guard < 4 * kMaxStack; ++guard) {
-        const uint32_t prev =
-            __hip_atomic_fetch_add(&arrivals[node], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == 0) return;
-        const int2 c = child[node];
-        const int64_t a = is_leaf(c.x) ? (int64_t)(n - 1) + leaf_index(c.x) : c.x;
-        const int64_t b = is_leaf(c.y) ? (int64_t)(n - 1) + leaf_index(c.y) : c.y;
-        const float4 alo = box[2 * a], ahi = box[2 * a + 1], blo = box[2 * b], bhi = box[2 * b + 1];
-        box[2 * (int64_t)node + 0] =
-            make_float4(fminf(alo.x, blo.x), fminf(alo.y, blo.y), fminf(alo.z, blo.z), 0.0f);
-        box[2 * (int64_t)node + 1] =
-            make_float4(fmaxf(ahi.x, bhi.x), fmaxf(ahi.y, bhi.y), fmaxf(ahi.z, bhi.z), 0.0f);
-        __atomic_thread_fence(__ATOMIC_RELEASE);
-        if (node == 0) return;
-        node = parent[node];
+        int32_t* b = ibox + 6 * (int64_t)node;
+        bool widened = false;
+        for (int k = 0; k < 3; ++k) widened |= atomicMin(&b[k], v[k]) > v[k];
+        for (int k = 3; k < 6; ++k) widened |= atomicMax(&b[k], v[k]) < v[k];
+        if (!widened) break;
+        node = node == 0 ? -1 : parent[node];
     }
 }
 
@@ -440,48 +449,144 @@ __global__ void k_check_refs(int n, const uint32_t* __restrict__ refs, BuildFlag
     if (refs[i] != want) atomicOr(&f->flags, (uint32_t)kBadTree);
 }
 
-// Traversal nodes: both children's boxes and links in 64 bytes.
-__global__ void k_pack(int n, const int2* __restrict__ child, const float4* __restrict__ box,
-                       float4* __restrict__ nodes)
+__device__ __forceinline__ void node_box(int n, int32_t link, const float4* __restrict__ box,
+                                         const int32_t* __restrict__ ibox, float4& lo, float4& hi)
+{
+    if (is_leaf(link)) {
+        const int64_t b = (int64_t)(n - 1) + leaf_index(link);
+        lo = box[2 * b];
+        hi = box[2 * b + 1];
+    } else {
+        const int32_t* q = ibox + 6 * (int64_t)link;
+        lo = make_float4(unordered(q[0]), unordered(q[1]), unordered(q[2]), 0.0f);
+        hi = make_float4(unordered(q[3]), unordered(q[4]), unordered(q[5]), 0.0f);
+    }
+}
+
+// Depth of every internal node of the binary tree (the root has depth 0).
+__global__ void k_node_depth(int n, const int32_t* __restrict__ parent, uint32_t* __restrict__ even, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
-    const int2 c = child[i];
-    const int64_t a = is_leaf(c.x) ? (int64_t)(n - 1) + leaf_index(c.x) : c.x;
-    const int64_t b = is_leaf(c.y) ? (int64_t)(n - 1) + leaf_index(c.y) : c.y;
-    const float4 alo = box[2 * a], ahi = box[2 * a + 1], blo = box[2 * b], bhi = box[2 * b + 1];
-    nodes[4 * (int64_t)i + 0] = make_float4(alo.x, alo.y, alo.z, ahi.x);
-    nodes[4 * (int64_t)i + 1] = make_float4(ahi.y, ahi.z, blo.x, blo.y);
-    nodes[4 * (int64_t)i + 2] = make_float4(blo.z, bhi.x, bhi.y, bhi.z);
-    nodes[4 * (int64_t)i + 3] = make_float4(__int_as_float(c.x), __int_as_float(c.y), 0.0f, 0.0f);
+    int d = 0;
+    for (int node = i; node != 0 && d <= 4 * kMaxStack; ++d) node = parent[node];
+    even[i] = (d % 2 == 0) ? 1u : 0u;
+    if (d % 2 == 0) atomicAdd(&f->n_nodes4, 1u);
 }
 
-// Depth of every leaf (edges to the root); the maximum sizes the traversal stack.
-__global__ void k_depth(int n, const int32_t* __restrict__ parent, BuildFlags* f)
+// Collapse of the binary tree into 4-wide nodes: every internal node at an
+// even depth becomes a 4-wide node whose slots are its children, with each
+// internal child replaced by that child's own two children (which sit at the
+// next even depth).  idx4 = exclusive prefix sum of the even-depth flags, so
+// the root becomes node 0 and nodes keep the Morton order of the binary tree.
+__global__ void k_collapse4(int n, const int2* __restrict__ child, const float4* __restrict__ box,
+                            const int32_t* __restrict__ ibox, const uint32_t* __restrict__ even,
+                            const uint32_t* __restrict__ idx4, float4* __restrict__ nodes)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1 || !even[i]) return;
+    int32_t links[4];
+    float4 lo[4], hi[4];
+    int k = 0;
+    const int2 c = child[i];
+    const int32_t cs[2] = {c.x, c.y};
+    for (int a = 0; a < 2; ++a) {
+        if (is_leaf(cs[a])) {
+            node_box(n, cs[a], box, ibox, lo[k], hi[k]);
+            links[k++] = cs[a];
+        } else {
+            const int2 g = child[cs[a]];
+            const int32_t gs[2] = {g.x, g.y};
+            for (int b = 0; b < 2; ++b) {
+                node_box(n, gs[b], box, ibox, lo[k], hi[k]);
+                links[k++] = is_leaf(gs[b]) ? gs[b] : (int32_t)idx4[gs[b]];
+            }
+        }
+    }
+    // Empty slots: a box at +inf, which the slab test reports either as a miss
+    // or as an entry at t = +inf -- both ignored by the traversal.  Its link is
+    // a leaf, never an internal node, so a visit could not loop.
+    for (; k < 4; ++k) {
+        lo[k] = make_float4(__builtin_inff(), __builtin_inff(), __builtin_inff(), 0.0f);
+        hi[k] = lo[k];
+        links[k] = leaf_link(0);
+    }
+    float4* o = nodes + (int64_t)kNode4 * idx4[i];
+    for (int j = 0; j < 4; ++j) {
+        o[2 * j] = make_float4(lo[j].x, lo[j].y, lo[j].z, __int_as_float(links[j]));
+        o[2 * j + 1] = make_float4(hi[j].x, hi[j].y, hi[j].z, 0.0f);
+    }
+}
+
+// Depth of every leaf (edges to the root) and the stack the 4-wide traversal
+// can need on its path: each 4-wide ancestor (an even-depth binary node)
+// pushes at most its slot count minus one.
+__global__ void k_depth(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
+                        const uint32_t* __restrict__ even, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int d = 0;
+    int d = 0, need = 0;
     int node = parent[(n - 1) + i];
     while (node >= 0 && d <= 4 * kMaxStack) {
         ++d;
+        if (even[node]) {
+            const int2 c = child[node];
+            need += (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1;
+        }
         node = node == 0 ? -1 : parent[node];
     }
     atomicMax(&f->max_depth, d);
+    atomicMax(&f->max_stack, need);
 }
+
+// Build temporaries come from one grow-only device arena per device, reused
+// by every scene_create (which holds the arena's lock and synchronises its
+// stream before returning), so a rebuild does not allocate.
+struct Arena {
+    std::mutex mu;
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+};
+Arena g_arena[16];
 
 template <class T>
 struct DevBuf {
     T* p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
+    size_t bytes = 0;
     hipError_t alloc(size_t n)
     {
-        return hipMalloc(&p, sizeof(T) * (n ? n : 1));
+        bytes = (sizeof(T) * (n ? n : 1) + 255) & ~(size_t)255;
+        return hipSuccess;
     }
 };
+
+// Lay out `bufs` in the arena (growing it when needed).
+template <class... B>
+hipError_t arena_place(Arena& a, B&... bufs)
+{
+    size_t need = 0;
+    ((need += bufs.bytes), ...);
+    if (need > a.cap) {
+        if (a.base) {
+            hipError_t e = hipFree(a.base);
+            if (e != hipSuccess) return e;
+            a.base = nullptr;
+            a.cap = 0;
+        }
+        hipError_t e = hipMalloc(&a.base, need + need / 4);
+        if (e != hipSuccess) return e;
+        a.cap = need + need / 4;
+    }
+    size_t off = 0;
+    auto put = [&](auto& b) {
+        b.p = reinterpret_cast<std::remove_reference_t<decltype(b.p)>>(a.base + off);
+        off += b.bytes;
+    };
+    (put(bufs), ...);
+    a.used = off;
+    return hipSuccess;
+}
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -532,22 +637,21 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                                   "scene_create: %s: %s", #expr, hipGetErrorString(e_)));         \
     } while (0)
 
+    int dev = sc->device;
+    if (dev < 0 || dev >= 16) return fail(set_error(RPR_EUNSUPPORTED, "scene_create: device %d", dev));
+    Arena& arena = g_arena[dev];
+    std::lock_guard<std::mutex> arena_lock(arena.mu);
     DevBuf<BuildFlags> flags;
     TRY(flags.alloc(1));
     TRY(hipMalloc(&sc->mats, sizeof(float) * kMatStride * n_materials));
     TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
-    TRY(hipMalloc(&sc->nodes, sizeof(float4) * 4 * (size_t)(n > 1 ? n - 1 : 1)));
-    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
-    hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
-                       n_materials, n_bands, sc->mats, flags.p);
-    TRY(hipGetLastError());
-
+    TRY(hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * (size_t)(n > 1 ? n - 1 : 1)));
+    DevBuf<float4> cent, box;
+    DevBuf<uint32_t> k0, v0, k1, v1, counts, seen, refs, even, idx4;
+    DevBuf<int32_t> ibox, parent;
+    DevBuf<int2> child;
+    const int n_tiles = (int)blocks(n > 0 ? n : 1, kSortTile);
     if (n > 0) {
-        const int n_tiles = (int)blocks(n, kSortTile);
-        DevBuf<float4> cent, box;
-        DevBuf<uint32_t> k0, v0, k1, v1, counts, arrivals, seen, refs;
-        DevBuf<int2> child;
-        DevBuf<int32_t> parent;
         TRY(cent.alloc(n));
         TRY(k0.alloc(n));
         TRY(v0.alloc(n));
@@ -557,9 +661,19 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(box.alloc(2 * (size_t)(2 * n - 1)));
         TRY(child.alloc(n > 1 ? n - 1 : 1));
         TRY(parent.alloc(2 * (size_t)n - 1));
-        TRY(arrivals.alloc(n > 1 ? n - 1 : 1));
+        TRY(ibox.alloc(6 * (size_t)(n > 1 ? n - 1 : 1)));
         TRY(seen.alloc(n));
+        TRY(even.alloc(n > 1 ? n - 1 : 1));
+        TRY(idx4.alloc(n > 1 ? n - 1 : 1));
         TRY(refs.alloc(2 * (size_t)n - 1));
+    }
+    TRY(arena_place(arena, flags, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, ibox, parent, child));
+    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
+    hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
+                       n_materials, n_bands, sc->mats, flags.p);
+    TRY(hipGetLastError());
+
+    if (n > 0) {
         TRY(hipMemsetAsync(seen.p, 0, sizeof(uint32_t) * n, st));
         TRY(hipMemsetAsync(refs.p, 0, sizeof(uint32_t) * (2 * (size_t)n - 1), st));
         hipLaunchKernelGGL(k_prep, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts, n_verts, tris,
@@ -578,7 +692,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         }
         // after four passes the sorted keys/ids are back in (k0, v0)
         TRY(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), st));
-        TRY(hipMemsetAsync(arrivals.p, 0, sizeof(uint32_t) * (n > 1 ? n - 1 : 1), st));
+
         hipLaunchKernelGGL(k_tri_records, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts,
                            n_verts, tris, tri_material, vi, n, sc->tris, box.p, seen.p, flags.p);
         if (n > 1) {
@@ -588,12 +702,18 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                                child.p, refs.p, flags.p);
             hipLaunchKernelGGL(k_check_refs, dim3(blocks(2 * (int64_t)n - 1, kBuildBlock)), dim3(kBuildBlock), 0,
                                st, n, refs.p, flags.p);
-            hipLaunchKernelGGL(k_refit, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
-                               parent.p, arrivals.p, box.p);
-            hipLaunchKernelGGL(k_pack, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
-                               box.p, sc->nodes);
+            hipLaunchKernelGGL(k_box_init, dim3(blocks(6 * (int64_t)(n - 1), kBuildBlock)), dim3(kBuildBlock), 0,
+                               st, 6 * (int64_t)(n - 1), ibox.p);
+            hipLaunchKernelGGL(k_refit, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p, box.p,
+                               ibox.p);
+            hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
+                               parent.p, even.p, flags.p);
+            TRY(hipMemcpyAsync(idx4.p, even.p, sizeof(uint32_t) * (n - 1), hipMemcpyDeviceToDevice, st));
+            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, idx4.p, (int64_t)(n - 1));
+            hipLaunchKernelGGL(k_collapse4, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
+                               box.p, ibox.p, even.p, idx4.p, sc->nodes);
             hipLaunchKernelGGL(k_depth, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,
-                               flags.p);
+                               child.p, even.p, flags.p);
         }
         TRY(hipGetLastError());
         BuildFlags hf;
@@ -606,14 +726,17 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
             return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
         if (hf.flags & kBadTree) return fail(set_error(RPR_EDEVICE, "scene_create: BVH consistency check failed"));
         sc->max_depth = hf.max_depth;
+        sc->stack_need = hf.max_stack;
+        sc->n_nodes4 = hf.n_nodes4;
         sc->n_degenerate = (int32_t)hf.n_degenerate;
         for (int a = 0; a < 3; ++a) {
             sc->lo[a] = unordered(hf.blo[a]);
             sc->hi[a] = unordered(hf.bhi[a]);
         }
-        if (sc->max_depth > kMaxStack)
-            return fail(set_error(RPR_EUNSUPPORTED, "scene_create: BVH depth %d exceeds the traversal stack %d",
-                                  sc->max_depth, kMaxStack));
+        if (sc->stack_need > kMaxStack)
+            return fail(set_error(RPR_EUNSUPPORTED,
+                                  "scene_create: BVH depth %d needs %d stack entries, more than the traversal's %d",
+                                  sc->max_depth, sc->stack_need, kMaxStack));
     } else {
         BuildFlags hf;
         TRY(hipMemcpyAsync(&hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, st));
@@ -652,8 +775,9 @@ extern "C" int scene_info(const RprScene* scene, RprSceneInfo* out)
     if (!scene || !out) return set_error(RPR_EINVAL, "scene_info: null argument");
     std::memset(out, 0, sizeof(*out));
     out->n_tris = scene->n_tris;
-    out->n_nodes = scene->n_tris > 1 ? scene->n_tris - 1 : 0;
+    out->n_nodes = scene->n_nodes4;
     out->max_depth = scene->max_depth;
+    out->stack_need = scene->stack_need;
     out->n_bands = scene->n_bands;
     out->n_materials = scene->n_materials;
     out->n_degenerate = scene->n_degenerate;

@@ -92,25 +92,39 @@ __device__ __forceinline__ void lambert_dir(float nx, float ny, float nz, float 
     dz = lx * b1z + ly * b2z + lz * nz;
 }
 
+// ---------------------------------------------------------------- memory
+// Loads through the global address space (plain pointers in structs would
+// otherwise become flat accesses, which wait on both memory counters).
+__device__ __forceinline__ float4 gld(const float4* p)
+{
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    const v4 v = *(const __attribute__((address_space(1))) v4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // ---------------------------------------------------------------- intersection
-// Slab test of one box against [0, tmax]; tmax is widened by a few ulps so
-// that flat boxes (axis-aligned walls) are not lost to rounding.
+// Slab test of one box against [0, tmax], with the plane distances formed as
+// lo * (1/d) - o * (1/d) (one fused multiply-add per plane; oi = o * (1/d));
+// tmax is widened by a few ulps so that flat boxes (axis-aligned walls) are
+// not lost to rounding.
 __device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz,
-                                     float ox, float oy, float oz, float ix, float iy, float iz, float tmax,
+                                     float oix, float oiy, float oiz, float ix, float iy, float iz, float tmax,
                                      float& tnear)
 {
-    const float t0x = (lox - ox) * ix, t1x = (hix - ox) * ix;
-    const float t0y = (loy - oy) * iy, t1y = (hiy - oy) * iy;
-    const float t0z = (loz - oz) * iz, t1z = (hiz - oz) * iz;
+    const float t0x = fmaf(lox, ix, -oix), t1x = fmaf(hix, ix, -oix);
+    const float t0y = fmaf(loy, iy, -oiy), t1y = fmaf(hiy, iy, -oiy);
+    const float t0z = fmaf(loz, iz, -oiz), t1z = fmaf(hiz, iz, -oiz);
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     tnear = tn;
     return tn <= tf * 1.00000048f;
 }
 
-// Moller-Trumbore against a precomputed (v0, e1, e2) record; the barycentric
-// bounds are widened by 1e-6 so that rays through a shared edge hit one of
-// its two triangles.  Returns t > 0 or +inf.
+// Moller-Trumbore against a precomputed (v0, e1, e2) record, with the
+// barycentric and distance tests done on the numerators scaled by |det| so
+// that only the accepted distance needs the reciprocal of det.  The
+// barycentric bounds are widened by 1e-6 so that rays through a shared edge
+// hit one of its two triangles.  Returns t > 0 or +inf.
 __device__ __forceinline__ float tri_test(const float4 a, const float4 b, const float4 c, float ox, float oy,
                                           float oz, float dx, float dy, float dz)
 {
@@ -118,15 +132,16 @@ __device__ __forceinline__ float tri_test(const float4 a, const float4 b, const 
     const float e2x = c.x, e2y = c.y, e2z = c.z;
     const float px = dy * e2z - dz * e2y, py = dz * e2x - dx * e2z, pz = dx * e2y - dy * e2x;
     const float det = e1x * px + e1y * py + e1z * pz;
-    const float inv = 1.0f / det;
     const float sx = ox - a.x, sy = oy - a.y, sz = oz - a.z;
-    const float u = (sx * px + sy * py + sz * pz) * inv;
     const float qx = sy * e1z - sz * e1y, qy = sz * e1x - sx * e1z, qz = sx * e1y - sy * e1x;
-    const float v = (dx * qx + dy * qy + dz * qz) * inv;
-    const float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
-    const float eps = 1e-6f;
-    const bool ok = det != 0.0f && u >= -eps && v >= -eps && u + v <= 1.0f + eps && t > 0.0f;
-    return ok ? t : __builtin_inff();
+    const float sg = det < 0.0f ? -1.0f : 1.0f;
+    const float ad = fabsf(det);
+    const float u = sg * (sx * px + sy * py + sz * pz);
+    const float v = sg * (dx * qx + dy * qy + dz * qz);
+    const float t = sg * (e2x * qx + e2y * qy + e2z * qz);
+    const float eps = 1e-6f * ad;
+    const bool ok = ad != 0.0f && u >= -eps && v >= -eps && u + v <= ad + eps && t > 0.0f;
+    return ok ? t / ad : __builtin_inff();
 }
 
 __device__ __forceinline__ float safe_inv(float d)
@@ -135,17 +150,32 @@ __device__ __forceinline__ float safe_inv(float d)
     return 1.0f / (fabsf(d) > m ? d : (d >= 0.0f ? m : -m));
 }
 
-// Closest hit with a per-lane stack in LDS (stack[slot * 64 + lane]).  The
-// leaf `exclude` (sorted index) is skipped: the triangle the ray just left.
-// Ties in t go to the lower original triangle index.  Returns the sorted leaf
-// index of the hit or -1, with t in `t_hit`.
+// Closest hit with a per-lane stack in LDS (stack[slot * 64 + lane]) over the
+// 4-wide BVH.  At an internal node all four child boxes are tested; the hit
+// children are ordered by entry distance, the nearest is visited next and the
+// others are pushed farthest first.  The leaf `exclude` (sorted index) is
+// skipped: the triangle the ray just left.  Ties in t go to the lower
+// original triangle index.  Returns the sorted leaf index of the hit or -1,
+// with t in `t_hit`.
+__device__ __forceinline__ void cswap(float& ta, int32_t& la, float& tb, int32_t& lb)
+{
+    const bool s = tb < ta;
+    const float t0 = s ? tb : ta, t1 = s ? ta : tb;
+    const int32_t l0 = s ? lb : la, l1 = s ? la : lb;
+    ta = t0;
+    tb = t1;
+    la = l0;
+    lb = l1;
+}
+
 template <int STACK, bool COUNT = false>
 __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float oy, float oz, float dx, float dy,
                                            float dz, int exclude, int32_t* __restrict__ stack, int lane,
                                            float& t_hit, uint32_t& hit_id, uint32_t* n_nodes = nullptr,
                                            uint32_t* n_tris = nullptr)
 {
-    float tb = __builtin_inff();
+    const float inf = __builtin_inff();
+    float tb = inf;
     int best = -1;
     uint32_t best_id = 0xFFFFFFFFu;
     if (sc.n_tris <= 0) {
@@ -154,41 +184,55 @@ __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float 
         return -1;
     }
     const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float oix = ox * ix, oiy = oy * iy, oiz = oz * iz;
     int sp = 0;
     int32_t node = sc.root;
     for (;;) {
         if (!is_leaf(node)) {
-            const float4* n = sc.nodes + 4 * (int64_t)node;
-            const float4 a = n[0], b = n[1], c = n[2], l = n[3];
-            if (COUNT) ++*n_nodes;
-            float t0, t1;
-            const bool h0 = slab(a.x, a.y, a.z, a.w, b.x, b.y, ox, oy, oz, ix, iy, iz, tb, t0);
-            const bool h1 = slab(b.z, b.w, c.x, c.y, c.z, c.w, ox, oy, oz, ix, iy, iz, tb, t1);
-            const int32_t l0 = __float_as_int(l.x), l1 = __float_as_int(l.y);
-            if (h0 && h1) {
-                const bool first0 = t0 <= t1;
-                const int32_t nearl = first0 ? l0 : l1, farl = first0 ? l1 : l0;
-                // The stack is at least as deep as the tree (checked when the
-                // scene is built); a full stack would drop the far child
-                // rather than write out of bounds.
-                if (sp < STACK) stack[sp++ * kWave + lane] = farl;
-                node = nearl;
-                continue;
+            const float4* nd = sc.nodes + (int64_t)kNode4 * node;
+            float t[4];
+            int32_t l[4];
+            float4 na[4], nb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                na[j] = gld(nd + 2 * j);
+                nb[j] = gld(nd + 2 * j + 1);
             }
-            if (h0 || h1) {
-                node = h0 ? l0 : l1;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 a = na[j], b = nb[j];
+                float tn;
+                const bool h = slab(a.x, a.y, a.z, b.x, b.y, b.z, oix, oiy, oiz, ix, iy, iz, tb, tn);
+                t[j] = h ? tn : inf;
+                l[j] = __float_as_int(a.w);
+            }
+            if (COUNT) ++*n_nodes;
+            // sorting network for four (t, link) pairs
+            cswap(t[0], l[0], t[1], l[1]);
+            cswap(t[2], l[2], t[3], l[3]);
+            cswap(t[0], l[0], t[2], l[2]);
+            cswap(t[1], l[1], t[3], l[3]);
+            cswap(t[1], l[1], t[2], l[2]);
+            if (t[0] < inf) {
+                // The stack holds what the deepest path can push (checked when
+                // the scene is built); a full stack would drop an entry rather
+                // than write out of bounds.
+#pragma unroll
+                for (int j = 3; j >= 1; --j)
+                    if (t[j] < inf && sp < STACK) stack[sp++ * kWave + lane] = l[j];
+                node = l[0];
                 continue;
             }
         } else {
             const int li = leaf_index(node);
             if (li != exclude) {
-                const float4* t = sc.tris + 3 * (int64_t)li;
-                const float4 a = t[0], b = t[1], c = t[2];
+                const float4* tr = sc.tris + 3 * (int64_t)li;
+                const float4 a = gld(tr), b = gld(tr + 1), c = gld(tr + 2);
                 if (COUNT) ++*n_tris;
                 const float th = tri_test(a, b, c, ox, oy, oz, dx, dy, dz);
                 const uint32_t id = __float_as_uint(a.w);
                 // a miss is +inf and must never win the tie-break against "no hit yet"
-                if (th < tb || (th == tb && th < __builtin_inff() && id < best_id)) {
+                if (th < tb || (th == tb && th < inf && id < best_id)) {
                     tb = th;
                     best = li;
                     best_id = id;

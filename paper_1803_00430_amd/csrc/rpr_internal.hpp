@@ -25,8 +25,15 @@ int set_error(int code, const char* fmt, ...);
     } while (0)
 
 constexpr int kWave = 64;
-constexpr int kMaxStack = 64;       // traversal stack entries per lane (>= max tree depth)
+constexpr int kMaxStack = 64;       // traversal stack entries per lane
+constexpr int kNode4 = 8;           // float4 per 4-wide node
 constexpr int kMatStride = 32;      // floats per material record
+// A reflected segment starts this far (metres) off the surface along the
+// normal facing the incoming ray.  FP32 hit points lie a few units in the last
+// place off their plane; with the origin on the plane, a ray reflected near
+// the shared edge of two coplanar triangles can meet the neighbour at t ~ 0 and
+// alternate between the two.  1 mm is >= 30 ulps for coordinates up to 500 m.
+constexpr float kSurfaceOffset = 1e-3f;
 // Material record: [0] p_diffuse, [1 + b] alpha_b, [9 + b] diffuse weight
 // (1-alpha_b) s_b / p_d, [17 + b] specular weight (1-alpha_b)(1-s_b)/(1-p_d).
 constexpr int kMatPd = 0, kMatAlpha = 1, kMatWd = 9, kMatWs = 17;
@@ -37,11 +44,10 @@ __host__ __device__ inline int32_t leaf_index(int32_t link) { return ~link; }
 __host__ __device__ inline int32_t leaf_link(int32_t i) { return ~i; }
 
 // One scene's BVH as consumed by the traversal kernels.
-//   nodes: 4 float4 per internal node:
-//     n0 = (c0.lo.x, c0.lo.y, c0.lo.z, c0.hi.x)
-//     n1 = (c0.hi.y, c0.hi.z, c1.lo.x, c1.lo.y)
-//     n2 = (c1.lo.z, c1.hi.x, c1.hi.y, c1.hi.z)
-//     n3 = (link0, link1, 0, 0) as int bits
+//   nodes: 4-wide nodes of 128 bytes (one cache line): four 32-byte child
+//     slots, slot j = float4 (lo.x, lo.y, lo.z, link bits), float4 (hi.x,
+//     hi.y, hi.z, 0).  An empty slot has the box lo = hi = +inf, whose entry
+//     distance is never finite, and a leaf link.
 //   tris: 3 float4 per triangle in Morton (leaf) order:
 //     (v0.xyz, original index bits), (e1.xyz, material bits), (e2.xyz, 0)
 struct SceneView {
@@ -95,7 +101,9 @@ struct RprScene {
     int64_t n_tris = 0;
     int32_t n_bands = 0;
     int32_t n_materials = 0;
-    int32_t max_depth = 0;
+    int32_t max_depth = 0;     // binary tree depth
+    int32_t stack_need = 0;    // traversal stack entries the 4-wide tree can need
+    int64_t n_nodes4 = 0;
     int32_t n_degenerate = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float4* nodes = nullptr;
@@ -111,6 +119,6 @@ int workspace_reserve(Workspace& ws, size_t pairs);
 void workspace_free(Workspace& ws);
 // Launch the persistent trace over `n_pairs` descriptors already in device memory.
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
-                 int nb, int max_depth, bool count_visits, int grid_override, hipStream_t stream);
+                 int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream);
 int device_cu_count();
 }  // namespace rpr

@@ -4,7 +4,7 @@
 // has terminated are refilled from a global queue of (pair, ray) slots with
 // one atomic per wave, so waves stay full while ray lifetimes differ (an
 // escape after one segment vs. a hundred bounces).  Closest hits use the
-// scene's linear BVH with a per-lane node stack in LDS.  Listener-sphere
+// scene's 4-wide BVH with a per-lane node stack in LDS.  Listener-sphere
 // deposits are gathered over the wave and issued as coalesced atomics: for
 // each depositing lane, the 64 lanes cover the band x SH-coefficient row of a
 // histogram bin (4 bands x 16 coefficients at SH order 3).
@@ -352,6 +352,10 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                         dz *= il;
                         h = fnv1a(h, 0u);
                     }
+                    // the reflected segment starts just off the surface, on its facing side
+                    ox = fmaf(kSurfaceOffset, nx, ox);
+                    oy = fmaf(kSurfaceOffset, ny, oy);
+                    oz = fmaf(kSurfaceOffset, nz, oz);
                     last = hit;
                 }
             }
@@ -523,13 +527,14 @@ void workspace_free(Workspace& ws)
 }
 
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,
-                 int max_depth, bool count_visits, int grid_override, hipStream_t stream)
+                 int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream)
 {
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
     int rc = ensure_variants();
     if (rc != RPR_OK) return rc;
-    const Variant& v = g_var[nb <= 4 ? 0 : 1][max_depth <= 32 ? 0 : 1][count_visits ? 1 : 0];
-    long long grid = grid_override > 0 ? grid_override : (long long)g_cus * v.blocks_per_cu;
+    const Variant& v = g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][count_visits ? 1 : 0];
+    const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, v.blocks_per_cu) : v.blocks_per_cu;
+    long long grid = grid_override > 0 ? grid_override : (long long)g_cus * per_cu;
     const long long need = (total_rays + kWave - 1) / kWave;
     grid = std::max(1ll, std::min(grid, need));
     hipLaunchKernelGGL(v.fn, dim3((unsigned)grid), dim3(kWave), 0, stream, d_pairs, n_pairs, d_queue,
@@ -557,6 +562,7 @@ extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_
     if (!(p->speed_of_sound > 0.f) || !std::isfinite(p->speed_of_sound))
         return set_error(RPR_EINVAL, "trace_ir: speed_of_sound must be > 0");
     if (p->max_bounces < 0) return set_error(RPR_EINVAL, "trace_ir: max_bounces < 0");
+    if (p->waves_per_cu < 0) return set_error(RPR_EINVAL, "trace_ir: waves_per_cu < 0");
     if (p->n_rays_total < 1) return set_error(RPR_EINVAL, "trace_ir: n_rays_total < 1");
     if (p->ray_begin < 0 || p->ray_end < p->ray_begin || p->ray_end > ((int64_t)1 << 32))
         return set_error(RPR_EINVAL, "trace_ir: bad ray range [%lld, %lld)", (long long)p->ray_begin,
@@ -633,8 +639,8 @@ extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_
                            hist_late, nl, 0.0f);
     }
     RPR_HIP_TRY(hipGetLastError());
-    return launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->max_depth,
-                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0, 0, st);
+    return launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need,
+                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0, p->waves_per_cu, 0, st);
 }
 
 extern "C" int scene_closest_hit(const RprScene* scene, const float* orig, const float* dir, int64_t n,

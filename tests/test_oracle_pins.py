@@ -224,10 +224,11 @@ def test_direct_sound_closed_form(orc):
     nz = ref_bins > 0
     assert np.array_equal(Im > 0, nz)  # bins 15..18 and nothing else
     assert np.all(np.abs(Im - ref_bins)[nz] < 5 * Ise[nz] + 1e-15)
-    # every band carries the same order-0 energy
+    # every band carries the same order-0 energy (OpenMP atomics may add in a
+    # different order per band, hence not bitwise)
     for r in runs:
         ec = r["stats"][0]["e_class"][0]
-        assert np.all(ec == ec[0])
+        assert np.allclose(ec, ec[0], rtol=1e-12, atol=0)
 
 
 def _images_order_1_2(src, dims):
@@ -278,7 +279,8 @@ def test_zero_absorption_conserves_energy(orc):
     assert np.all(st["e_absorbed"] == 0)
     assert np.allclose(st["e_alive_at_stop"], 1.0, rtol=1e-12)
     H = r["hist"][0]
-    assert np.all(H[:, 1:, :] == H[:, :1, :])  # all bands identical
+    # all bands identical up to the order of the FP64 atomic additions
+    assert np.allclose(H[:, 1:, :], H[:, :1, :], rtol=1e-12, atol=1e-14 * np.abs(H).max())
     I = math.sqrt(4 * math.pi) * H[:, 0, 0]
     late = I[300:].mean()
     assert abs(late / (1e-3 / 210.0) - 1) < 0.03, late
