@@ -201,6 +201,69 @@ int estimate_reverb(const float* hist, const float* hist_late, const RprIrStats*
                     int32_t n_bins, int32_t n_bands, int32_t sh_order, float bin_width_s,
                     const RprEstimateParams* ep, RprReverbParams* out, void* hip_stream);
 
+/* ------------------------------------------------------------------ batches
+ * Many source-listener pairs over several scenes traced by one persistent
+ * launch (the paper traces every source of a frame; Section 5 "Sound
+ * Propagation").  A batch is planned once and then run any number of times;
+ * each run resets the outputs, traces every ray of every pair and estimates
+ * the reverb parameters of every pair, with results that do not depend on the
+ * launch shape. */
+typedef struct RprBatch RprBatch;
+
+typedef struct {
+    int32_t scene;        /* index into the scenes passed to batch_create */
+    int32_t pair_id;      /* RNG counter word 1 of this pair's rays */
+    float src[3];
+    float lst[3];
+    float radius;         /* listener sphere radius, > 0 */
+    int32_t max_bounces;  /* K >= 0 */
+    int64_t n_rays;       /* rays of this pair (>= 1); each starts with energy 1/n_rays */
+    uint64_t seed;        /* Philox key of this pair */
+} RprPair;
+
+typedef struct {
+    int32_t n_bins;       /* T, shared by all pairs */
+    int32_t sh_order;     /* 0..3 */
+    float bin_width_s;
+    float speed_of_sound;
+    int32_t rt60_source;  /* as RprEstimateParams */
+    int32_t tail_iters;
+    int32_t autotune;     /* 1: time the candidate launch shapes at creation and keep the fastest */
+    int32_t use_graph;    /* 1: capture the run (reset, trace, estimate) into a HIP graph */
+    int32_t waves_per_cu; /* launch width when autotune = 0 (0 = library default) */
+    int32_t order;        /* queue order when autotune = 0: 0 as given, 1 most rays x bounces first */
+} RprBatchParams;
+
+typedef struct {
+    int64_t total_rays;
+    int32_t n_pairs;
+    int32_t waves_per_cu;  /* chosen launch width */
+    int32_t order;         /* chosen queue order */
+    int32_t stack_need;
+    int32_t graph;         /* 1 if runs replay a captured graph */
+    int32_t n_candidates;  /* launch shapes timed by the autotuner (0 without autotune) */
+    float best_ms;         /* autotuner's best trace time */
+    float worst_ms;        /* autotuner's worst trace time */
+} RprBatchInfo;
+
+/* Plan a batch.
+ *   scenes     host [n_scenes] pointers; all scenes must have the same band count
+ *   pairs      host [n_pairs], copied
+ *   hist       device [n_pairs][n_bins][n_bands][(sh_order+1)^2] f32 (outputs of each run)
+ *   hist_late  device [n_pairs][n_bins][n_bands] f32, or NULL
+ *   stats      device [n_pairs]
+ *   params     device [n_pairs]
+ * The caller keeps the scenes and output buffers alive until batch_destroy.
+ * Synchronises hip_stream (uploads the pair table; the autotuner runs the
+ * batch once per candidate shape). */
+int batch_create(const RprScene* const* scenes, int32_t n_scenes, const RprPair* pairs, int32_t n_pairs,
+                 const RprBatchParams* bp, float* hist, float* hist_late, RprIrStats* stats,
+                 RprReverbParams* params, void* hip_stream, RprBatch** out);
+/* Enqueue one run on hip_stream (a graph launch when use_graph = 1). */
+int batch_run(RprBatch* batch, void* hip_stream);
+int batch_info(const RprBatch* batch, RprBatchInfo* out /* host */);
+int batch_destroy(RprBatch* batch);
+
 /* Closest hit of arbitrary rays against the scene's BVH, with the same
  * traversal and triangle test as trace_ir (no triangle excluded).
  *   orig, dir device [n][3] f32;  t_out device [n] f32 (INFINITY on a miss);

@@ -65,6 +65,24 @@ class SceneInfo(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class Pair(C.Structure):
+    _fields_ = [("scene", C.c_int32), ("pair_id", C.c_int32), ("src", C.c_float * 3), ("lst", C.c_float * 3),
+                ("radius", C.c_float), ("max_bounces", C.c_int32), ("n_rays", C.c_int64), ("seed", C.c_uint64)]
+
+
+class BatchParams(C.Structure):
+    _fields_ = [("n_bins", C.c_int32), ("sh_order", C.c_int32), ("bin_width_s", C.c_float),
+                ("speed_of_sound", C.c_float), ("rt60_source", C.c_int32), ("tail_iters", C.c_int32),
+                ("autotune", C.c_int32), ("use_graph", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("order", C.c_int32)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("total_rays", C.c_int64), ("n_pairs", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("order", C.c_int32), ("stack_need", C.c_int32), ("graph", C.c_int32),
+                ("n_candidates", C.c_int32), ("best_ms", C.c_float), ("worst_ms", C.c_float)]
+
+
 # Host views of the device structs (same layout as include/rpr.h).
 IR_STATS_DTYPE = np.dtype([
     ("n_segments", "<i8"), ("n_finite_segments", "<i8"), ("n_escaped", "<i8"), ("n_rays", "<i8"),
@@ -97,6 +115,11 @@ SIGNATURES = {
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "debug_philox": (C.c_int, [_vp, _i64, _vp, _vp]),
     "debug_sh_eval": (C.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    "batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(Pair), _i32, C.POINTER(BatchParams), _vp, _vp,
+                               _vp, _vp, _vp, C.POINTER(_vp)]),
+    "batch_run": (C.c_int, [_vp, _vp]),
+    "batch_info": (C.c_int, [_vp, C.POINTER(BatchInfo)]),
+    "batch_destroy": (C.c_int, [_vp]),
     "last_error": (C.c_char_p, []),
     "rpr_version": (C.c_char_p, []),
 }
@@ -277,6 +300,60 @@ def debug_sh_eval(dirs, order, stream=None):
     out = torch.empty((d.shape[0], MAX_COEFFS), dtype=torch.float32, device="cuda")
     _check(lib().debug_sh_eval(_ptr(d), d.shape[0], int(order), _ptr(out), _stream(stream)))
     return out
+
+
+class Batch:
+    """A planned batch of source-listener pairs over several scenes; `run()`
+    enqueues reset + trace + estimate (a graph replay when use_graph)."""
+
+    def __init__(self, scenes, pairs, *, n_bins, sh_order, bin_width_s, speed_of_sound=343.0, rt60_source=0,
+                 tail_iters=3, autotune=True, use_graph=True, waves_per_cu=0, order=0, late=True, device="cuda",
+                 stream=None):
+        import torch
+        self.scenes = list(scenes)  # kept alive for the batch's lifetime
+        n = len(pairs)
+        arr = (Pair * n)()
+        for i, p in enumerate(pairs):
+            arr[i].scene = int(p["scene"])
+            arr[i].pair_id = int(p.get("pair_id", i))
+            arr[i].src[:] = [float(x) for x in p["source"]]
+            arr[i].lst[:] = [float(x) for x in p["listener"]]
+            arr[i].radius = float(p["radius"])
+            arr[i].max_bounces = int(p["max_bounces"])
+            arr[i].n_rays = int(p["n_rays"])
+            arr[i].seed = int(p["seed"])
+        nb = self.scenes[0].n_bands
+        self.n_pairs, self.n_bins, self.n_bands, self.sh_order = n, n_bins, nb, sh_order
+        self.hist, self.hist_late, self.stats, _ = alloc_trace_outputs(n, n_bins, nb, sh_order, device=device,
+                                                                       late=late)
+        self.params = alloc_params(n, device=device)
+        bp = BatchParams(int(n_bins), int(sh_order), float(bin_width_s), float(speed_of_sound), int(rt60_source),
+                         int(tail_iters), int(bool(autotune)), int(bool(use_graph)), int(waves_per_cu), int(order))
+        handles = (C.c_void_p * len(self.scenes))(*[sc.handle.value for sc in self.scenes])
+        h = C.c_void_p()
+        _check(lib().batch_create(handles, len(self.scenes), arr, n, C.byref(bp), _ptr(self.hist),
+                                  _ptr(self.hist_late), _ptr(self.stats), _ptr(self.params), _stream(stream),
+                                  C.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().batch_run(self._h, _stream(stream)))
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        _check(lib().batch_info(self._h, C.byref(bi)))
+        return {k: getattr(bi, k) for k, _ in BatchInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def header_functions(path: str = HEADER) -> list[str]:

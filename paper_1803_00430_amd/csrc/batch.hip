@@ -1,0 +1,338 @@
+// Batches: many source-listener pairs over several scenes in one persistent
+// trace launch.
+//
+// The pair table (one PairDesc per pair, each pointing at its scene's BVH and
+// at its slices of the caller's output buffers) is uploaded once.  A run is
+// four launches on one stream -- reset the statistics and the ray queue, zero
+// the histograms, trace every ray of every pair through the shared queue,
+// estimate every pair -- which can be captured into a HIP graph and replayed.
+//
+// Launch shape: the resident waves per compute unit and the order in which
+// pairs enter the queue (as given, or most rays x bounces first so that the
+// longest pairs start early and the tail is shorter).  The autotuner times
+// every candidate shape on the batch itself and keeps the fastest; the choice
+// is cached per (device, pairs, total-ray bucket, stack variant).  Results do
+// not depend on the shape: every ray is a function of (pair, ray id).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <tuple>
+#include <vector>
+
+#include "rpr_internal.hpp"
+
+struct RprBatch {
+    int device = 0;
+    int n_pairs = 0, nb = 0, nc = 0, T = 0, sh_order = 0;
+    float dt = 0.f;
+    int64_t total = 0;
+    int stack_need = 0;
+    int waves_per_cu = 0, order = 0;
+    RprEstimateParams ep{0, 3};
+    std::vector<rpr::PairDesc> pairs;  // caller order
+    rpr::PairDesc* d_pairs = nullptr;  // queue order
+    unsigned long long* d_queue = nullptr;
+    float* hist = nullptr;
+    float* hist_late = nullptr;
+    RprIrStats* stats = nullptr;
+    RprReverbParams* params = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    RprBatchInfo info{};
+};
+
+namespace rpr {
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune_cache;
+
+// Upload the pair table in queue order `ord` (indices into b.pairs).
+int upload_order(RprBatch& b, int ord, hipStream_t st)
+{
+    std::vector<int> idx(b.n_pairs);
+    std::iota(idx.begin(), idx.end(), 0);
+    if (ord == 1) {
+        std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+            const double cx = (double)b.pairs[x].n_rays * (b.pairs[x].max_bounces + 1);
+            const double cy = (double)b.pairs[y].n_rays * (b.pairs[y].max_bounces + 1);
+            return cx > cy;
+        });
+    }
+    std::vector<PairDesc> q(b.n_pairs);
+    int64_t off = 0;
+    for (int i = 0; i < b.n_pairs; ++i) {
+        q[i] = b.pairs[idx[i]];
+        q[i].queue_begin = off;
+        off += q[i].n_rays;
+    }
+    RPR_HIP_TRY(hipMemcpyAsync(b.d_pairs, q.data(), sizeof(PairDesc) * b.n_pairs, hipMemcpyHostToDevice, st));
+    RPR_HIP_TRY(hipStreamSynchronize(st));
+    b.order = ord;
+    return RPR_OK;
+}
+
+int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
+{
+    int rc = enqueue_stats_reset(b.stats, b.n_pairs, b.d_queue, st);
+    if (rc != RPR_OK) return rc;
+    rc = enqueue_fill_zero(b.hist, (size_t)b.n_pairs * b.T * b.nb * b.nc, st);
+    if (rc != RPR_OK) return rc;
+    if (b.hist_late) {
+        rc = enqueue_fill_zero(b.hist_late, (size_t)b.n_pairs * b.T * b.nb, st);
+        if (rc != RPR_OK) return rc;
+    }
+    if (t0) RPR_HIP_TRY(hipEventRecord(t0, st));
+    rc = launch_trace(b.d_pairs, b.n_pairs, b.d_queue, b.total, b.nb, b.stack_need, false, b.waves_per_cu, 0, st);
+    if (rc != RPR_OK) return rc;
+    if (t1) RPR_HIP_TRY(hipEventRecord(t1, st));
+    return estimate_reverb(b.hist, b.hist_late, b.stats, b.n_pairs, b.T, b.nb, b.sh_order, b.dt, &b.ep, b.params,
+                           st);
+}
+
+// Time the trace of one run with the current shape (best of `reps`).
+int time_shape(RprBatch& b, hipStream_t st, int reps, float& best_ms)
+{
+    hipEvent_t e0, e1;
+    RPR_HIP_TRY(hipEventCreate(&e0));
+    RPR_HIP_TRY(hipEventCreate(&e1));
+    best_ms = 1e30f;
+    int rc = RPR_OK;
+    for (int r = 0; r < reps && rc == RPR_OK; ++r) {
+        rc = enqueue_run(b, st, e0, e1);
+        if (rc != RPR_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = set_error(RPR_EDEVICE, "batch autotune: event wait failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0 || reps == 1) best_ms = std::min(best_ms, ms);  // the first run warms the caches
+    }
+    if (rc == RPR_OK && hipStreamSynchronize(st) != hipSuccess) rc = set_error(RPR_EDEVICE, "batch autotune sync");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+void batch_free(RprBatch* b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_pairs) (void)hipFree(b->d_pairs);
+    if (b->d_queue) (void)hipFree(b->d_queue);
+    delete b;
+}
+
+}  // namespace
+}  // namespace rpr
+
+using namespace rpr;
+
+extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, const RprPair* pairs, int32_t n_pairs,
+                            const RprBatchParams* bp, float* hist, float* hist_late, RprIrStats* stats,
+                            RprReverbParams* params, void* hip_stream, RprBatch** out)
+{
+    if (!out) return set_error(RPR_EINVAL, "batch_create: out is null");
+    *out = nullptr;
+    if (!scenes || n_scenes < 1 || !pairs || n_pairs < 1 || !bp || !hist || !stats || !params)
+        return set_error(RPR_EINVAL, "batch_create: null or empty argument");
+    if (bp->n_bins < 1 || bp->sh_order < 0 || bp->sh_order > RPR_MAX_SH_ORDER || !(bp->bin_width_s > 0.f) ||
+        !(bp->speed_of_sound > 0.f) || bp->waves_per_cu < 0 || bp->order < 0 || bp->order > 1 ||
+        bp->tail_iters < 0 || bp->tail_iters > 100 || (bp->rt60_source != 0 && bp->rt60_source != 1) ||
+        (bp->rt60_source == 1 && !hist_late))
+        return set_error(RPR_EINVAL, "batch_create: bad batch parameters");
+    const int nb = scenes[0] ? scenes[0]->n_bands : 0;
+    int stack_need = 1;
+    for (int i = 0; i < n_scenes; ++i) {
+        if (!scenes[i]) return set_error(RPR_EINVAL, "batch_create: scene %d is null", i);
+        if (scenes[i]->n_bands != nb) return set_error(RPR_EINVAL, "batch_create: scenes differ in band count");
+        stack_need = std::max(stack_need, scenes[i]->stack_need);
+    }
+    const int nc = (bp->sh_order + 1) * (bp->sh_order + 1);
+    int64_t total = 0;
+    for (int i = 0; i < n_pairs; ++i) {
+        const RprPair& p = pairs[i];
+        if (p.scene < 0 || p.scene >= n_scenes) return set_error(RPR_EINVAL, "batch_create: pair %d scene index", i);
+        if (p.n_rays < 1 || p.n_rays > ((int64_t)1 << 32) || p.max_bounces < 0 || p.max_bounces > 10000000 ||
+            !(p.radius > 0.f) || !std::isfinite(p.radius))
+            return set_error(RPR_EINVAL, "batch_create: pair %d parameters", i);
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(p.src[a]) || !std::isfinite(p.lst[a]))
+                return set_error(RPR_EINVAL, "batch_create: pair %d position", i);
+        total += p.n_rays;
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    RprBatch* b = new RprBatch();
+    RPR_HIP_TRY(hipGetDevice(&b->device));
+    b->n_pairs = n_pairs;
+    b->nb = nb;
+    b->nc = nc;
+    b->T = bp->n_bins;
+    b->sh_order = bp->sh_order;
+    b->dt = bp->bin_width_s;
+    b->total = total;
+    b->stack_need = stack_need;
+    b->ep = RprEstimateParams{bp->rt60_source, bp->tail_iters};
+    b->hist = hist;
+    b->hist_late = hist_late;
+    b->stats = stats;
+    b->params = params;
+    b->pairs.resize(n_pairs);
+    const size_t hstride = (size_t)bp->n_bins * nb * nc, lstride = (size_t)bp->n_bins * nb;
+    for (int i = 0; i < n_pairs; ++i) {
+        const RprPair& p = pairs[i];
+        PairDesc d;
+        std::memset(&d, 0, sizeof(d));
+        d.scene = scenes[p.scene]->view;
+        for (int a = 0; a < 3; ++a) {
+            d.src[a] = p.src[a];
+            d.lst[a] = p.lst[a];
+        }
+        d.radius = p.radius;
+        d.inv_vs = (float)(1.0 / (4.0 / 3.0 * M_PI * (double)p.radius * p.radius * p.radius));
+        d.c = bp->speed_of_sound;
+        d.dt = bp->bin_width_s;
+        d.l_window = (float)((double)bp->speed_of_sound * (double)bp->n_bins * (double)bp->bin_width_s);
+        d.e0 = (float)(1.0 / (double)p.n_rays);
+        d.n_bins = bp->n_bins;
+        d.max_bounces = p.max_bounces;
+        d.sh_order = bp->sh_order;
+        d.n_coeffs = nc;
+        d.key0 = (uint32_t)(p.seed & 0xFFFFFFFFull);
+        d.key1 = (uint32_t)(p.seed >> 32);
+        d.pair_id = (uint32_t)p.pair_id;
+        d.ray_begin = 0;
+        d.n_rays = p.n_rays;
+        d.hist = hist + (size_t)i * hstride;
+        d.hist_late = hist_late ? hist_late + (size_t)i * lstride : nullptr;
+        d.stats = stats + i;
+        d.ray_hash = nullptr;
+        b->pairs[i] = d;
+    }
+    auto fail = [&](int code) {
+        batch_free(b);
+        return code;
+    };
+    if (hipMalloc(&b->d_pairs, sizeof(PairDesc) * n_pairs) != hipSuccess ||
+        hipMalloc(&b->d_queue, 256) != hipSuccess)
+        return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
+    if (device_cu_count() <= 0) return fail(set_error(RPR_EDEVICE, "batch_create: no device"));
+    const int max_wpc = trace_max_waves_per_cu(nb, stack_need);
+
+    // launch shape: cached, autotuned or as requested
+    int rc = RPR_OK;
+    b->info.n_candidates = 0;
+    if (bp->autotune) {
+        const int bucket = (int)std::floor(std::log2((double)total));
+        const auto key = std::make_tuple(b->device, n_pairs, bucket, stack_need <= 32 ? 32 : 64);
+        bool cached = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                b->waves_per_cu = it->second.first;
+                b->order = it->second.second;
+                cached = true;
+            }
+        }
+        if (cached) {
+            rc = upload_order(*b, b->order, st);
+            if (rc != RPR_OK) return fail(rc);
+        } else {
+            std::vector<int> widths;
+            for (int w : {max_wpc / 4, max_wpc / 2, (3 * max_wpc) / 4, max_wpc})
+                if (w >= 1 && std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+            float best = 1e30f, worst = 0.f;
+            int best_w = max_wpc, best_o = 0;
+            for (int o = 0; o < 2; ++o) {
+                rc = upload_order(*b, o, st);
+                if (rc != RPR_OK) return fail(rc);
+                for (int w : widths) {
+                    b->waves_per_cu = w;
+                    float ms = 0.f;
+                    rc = time_shape(*b, st, 3, ms);
+                    if (rc != RPR_OK) return fail(rc);
+                    ++b->info.n_candidates;
+                    worst = std::max(worst, ms);
+                    if (ms < best) {
+                        best = ms;
+                        best_w = w;
+                        best_o = o;
+                    }
+                }
+            }
+            b->info.best_ms = best;
+            b->info.worst_ms = worst;
+            b->waves_per_cu = best_w;
+            rc = upload_order(*b, best_o, st);
+            if (rc != RPR_OK) return fail(rc);
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tune_cache[key] = {best_w, best_o};
+        }
+    } else {
+        b->waves_per_cu = bp->waves_per_cu > 0 ? std::min(bp->waves_per_cu, max_wpc) : max_wpc;
+        rc = upload_order(*b, bp->order, st);
+        if (rc != RPR_OK) return fail(rc);
+    }
+
+    if (bp->use_graph) {
+        hipStream_t cap;
+        if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+            return fail(set_error(RPR_EDEVICE, "batch_create: stream creation failed"));
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = enqueue_run(*b, cap);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cap, &g);
+            if (rc == RPR_OK && e2 != hipSuccess) rc = set_error(RPR_EDEVICE, "batch_create: capture failed");
+            b->graph = g;
+            if (rc == RPR_OK && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+                rc = set_error(RPR_EDEVICE, "batch_create: graph instantiation failed");
+        } else {
+            rc = set_error(RPR_EDEVICE, "batch_create: capture could not start");
+        }
+        (void)hipStreamDestroy(cap);
+        if (rc != RPR_OK) return fail(rc);
+    }
+    b->info.total_rays = total;
+    b->info.n_pairs = n_pairs;
+    b->info.waves_per_cu = b->waves_per_cu;
+    b->info.order = b->order;
+    b->info.stack_need = stack_need;
+    b->info.graph = b->exec ? 1 : 0;
+    *out = b;
+    return RPR_OK;
+}
+
+extern "C" int batch_run(RprBatch* batch, void* hip_stream)
+{
+    if (!batch) return set_error(RPR_EINVAL, "batch_run: null batch");
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (batch->exec) {
+        RPR_HIP_TRY(hipGraphLaunch(batch->exec, st));
+        return RPR_OK;
+    }
+    return enqueue_run(*batch, st);
+}
+
+extern "C" int batch_info(const RprBatch* batch, RprBatchInfo* out)
+{
+    if (!batch || !out) return set_error(RPR_EINVAL, "batch_info: null argument");
+    *out = batch->info;
+    return RPR_OK;
+}
+
+extern "C" int batch_destroy(RprBatch* batch)
+{
+    if (!batch) return RPR_OK;
+    (void)hipDeviceSynchronize();
+    batch_free(batch);
+    return RPR_OK;
+}

@@ -121,4 +121,10 @@ void workspace_free(Workspace& ws);
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
                  int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream);
 int device_cu_count();
+// Largest resident waves per CU of the trace variant for (nb, stack_need).
+int trace_max_waves_per_cu(int nb, int stack_need);
+// Zero n floats (a kernel, so that it can be captured into a graph).
+int enqueue_fill_zero(float* p, size_t n, hipStream_t stream);
+// Initialise n statistics records and zero the ray queue counter.
+int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hipStream_t stream);
 }  // namespace rpr

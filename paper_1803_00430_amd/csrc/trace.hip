@@ -370,6 +370,20 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     dep_acc_flush<NB>(dep, pairs, lane);
 }
 
+__device__ __forceinline__ void stats_init(RprIrStats* S)
+{
+    S->n_segments = S->n_finite_segments = S->n_escaped = S->n_rays = 0;
+    S->seg_len_sum = 0.0;
+    S->e_emitted = 0.0;
+    S->first_arrival_bin = INT_MAX;
+    S->first_late_bin = INT_MAX;
+    S->n_node_visits = S->n_tri_tests = 0;
+    for (int b = 0; b < RPR_MAX_BANDS; ++b) {
+        S->e_class[0][b] = S->e_class[1][b] = S->e_class[2][b] = 0.0;
+        S->e_escaped[b] = S->e_alive_at_stop[b] = S->e_alive_at_bounce_cap[b] = S->e_absorbed[b] = 0.0;
+    }
+}
+
 // ---------------------------------------------------------------- setup kernels
 struct SetupArgs {
     PairDesc base;
@@ -397,17 +411,14 @@ __global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
     d.stats = a.base.stats + s;
     d.ray_hash = a.base.ray_hash ? a.base.ray_hash + (size_t)s * a.rays_per_src : nullptr;
     out[s] = d;
-    RprIrStats* S = d.stats;
-    S->n_segments = S->n_finite_segments = S->n_escaped = S->n_rays = 0;
-    S->seg_len_sum = 0.0;
-    S->e_emitted = 0.0;
-    S->first_arrival_bin = INT_MAX;
-    S->first_late_bin = INT_MAX;
-    S->n_node_visits = S->n_tri_tests = 0;
-    for (int b = 0; b < RPR_MAX_BANDS; ++b) {
-        S->e_class[0][b] = S->e_class[1][b] = S->e_class[2][b] = 0.0;
-        S->e_escaped[b] = S->e_alive_at_stop[b] = S->e_alive_at_bounce_cap[b] = S->e_absorbed[b] = 0.0;
-    }
+    stats_init(d.stats);
+}
+
+__global__ void k_stats_reset(RprIrStats* __restrict__ stats, int n, unsigned long long* __restrict__ queue)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && queue) *queue = 0ull;
+    if (i < n) stats_init(stats + i);
 }
 
 __global__ void k_fill(float* __restrict__ p, size_t n, float v)
@@ -524,6 +535,28 @@ void workspace_free(Workspace& ws)
     if (ws.dev) (void)hipFree(ws.dev);
     if (ws.host_pin) (void)hipHostFree(ws.host_pin);
     ws = Workspace{};
+}
+
+int trace_max_waves_per_cu(int nb, int stack_need)
+{
+    if (ensure_variants() != RPR_OK) return 1;
+    return g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][0].blocks_per_cu;
+}
+
+int enqueue_fill_zero(float* p, size_t n, hipStream_t stream)
+{
+    if (n == 0) return RPR_OK;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((n + 255) / 256, 16384)), dim3(256), 0, stream, p, n,
+                       0.0f);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_stats_reset, dim3((unsigned)((n + 255) / 256 + 1)), dim3(256), 0, stream, stats, n, queue);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
 }
 
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,

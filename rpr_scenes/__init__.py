@@ -273,14 +273,28 @@ def learn_room(seed: int, n_bands=4):
                 sources=s[None].astype(np.float32), listener=l.astype(np.float32), radius=0.5)
 
 
+def _box_tri_count(d, edge):
+    """Triangles of the six tessellated faces of a box with sides d."""
+    nx, ny, nz = (_n(v, edge) for v in d)
+    return 2 * 2 * (ny * nz + nx * nz + nx * ny)
+
+
 def _room_tri_count(kind, dims, notch, edge, clutter):
+    """Triangle count of the tessellated room (same rule as `rect`: two
+    triangles per panel), without building the geometry."""
+    Lx, Ly, Lz = (float(v) for v in dims)
     if kind == "lroom":
-        parts = lroom(dims, notch, edge)
+        ax, ay = notch[0] * Lx, notch[1] * Ly
+        outline = [(0, 0), (Lx, 0), (Lx, ay), (ax, ay), (ax, Ly), (0, Ly)]
+        n = 0
+        for k in range(6):
+            p, q = np.array(outline[k]), np.array(outline[(k + 1) % 6])
+            n += 2 * _n(float(np.linalg.norm(q - p)), edge) * _n(Lz, edge)
+        n += 2 * 2 * (_n(Lx, edge) * _n(ay, edge) + _n(ax, edge) * _n(Ly - ay, edge))
     else:
-        parts = box_surfaces((0, 0, 0), dims, edge)
-    n = sum(len(t) for _, t in parts)
+        n = _box_tri_count((Lx, Ly, Lz), edge)
     for (lo, hi) in clutter:
-        n += sum(len(t) for _, t in box_surfaces(lo, hi, edge))
+        n += _box_tri_count(np.asarray(hi) - np.asarray(lo), edge)
     return n
 
 

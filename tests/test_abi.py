@@ -46,6 +46,9 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void) {
   printf("RprIrStats %zu\nRprReverbParams %zu\nRprTraceParams %zu\nRprSceneInfo %zu\n",
          sizeof(RprIrStats), sizeof(RprReverbParams), sizeof(RprTraceParams), sizeof(RprSceneInfo));
+  printf("RprPair %zu\nRprBatchParams %zu\nRprBatchInfo %zu\n", sizeof(RprPair), sizeof(RprBatchParams),
+         sizeof(RprBatchInfo));
+  P(RprPair, n_rays); P(RprPair, seed); P(RprBatchInfo, best_ms);
   P(RprIrStats, seg_len_sum); P(RprIrStats, first_arrival_bin); P(RprIrStats, e_class);
   P(RprIrStats, e_escaped); P(RprIrStats, e_absorbed); P(RprIrStats, n_tri_tests);
   P(RprReverbParams, g_reverb); P(RprReverbParams, predelay_s); P(RprReverbParams, dir_loudness);
@@ -59,6 +62,11 @@ int main(void) {
     assert int(got["RprReverbParams"]) == P.REVERB_PARAMS_DTYPE.itemsize
     assert int(got["RprTraceParams"]) == C.sizeof(P.TraceParams)
     assert int(got["RprSceneInfo"]) == C.sizeof(P.SceneInfo)
+    assert int(got["RprPair"]) == C.sizeof(P.Pair) and int(got["RprPair.n_rays"]) == P.Pair.n_rays.offset
+    assert int(got["RprPair.seed"]) == P.Pair.seed.offset
+    assert int(got["RprBatchParams"]) == C.sizeof(P.BatchParams)
+    assert int(got["RprBatchInfo"]) == C.sizeof(P.BatchInfo)
+    assert int(got["RprBatchInfo.best_ms"]) == P.BatchInfo.best_ms.offset
     for name in ("seg_len_sum", "first_arrival_bin", "e_class", "e_escaped", "e_absorbed", "n_tri_tests"):
         assert int(got[f"RprIrStats.{name}"]) == P.IR_STATS_DTYPE.fields[name][1], name
     for name in ("g_reverb", "predelay_s", "dir_loudness"):
