@@ -11,8 +11,9 @@ Contents
     in numpy FP64 (Schroeder backward integration and least squares for RT60,
     Eq. 5-8 for the reverb gain, the predelay, the mean free path and the
     energy-weighted directivity of Eq. 1);
-  * `mlp_*`: FP64 forward / backward of the learned estimator's MLP and its
-    Gaussian negative log-likelihood, for gradient checks.
+  * `oracle.mlp` (its own module): FP64 featurisation, forward / backward of
+    the learned estimator's MLP, its Gaussian negative log-likelihood, Adam,
+    and the decoding of the network output, for gradient checks.
 
 Parity pins (what each function is checked against) are listed in the tests;
 functions with none say "parity unpinned".

@@ -1,0 +1,183 @@
+"""FP64 oracle of the learned reverb-parameter estimator.
+
+TEST INFRASTRUCTURE ONLY, like the rest of `oracle/`: imported by tests/, the
+smoke check and the benchmark's CPU leg, never by the product library, and it
+shares no code with the HIP path.
+
+The paper has no learned component.  Its low-ray-count denoiser is temporal
+smoothing of the estimated parameters (Section 4.2, Eq. 4); the learned
+estimator replaces that step: a 4-layer MLP maps the SH x band histogram of a
+cheap trace (1k rays, 200 bins of 10 ms) to the parameters that the plain
+estimator (Section 4.2) returns on a converged trace, with a per-output
+variance.  Everything here is the plain definition, in float64:
+
+  featurize   histogram -> input vector (signed log of the energy-normalised
+              histogram, in the histogram's own bin-major order)
+  targets     ReverbParams of a converged trace -> the 4B regression targets
+              and their validity mask
+  forward     z_l = h_l W_l^T + b_l, h_{l+1} = relu(z_l), last layer linear
+  nll         Gaussian negative log-likelihood, mean over the batch
+  backward    gradients of nll w.r.t. every W_l and b_l (chain rule)
+  adam_step   Adam (Kingma and Ba, 2015) with bias correction and decoupled
+              weight decay on the matrices (Loshchilov and Hutter, 2019)
+  decode      network output -> per-band RT60, energies, sigma, gate
+
+Pins: tests/test_oracle_mlp.py (a hand-built ReLU network, finite
+differences, the Gaussian NLL's closed-form stationary points, hand-computed
+Adam steps, bf16 rounding against torch's conversion, featurize invariances).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+FEAT_GAIN = 1.0e6       # u -> log1p(FEAT_GAIN |u|): -60 dB of u still maps to a value of order 1
+FEAT_SCALE = 0.125      # brings the features to order one
+ENERGY_FLOOR = 1.0e-4   # log(E / e_in + floor): absent classes (an occluded direct path) stay finite
+ST_INVALID_FIT = 1 | 2 | 4   # NO_ENERGY | BAD_FIT | NO_RANGE
+
+
+def bf16_round(x):
+    """Round float64 values to the nearest bfloat16 (ties to even), through
+    float32 (exact for values that are already float32)."""
+    f = np.asarray(x, np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    r = r.astype(np.uint32)
+    nan = np.isnan(f)
+    r[nan] = 0x7FC00000
+    return r.view(np.float32).astype(np.float64)
+
+
+def input_energy(hist):
+    """e_in: the mean over bands of the time-integrated intensity,
+    (1/B) sum_{m,b} sqrt(4 pi) H[m][b][0] (intensity from the l=0 coefficient,
+    as in the estimator of Section 4.2)."""
+    H = np.asarray(hist, np.float64)
+    return math.sqrt(4.0 * math.pi) * H[:, :, 0].sum() / H.shape[1]
+
+
+def featurize(hist):
+    """hist [T][B][NC] -> features [T*B*NC] (same order):
+    f = sign(u) log1p(FEAT_GAIN |u|) FEAT_SCALE with u = H / e_in; all zero
+    when the trace carries no energy.  Returns (features, e_in)."""
+    H = np.asarray(hist, np.float64)
+    e = input_energy(H)
+    if not e > 0.0:
+        return np.zeros(H.size), 0.0
+    u = H.reshape(-1) / e
+    return np.sign(u) * np.log1p(FEAT_GAIN * np.abs(u)) * FEAT_SCALE, e
+
+
+def targets(params, e_in, n_bands):
+    """Regression targets of one IR from the estimator output of a converged
+    trace (a dict as returned by oracle.estimate_reverb) and the cheap trace's
+    e_in: [log RT60_b | log(E_direct_b/e_in + floor) | same for early | late],
+    with mask 1 where the target is defined (RT60: a fit without the
+    NO_ENERGY, BAD_FIT or NO_RANGE flags and RT60 > 0; energies: e_in > 0)."""
+    B = n_bands
+    t = np.zeros(4 * B)
+    w = np.zeros(4 * B)
+    for b in range(B):
+        rt = float(params["rt60"][b])
+        if rt > 0.0 and not (int(params["status"][b]) & ST_INVALID_FIT):
+            t[b] = math.log(rt)
+            w[b] = 1.0
+        if e_in > 0.0:
+            for c, key in enumerate(("e_direct", "e_early", "e_late")):
+                t[(c + 1) * B + b] = math.log(float(params[key][b]) / e_in + ENERGY_FLOOR)
+                w[(c + 1) * B + b] = 1.0
+    return t, w
+
+
+def forward(params, X):
+    """params: list of (W [d_out][d_in], b [d_out]); X [M][d_0].
+    Returns (pre-activations z_l, activations h_l with h_0 = X); the network
+    output is z[-1]."""
+    h = [np.asarray(X, np.float64)]
+    z = []
+    L = len(params)
+    for l, (W, b) in enumerate(params):
+        zl = h[-1] @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
+        z.append(zl)
+        if l < L - 1:
+            h.append(np.maximum(zl, 0.0))
+    return z, h
+
+
+def nll(out, T, Wm):
+    """Mean over the batch of sum_j 1/2 w_j ((mu_j - t_j)^2 exp(-s_j) + s_j),
+    out = [mu | s] with s = log sigma^2.  Returns (loss, d loss / d out)."""
+    out = np.asarray(out, np.float64)
+    M, n2 = out.shape
+    n = n2 // 2
+    mu, s = out[:, :n], out[:, n:]
+    r = mu - T
+    e = np.exp(-s)
+    loss = 0.5 * np.sum(Wm * (r * r * e + s)) / M
+    g = np.empty_like(out)
+    g[:, :n] = Wm * r * e / M
+    g[:, n:] = 0.5 * Wm * (1.0 - r * r * e) / M
+    return loss, g
+
+
+def backward(params, X, T, Wm):
+    """Loss and its gradients [(dW_l, db_l)] by the chain rule."""
+    z, h = forward(params, X)
+    loss, g = nll(z[-1], T, Wm)
+    grads = [None] * len(params)
+    for l in range(len(params) - 1, -1, -1):
+        W = np.asarray(params[l][0], np.float64)
+        grads[l] = (g.T @ h[l], g.sum(axis=0))
+        if l > 0:
+            g = (g @ W) * (z[l - 1] > 0.0)
+    return loss, grads
+
+
+def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """One Adam step in place.  state: dict(t, m, v) with m, v lists shaped
+    like params (created on the first call).  Decoupled weight decay scales
+    the matrices only: W -= lr * weight_decay * W."""
+    if "m" not in state:
+        state["t"] = 0
+        state["m"] = [(np.zeros_like(W, dtype=np.float64), np.zeros_like(b, dtype=np.float64)) for W, b in params]
+        state["v"] = [(np.zeros_like(W, dtype=np.float64), np.zeros_like(b, dtype=np.float64)) for W, b in params]
+    state["t"] += 1
+    t = state["t"]
+    c1 = 1.0 - beta1 ** t
+    c2 = 1.0 - beta2 ** t
+    new = []
+    for l, ((W, b), (gW, gb)) in enumerate(zip(params, grads)):
+        out = []
+        for i, (p, g) in enumerate(((W, gW), (b, gb))):
+            m = state["m"][l][i]
+            v = state["v"][l][i]
+            m *= beta1
+            m += (1.0 - beta1) * g
+            v *= beta2
+            v += (1.0 - beta2) * g * g
+            step = (m / c1) / (np.sqrt(v / c2) + eps)
+            p = np.asarray(p, np.float64)
+            if i == 0 and weight_decay:
+                p = p - lr * weight_decay * p
+            out.append(p - lr * step)
+        new.append((out[0], out[1]))
+    return new
+
+
+def decode(out, e_in, n_bands, kappa):
+    """Network output [mu | s] of one IR -> dict(rt60, sigma (per RT60 output,
+    sigma = exp(s/2), the standard deviation of log RT60), e_direct, e_early,
+    e_late, uncertain).  The IR is uncertain when it carried no energy or when
+    any band's sigma exceeds kappa; the caller then re-traces it."""
+    out = np.asarray(out, np.float64)
+    B = n_bands
+    n = 4 * B
+    mu, s = out[:n], out[n:]
+    res = dict(rt60=np.exp(mu[:B]), sigma=np.exp(0.5 * s[:B]))
+    for c, key in enumerate(("e_direct", "e_early", "e_late")):
+        res[key] = np.maximum(np.exp(mu[(c + 1) * B:(c + 2) * B]) - ENERGY_FLOOR, 0.0) * e_in
+    res["uncertain"] = bool(not e_in > 0.0 or np.any(res["sigma"] > kappa))
+    return res
