@@ -24,6 +24,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per k_trace launch on the city workload, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE passes scaled by a copy kernel of known size
+# (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
+# was measured on: reported as null once they change.
+TRACE_TRAFFIC = {"bytes": 35496555.0,
+                 "sources_sha256": "9713a245ce7f7732eb408fcdb417adc77e3d3c50f175752dde4e1c4fd1801b3b"}
+TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
+                 "paper_1803_00430_amd/csrc/rpr_internal.hpp")
+
+
+def trace_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRACE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -196,6 +214,7 @@ def main():
     value = segs * a.steps / wall
     trace_ms = float(np.mean(t_trace))
     achieved = segs * bytes_per_seg / (trace_ms * 1e-3) / 1e9
+    traffic = TRACE_TRAFFIC["bytes"] if TRACE_TRAFFIC["sources_sha256"] == trace_sources_sha256() else None
     pg = P.params_host(params)
 
     out = {
@@ -208,7 +227,7 @@ def main():
                    "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
                    "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_trace", "bytes_per_ray_bounce": bytes_per_seg,
                      "node_visits_per_ray_bounce": vn, "tri_tests_per_ray_bounce": vt,
                      "kernel_ms": trace_ms},
