@@ -25,9 +25,9 @@
  *  - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the legacy
  *    default stream) and is complete when that stream is synchronised,
  *    unless the entry point says it synchronises.
- *  - Calls that use the same RprScene or RprBatch must be ordered on one
- *    stream: each object owns a small workspace (queue counter, pair table)
- *    that concurrent calls would share.
+ *  - Calls that use the same RprScene, RprBatch or RprModel must be ordered
+ *    on one stream: each object owns a workspace (queue counter, pair table,
+ *    activations) that concurrent calls would share.
  *  - A device fault is reported as RPR_EDEVICE by the call that observes it.
  */
 #ifndef RPR_H
@@ -263,6 +263,111 @@ int batch_create(const RprScene* const* scenes, int32_t n_scenes, const RprPair*
 int batch_run(RprBatch* batch, void* hip_stream);
 int batch_info(const RprBatch* batch, RprBatchInfo* out /* host */);
 int batch_destroy(RprBatch* batch);
+
+/* --------------------------------------------------------- learned estimator
+ * The paper denoises the parameters of a low-ray-count trace by temporal
+ * smoothing across frames (Section 4.2, Eq. 4).  The learned estimator maps
+ * the SH x band histogram of a cheap trace (e.g. 1k rays, 200 bins of 10 ms)
+ * directly to the parameters that the estimator above returns on a converged
+ * trace, with an uncertainty per output; where the uncertainty is high the
+ * caller re-traces the pair with more rays.
+ *
+ * Network: an MLP with layers dims[0] -> dims[1] -> ... -> dims[n_layers]
+ * (ReLU between layers, the last layer linear).  For B bands the output has
+ * 8B entries: mu = [log RT60_b | log(E_direct_b / e_in + 1e-4) | same for
+ * early | late] and s = log sigma^2 of each, where e_in is the cheap trace's
+ * mean per-band time-integrated intensity.  Training minimises the Gaussian
+ * negative log-likelihood mean_i sum_j w_ij/2 ((mu_ij - t_ij)^2 exp(-s_ij) +
+ * s_ij) by Adam.  Products run on BF16 matrix cores with FP32 accumulation;
+ * master weights, gradients and Adam moments are FP32.
+ *
+ * Parameter vector (FP32, n_params floats): for each layer l, W_l
+ * [dims[l+1]][dims[l]] row-major then b_l [dims[l+1]].
+ * Features are BF16 (raw 16-bit patterns, uint16_t), [n][dims[0]]. */
+typedef struct RprModel RprModel;
+
+#define RPR_MODEL_MAX_LAYERS 8
+#define RPR_ST_LEARNED 32       /* RprReverbParams.status: the values come from the learned estimator */
+#define RPR_ST_UNCERTAIN 64     /* ... whose uncertainty exceeded the threshold */
+
+typedef struct {
+    int64_t n_params;
+    int32_t n_layers;
+    int32_t dims[RPR_MODEL_MAX_LAYERS + 1];
+    int32_t max_batch;
+    int64_t step;         /* Adam steps taken */
+} RprModelInfo;
+
+typedef struct {
+    float lr;
+    float beta1;          /* 0.9 */
+    float beta2;          /* 0.999 */
+    float eps;            /* 1e-8 */
+    float weight_decay;   /* decoupled, matrices only: W -= lr * weight_decay * W */
+    float reserved;
+} RprAdamParams;
+
+/* Create a model.  dims host [n_layers + 1], every entry a multiple of 32 and
+ * <= 65536, n_layers in 1..8; max_batch in 1..8192 bounds the rows of one
+ * training step and of one forward chunk.  Weights are initialised from
+ * Philox4x32-10 under `seed`: W_l uniform in +-sqrt(6 / dims[l]) (scaled by
+ * 0.1 for the last layer), biases 0.  Synchronises hip_stream. */
+int reverb_model_create(const int32_t* dims, int32_t n_layers, int32_t max_batch, uint64_t seed,
+                        void* hip_stream, RprModel** out);
+int reverb_model_destroy(RprModel* model);
+int reverb_model_info(const RprModel* model, RprModelInfo* out /* host */);
+/* Replace / copy out the FP32 parameter vector (device [n], n = n_params).
+ * load also refreshes the BF16 copies and resets the Adam moments and step. */
+int reverb_model_load(RprModel* model, const float* params, int64_t n, void* hip_stream);
+int reverb_model_save(const RprModel* model, float* params, int64_t n, void* hip_stream);
+
+/* Input features of n_ir histograms (device [n_ir][n_bins][n_bands][n_coeffs]
+ * f32, the layout trace_ir writes): with e_in = (1/B) sum_{m,b} sqrt(4 pi)
+ * H[m][b][0] and u = H / e_in, feature = sign(u) log1p(1e6 |u|) / 8 in the
+ * histogram's own order, rounded to BF16; all zero when e_in = 0.
+ *   features device [n_ir][n_bins * n_bands * n_coeffs] u16 (BF16)
+ *   e_in     device [n_ir] f32 */
+int reverb_model_featurize(const float* hist, int32_t n_ir, int32_t n_bins, int32_t n_bands, int32_t n_coeffs,
+                           uint16_t* features, float* e_in, void* hip_stream);
+/* Training targets from the parameters of converged traces (device
+ * [n_ir]) and the cheap traces' e_in (device [n_ir]):
+ *   t device [n_ir][4B] f32 = [log rt60 | log(e_direct/e_in + 1e-4) | early | late]
+ *   w device [n_ir][4B] f32 = 1 where defined (RT60: status without
+ *     NO_ENERGY / BAD_FIT / NO_RANGE and rt60 > 0; energies: e_in > 0), else 0 */
+int reverb_model_targets(const RprReverbParams* ref, const float* e_in, int32_t n_ir, int32_t n_bands, float* t,
+                         float* w, void* hip_stream);
+/* Network output for n feature rows (device [n][dims[0]] BF16) into out
+ * (device [n][dims[n_layers]] f32); any n >= 0 (chunks of max_batch). */
+int reverb_model_forward(RprModel* model, const uint16_t* features, int64_t n, float* out, void* hip_stream);
+/* Loss and gradients of one minibatch: rows i = 0..m-1 are dataset rows
+ * rows[i] (device [m] i32, or NULL for 0..m-1) of a dataset of n_rows rows:
+ * features (device [n_rows][dims[0]] BF16), t and w (device
+ * [n_rows][dims[n_layers]/2] f32).  m in 1..max_batch.  A row index outside
+ * [0, n_rows) contributes a zero feature row with zero weights.  Gradients
+ * stay in the model (reverb_model_grads copies them out, in the layout of the
+ * parameter vector); loss (device, 1 f64) receives the mean NLL over the m
+ * rows. */
+int reverb_model_backward(RprModel* model, const uint16_t* features, int64_t n_rows, const int32_t* rows,
+                          int32_t m, const float* t, const float* w, double* loss, void* hip_stream);
+int reverb_model_grads(const RprModel* model, float* grads, int64_t n, void* hip_stream);
+/* One Adam step with the gradients of the last backward (host `ap`). */
+int reverb_model_adam(RprModel* model, const RprAdamParams* ap, void* hip_stream);
+/* backward followed by adam. */
+int reverb_model_train_step(RprModel* model, const uint16_t* features, int64_t n_rows, const int32_t* rows,
+                            int32_t m, const float* t, const float* w, const RprAdamParams* ap, double* loss,
+                            void* hip_stream);
+/* Reverb parameters from network outputs (device [n][8B]) and e_in (device
+ * [n]): rt60 = exp(mu), energies = max(exp(mu) - 1e-4, 0) e_in, g_reverb by
+ * Eq. 5 with Eq. 8, status RPR_ST_LEARNED, plus RPR_ST_UNCERTAIN (and
+ * uncertain[i] = 1) where e_in = 0 or any band's sigma = exp(s/2) of its log
+ * RT60 exceeds kappa.  Fields the network does not predict are zero.
+ *   params device [n], sigma device [n][B] f32 or NULL, uncertain device [n] i32 or NULL */
+int reverb_model_decode(const float* out, const float* e_in, int64_t n, int32_t n_bands, float kappa,
+                        RprReverbParams* params, float* sigma, int32_t* uncertain, void* hip_stream);
+/* dst[idx[i]] = src[i] for i < n (device arrays): merges the parameters of
+ * re-traced pairs into a learned result. */
+int reverb_params_scatter(const RprReverbParams* src, const int32_t* idx, int64_t n, RprReverbParams* dst,
+                          void* hip_stream);
 
 /* Closest hit of arbitrary rays against the scene's BVH, with the same
  * traversal and triangle test as trace_ir (no triangle excluded).

@@ -92,15 +92,22 @@ def targets(params, e_in, n_bands):
     return t, w
 
 
-def forward(params, X):
+def _identity(x):
+    return x
+
+
+def forward(params, X, rnd=None):
     """params: list of (W [d_out][d_in], b [d_out]); X [M][d_0].
     Returns (pre-activations z_l, activations h_l with h_0 = X); the network
-    output is z[-1]."""
+    output is z[-1].  `rnd`, if given, rounds every activation where it
+    enters a product (e.g. bf16_round, to take the ReLU decisions of the next
+    layers in the precision of a BF16 implementation); default: exact."""
+    r = rnd or _identity
     h = [np.asarray(X, np.float64)]
     z = []
     L = len(params)
     for l, (W, b) in enumerate(params):
-        zl = h[-1] @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
+        zl = r(h[-1]) @ np.asarray(W, np.float64).T + np.asarray(b, np.float64)
         z.append(zl)
         if l < L - 1:
             h.append(np.maximum(zl, 0.0))
@@ -123,16 +130,19 @@ def nll(out, T, Wm):
     return loss, g
 
 
-def backward(params, X, T, Wm):
-    """Loss and its gradients [(dW_l, db_l)] by the chain rule."""
-    z, h = forward(params, X)
+def backward(params, X, T, Wm, rnd=None):
+    """Loss and its gradients [(dW_l, db_l)] by the chain rule.  `rnd` as in
+    forward, applied also to the gradient where it enters a product (the
+    bias gradient sums the unrounded gradient)."""
+    r = rnd or _identity
+    z, h = forward(params, X, rnd)
     loss, g = nll(z[-1], T, Wm)
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W = np.asarray(params[l][0], np.float64)
-        grads[l] = (g.T @ h[l], g.sum(axis=0))
+        grads[l] = (r(g).T @ r(h[l]), g.sum(axis=0))
         if l > 0:
-            g = (g @ W) * (z[l - 1] > 0.0)
+            g = (r(g) @ W) * (z[l - 1] > 0.0)
     return loss, grads
 
 

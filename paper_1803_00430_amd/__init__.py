@@ -84,6 +84,20 @@ class BatchInfo(C.Structure):
 
 
 # Host views of the device structs (same layout as include/rpr.h).
+class ModelInfo(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("n_layers", C.c_int32), ("dims", C.c_int32 * 9), ("max_batch", C.c_int32),
+                ("step", C.c_int64)]
+
+
+class AdamParams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("weight_decay", C.c_float), ("reserved", C.c_float)]
+
+
+ST_LEARNED = 32
+ST_UNCERTAIN = 64
+
+
 IR_STATS_DTYPE = np.dtype([
     ("n_segments", "<i8"), ("n_finite_segments", "<i8"), ("n_escaped", "<i8"), ("n_rays", "<i8"),
     ("seg_len_sum", "<f8"), ("e_emitted", "<f8"), ("first_arrival_bin", "<i4"), ("first_late_bin", "<i4"),
@@ -120,6 +134,20 @@ SIGNATURES = {
     "batch_run": (C.c_int, [_vp, _vp]),
     "batch_info": (C.c_int, [_vp, C.POINTER(BatchInfo)]),
     "batch_destroy": (C.c_int, [_vp]),
+    "reverb_model_create": (C.c_int, [C.POINTER(_i32), _i32, _i32, C.c_uint64, _vp, C.POINTER(_vp)]),
+    "reverb_model_destroy": (C.c_int, [_vp]),
+    "reverb_model_info": (C.c_int, [_vp, C.POINTER(ModelInfo)]),
+    "reverb_model_load": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "reverb_model_save": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "reverb_model_featurize": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "reverb_model_targets": (C.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "reverb_model_forward": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "reverb_model_backward": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp]),
+    "reverb_model_grads": (C.c_int, [_vp, _vp, _i64, _vp]),
+    "reverb_model_adam": (C.c_int, [_vp, C.POINTER(AdamParams), _vp]),
+    "reverb_model_train_step": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, C.POINTER(AdamParams), _vp, _vp]),
+    "reverb_model_decode": (C.c_int, [_vp, _vp, _i64, _i32, C.c_float, _vp, _vp, _vp, _vp]),
+    "reverb_params_scatter": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "last_error": (C.c_char_p, []),
     "rpr_version": (C.c_char_p, []),
 }
@@ -354,6 +382,125 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ learned estimator
+LEARN_DIMS = (12800, 512, 512, 512, 32)  # 200 bins x 4 bands x 16 SH coefficients -> 16 means + 16 log-variances
+
+
+class Model:
+    """The learned reverb-parameter estimator (an MLP trained by the library's
+    own BF16 matrix-core kernels).  Parameters are an FP32 vector in the
+    layout of include/rpr.h (W_l row-major then b_l, per layer)."""
+
+    def __init__(self, dims=LEARN_DIMS, *, max_batch=256, seed=0, stream=None):
+        arr = (C.c_int32 * len(dims))(*[int(d) for d in dims])
+        h = C.c_void_p()
+        _check(lib().reverb_model_create(arr, len(dims) - 1, int(max_batch), int(seed), _stream(stream), C.byref(h)))
+        self._h = h
+        self.dims = tuple(int(d) for d in dims)
+        self.max_batch = int(max_batch)
+
+    def info(self) -> dict:
+        mi = ModelInfo()
+        _check(lib().reverb_model_info(self._h, C.byref(mi)))
+        return dict(n_params=mi.n_params, n_layers=mi.n_layers, dims=list(mi.dims[:mi.n_layers + 1]),
+                    max_batch=mi.max_batch, step=mi.step)
+
+    @property
+    def n_params(self) -> int:
+        return self.info()["n_params"]
+
+    def load(self, params, stream=None):
+        _check(lib().reverb_model_load(self._h, _ptr(params), params.numel(), _stream(stream)))
+
+    def save(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().reverb_model_save(self._h, _ptr(out), out.numel(), _stream(stream)))
+        return out
+
+    def grads(self, stream=None):
+        import torch
+        out = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        _check(lib().reverb_model_grads(self._h, _ptr(out), out.numel(), _stream(stream)))
+        return out
+
+    def forward(self, features, out=None, stream=None):
+        import torch
+        n = features.shape[0]
+        if out is None:
+            out = torch.empty((n, self.dims[-1]), dtype=torch.float32, device=features.device)
+        _check(lib().reverb_model_forward(self._h, _ptr(features), n, _ptr(out), _stream(stream)))
+        return out
+
+    def backward(self, features, t, w, rows=None, m=None, loss=None, stream=None):
+        import torch
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=features.device)
+        m = int(rows.shape[0] if rows is not None else features.shape[0]) if m is None else int(m)
+        _check(lib().reverb_model_backward(self._h, _ptr(features), features.shape[0], _ptr(rows), m, _ptr(t),
+                                           _ptr(w), _ptr(loss), _stream(stream)))
+        return loss
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
+        ap = AdamParams(lr, beta1, beta2, eps, weight_decay, 0.0)
+        _check(lib().reverb_model_adam(self._h, C.byref(ap), _stream(stream)))
+
+    def train_step(self, features, t, w, rows, loss, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
+                   m=None, stream=None):
+        ap = AdamParams(lr, beta1, beta2, eps, weight_decay, 0.0)
+        m = int(rows.shape[0]) if m is None else int(m)
+        _check(lib().reverb_model_train_step(self._h, _ptr(features), features.shape[0], _ptr(rows), m, _ptr(t),
+                                             _ptr(w), C.byref(ap), _ptr(loss), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().reverb_model_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def featurize(hist, n_bins, n_bands, n_coeffs, stream=None):
+    """BF16 features [n][T*B*NC] (raw uint16 in an int16 tensor) and e_in [n]."""
+    import torch
+    n = hist.shape[0]
+    f = torch.empty((n, n_bins * n_bands * n_coeffs), dtype=torch.int16, device=hist.device)
+    e = torch.empty(n, dtype=torch.float32, device=hist.device)
+    _check(lib().reverb_model_featurize(_ptr(hist), n, int(n_bins), int(n_bands), int(n_coeffs), _ptr(f), _ptr(e),
+                                        _stream(stream)))
+    return f, e
+
+
+def targets(ref_params, e_in, n_bands, stream=None):
+    import torch
+    n = e_in.shape[0]
+    t = torch.empty((n, 4 * n_bands), dtype=torch.float32, device=e_in.device)
+    w = torch.empty((n, 4 * n_bands), dtype=torch.float32, device=e_in.device)
+    _check(lib().reverb_model_targets(_ptr(ref_params), _ptr(e_in), n, int(n_bands), _ptr(t), _ptr(w),
+                                      _stream(stream)))
+    return t, w
+
+
+def decode(out, e_in, n_bands, kappa, stream=None):
+    """(params [n] ReverbParams, sigma [n][B], uncertain [n] i32) from network outputs."""
+    import torch
+    n = out.shape[0]
+    params = alloc_params(n, device=out.device)
+    sigma = torch.empty((n, n_bands), dtype=torch.float32, device=out.device)
+    unc = torch.empty(n, dtype=torch.int32, device=out.device)
+    _check(lib().reverb_model_decode(_ptr(out), _ptr(e_in), n, int(n_bands), float(kappa), _ptr(params),
+                                     _ptr(sigma), _ptr(unc), _stream(stream)))
+    return params, sigma, unc
+
+
+def params_scatter(src, idx, dst, stream=None):
+    _check(lib().reverb_params_scatter(_ptr(src), _ptr(idx), idx.shape[0], _ptr(dst), _stream(stream)))
 
 
 def header_functions(path: str = HEADER) -> list[str]:

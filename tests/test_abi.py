@@ -34,6 +34,16 @@ def test_invalid_arguments_fail_before_any_launch():
     ep = P.EstimateParams(0, 3)
     assert L.estimate_reverb(None, None, None, 1, 10, 4, 4, 1e-3, C.byref(ep), None, None) == -1
     assert L.estimate_reverb(None, None, None, 0, 10, 4, 2, 1e-3, C.byref(ep), None, None) == 0  # empty: no-op
+    # learned estimator: shapes are checked on the host
+    dims = (C.c_int32 * 3)(100, 64, 32)  # 100 is not a multiple of 32
+    assert L.reverb_model_create(dims, 2, 16, 0, None, C.byref(out)) == -1 and out.value is None
+    assert b"multiple of 32" in L.last_error()
+    dims = (C.c_int32 * 3)(64, 64, 32)
+    assert L.reverb_model_create(dims, 2, 0, 0, None, C.byref(out)) == -1
+    assert L.reverb_model_featurize(None, 1, 0, 4, 16, None, None, None) == -1
+    assert L.reverb_model_featurize(None, 0, 10, 4, 16, None, None, None) == 0  # empty: no-op
+    assert L.reverb_model_decode(None, None, 1, 9, 1.0, None, None, None, None) == -1
+    assert L.reverb_model_forward(None, None, 1, None, None) == -1
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -48,6 +58,8 @@ int main(void) {
          sizeof(RprIrStats), sizeof(RprReverbParams), sizeof(RprTraceParams), sizeof(RprSceneInfo));
   printf("RprPair %zu\nRprBatchParams %zu\nRprBatchInfo %zu\n", sizeof(RprPair), sizeof(RprBatchParams),
          sizeof(RprBatchInfo));
+  printf("RprModelInfo %zu\nRprAdamParams %zu\n", sizeof(RprModelInfo), sizeof(RprAdamParams));
+  P(RprModelInfo, max_batch); P(RprModelInfo, step); P(RprAdamParams, weight_decay);
   P(RprPair, n_rays); P(RprPair, seed); P(RprBatchInfo, best_ms);
   P(RprIrStats, seg_len_sum); P(RprIrStats, first_arrival_bin); P(RprIrStats, e_class);
   P(RprIrStats, e_escaped); P(RprIrStats, e_absorbed); P(RprIrStats, n_tri_tests);
@@ -67,6 +79,10 @@ int main(void) {
     assert int(got["RprBatchParams"]) == C.sizeof(P.BatchParams)
     assert int(got["RprBatchInfo"]) == C.sizeof(P.BatchInfo)
     assert int(got["RprBatchInfo.best_ms"]) == P.BatchInfo.best_ms.offset
+    assert int(got["RprModelInfo"]) == C.sizeof(P.ModelInfo) and int(got["RprAdamParams"]) == C.sizeof(P.AdamParams)
+    assert int(got["RprModelInfo.max_batch"]) == P.ModelInfo.max_batch.offset
+    assert int(got["RprModelInfo.step"]) == P.ModelInfo.step.offset
+    assert int(got["RprAdamParams.weight_decay"]) == P.AdamParams.weight_decay.offset
     for name in ("seg_len_sum", "first_arrival_bin", "e_class", "e_escaped", "e_absorbed", "n_tri_tests"):
         assert int(got[f"RprIrStats.{name}"]) == P.IR_STATS_DTYPE.fields[name][1], name
     for name in ("g_reverb", "predelay_s", "dir_loudness"):
