@@ -84,12 +84,12 @@ def lib():
         L.orc_closest_hit_batch.argtypes = [dp, C.POINTER(C.c_int32), C.c_int64, dp, dp, C.c_int64,
                                             dp, C.POINTER(C.c_int64)]
         L.orc_trace_ir.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int32),
-                                   dp, dp, dp, C.c_int32, C.c_int32, dp, C.c_int32, dp,
+                                   dp, dp, C.c_int32, C.c_int32, dp, C.c_int32, dp,
                                    C.POINTER(TraceParams), dp, dp, C.POINTER(IrStats),
                                    C.POINTER(C.c_uint32)]
         L.orc_trace_ir.restype = C.c_int
         L.orc_num_threads.restype = C.c_int
-        L.orc_trace_path.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp, dp,
+        L.orc_trace_path.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp,
                                      C.c_int32, dp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_double,
                                      C.c_int32, dp, dp, dp, C.POINTER(C.c_int64)]
         L.orc_trace_path.restype = C.c_int
@@ -175,14 +175,6 @@ def closest_hit(verts, tris, orig, dirs):
     return tout, iout
 
 
-def p_diffuse(scattering) -> np.ndarray:
-    """Per-material probability of a diffuse bounce: the band mean of the
-    scattering coefficients, rounded to FP32 (the precision in which the HIP
-    path compares it with the exact uniform draw)."""
-    s = np.asarray(scattering, np.float64)
-    return s.mean(axis=1).astype(np.float32).astype(np.float64)
-
-
 def stats_to_dict(st: IrStats, nb: int) -> dict:
     return dict(
         n_segments=int(st.n_segments), n_finite_segments=int(st.n_finite_segments),
@@ -208,7 +200,6 @@ def trace_ir(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray
     tri_mat = np.ascontiguousarray(scene["tri_mat"], np.int32)
     ab = np.ascontiguousarray(scene["absorption"], np.float64)
     sc = np.ascontiguousarray(scene["scattering"], np.float64)
-    pdf = np.ascontiguousarray(p_diffuse(scene["scattering"]))
     M, B = ab.shape
     srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float64)
     S = len(srcs)
@@ -222,7 +213,7 @@ def trace_ir(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray
     p = TraceParams(n_rays_total, ray_begin, ray_end, max_bounces, sh_order, n_bins, pair_base,
                     bin_width_s, speed_of_sound, seed)
     rc = lib().orc_trace_ir(_dp(verts), len(verts), tris.ctypes.data_as(C.POINTER(C.c_int32)), len(tris),
-                            tri_mat.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), _dp(pdf), M, B,
+                            tri_mat.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), M, B,
                             _dp(srcs), S, _dp(lst), C.byref(p), _dp(hist), _dp(hist_late), stats,
                             rh.ctypes.data_as(C.POINTER(C.c_uint32)) if rh is not None else None)
     if rc != 0:
@@ -238,11 +229,10 @@ def trace_path(scene, source, *, seed, ray, pair, max_bounces, window_len, max_s
     tm = np.ascontiguousarray(scene["tri_mat"], np.int32)
     ab = np.ascontiguousarray(scene["absorption"], np.float64)
     sc = np.ascontiguousarray(scene["scattering"], np.float64)
-    pdf = np.ascontiguousarray(p_diffuse(scene["scattering"]))
     src = np.ascontiguousarray(source, np.float64)
     o = np.zeros((max_seg, 3)); d = np.zeros((max_seg, 3)); t = np.zeros(max_seg); tri = np.zeros(max_seg, np.int64)
     n = lib().orc_trace_path(_dp(verts), len(tris), tris.ctypes.data_as(C.POINTER(C.c_int32)),
-                             tm.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), _dp(pdf), ab.shape[1],
+                             tm.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), ab.shape[1],
                              _dp(src), seed, ray, pair, max_bounces, window_len, max_seg, _dp(o), _dp(d), _dp(t),
                              tri.ctypes.data_as(C.POINTER(C.c_int64)))
     return dict(orig=o[:n], dir=d[:n], t=t[:n], tri=tri[:n])

@@ -353,9 +353,19 @@ static void deposit(const double o[3], const double d[3], double t_hit, double L
 
 /* Trace rays [ray_begin, ray_end) of every source.
  *   verts [V][3], tris [T][3], tri_mat [T] (NULL = material 0)
- *   absorption, scattering [M][nb], p_diffuse [M] (probability of a diffuse
- *     bounce; the caller passes mean_b scattering rounded to FP32, the
- *     precision in which the HIP path takes the same decision)
+ *   absorption, scattering [M][nb]
+ * Reflection (the paper leaves the specular / diffuse mix open): each ray
+ * follows one path.  Its hero band h = ray mod nb picks the kind at every
+ * bounce, diffuse with probability s_h.  Every band b keeps the path's
+ * probability under its own choice rule, Q_b = prod q_b with q_b = s_b
+ * (diffuse) or 1 - s_b (specular).  Its energy is weighted by the balance
+ * heuristic over the nb rules, Q_b / mean_j Q_j: one-sample multiple
+ * importance sampling over the bands (Veach and Guibas 1995, as in hero
+ * wavelength spectral sampling, Wilkie et al. 2014).  The estimate is
+ * unbiased for every band and the weight stays in [0, nb] times the
+ * absorption product; weights s_b / mean_j s_j alone would grow
+ * geometrically with the reflection order when the bands' scattering
+ * differ.  Q is kept normalised to mean 1.
  *   srcs [n_src][3], listener[4] = centre xyz, radius
  *   hist      [n_src][T][nb][(n+1)^2]  zeroed and filled
  *   hist_late [n_src][T][nb] or NULL    (orders >= 3 only)
@@ -366,7 +376,7 @@ static void deposit(const double o[3], const double d[3], double t_hit, double L
  * Returns 0, or -1 on invalid arguments. */
 int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                  const int32_t *tri_mat, const double *absorption, const double *scattering,
-                 const double *p_diffuse, int32_t n_materials, int32_t nb, const double *srcs,
+                 int32_t n_materials, int32_t nb, const double *srcs,
                  int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
                  double *hist_late, OrcIrStats *stats, uint32_t *ray_hash)
 {
@@ -398,11 +408,15 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
             double *HL = hist_late ? hist_late + (size_t)s * T * nb : NULL;
             const uint32_t ray = (uint32_t)(p->ray_begin + ri);
             const uint32_t pair = (uint32_t)(p->pair_base + s);
-            double u[4], o[3], d[3], E[ORC_MAX_BANDS];
+            double u[4], o[3], d[3], E[ORC_MAX_BANDS], Q[ORC_MAX_BANDS];
+            const int hero = (int)(ray % (uint32_t)nb);
             draw(p->seed, ray, pair, 0u, u);
             orc_emission_dir(u, d);
             for (int i = 0; i < 3; ++i) o[i] = srcs[3 * s + i];
-            for (int b = 0; b < nb; ++b) E[b] = e0;
+            for (int b = 0; b < nb; ++b) {
+                E[b] = e0;
+                Q[b] = 1.0;
+            }
             double L = 0.0;
             int k = 0;
             int64_t last = -1;
@@ -453,15 +467,23 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
                 int mat = tri_mat ? tri_mat[tri] : 0;
                 const double *al = absorption + (int64_t)mat * nb;
                 const double *sc = scattering + (int64_t)mat * nb;
-                double pd = p_diffuse[mat];
                 draw(p->seed, ray, pair, (uint32_t)k, u);
                 for (int b = 0; b < nb; ++b) absorbed[b] += al[b] * E[b];
-                if (u[0] < pd) {
-                    for (int b = 0; b < nb; ++b) E[b] *= (1.0 - al[b]) * sc[b] / pd;
+                const int diffuse = u[0] < sc[hero];
+                double q[ORC_MAX_BANDS], mean_q = 0.0;
+                for (int b = 0; b < nb; ++b) {
+                    q[b] = diffuse ? sc[b] : 1.0 - sc[b];
+                    mean_q += Q[b] * q[b];
+                }
+                mean_q /= nb;
+                for (int b = 0; b < nb; ++b) {
+                    Q[b] *= q[b] / mean_q;
+                    E[b] *= (1.0 - al[b]) * q[b] / mean_q;
+                }
+                if (diffuse) {
                     orc_diffuse_dir(nf, u, d);
                     h = fnv(h, 1u);
                 } else {
-                    for (int b = 0; b < nb; ++b) E[b] *= (1.0 - al[b]) * (1.0 - sc[b]) / (1.0 - pd);
                     double dn = dot3(d, nf);
                     for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
                     h = fnv(h, 0u);
@@ -495,14 +517,13 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
  * segment's origin, direction, hit distance (INFINITY on escape) and hit
  * triangle (-1 on escape).  Returns the number of segments written. */
 int orc_trace_path(const double *verts, int64_t n_tris, const int32_t *tris, const int32_t *tri_mat,
-                   const double *absorption, const double *scattering, const double *p_diffuse, int32_t nb,
+                   const double *absorption, const double *scattering, int32_t nb,
                    const double src[3], uint64_t seed, uint32_t ray, uint32_t pair, int32_t max_bounces,
                    double window_len, int32_t max_seg, double *orig, double *dir, double *t_out, int64_t *tri_out)
 {
     (void)absorption;
-    (void)scattering;
-    (void)nb;
     double u[4], o[3], d[3];
+    const int hero = (int)(ray % (uint32_t)nb);
     draw(seed, ray, pair, 0u, u);
     orc_emission_dir(u, d);
     for (int i = 0; i < 3; ++i) o[i] = src[i];
@@ -537,7 +558,7 @@ int orc_trace_path(const double *verts, int64_t n_tris, const int32_t *tris, con
         for (int i = 0; i < 3; ++i) nf[i] = sgn * nrm[i];
         int mat = tri_mat ? tri_mat[tri] : 0;
         draw(seed, ray, pair, (uint32_t)k, u);
-        if (u[0] < p_diffuse[mat]) {
+        if (u[0] < scattering[(int64_t)mat * nb + hero]) {
             orc_diffuse_dir(nf, u, d);
         } else {
             double dn = dot3(d, nf);

@@ -268,7 +268,7 @@ def learn_room(seed: int, n_bands=4):
     absorption = g.uniform(0.02, 0.6, (1, n_bands)).astype(np.float32)
     scattering = g.uniform(0.1, 0.9, (1, n_bands)).astype(np.float32)
     s, l = _sample_pair(g, kind, dims, notch)
-    return dict(name=f"learn{seed}", kind=kind, dims=dims, notch=notch, verts=verts, tris=tris,
+    return dict(name=f"learn{seed}", seed=seed, kind=kind, dims=dims, notch=notch, verts=verts, tris=tris,
                 tri_mat=tri_mat, absorption=absorption, scattering=scattering,
                 sources=s[None].astype(np.float32), listener=l.astype(np.float32), radius=0.5)
 

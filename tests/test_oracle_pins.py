@@ -286,6 +286,47 @@ def test_zero_absorption_conserves_energy(orc):
     assert abs(late / (1e-3 / 210.0) - 1) < 0.03, late
 
 
+def test_band_weights_unbiased_with_band_dependent_scattering(orc):
+    """Zero absorption, scattering different in every band: each band's path
+    weight is a multiple-importance-sampling ratio that varies per ray, but
+    its expectation is one, so every band's late level is still dt / V (the
+    track-length estimator of a uniform stationary field) and the energy
+    alive at the window end is still the emitted energy."""
+    c = R.tiny_config()
+    sc = dict(c, absorption=np.zeros((1, 4), np.float32),
+              scattering=np.array([[0.05, 0.35, 0.65, 0.95]], np.float32))
+    r = orc.trace_ir(sc, c["sources"], c["listener"], c["radius"], n_rays_total=16384, max_bounces=100000,
+                     sh_order=0, n_bins=2000, bin_width_s=1e-3, seed=17)
+    st = r["stats"][0]
+    assert np.all(st["e_absorbed"] == 0) and st["n_escaped"] == 0
+    assert np.allclose(st["e_alive_at_stop"], 1.0, rtol=0.03), st["e_alive_at_stop"]
+    I = math.sqrt(4 * math.pi) * r["hist"][0][:, :, 0]
+    late = I[300:].mean(axis=0)
+    assert np.all(np.abs(late / (1e-3 / 210.0) - 1) < 0.04), late
+    # the bands no longer share one weight
+    assert not np.allclose(I[:, 0], I[:, 3])
+
+
+@pytest.mark.slow
+def test_band_weights_pure_specular_band_matches_image_sources(orc):
+    """Two bands, scattering 0 and 1.  Rays whose hero band is 0 reflect
+    specularly and carry band 0 with weight 2 (the balance heuristic over two
+    rules, one of which never picks their path); the others carry band 1.
+    Band 0 is therefore the image-source answer of a specular shoebox."""
+    c = R.tiny_config()
+    sc = dict(c, absorption=np.array([[0.1, 0.2]], np.float32), scattering=np.array([[0.0, 1.0]], np.float32))
+    dims = np.array([10.0, 7.0, 3.0])
+    imgs = _images_order_1_2(c["sources"][0].astype(np.float64), dims)
+    runs = _batched(orc, sc, 2**22, 32, max_bounces=2, sh_order=0, n_bins=200, bin_width_s=1e-3, seed=18)
+    lp = c["listener"].astype(np.float64)
+    e, se = _mean_se([r["stats"][0]["e_class"][1][0] for r in runs])
+    ref = sum(0.9 ** o * _direct_energy(float(np.linalg.norm(p - lp)), c["radius"]) for p, o in imgs)
+    assert abs(e - ref) < 5 * se, (e, ref, se)
+    # the direct sound is not reflected: both bands get every ray with weight 1
+    ed = [r["stats"][0]["e_class"][0] for r in runs]
+    assert np.allclose([x[0] for x in ed], [x[1] for x in ed], rtol=1e-12)
+
+
 def test_energy_budget_open_box(orc):
     verts, tris, tm = R.merge(R.box_surfaces((0, 0, 0), (10, 7, 3), faces=("x0", "x1", "y0", "y1", "z0")), [0] * 5)
     sc = dict(verts=verts, tris=tris, tri_mat=tm, absorption=np.array([[0.05, 0.2, 0.5, 0.9]], np.float32),
