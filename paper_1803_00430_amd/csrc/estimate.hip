@@ -54,12 +54,16 @@ __device__ __forceinline__ double I_fit(const EstArgs& a, const float* H, const 
 }
 
 // Backward integral without the tail constant, Sb[m] = sum_{j=m..m_last} I[j],
-// evaluated chunk by chunk from the end (inclusive suffix sums within a chunk
-// of 64 bins plus a running carry); S[m] = C + Sb[m].  Every use of S -- its
-// value at 0 and at the range-test bin, and the decay curve -- is formed the
-// same way from the same Sb, so y[0] is exactly 0 dB and no threshold
-// decision depends on two differently rounded sums of one quantity.  With
-// LDS, Sb is computed once and kept (T <= kLdsBins); otherwise it is
+// accumulated in FP64 strictly from the last bin down (Sb[m] = Sb[m+1] +
+// I[m]), one chunk of 64 bins at a time with each lane's value broadcast in
+// turn; S[m] = C + Sb[m].  That order makes S exactly non-increasing: bins
+// without energy (before the first arrival, or gaps in a sparse decay) keep
+// S exactly constant, so their decay-curve value is exactly 0 dB, or exactly
+// that of the next bin, and a range whose top is 0 dB (EDT) takes them all.
+// A tree-shaped suffix sum would round such plateaus up or down by an ulp
+// and drop some of them from the fit.  Every use of S -- its value at 0 and
+// at the range-test bin, and the decay curve -- is formed from the same Sb.
+// With LDS, Sb is computed once and kept (T <= kLdsBins); otherwise it is
 // recomputed by every pass.
 constexpr int kLdsBins = 8192;
 
@@ -78,15 +82,14 @@ struct SbSource {
         const int n_chunks = (m_last + kWave) / kWave;
         for (int ch = n_chunks - 1; ch >= 0; --ch) {
             const int m = ch * kWave + lane;
-            double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
-#pragma unroll
-            for (int o = 1; o < kWave; o <<= 1) {
-                const double t = __shfl_down(v, o, kWave);
-                if (lane + o < kWave) v += t;
+            const double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
+            const int top = min(kWave - 1, m_last - ch * kWave);
+            double mine = 0.0;
+            for (int j = top; j >= 0; --j) {
+                carry += __shfl(v, j, kWave);
+                if (lane == j) mine = carry;
             }
-            const double Sb = carry + v;
-            carry += __shfl(v, 0, kWave);
-            if (m <= m_last) visit(m, Sb);
+            if (m <= m_last) visit(m, mine);
         }
         return carry;
     }

@@ -82,23 +82,19 @@ __global__ void k_materials(const float* __restrict__ absorption, const float* _
 {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= nm) return;
-    double ssum = 0.0;
     bool bad = false;
     for (int b = 0; b < nb; ++b) {
         const float a = absorption[m * nb + b], s = scattering[m * nb + b];
         if (!(a >= 0.0f && a <= 1.0f) || !(s >= 0.0f && s <= 1.0f)) bad = true;
-        ssum += (double)s;
     }
     if (bad) atomicOr(&f->flags, (uint32_t)kBadCoeff);
-    const float pd = (float)(ssum / (double)nb);
     float* r = mats + (int64_t)m * kMatStride;
     for (int i = 0; i < kMatStride; ++i) r[i] = 0.0f;
-    r[kMatPd] = pd;
     for (int b = 0; b < nb; ++b) {
-        const double a = absorption[m * nb + b], s = scattering[m * nb + b];
-        r[kMatAlpha + b] = (float)a;
-        r[kMatWd + b] = pd > 0.0f ? (float)((1.0 - a) * s / (double)pd) : 0.0f;
-        r[kMatWs + b] = pd < 1.0f ? (float)((1.0 - a) * (1.0 - s) / (1.0 - (double)pd)) : 0.0f;
+        const float a = absorption[m * nb + b];
+        r[kMatAlpha + b] = a;
+        r[kMatS + b] = scattering[m * nb + b];
+        r[kMatKeep + b] = (float)(1.0 - (double)a);
     }
 }
 

@@ -34,9 +34,8 @@ constexpr int kMatStride = 32;      // floats per material record
 // the shared edge of two coplanar triangles can meet the neighbour at t ~ 0 and
 // alternate between the two.  1 mm is >= 30 ulps for coordinates up to 500 m.
 constexpr float kSurfaceOffset = 1e-3f;
-// Material record: [0] p_diffuse, [1 + b] alpha_b, [9 + b] diffuse weight
-// (1-alpha_b) s_b / p_d, [17 + b] specular weight (1-alpha_b)(1-s_b)/(1-p_d).
-constexpr int kMatPd = 0, kMatAlpha = 1, kMatWd = 9, kMatWs = 17;
+// Material record: [1 + b] alpha_b, [9 + b] scattering s_b, [17 + b] 1 - alpha_b.
+constexpr int kMatAlpha = 1, kMatS = 9, kMatKeep = 17;
 
 // Node links: >= 0 internal node index, < 0 leaf = ~sorted triangle index.
 __host__ __device__ inline bool is_leaf(int32_t link) { return link < 0; }

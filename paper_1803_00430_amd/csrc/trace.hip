@@ -148,9 +148,11 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f, L = 0.f;
     int k = 0, last = -1;
     uint32_t h = 0;
-    float E[NB];
+    // E[b]: band energy; Q[b]: the path's probability under band b's choice
+    // rule relative to the mean over the bands (see the bounce below).
+    float E[NB], Q[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) E[b] = 0.f;
+    for (int b = 0; b < NB; ++b) E[b] = Q[b] = 0.f;
     SceneView sc{};
     LaneAcc<NB> acc;
     lane_acc_zero(acc);
@@ -189,9 +191,12 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                     k = 0;
                     last = -1;
                     h = 2166136261u;
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) E[b] = P.e0;
                     sc = P.scene;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        E[b] = P.e0;
+                        Q[b] = b < sc.n_bands ? 1.f : 0.f;
+                    }
                     alive = true;
                 }
             }
@@ -334,14 +339,33 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                     const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, (uint32_t)k, 0u), P.key0, P.key1);
 #pragma unroll
                     for (int b = 0; b < NB; ++b) acc.absb[b] += mr[kMatAlpha + b] * E[b];
-                    if (u01(x.x) < mr[kMatPd]) {
+                    // The ray's hero band (ray id mod bands) picks the kind of
+                    // reflection with its own scattering coefficient; each band
+                    // is weighted by its rule's path probability over the mean
+                    // of all bands' (balance heuristic, one-sample multiple
+                    // importance sampling over the bands).  Q is renormalised
+                    // to mean 1 at every bounce.
+                    const int nbr = sc.n_bands;
+                    const bool diffuse = u01(x.x) < mr[kMatS + (int)(ray % (uint32_t)nbr)];
+                    float q[NB], mean_q = 0.f;
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) E[b] *= mr[kMatWd + b];
+                    for (int b = 0; b < NB; ++b) {
+                        q[b] = diffuse ? mr[kMatS + b] : 1.f - mr[kMatS + b];
+                        mean_q += Q[b] * q[b];
+                    }
+                    // mean_q >= Q_hero q_hero / bands > 0 in exact arithmetic; the
+                    // floor only guards an FP32 underflow of every term
+                    const float inv_mean = (float)nbr / fmaxf(mean_q, 1e-30f);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float r = q[b] * inv_mean;
+                        Q[b] *= r;
+                        E[b] *= mr[kMatKeep + b] * r;
+                    }
+                    if (diffuse) {
                         lambert_dir(nx, ny, nz, u01(x.y), u01(x.z), dx, dy, dz);
                         h = fnv1a(h, 1u);
                     } else {
-#pragma unroll
-                        for (int b = 0; b < NB; ++b) E[b] *= mr[kMatWs + b];
                         const float dn = 2.0f * (dx * nx + dy * ny + dz * nz);
                         dx -= dn * nx;
                         dy -= dn * ny;

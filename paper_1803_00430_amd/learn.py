@@ -1,0 +1,145 @@
+"""Dataset, training and evaluation loop of the learned reverb-parameter
+estimator, over the C ABI (every step runs in the library's kernels; this
+module only orders the calls and moves indices).
+
+  trace_rooms     trace one source-listener pair per room with the batched
+                  persistent launch, in chunks, keeping the reverb parameters
+                  and, if asked, the BF16 features of the histograms
+  make_dataset    features of a cheap trace + targets from a converged trace
+  train           minibatch Adam on the GPU (Gaussian NLL)
+  predict         features -> network output -> reverb parameters + gate
+  rt60_error      per-band relative RT60 error against reference parameters
+
+A room is a scene dict (verts, tris, tri_mat, absorption, scattering) with one
+source and one listener (as `rpr_scenes.learn_room` builds them).  Seeds: the
+pair of room r traced with `seed_offset` uses the Philox key r + seed_offset,
+so the cheap input, the training target and the evaluation reference of one
+room are independent streams.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from . import (Batch, Model, Scene, decode, featurize, params_host, targets, LEARN_DIMS, ST_BAD_FIT,
+               ST_NO_ENERGY, ST_NO_RANGE)
+
+SH_ORDER = 3
+MAX_BOUNCES = 1000
+INPUT = dict(n_bins=200, bin_width_s=0.01)       # 1k-ray input histogram: 200 bins of 10 ms
+CONVERGED = dict(n_bins=2000, bin_width_s=0.001)  # targets and references: 2000 bins of 1 ms
+SEED_INPUT = 1 << 32
+SEED_TARGET = 1 << 33
+SEED_REFERENCE = 1 << 34
+SEED_SWEEP = 1 << 35  # + n_rays: the plain method's own traces in the ray-count sweep
+INVALID_FIT = ST_NO_ENERGY | ST_BAD_FIT | ST_NO_RANGE
+
+
+def room_pairs(rooms, n_rays, seed_offset, max_bounces=MAX_BOUNCES):
+    return [dict(scene=i, source=r["sources"][0], listener=r["listener"], radius=r["radius"], n_rays=int(n_rays),
+                 max_bounces=int(max_bounces), seed=int(r["seed"]) + int(seed_offset), pair_id=0)
+            for i, r in enumerate(rooms)]
+
+
+def trace_rooms(scenes, rooms, *, n_rays, n_bins, bin_width_s, seed_offset, want_features=False, chunk=512,
+                device="cuda", log=None):
+    """Trace every room once (one pair each) in chunks of `chunk` pairs.
+    Returns dict(params uint8 [n][752] on the device, features int16 [n][F]
+    (BF16 bits) and e_in [n] if want_features, segments, seconds)."""
+    import torch
+    n = len(rooms)
+    out = dict(params=torch.empty((n, 752), dtype=torch.uint8, device=device), segments=0, seconds=0.0)
+    nc = (SH_ORDER + 1) ** 2
+    nb = scenes[0].n_bands
+    if want_features:
+        out["features"] = torch.empty((n, n_bins * nb * nc), dtype=torch.int16, device=device)
+        out["e_in"] = torch.empty(n, dtype=torch.float32, device=device)
+    pairs = room_pairs(rooms, n_rays, seed_offset)
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        sub = [dict(p, scene=p["scene"] - c0, pair_id=k) for k, p in enumerate(pairs[c0:c1])]
+        t0 = time.perf_counter()
+        b = Batch(scenes[c0:c1], sub, n_bins=n_bins, sh_order=SH_ORDER, bin_width_s=bin_width_s, autotune=False,
+                  use_graph=False, late=False, device=device)
+        b.run()
+        if want_features:
+            f, e = featurize(b.hist, n_bins, nb, nc)
+            out["features"][c0:c1] = f
+            out["e_in"][c0:c1] = e
+        out["params"][c0:c1] = b.params
+        torch.cuda.synchronize()
+        out["seconds"] += time.perf_counter() - t0
+        from . import stats_host
+        out["segments"] += int(stats_host(b.stats)["n_segments"].sum())
+        b.close()
+        if log:
+            log(f"  traced rooms {c0}..{c1 - 1} at {n_rays} rays ({out['seconds']:.1f} s)")
+    return out
+
+
+def make_scenes(rooms, device="cuda"):
+    return [Scene.from_dict(r, device=device) for r in rooms]
+
+
+def make_dataset(scenes, rooms, *, n_input=1024, n_target=262144, chunk=512, log=None):
+    """Features of an n_input-ray trace (200 x 10 ms bins) and the targets
+    from the reverb parameters of an independent n_target-ray trace
+    (2000 x 1 ms bins).  Returns dict(features, e_in, t, w, target_params)."""
+    nb = scenes[0].n_bands
+    cheap = trace_rooms(scenes, rooms, n_rays=n_input, seed_offset=SEED_INPUT, want_features=True, chunk=chunk,
+                        log=log, **INPUT)
+    conv = trace_rooms(scenes, rooms, n_rays=n_target, seed_offset=SEED_TARGET, chunk=chunk, log=log, **CONVERGED)
+    t, w = targets(conv["params"], cheap["e_in"], nb)
+    return dict(features=cheap["features"], e_in=cheap["e_in"], t=t, w=w, target_params=conv["params"],
+                trace_seconds=cheap["seconds"] + conv["seconds"], segments=cheap["segments"] + conv["segments"])
+
+
+def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-4, seed=0, log=None):
+    """Minibatch Adam over the dataset's rows (a fresh permutation per
+    epoch), learning rate decayed by a cosine to 5% of `lr`.  Returns the
+    mean loss of each epoch."""
+    import torch
+    X, t, w = data["features"], data["t"], data["w"]
+    n = X.shape[0]
+    steps_per_epoch = max(1, n // batch)
+    total = epochs * steps_per_epoch
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    losses = []
+    step = 0
+    loss = torch.zeros(steps_per_epoch, dtype=torch.float64, device=X.device)
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=gen).to(device=X.device, dtype=torch.int32)
+        for i in range(steps_per_epoch):
+            frac = step / max(1, total - 1)
+            lr_i = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * frac)))
+            model.train_step(X, t, w, perm[i * batch:(i + 1) * batch], loss[i:i + 1], lr=lr_i,
+                             weight_decay=weight_decay)
+            step += 1
+        losses.append(float(loss.mean().cpu()))
+        if log:
+            log(f"  epoch {ep}: loss {losses[-1]:.4f}")
+    return losses
+
+
+def predict(model: Model, features, e_in, n_bands, kappa):
+    """(params uint8 [n][752], sigma [n][B], uncertain [n]) on the device."""
+    out = model.forward(features)
+    return decode(out, e_in, n_bands, kappa)
+
+
+def rt60_error(params, ref_params, n_bands):
+    """|RT60 - RT60_ref| / RT60_ref per (room, band) on the host, for the
+    rooms and bands whose reference fit is valid; an invalid estimate counts
+    as an error of 1.  Returns (errors [n][B] with NaN where the reference is
+    invalid)."""
+    p = params_host(params)
+    r = params_host(ref_params)
+    B = n_bands
+    rt, st = p["rt60"][:, :B].astype(np.float64), p["status"][:, :B]
+    rr, sr = r["rt60"][:, :B].astype(np.float64), r["status"][:, :B]
+    ref_ok = (rr > 0) & ((sr & INVALID_FIT) == 0)
+    est_ok = (rt > 0) & ((st & INVALID_FIT) == 0)
+    err = np.where(est_ok, np.abs(rt - rr) / np.where(ref_ok, rr, 1.0), 1.0)
+    return np.where(ref_ok, err, np.nan)

@@ -189,6 +189,47 @@ def test_estimate_parity_on_identical_input(torch_cuda):
             assert abs(pg["mean_free_path_m"] - po["mean_free_path_m"]) <= 1e-6 * po["mean_free_path_m"]
 
 
+def test_estimate_exact_on_plateaus(torch_cuda):
+    """Synthetic decays with an empty prefix (before the first arrival) and
+    empty bins inside the decay: the backward integral is constant across
+    them, the EDT range takes every prefix bin at exactly 0 dB, and GPU and
+    oracle make the same range, point-set and tail decisions (regression: a
+    tree-shaped suffix sum rounded plateaus by an ulp and dropped prefix
+    bins from the EDT fit)."""
+    import torch
+    g = np.random.default_rng(7)
+    n, T, B = 48, 800, 4
+    dt = 1e-3
+    t = np.arange(T) * dt
+    H = np.zeros((n, T, B, 1))
+    for i in range(n):
+        for b in range(B):
+            rt = g.uniform(0.5, 8.0)
+            start = int(g.integers(0, 60))
+            I = np.exp(-6.0 * np.log(10.0) * t / rt) * (t >= start * dt)
+            I *= g.uniform(0.5, 1.5, T)
+            I[g.uniform(0, 1, T) < g.uniform(0.0, 0.6)] = 0.0  # sparse gaps
+            H[i, :, b, 0] = I / math.sqrt(4 * math.pi)
+    H = H.astype(np.float32)
+    st = np.zeros(n, P.IR_STATS_DTYPE)
+    st["e_emitted"] = 1.0
+    st["first_arrival_bin"] = st["first_late_bin"] = P.INT32_MAX
+    hist = torch.as_tensor(H, device="cuda")
+    stats = torch.as_tensor(st.view(np.uint8).reshape(n, -1), device="cuda")
+    out = P.alloc_params(n)
+    P.estimate_reverb(hist, None, stats, T, B, 0, dt, out)
+    pg = P.params_host(out)
+    n_edt = 0
+    for i in range(n):
+        sd = {k: st[i][k] for k in st.dtype.names}
+        po = oracle.estimate_reverb(H[i].astype(np.float64), None, sd, dt)
+        assert np.array_equal(pg["rt60_range"][i][:B], po["rt60_range"]), i
+        assert np.array_equal(pg["status"][i][:B], po["status"]), i
+        assert np.allclose(pg["rt60"][i][:B], po["rt60"], rtol=1e-6), i
+        n_edt += int(np.sum(po["rt60_range"] == 3))
+    assert n_edt > 10  # the EDT range (top at 0 dB) is exercised
+
+
 def test_zero_absorption_invariants(torch_cuda):
     c = R.tiny_config()
     sd = dict(c, absorption=np.zeros((1, 4), np.float32))
@@ -201,8 +242,11 @@ def test_zero_absorption_invariants(torch_cuda):
     assert np.all(st["e_absorbed"][:4] == 0)
     assert np.allclose(st["e_alive_at_stop"][:4] + st["e_escaped"][:4], 1.0, rtol=1e-5)
     H = g["hist"][0]
-    # every band carries the same energy; FP32 atomics may add in different orders per band
-    assert np.allclose(H[:, 1:, :], H[:, :1, :], rtol=1e-5, atol=1e-12 * np.abs(H).max())
+    # every band carries the same energy; FP32 atomics may add in different
+    # orders per band, so cells (signed SH sums among them) agree to the FP32
+    # accumulation bound relative to their row's absolute sum
+    for b in range(1, 4):
+        assert_hist_close(H[:, b, :], H[:, 0, :], tol=1e-5, what=f"band {b} vs band 0")
 
 
 def test_edge_cases(torch_cuda):
