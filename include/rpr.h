@@ -321,14 +321,33 @@ int reverb_model_info(const RprModel* model, RprModelInfo* out /* host */);
 int reverb_model_load(RprModel* model, const float* params, int64_t n, void* hip_stream);
 int reverb_model_save(const RprModel* model, float* params, int64_t n, void* hip_stream);
 
-/* Input features of n_ir histograms (device [n_ir][n_bins][n_bands][n_coeffs]
- * f32, the layout trace_ir writes): with e_in = (1/B) sum_{m,b} sqrt(4 pi)
- * H[m][b][0] and u = H / e_in, feature = sign(u) log1p(1e6 |u|) / 8 in the
- * histogram's own order, rounded to BF16; all zero when e_in = 0.
- *   features device [n_ir][n_bins * n_bands * n_coeffs] u16 (BF16)
+/* Input features of n_ir traces, rounded to BF16; one row of
+ * n_bins * n_bands * n_coeffs + 64 values per trace.
+ *
+ * Histogram part (hist device [n_ir][n_bins][n_bands][n_coeffs] f32, the
+ * layout trace_ir writes), in the histogram's own order; e_in = (1/B)
+ * sum_{m,b} sqrt(4 pi) H[m][b][0]:
+ *   coefficient 0 of band b: its Schroeder decay curve, the backward integral
+ *     S_b[m] = sum_{j>=m} sqrt(4 pi) H[j][b][0] (Section 4.2): bin 0 holds
+ *     ln(S_b[0] / e_in), bins m >= 1 hold 10 log10(S_b[m] / S_b[0]) / 60
+ *     clipped below at -1; zero for a band without energy;
+ *   coefficients k >= 1: sign(u) log1p(1e6 |u|) / 8 with u = H / e_in;
+ *   all zero when e_in = 0.
+ * Statistics part (stats device [n_ir], or NULL for zeros), 64 values, with
+ * r(x) = ln(max(x / e_emitted, floor)): for each band b, [4b]
+ * ln(max(-r(e_alive_at_stop), 1e-3)) / 5 (floor 1e-300; the log of the ray
+ * population's decay exponent over the window), [4b+1] r(e_absorbed) / 10,
+ * [4b+2] r(e_escaped) / 10 (floor 1e-12), [4b+3] r(e_alive_at_bounce_cap) / 60
+ * (other floors 1e-30); [32] ln(mean free
+ * path / 1 m) / 3, [33] ln(segments per ray) / 5, [34] escaped rays / rays,
+ * [35] first arrival bin / n_bins, [36] min(first late bin, n_bins) / n_bins;
+ * the rest 0.  The ray population's decay over the window uses every ray,
+ * not only those that cross the listener sphere.
+ * n_bins * n_bands <= 7936 (RPR_EUNSUPPORTED above).
+ *   features device [n_ir][n_bins * n_bands * n_coeffs + 64] u16 (BF16)
  *   e_in     device [n_ir] f32 */
-int reverb_model_featurize(const float* hist, int32_t n_ir, int32_t n_bins, int32_t n_bands, int32_t n_coeffs,
-                           uint16_t* features, float* e_in, void* hip_stream);
+int reverb_model_featurize(const float* hist, const RprIrStats* stats, int32_t n_ir, int32_t n_bins,
+                           int32_t n_bands, int32_t n_coeffs, uint16_t* features, float* e_in, void* hip_stream);
 /* Training targets from the parameters of converged traces (device
  * [n_ir]) and the cheap traces' e_in (device [n_ir]):
  *   t device [n_ir][4B] f32 = [log rt60 | log(e_direct/e_in + 1e-4) | early | late]

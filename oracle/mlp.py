@@ -11,8 +11,10 @@ cheap trace (1k rays, 200 bins of 10 ms) to the parameters that the plain
 estimator (Section 4.2) returns on a converged trace, with a per-output
 variance.  Everything here is the plain definition, in float64:
 
-  featurize   histogram -> input vector (signed log of the energy-normalised
-              histogram, in the histogram's own bin-major order)
+  featurize   trace -> input vector: the histogram in its bin-major order
+              (per band the Schroeder decay curve in the l = 0 channel, the
+              signed log of the energy-normalised directional coefficients)
+              followed by 64 features of the trace's statistics
   targets     ReverbParams of a converged trace -> the 4B regression targets
               and their validity mask
   forward     z_l = h_l W_l^T + b_l, h_{l+1} = relu(z_l), last layer linear
@@ -34,6 +36,8 @@ import numpy as np
 
 FEAT_GAIN = 1.0e6       # u -> log1p(FEAT_GAIN |u|): -60 dB of u still maps to a value of order 1
 FEAT_SCALE = 0.125      # brings the features to order one
+DECAY_FLOOR_DB = -60.0  # the decay-curve channel is clipped at -60 dB and scaled to [-1, 0]
+STAT_FEATURES = 64      # trace statistics appended to the histogram features (4 per band for up to 8 bands + 5)
 ENERGY_FLOOR = 1.0e-4   # log(E / e_in + floor): absent classes (an occluded direct path) stay finite
 ST_INVALID_FIT = 1 | 2 | 4   # NO_ENERGY | BAD_FIT | NO_RANGE
 
@@ -59,16 +63,63 @@ def input_energy(hist):
     return math.sqrt(4.0 * math.pi) * H[:, :, 0].sum() / H.shape[1]
 
 
-def featurize(hist):
-    """hist [T][B][NC] -> features [T*B*NC] (same order):
-    f = sign(u) log1p(FEAT_GAIN |u|) FEAT_SCALE with u = H / e_in; all zero
-    when the trace carries no energy.  Returns (features, e_in)."""
+def featurize(hist, stats=None):
+    """One trace -> features [T*B*NC + STAT_FEATURES].
+
+    Histogram part (hist [T][B][NC], in the histogram's own order): channel
+    k = 0 carries each band's Schroeder decay curve, the backward integral
+    S_b[m] = sum_{j>=m} I_b[j] of the intensity I_b = sqrt(4 pi) H_b,0 (summed
+    from the last bin down): bin 0 holds ln(S_b[0] / e_in), bins m >= 1 hold
+    10 log10(S_b[m] / S_b[0]) / 60 clipped below at -1 (-60 dB).  Channels
+    k >= 1 (the directional coefficients) hold sign(u) log1p(FEAT_GAIN |u|)
+    FEAT_SCALE with u = H / e_in.  All zero when the trace carries no energy;
+    a band without energy has a zero channel 0.
+
+    Statistics part (the same trace's IrStats as a dict, or None for zeros),
+    with r(x) = ln(max(x / e_emitted, floor)):
+      [4b + 0]  ln(max(-r(e_alive_at_stop[b]), 1e-3)) / 5, floor 1e-300: the
+                log of the ray population's decay exponent over the window
+                (all rays, not only sphere crossings; a diffuse decay gives
+                log RT60 = ln(6 ln 10 x window) - 5 x this)
+      [4b + 1]  r(e_absorbed[b]) / 10, floor 1e-30
+      [4b + 2]  r(e_escaped[b]) / 10, floor 1e-12
+      [4b + 3]  r(e_alive_at_bounce_cap[b]) / 60, floor 1e-30
+      [32] ln(mean free path / 1 m) / 3, [33] ln(segments per ray) / 5,
+      [34] escaped rays / rays, [35] first arrival bin / T, [36] first late
+      bin / T (1 when none); the rest zero.  All zero without rays.
+    Returns (features, e_in)."""
     H = np.asarray(hist, np.float64)
+    T, B, NC = H.shape
+    fs = np.zeros(STAT_FEATURES)
+    if stats is not None and stats["n_rays"] > 0 and stats["e_emitted"] > 0:
+        em = float(stats["e_emitted"])
+        for b in range(B):
+            for j, (key, fl, sc) in enumerate((("e_alive_at_stop", 1e-300, 5.0), ("e_absorbed", 1e-30, 10.0),
+                                                ("e_escaped", 1e-12, 10.0), ("e_alive_at_bounce_cap", 1e-30, 60.0))):
+                r = math.log(max(float(stats[key][b]) / em, fl))
+                fs[4 * b + j] = (math.log(max(-r, 1e-3)) if j == 0 else r) / sc
+        nf = stats["n_finite_segments"]
+        fs[32] = math.log(stats["seg_len_sum"] / nf) / 3.0 if nf > 0 and stats["seg_len_sum"] > 0 else 0.0
+        fs[33] = math.log(stats["n_segments"] / stats["n_rays"]) / 5.0
+        fs[34] = stats["n_escaped"] / stats["n_rays"]
+        fa, fl_ = stats["first_arrival_bin"], stats["first_late_bin"]
+        fs[35] = min(fa, T) / T
+        fs[36] = min(fl_, T) / T
     e = input_energy(H)
     if not e > 0.0:
-        return np.zeros(H.size), 0.0
-    u = H.reshape(-1) / e
-    return np.sign(u) * np.log1p(FEAT_GAIN * np.abs(u)) * FEAT_SCALE, e
+        return np.concatenate([np.zeros(H.size), fs]), 0.0
+    u = H / e
+    f = np.sign(u) * np.log1p(FEAT_GAIN * np.abs(u)) * FEAT_SCALE
+    I = math.sqrt(4.0 * math.pi) * H[:, :, 0]
+    for b in range(B):
+        S = np.cumsum(I[::-1, b])[::-1]
+        f[:, b, 0] = 0.0
+        if S[0] > 0.0:
+            f[0, b, 0] = math.log(S[0] / e)
+            with np.errstate(divide="ignore"):
+                db = 10.0 * np.log10(S[1:] / S[0])
+            f[1:, b, 0] = np.maximum(db, DECAY_FLOOR_DB) / -DECAY_FLOOR_DB
+    return np.concatenate([f.reshape(-1), fs]), e
 
 
 def targets(params, e_in, n_bands):

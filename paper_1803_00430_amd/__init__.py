@@ -139,7 +139,7 @@ SIGNATURES = {
     "reverb_model_info": (C.c_int, [_vp, C.POINTER(ModelInfo)]),
     "reverb_model_load": (C.c_int, [_vp, _vp, _i64, _vp]),
     "reverb_model_save": (C.c_int, [_vp, _vp, _i64, _vp]),
-    "reverb_model_featurize": (C.c_int, [_vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
+    "reverb_model_featurize": (C.c_int, [_vp, _vp, _i32, _i32, _i32, _i32, _vp, _vp, _vp]),
     "reverb_model_targets": (C.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp]),
     "reverb_model_forward": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "reverb_model_backward": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp]),
@@ -385,7 +385,9 @@ class Batch:
 
 
 # ------------------------------------------------------------------ learned estimator
-LEARN_DIMS = (12800, 512, 512, 512, 32)  # 200 bins x 4 bands x 16 SH coefficients -> 16 means + 16 log-variances
+STAT_FEATURES = 64
+# input: 200 bins x 4 bands x 16 SH coefficients + 64 trace statistics -> 16 means + 16 log-variances
+LEARN_DIMS = (12800 + STAT_FEATURES, 512, 512, 512, 32)
 
 
 class Model:
@@ -466,14 +468,14 @@ class Model:
             pass
 
 
-def featurize(hist, n_bins, n_bands, n_coeffs, stream=None):
-    """BF16 features [n][T*B*NC] (raw uint16 in an int16 tensor) and e_in [n]."""
+def featurize(hist, n_bins, n_bands, n_coeffs, stats=None, stream=None):
+    """BF16 features [n][T*B*NC + 64] (raw uint16 in an int16 tensor) and e_in [n]."""
     import torch
     n = hist.shape[0]
-    f = torch.empty((n, n_bins * n_bands * n_coeffs), dtype=torch.int16, device=hist.device)
+    f = torch.empty((n, n_bins * n_bands * n_coeffs + STAT_FEATURES), dtype=torch.int16, device=hist.device)
     e = torch.empty(n, dtype=torch.float32, device=hist.device)
-    _check(lib().reverb_model_featurize(_ptr(hist), n, int(n_bins), int(n_bands), int(n_coeffs), _ptr(f), _ptr(e),
-                                        _stream(stream)))
+    _check(lib().reverb_model_featurize(_ptr(hist), _ptr(stats), n, int(n_bins), int(n_bands), int(n_coeffs),
+                                        _ptr(f), _ptr(e), _stream(stream)))
     return f, e
 
 

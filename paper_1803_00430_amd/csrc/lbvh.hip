@@ -248,6 +248,60 @@ __global__ void __launch_bounds__(1024) k_radix_scan(uint32_t* __restrict__ coun
     }
 }
 
+// Device-wide exclusive scan of u32 in tiles of kSortTile elements (thread t
+// of a tile owns elements 8t..8t+7): per-tile sums, an exclusive scan of the
+// tile sums by k_radix_scan, then each tile scans itself and adds its
+// offset.  Replaces a single-workgroup scan whose serial per-thread chunks
+// made it latency bound for long arrays.
+__device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t* s_wave)
+{
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) s_wave[w] = inc;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int i = 0; i < w; ++i) wbase += s_wave[i];
+    return wbase + inc - v;
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_scan_sums(const uint32_t* __restrict__ in, int64_t len,
+                                                           uint32_t* __restrict__ sums)
+{
+    __shared__ uint32_t s_wave[kBuildBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i)
+        if (base + i < len) v += in[base + i];
+    const uint32_t ex = block_exclusive(v, s_wave);
+    if (threadIdx.x == kBuildBlock - 1) sums[blockIdx.x] = ex + v;
+}
+
+__global__ void __launch_bounds__(kBuildBlock) k_scan_apply(uint32_t* __restrict__ data, int64_t len,
+                                                            const uint32_t* __restrict__ offsets)
+{
+    __shared__ uint32_t s_wave[kBuildBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+    uint32_t x[kSortItems];
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        x[i] = base + i < len ? data[base + i] : 0u;
+        v += x[i];
+    }
+    uint32_t run = block_exclusive(v, s_wave) + (offsets ? offsets[blockIdx.x] : 0u);
+#pragma unroll
+    for (int i = 0; i < kSortItems; ++i) {
+        if (base + i < len) data[base + i] = run;
+        run += x[i];
+    }
+}
+
 // Stable scatter: each tile is processed in rounds of 256 keys; within a
 // round, lanes of a wave with equal digits are matched by eight ballots and
 // ranked by position, and waves are ordered through per-digit counters.
@@ -586,6 +640,17 @@ hipError_t arena_place(Arena& a, B&... bufs)
 
 inline unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// In-place exclusive scan of len u32; `sums` holds blocks(len, kSortTile) entries.
+void scan_exclusive(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st)
+{
+    const unsigned nb = blocks(len, kSortTile);
+    if (nb > 1) {
+        hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kBuildBlock), 0, st, data, len, sums);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, sums, (int64_t)nb);
+    }
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBuildBlock), 0, st, data, len, nb > 1 ? sums : nullptr);
+}
+
 }  // namespace
 }  // namespace rpr
 
@@ -643,7 +708,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
     TRY(hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * (size_t)(n > 1 ? n - 1 : 1)));
     DevBuf<float4> cent, box;
-    DevBuf<uint32_t> k0, v0, k1, v1, counts, seen, refs, even, idx4;
+    DevBuf<uint32_t> k0, v0, k1, v1, counts, seen, refs, even, idx4, scan_sums;
     DevBuf<int32_t> ibox, parent;
     DevBuf<int2> child;
     const int n_tiles = (int)blocks(n > 0 ? n : 1, kSortTile);
@@ -662,8 +727,10 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(even.alloc(n > 1 ? n - 1 : 1));
         TRY(idx4.alloc(n > 1 ? n - 1 : 1));
         TRY(refs.alloc(2 * (size_t)n - 1));
+        TRY(scan_sums.alloc(std::max<size_t>(blocks((int64_t)256 * n_tiles, kSortTile), blocks(n, kSortTile))));
     }
-    TRY(arena_place(arena, flags, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, ibox, parent, child));
+    TRY(arena_place(arena, flags, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, ibox, parent, child,
+                    scan_sums));
     hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
     hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
                        n_materials, n_bands, sc->mats, flags.p);
@@ -680,7 +747,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_count, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n_tris, shift, counts.p,
                                n_tiles);
-            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, counts.p, (int64_t)256 * n_tiles);
+            scan_exclusive(counts.p, (int64_t)256 * n_tiles, scan_sums.p, st);
             hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, vi, n_tris, shift,
                                counts.p, n_tiles, ko, vo, flags.p);
             std::swap(ki, ko);
@@ -705,7 +772,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
             hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
                                parent.p, even.p, flags.p);
             TRY(hipMemcpyAsync(idx4.p, even.p, sizeof(uint32_t) * (n - 1), hipMemcpyDeviceToDevice, st));
-            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, idx4.p, (int64_t)(n - 1));
+            scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
             hipLaunchKernelGGL(k_collapse4, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
                                box.p, ibox.p, even.p, idx4.p, sc->nodes);
             hipLaunchKernelGGL(k_depth, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,

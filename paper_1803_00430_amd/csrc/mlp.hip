@@ -43,6 +43,8 @@ constexpr int kMaxDim = 65536;
 constexpr float kFeatGain = 1.0e6f;
 constexpr float kFeatScale = 0.125f;
 constexpr float kEnergyFloor = 1.0e-4f;
+constexpr int kStatFeatures = 64;        // trace statistics appended to every feature row
+constexpr int kFeatMaxBinsBands = 7936;  // decay curves in LDS: 8 bytes each, with the 2 KB reduction buffer <= 64 KB
 constexpr size_t kPartialFloats = size_t(32) << 20;  // split-K partial sums (128 MB)
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet).
@@ -297,14 +299,54 @@ __global__ void k_init_uniform(float* __restrict__ p, long long n, int layer, fl
 }
 
 // ------------------------------------------------------------------ features, targets, decoding
-// One workgroup per IR: e_in = sqrt(4 pi) / B * sum_{m,b} H[m][b][0] (FP64,
-// fixed order), then feature = sign(u) log1p(gain |u|) scale with u = H / e_in.
-__global__ void __launch_bounds__(256) k_featurize(const float* __restrict__ hist, int T, int B, int NC,
+// One workgroup per IR.  e_in = sqrt(4 pi) / B * sum_{m,b} H[m][b][0] (FP64,
+// fixed order).  Channel 0 of every band becomes its Schroeder decay curve:
+// one thread per band sums S_b[m] = sum_{j>=m} sqrt(4 pi) H[j][b][0] from the
+// last bin down in FP64 (kept in LDS), bin 0 then holds ln(S_b[0] / e_in) and
+// bins m >= 1 hold 10 log10(S_b[m] / S_b[0]) / 60 clipped at -1.  The other
+// channels hold sign(u) log1p(gain |u|) scale with u = H / e_in.
+__global__ void __launch_bounds__(256) k_featurize(const float* __restrict__ hist,
+                                                   const RprIrStats* __restrict__ stats, int T, int B, int NC,
                                                    uint16_t* __restrict__ feat, float* __restrict__ e_in)
 {
     __shared__ double red[256];
+    extern __shared__ double sS[];  // [B][T]
     const size_t F = (size_t)T * B * NC;
     const float* h = hist + blockIdx.x * F;
+    uint16_t* f = feat + blockIdx.x * (F + kStatFeatures);
+    // statistics block: the ray population's energies relative to the emitted
+    // energy (log, floored), mean free path, segments per ray, escapes, first bins
+    if (threadIdx.x < kStatFeatures) {
+        const int j = threadIdx.x;
+        float v = 0.f;
+        if (stats) {
+            const RprIrStats& S = stats[blockIdx.x];
+            if (S.n_rays > 0 && S.e_emitted > 0.0) {
+                const double em = S.e_emitted;
+                if (j < 4 * B) {
+                    const int b = j / 4, q = j % 4;
+                    const double x = q == 0 ? S.e_alive_at_stop[b] : q == 1 ? S.e_absorbed[b]
+                                     : q == 2 ? S.e_escaped[b] : S.e_alive_at_bounce_cap[b];
+                    const double fl = q == 0 ? 1e-300 : q == 2 ? 1e-12 : 1e-30;
+                    const double r = log(fmax(x / em, fl));
+                    // [4b]: log of the population's decay exponent; others: log fractions
+                    v = q == 0 ? (float)(log(fmax(-r, 1e-3)) / 5.0) : (float)(r / (q == 3 ? 60.0 : 10.0));
+                } else if (j == 32) {
+                    v = (S.n_finite_segments > 0 && S.seg_len_sum > 0.0)
+                            ? (float)(log(S.seg_len_sum / (double)S.n_finite_segments) / 3.0) : 0.f;
+                } else if (j == 33) {
+                    v = (float)(log((double)S.n_segments / (double)S.n_rays) / 5.0);
+                } else if (j == 34) {
+                    v = (float)((double)S.n_escaped / (double)S.n_rays);
+                } else if (j == 35) {
+                    v = (float)((double)min(S.first_arrival_bin, T) / (double)T);
+                } else if (j == 36) {
+                    v = (float)((double)min(S.first_late_bin, T) / (double)T);
+                }
+            }
+        }
+        f[F + j] = f2bf(v);
+    }
     double s = 0.0;
     for (int i = threadIdx.x; i < T * B; i += 256) s += (double)h[(size_t)i * NC];
     red[threadIdx.x] = s;
@@ -315,15 +357,39 @@ __global__ void __launch_bounds__(256) k_featurize(const float* __restrict__ his
     }
     const double e = red[0] * 3.5449077018110318 / (double)B;  // sqrt(4 pi)
     if (threadIdx.x == 0) e_in[blockIdx.x] = (float)e;
-    uint16_t* f = feat + blockIdx.x * F;
     if (!(e > 0.0)) {
         for (size_t i = threadIdx.x; i < F; i += 256) f[i] = 0;
         return;
     }
+    if ((int)threadIdx.x < B) {
+        const int b = threadIdx.x;
+        double acc = 0.0;
+        for (int m = T - 1; m >= 0; --m) {
+            acc += 3.5449077018110318 * (double)h[((size_t)m * B + b) * NC];
+            sS[b * T + m] = acc;
+        }
+    }
+    __syncthreads();
     const float inv = (float)(1.0 / e);
     for (size_t i = threadIdx.x; i < F; i += 256) {
-        const float u = h[i] * inv;
-        f[i] = f2bf(copysignf(log1pf(kFeatGain * fabsf(u)), u) * kFeatScale);
+        const int k = (int)(i % NC);
+        if (k == 0) {
+            const int b = (int)((i / NC) % B), m = (int)(i / ((size_t)NC * B));
+            const double S0 = sS[b * T];
+            float v = 0.f;
+            if (S0 > 0.0) {
+                if (m == 0) {
+                    v = (float)log(S0 / e);
+                } else {
+                    const double db = 10.0 * log10(sS[b * T + m] / S0);
+                    v = (float)(fmax(db, -60.0) / 60.0);
+                }
+            }
+            f[i] = f2bf(v);
+        } else {
+            const float u = h[i] * inv;
+            f[i] = f2bf(copysignf(log1pf(kFeatGain * fabsf(u)), u) * kFeatScale);
+        }
     }
 }
 
@@ -759,16 +825,19 @@ extern "C" int reverb_model_grads(const RprModel* model, float* grads, int64_t n
     return RPR_OK;
 }
 
-extern "C" int reverb_model_featurize(const float* hist, int32_t n_ir, int32_t n_bins, int32_t n_bands,
-                                      int32_t n_coeffs, uint16_t* features, float* e_in, void* hip_stream)
+extern "C" int reverb_model_featurize(const float* hist, const RprIrStats* stats, int32_t n_ir, int32_t n_bins,
+                                      int32_t n_bands, int32_t n_coeffs, uint16_t* features, float* e_in,
+                                      void* hip_stream)
 {
     if (n_ir < 0 || n_bins < 1 || n_bands < 1 || n_bands > RPR_MAX_BANDS || n_coeffs < 1 ||
         n_coeffs > RPR_MAX_COEFFS)
         return set_error(RPR_EINVAL, "featurize: invalid sizes");
     if (n_ir == 0) return RPR_OK;
     if (!hist || !features || !e_in) return set_error(RPR_EINVAL, "featurize: NULL buffer");
-    hipLaunchKernelGGL(k_featurize, dim3(n_ir), dim3(256), 0, (hipStream_t)hip_stream, hist, n_bins, n_bands,
-                       n_coeffs, features, e_in);
+    if ((int64_t)n_bins * n_bands > kFeatMaxBinsBands)
+        return set_error(RPR_EUNSUPPORTED, "featurize: n_bins x n_bands must be <= %d", kFeatMaxBinsBands);
+    hipLaunchKernelGGL(k_featurize, dim3(n_ir), dim3(256), sizeof(double) * n_bins * n_bands,
+                       (hipStream_t)hip_stream, hist, stats, n_bins, n_bands, n_coeffs, features, e_in);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }

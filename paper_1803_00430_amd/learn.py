@@ -23,8 +23,8 @@ import time
 
 import numpy as np
 
-from . import (Batch, Model, Scene, decode, featurize, params_host, targets, LEARN_DIMS, ST_BAD_FIT,
-               ST_NO_ENERGY, ST_NO_RANGE)
+from . import (Batch, Model, Scene, decode, featurize, params_host, targets, LEARN_DIMS, STAT_FEATURES,
+               ST_BAD_FIT, ST_NO_ENERGY, ST_NO_RANGE)
 
 SH_ORDER = 3
 MAX_BOUNCES = 1000
@@ -54,7 +54,7 @@ def trace_rooms(scenes, rooms, *, n_rays, n_bins, bin_width_s, seed_offset, want
     nc = (SH_ORDER + 1) ** 2
     nb = scenes[0].n_bands
     if want_features:
-        out["features"] = torch.empty((n, n_bins * nb * nc), dtype=torch.int16, device=device)
+        out["features"] = torch.empty((n, n_bins * nb * nc + STAT_FEATURES), dtype=torch.int16, device=device)
         out["e_in"] = torch.empty(n, dtype=torch.float32, device=device)
     pairs = room_pairs(rooms, n_rays, seed_offset)
     for c0 in range(0, n, chunk):
@@ -65,7 +65,7 @@ def trace_rooms(scenes, rooms, *, n_rays, n_bins, bin_width_s, seed_offset, want
                   use_graph=False, late=False, device=device)
         b.run()
         if want_features:
-            f, e = featurize(b.hist, n_bins, nb, nc)
+            f, e = featurize(b.hist, n_bins, nb, nc, stats=b.stats)
             out["features"][c0:c1] = f
             out["e_in"][c0:c1] = e
         out["params"][c0:c1] = b.params
@@ -143,3 +143,86 @@ def rt60_error(params, ref_params, n_bands):
     est_ok = (rt > 0) & ((st & INVALID_FIT) == 0)
     err = np.where(est_ok, np.abs(rt - rr) / np.where(ref_ok, rr, 1.0), 1.0)
     return np.where(ref_ok, err, np.nan)
+
+
+def rt60_error_summary(err):
+    e = err[np.isfinite(err)]
+    return dict(mean=float(e.mean()) if e.size else float("nan"),
+                p90=float(np.percentile(e, 90)) if e.size else float("nan"), n=int(e.size))
+
+
+def choose_kappa(sigma_max, err_learned, err_fallback, target=0.05):
+    """Largest threshold kappa on the per-room maximum sigma such that the
+    mean error, with rooms above kappa taking the fallback's error, stays at
+    or below `target` (errors [rooms][bands], NaN where undefined).  Returns
+    (kappa, fallback fraction, mean error); kappa = 0 sends every room to
+    the fallback."""
+    order = np.argsort(sigma_max)
+    el = np.nan_to_num(err_learned, nan=0.0)
+    ef = np.nan_to_num(err_fallback, nan=0.0)
+    cnt = np.isfinite(err_learned).sum(axis=1)
+    n = len(order)
+    best = (0.0, 1.0, float(ef.sum() / max(1, cnt.sum())))
+    # rooms sorted by sigma: the first j use the network, the rest fall back
+    cum_l = np.concatenate([[0.0], np.cumsum(el[order].sum(axis=1))])
+    cum_f = np.concatenate([[0.0], np.cumsum(ef[order].sum(axis=1))])
+    total = max(1, cnt.sum())
+    for j in range(1, n + 1):
+        mean = (cum_l[j] + (cum_f[n] - cum_f[j])) / total
+        if mean <= target:
+            best = (float(sigma_max[order[j - 1]]), 1.0 - j / n, float(mean))
+    return best
+
+
+def timed_plain(scenes, rooms, n_rays, *, steps=3, device="cuda"):
+    """IRs per second of the plain method at n_rays per pair: one graph-
+    captured batch (reset, trace, estimate) over all rooms, replayed `steps`
+    times after one warm-up.  Returns (IRs/s, params of the last replay)."""
+    import torch
+    b = Batch(scenes, [dict(p, pair_id=k) for k, p in enumerate(room_pairs(rooms, n_rays, SEED_SWEEP + n_rays))],
+              n_bins=CONVERGED["n_bins"], sh_order=SH_ORDER, bin_width_s=CONVERGED["bin_width_s"], autotune=False,
+              use_graph=True, late=False, device=device)
+    b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    params = b.params.clone()
+    b.close()
+    return len(rooms) / dt, params
+
+
+def learned_estimate(model, scenes, rooms, kappa, n_fallback, *, cheap=None, device="cuda"):
+    """The learned path for a set of rooms: a 1k-ray trace (one graph replay
+    of `cheap`, a planned Batch over the rooms at INPUT bins, built here when
+    None), features, network, decoding; rooms whose uncertainty exceeds kappa
+    are traced again at n_fallback rays by the plain method and their
+    parameters replace the network's.  Returns (params, uncertain mask,
+    cheap batch)."""
+    import torch
+    nb = scenes[0].n_bands
+    nc = (SH_ORDER + 1) ** 2
+    if cheap is None:
+        cheap = Batch(scenes, [dict(p, pair_id=k) for k, p in enumerate(room_pairs(rooms, 1024, SEED_INPUT))],
+                      n_bins=INPUT["n_bins"], sh_order=SH_ORDER, bin_width_s=INPUT["bin_width_s"], autotune=False,
+                      use_graph=True, late=False, device=device)
+    cheap.run()
+    f, e = featurize(cheap.hist, INPUT["n_bins"], nb, nc, stats=cheap.stats)
+    params, sigma, unc = predict(model, f, e, nb, kappa)
+    idx = torch.nonzero(unc).flatten().to(torch.int32)
+    n_fb = int(idx.numel())  # synchronises
+    if n_fb:
+        sel = idx.cpu().numpy()
+        sub_scenes = [scenes[i] for i in sel]
+        pairs = [dict(p, scene=k, pair_id=k) for k, p in
+                 enumerate(room_pairs([rooms[i] for i in sel], n_fallback, SEED_SWEEP + n_fallback))]
+        fb = Batch(sub_scenes, pairs, n_bins=CONVERGED["n_bins"], sh_order=SH_ORDER,
+                   bin_width_s=CONVERGED["bin_width_s"], autotune=False, use_graph=False, late=False, device=device)
+        fb.run()
+        from . import params_scatter
+        params_scatter(fb.params, idx, params)
+        torch.cuda.synchronize()
+        fb.close()
+    return params, unc, cheap

@@ -40,8 +40,8 @@ def test_invalid_arguments_fail_before_any_launch():
     assert b"multiple of 32" in L.last_error()
     dims = (C.c_int32 * 3)(64, 64, 32)
     assert L.reverb_model_create(dims, 2, 0, 0, None, C.byref(out)) == -1
-    assert L.reverb_model_featurize(None, 1, 0, 4, 16, None, None, None) == -1
-    assert L.reverb_model_featurize(None, 0, 10, 4, 16, None, None, None) == 0  # empty: no-op
+    assert L.reverb_model_featurize(None, None, 1, 0, 4, 16, None, None, None) == -1
+    assert L.reverb_model_featurize(None, None, 0, 10, 4, 16, None, None, None) == 0  # empty: no-op
     assert L.reverb_model_decode(None, None, 1, 9, 1.0, None, None, None, None) == -1
     assert L.reverb_model_forward(None, None, 1, None, None) == -1
 

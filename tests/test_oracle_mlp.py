@@ -119,7 +119,7 @@ def test_featurize_invariances_and_values():
     H = g.normal(0, 1e-6, (200, 4, 16))
     H[:, :, 0] = np.abs(H[:, :, 0])
     f, e = M.featurize(H)
-    assert f.shape == (200 * 4 * 16,) and e > 0
+    assert f.shape == (200 * 4 * 16 + M.STAT_FEATURES,) and e > 0 and not f[-M.STAT_FEATURES:].any()
     # scale invariance (the level is carried by e_in, not by the features)
     f2, e2 = M.featurize(H * 37.0)
     assert np.allclose(f2, f, rtol=1e-12, atol=1e-14) and e2 == pytest.approx(37.0 * e, rel=1e-14)
@@ -129,17 +129,70 @@ def test_featurize_invariances_and_values():
     H2[9, 1, 3] = 0.0
     f3, _ = M.featurize(H2)
     assert f3[(5 * 4 + 2) * 16 + 7] == -f[(5 * 4 + 2) * 16 + 7] and f3[(9 * 4 + 1) * 16 + 3] == 0.0
-    # a value with FEAT_GAIN |u| = e - 1 maps to exactly FEAT_SCALE
-    H3 = np.zeros((2, 1, 1))
+    # a directional value with FEAT_GAIN |u| = e - 1 maps to exactly FEAT_SCALE
+    H3 = np.zeros((2, 1, 2))
     H3[0, 0, 0] = 1.0
-    e3 = math.sqrt(4 * math.pi)
-    a = (math.e - 1.0) / M.FEAT_GAIN  # wanted u of bin 1; e_in = sqrt(4 pi) (1 + H1), so H1 = a e3 / (1 - a e3)
-    H3[1, 0, 0] = a * e3 / (1.0 - a * e3)
-    f4, e4 = M.featurize(H3)
-    assert f4[1] == pytest.approx(M.FEAT_SCALE, rel=1e-12)
+    e3 = math.sqrt(4 * math.pi)  # e_in of H3
+    H3[1, 0, 1] = (math.e - 1.0) / M.FEAT_GAIN * e3
+    f4, _ = M.featurize(H3)
+    assert f4[3] == pytest.approx(M.FEAT_SCALE, rel=1e-12)
     # no energy: zero features, e_in = 0
     f5, e5 = M.featurize(np.zeros((3, 2, 4)))
     assert e5 == 0.0 and not f5.any()
+
+
+def test_featurize_decay_channel_closed_form():
+    """Channel 0 of a pure exponential decay I[m] = r^m over T bins: the
+    backward integral is S[m] = (r^m - r^T) / (1 - r), so the curve is
+    10 log10((r^m - r^T) / (1 - r^T)) / 60, clipped at -1; bin 0 holds
+    ln(S_b[0] / e_in), 0 when all bands are equal and ln 2 - ln 1.5 for a
+    band twice as loud as the other."""
+    T, r = 120, 0.9
+    m = np.arange(T)
+    I = r ** m
+    H = np.zeros((T, 2, 4))
+    H[:, 0, 0] = I / math.sqrt(4 * math.pi)
+    H[:, 1, 0] = 2 * I / math.sqrt(4 * math.pi)
+    f, e = M.featurize(H)
+    f = f[:-M.STAT_FEATURES].reshape(T, 2, 4)
+    want = np.maximum(10 * np.log10((r ** m[1:] - r ** T) / (1 - r ** T)), -60.0) / 60.0
+    assert np.allclose(f[1:, 0, 0], want, rtol=1e-12, atol=1e-14)
+    assert np.allclose(f[1:, 1, 0], want, rtol=1e-12, atol=1e-14)
+    assert np.any(want == -1.0) and np.any(want > -1.0)
+    assert f[0, 0, 0] == pytest.approx(math.log(1 / 1.5), rel=1e-12)
+    assert f[0, 1, 0] == pytest.approx(math.log(2 / 1.5), rel=1e-12)
+    # a band without energy has a zero decay channel
+    H[:, 1, 0] = 0.0
+    f, _ = M.featurize(H)
+    assert not f[:-M.STAT_FEATURES].reshape(T, 2, 4)[:, 1, 0].any()
+
+
+def test_featurize_statistics_by_hand():
+    st = dict(n_rays=1000, e_emitted=0.5, n_segments=50000, n_finite_segments=49000, seg_len_sum=49000 * 7.0,
+              n_escaped=10, first_arrival_bin=12, first_late_bin=2**31 - 1,
+              e_alive_at_stop=np.array([0.5 * math.exp(-30.0), 0.0]), e_absorbed=np.array([0.25, 0.5]),
+              e_escaped=np.array([0.0, 0.05]), e_alive_at_bounce_cap=np.array([0.0, 0.5 * math.exp(-6.0)]))
+    H = np.zeros((40, 2, 4))
+    H[5, :, 0] = 1.0
+    f, e = M.featurize(H, st)
+    s = f[-M.STAT_FEATURES:]
+    assert s[0] == pytest.approx(math.log(30.0) / 5, rel=1e-12)          # alive, band 0: ln of the decay exponent
+    assert s[4] == pytest.approx(math.log(-math.log(1e-300)) / 5, rel=1e-12)  # alive, band 1: floored
+    assert s[1] == pytest.approx(math.log(0.5) / 10, rel=1e-12) and s[5] == 0.0  # absorbed
+    assert s[2] == pytest.approx(math.log(1e-12) / 10, rel=1e-12)        # escaped, band 0: floored
+    assert s[6] == pytest.approx(math.log(0.1) / 10, rel=1e-12)
+    assert s[7] == pytest.approx(-6.0 / 60, rel=1e-12)                   # alive at the bounce cap, band 1
+    assert s[32] == pytest.approx(math.log(7.0) / 3, rel=1e-12)          # mean free path
+    assert s[33] == pytest.approx(math.log(50.0) / 5, rel=1e-12)         # segments per ray
+    assert s[34] == pytest.approx(0.01, rel=1e-12)
+    assert s[35] == pytest.approx(12 / 40, rel=1e-12) and s[36] == 1.0
+    assert not s[8:32].any() and not s[37:].any()
+    # no decay at all (alive = emitted): the exponent is floored at 1e-3
+    f1, _ = M.featurize(H, dict(st, e_alive_at_stop=np.array([0.5, 0.5])))
+    assert f1[-M.STAT_FEATURES] == pytest.approx(math.log(1e-3) / 5, rel=1e-12)
+    # the statistics do not depend on the histogram, nor the histogram part on them
+    f0, _ = M.featurize(H)
+    assert np.array_equal(f[:-M.STAT_FEATURES], f0[:-M.STAT_FEATURES])
 
 
 def test_targets_and_decode_by_hand():
