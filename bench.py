@@ -51,9 +51,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=2048, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("city", "batch"), default="city",
+    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital"), default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
-                         "16 scenes in one persistent graph-captured launch")
+                         "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
+                         "learned estimator vs plain ray trace (builds its dataset and trains first)")
+    ap.add_argument("--learn-train", type=int, default=8192, help="training rooms of the learn workload")
+    ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
+    ap.add_argument("--learn-epochs", type=int, default=30)
+    ap.add_argument("--frames", type=int, default=8, help="frames of the hospital workload")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
                          "(a known-size reference for the HBM byte counters)")
@@ -119,6 +124,164 @@ def run_batch(a):
     print(json.dumps(out), flush=True)
 
 
+def run_learn(a):
+    """The learned reverb estimator against the plain method (see
+    paper_1803_00430_amd/learn.py).  Rooms: shoeboxes and L-rooms (dims
+    U[3,40] m, per-band absorption U[0.02,0.6], scattering U[0.1,0.9]).
+    Training set: `--learn-train` rooms, input = 1,024-ray trace (200 x 10 ms
+    bins x 4 bands x 16 SH coefficients + 64 trace statistics), target = the
+    estimator's output on an independent 262,144-ray trace.  Error = mean over
+    held-out rooms x bands of |RT60 - RT60_ref| / RT60_ref, RT60_ref from a
+    third independent 262,144-ray trace.  Plain: the smallest ray count of a
+    sweep whose error is <= 5% (N*), timed as one graph-captured batch over the
+    held-out rooms.  Learned: 1k-ray batch + features + network + decoding,
+    rooms whose sigma exceeds kappa (chosen on a calibration split for <= 5%)
+    re-traced at N*; timed end to end."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+    from paper_1803_00430_amd import learn as L
+
+    q = a.quiet
+    t_all = time.perf_counter()
+    rooms = {"train": [R.learn_room(10000 + i) for i in range(a.learn_train)],
+             "cal": [R.learn_room(150000 + i) for i in range(a.learn_eval)],
+             "eval": [R.learn_room(200000 + i) for i in range(a.learn_eval)]}
+    scenes = {k: L.make_scenes(v) for k, v in rooms.items()}
+    t0 = time.perf_counter()
+    data = L.make_dataset(scenes["train"], rooms["train"], chunk=1024, log=lambda m: log(m, q))
+    t_data = time.perf_counter() - t0
+    cal = L.make_dataset(scenes["cal"], rooms["cal"], chunk=1024)
+    refs = {k: L.trace_rooms(scenes[k], rooms[k], n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024,
+                             **L.CONVERGED)["params"] for k in ("cal", "eval")}
+    sweep = {}
+    for N in (1024, 4096, 16384, 32768, 65536, 131072, 262144):
+        tr = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=N, seed_offset=L.SEED_SWEEP + N, chunk=1024,
+                           **L.CONVERGED)
+        sweep[N] = L.rt60_error_summary(L.rt60_error(tr["params"], refs["eval"], 4))
+        log(f"plain N={N}: {sweep[N]}", q)
+    ok = [N for N in sweep if sweep[N]["mean"] <= 0.05]
+    n_star = min(ok) if ok else max(sweep)
+    model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    t0 = time.perf_counter()
+    losses = L.train(model, data, epochs=a.learn_epochs, lr=1e-3, weight_decay=1e-2, batch=64)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    fb = L.trace_rooms(scenes["cal"], rooms["cal"], n_rays=n_star, seed_offset=L.SEED_SWEEP + n_star, chunk=1024,
+                       **L.CONVERGED)
+    prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
+    kappa, fb_frac_cal, err_cal = L.choose_kappa(sig.max(dim=1).values.cpu().numpy(),
+                                                 L.rt60_error(prm, refs["cal"], 4),
+                                                 L.rt60_error(fb["params"], refs["cal"], 4))
+    # held-out: ungated network error, then the gated path, timed
+    cheap_data = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=1024, seed_offset=L.SEED_INPUT,
+                               want_features=True, chunk=1024, **L.INPUT)
+    prm, _, _ = L.predict(model, cheap_data["features"], cheap_data["e_in"], 4, 1e9)
+    err_net = L.rt60_error_summary(L.rt60_error(prm, refs["eval"], 4))
+    prm, unc, cheap = L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star)
+    err_learned = L.rt60_error_summary(L.rt60_error(prm, refs["eval"], 4))
+    fb_frac = float(unc.float().mean())
+    for _ in range(a.warmup):
+        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star, cheap=cheap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star, cheap=cheap)
+    torch.cuda.synchronize()
+    t_learned = (time.perf_counter() - t0) / a.steps
+    ips_plain, _ = L.timed_plain(scenes["eval"], rooms["eval"], n_star, steps=a.steps)
+    n_ev = len(rooms["eval"])
+    out = {
+        "metric": "IRs/s at <=5% RT60 error, learned vs plain ray trace", "value": n_ev / t_learned,
+        "unit": "IRs/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": t_learned * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 trace, bf16 mlp",
+        "data": "synthetic",
+        "config": {"workload": f"learn: {n_ev} held-out shoebox/L-rooms (dims U[3,40] m); step = learned estimate "
+                               f"of every room (1k-ray trace + MLP + fallback at N*); "
+                               f"{a.learn_train} training rooms (100k named for this workload), 262,144-ray "
+                               f"targets and references", "train_rooms": a.learn_train, "eval_rooms": n_ev},
+        "plain": {"n_star": n_star, "irs_per_s": ips_plain, "sweep": {str(k): v for k, v in sweep.items()}},
+        "learned": {"irs_per_s": n_ev / t_learned, "rt60_err": err_learned, "fallback_fraction": fb_frac,
+                    "kappa": kappa, "network_only_rt60_err": err_net, "cal_fallback_fraction": fb_frac_cal,
+                    "cal_rt60_err": err_cal},
+        "speedup_learned_vs_plain": (n_ev / t_learned) / ips_plain,
+        "training": {"dataset_s": t_data, "dataset_segments": data["segments"], "train_s": t_train,
+                     "epochs": a.learn_epochs, "final_loss": losses[-1]},
+        "total_s": time.perf_counter() - t_all,
+    }
+    model.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_hospital(a):
+    """Large interactive scene: a hospital-like interior of ~1M triangles
+    (rooms 4-12 m on a grid, corridors, doorways, clutter), 64 sources moving
+    along the corridors at 1.4 m/s, one listener; per frame (0.1 s of motion)
+    every source is traced with 131,072 rays, 200 bounces, SH order 3, 4
+    bands, 3000 bins of 1 ms, and its reverb parameters are estimated.  The
+    scene's BVH is built once (static geometry).  Reports per-frame p50/p99
+    latency and IRs/s of the plain method."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+
+    q = a.quiet
+    dev = torch.device("cuda:0")
+    cfg = R.hospital_config()
+    t0 = time.perf_counter()
+    scene = P.Scene.from_dict(cfg, device=dev)
+    build_ms = (time.perf_counter() - t0) * 1e3
+    S = len(cfg["sources"])
+    N, K, T, n, dt = cfg["n_rays"], cfg["max_bounces"], cfg["n_bins"], cfg["sh_order"], cfg["bin_width_s"]
+    B = cfg["absorption"].shape[1]
+    hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
+    params = P.alloc_params(S, device=dev)
+    prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+    x_max = float(cfg["verts"][:, 0].max()) - 2.5
+    g = np.random.default_rng(7)
+    heading = np.where(g.uniform(0, 1, S) < 0.5, -1.0, 1.0)
+
+    def sources_at(f):
+        src = cfg["sources"].astype(np.float64).copy()
+        x = src[:, 0] - 0.5 + heading * 1.4 * 0.1 * f
+        period = 2.0 * (x_max - 1.0)
+        x = np.mod(x, period)
+        src[:, 0] = 0.5 + np.where(x <= period / 2, x, period - x)
+        return src.astype(np.float32)
+
+    def frame(f):
+        P.trace_ir(scene, sources_at(f), cfg["listener"], cfg["radius"], prm, hist, late, stats)
+        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+
+    for f in range(a.warmup):
+        frame(-1 - f)
+    torch.cuda.synchronize()
+    times, segs = [], 0
+    for f in range(a.frames):
+        t1 = time.perf_counter()
+        frame(f)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        segs += int(P.stats_host(stats)["n_segments"].sum())
+        log(f"frame {f}: {times[-1] * 1e3:.1f} ms", q)
+    times = np.array(times)
+    ms = times.mean() * 1e3
+    out = {
+        "metric": "per-frame latency p50/p99 and IRs/s (plain ray trace)", "value": S / times.mean(),
+        "unit": "IRs/s", "n_gpus": 1, "steps": a.frames, "warmup": a.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"hospital: {len(cfg['tris'])} triangles, {S} moving sources x {N} rays, "
+                               f"{K} bounces, SH order {n}, {B} bands, {T} x 1 ms bins; step = one frame "
+                               f"(trace + estimate of every source; BVH built once)"},
+        "p50_ms": float(np.percentile(times, 50) * 1e3), "p99_ms": float(np.percentile(times, 99) * 1e3),
+        "build_ms": build_ms, "ray_bounces_per_s": segs / times.sum(),
+    }
+    scene.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -137,6 +300,12 @@ def main():
     torch.cuda.set_device(dev)
     if a.workload == "batch":
         run_batch(a)
+        return
+    if a.workload == "learn":
+        run_learn(a)
+        return
+    if a.workload == "hospital":
+        run_hospital(a)
         return
     cfg = R.city_config()
     S = len(cfg["sources"])

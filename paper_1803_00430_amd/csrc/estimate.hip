@@ -28,6 +28,7 @@ struct EstArgs {
     int n_ir, T, nb, nc;
     double dt;
     int rt60_source, tail_iters;
+    int vec4;  // nc == 16 and 16-byte aligned rows
     RprReverbParams* out;
 };
 
@@ -84,9 +85,13 @@ struct SbSource {
             const int m = ch * kWave + lane;
             const double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
             const int top = min(kWave - 1, m_last - ch * kWave);
+            // each lane's value in turn, read as a scalar (no LDS round trip per step)
+            const uint64_t vb = (uint64_t)__double_as_longlong(v);
+            const uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
             double mine = 0.0;
             for (int j = top; j >= 0; --j) {
-                carry += __shfl(v, j, kWave);
+                const uint32_t l = __builtin_amdgcn_readlane(lo, j), h = __builtin_amdgcn_readlane(hi, j);
+                carry += __longlong_as_double((long long)(((uint64_t)h << 32) | l));
                 if (lane == j) mine = carry;
             }
             if (m <= m_last) visit(m, mine);
@@ -176,14 +181,33 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
     double dsum[RPR_MAX_COEFFS];
 #pragma unroll
     for (int c = 0; c < RPR_MAX_COEFFS; ++c) dsum[c] = 0.0;
-    for (int m = lane; m < T; m += kWave) {
-        const double v = I_fit(a, H, HL, m, b);
-        if (v > 0.0) m_last = m;
-        const float* row = H + ((size_t)m * nb + b) * nc;
-        tot_all += 3.5449077018110318 * (double)row[0];
+    if (a.vec4) {
+        // 16 coefficients per (bin, band): four 16-byte loads per row
+#pragma unroll 2
+        for (int m = lane; m < T; m += kWave) {
+            const float4* row = reinterpret_cast<const float4*>(H + ((size_t)m * nb + b) * 16);
+            const float4 q[4] = {row[0], row[1], row[2], row[3]};
+            const double v = a.rt60_source == 1 ? (double)HL[(size_t)m * nb + b] : 3.5449077018110318 * (double)q[0].x;
+            if (v > 0.0) m_last = m;
+            tot_all += 3.5449077018110318 * (double)q[0].x;
 #pragma unroll
-        for (int c = 0; c < RPR_MAX_COEFFS; ++c)
-            if (c < nc) dsum[c] += (double)row[c];
+            for (int c = 0; c < 4; ++c) {
+                dsum[4 * c] += (double)q[c].x;
+                dsum[4 * c + 1] += (double)q[c].y;
+                dsum[4 * c + 2] += (double)q[c].z;
+                dsum[4 * c + 3] += (double)q[c].w;
+            }
+        }
+    } else {
+        for (int m = lane; m < T; m += kWave) {
+            const double v = I_fit(a, H, HL, m, b);
+            if (v > 0.0) m_last = m;
+            const float* row = H + ((size_t)m * nb + b) * nc;
+            tot_all += 3.5449077018110318 * (double)row[0];
+#pragma unroll
+            for (int c = 0; c < RPR_MAX_COEFFS; ++c)
+                if (c < nc) dsum[c] += (double)row[c];
+        }
     }
     m_last = wmax(m_last);
     tot_all = wsum(tot_all);
@@ -267,8 +291,10 @@ extern "C" int estimate_reverb(const float* hist, const float* hist_late, const 
     if (e.rt60_source == 1 && !hist_late)
         return set_error(RPR_EINVAL, "estimate_reverb: rt60_source=1 needs hist_late");
     if (e.tail_iters < 0 || e.tail_iters > 100) return set_error(RPR_EINVAL, "estimate_reverb: bad tail_iters");
-    EstArgs a{hist, hist_late, stats, n_ir, n_bins, n_bands, (sh_order + 1) * (sh_order + 1), (double)bin_width_s,
-              e.rt60_source, e.tail_iters, out};
+    const int nc = (sh_order + 1) * (sh_order + 1);
+    const int vec4 = nc == 16 && ((uintptr_t)hist % 16) == 0;
+    EstArgs a{hist, hist_late, stats, n_ir, n_bins, n_bands, nc, (double)bin_width_s, e.rt60_source, e.tail_iters,
+              vec4, out};
     const long long grid = (long long)n_ir * n_bands;
     if (grid > 0x7FFFFFFF) return set_error(RPR_EUNSUPPORTED, "estimate_reverb: too many IRs");
     if (n_bins <= kLdsBins)

@@ -83,17 +83,36 @@ def make_scenes(rooms, device="cuda"):
     return [Scene.from_dict(r, device=device) for r in rooms]
 
 
-def make_dataset(scenes, rooms, *, n_input=1024, n_target=262144, chunk=512, log=None):
-    """Features of an n_input-ray trace (200 x 10 ms bins) and the targets
-    from the reverb parameters of an independent n_target-ray trace
-    (2000 x 1 ms bins).  Returns dict(features, e_in, t, w, target_params)."""
+def make_dataset(scenes, rooms, *, n_input=1024, n_target=262144, inputs_per_room=1, chunk=512, log=None):
+    """Features of n_input-ray traces (200 x 10 ms bins) and the targets from
+    the reverb parameters of an independent n_target-ray trace (2000 x 1 ms
+    bins).  With inputs_per_room = k > 1 every room is traced k times at
+    n_input rays with independent keys (SEED_INPUT + j 2^36), giving k rows
+    that share one converged target: the network then sees several noisy
+    views of each room.  Returns dict(features, e_in, t, w, target_params)
+    with rows ordered room-major."""
+    import torch
     nb = scenes[0].n_bands
-    cheap = trace_rooms(scenes, rooms, n_rays=n_input, seed_offset=SEED_INPUT, want_features=True, chunk=chunk,
-                        log=log, **INPUT)
     conv = trace_rooms(scenes, rooms, n_rays=n_target, seed_offset=SEED_TARGET, chunk=chunk, log=log, **CONVERGED)
-    t, w = targets(conv["params"], cheap["e_in"], nb)
-    return dict(features=cheap["features"], e_in=cheap["e_in"], t=t, w=w, target_params=conv["params"],
-                trace_seconds=cheap["seconds"] + conv["seconds"], segments=cheap["segments"] + conv["segments"])
+    feats, e_ins, ts, ws = [], [], [], []
+    secs, segs = conv["seconds"], conv["segments"]
+    for j in range(inputs_per_room):
+        cheap = trace_rooms(scenes, rooms, n_rays=n_input, seed_offset=SEED_INPUT + (j << 36), want_features=True,
+                            chunk=chunk, log=log, **INPUT)
+        t, w = targets(conv["params"], cheap["e_in"], nb)
+        feats.append(cheap["features"])
+        e_ins.append(cheap["e_in"])
+        ts.append(t)
+        ws.append(w)
+        secs += cheap["seconds"]
+        segs += cheap["segments"]
+    k = inputs_per_room
+
+    def interleave(xs):
+        return torch.stack(xs, dim=1).reshape((-1,) + tuple(xs[0].shape[1:])) if k > 1 else xs[0]
+
+    return dict(features=interleave(feats), e_in=interleave(e_ins), t=interleave(ts), w=interleave(ws),
+                target_params=conv["params"], trace_seconds=secs, segments=segs)
 
 
 def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-4, seed=0, log=None):
