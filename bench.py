@@ -57,7 +57,8 @@ def parse():
                          "learned estimator vs plain ray trace (builds its dataset and trains first)")
     ap.add_argument("--learn-train", type=int, default=8192, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
-    ap.add_argument("--learn-epochs", type=int, default=30)
+    ap.add_argument("--learn-epochs", type=int, default=16)
+    ap.add_argument("--learn-views", type=int, default=4, help="1k-ray input traces per training room")
     ap.add_argument("--frames", type=int, default=8, help="frames of the hospital workload")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
@@ -128,9 +129,10 @@ def run_learn(a):
     """The learned reverb estimator against the plain method (see
     paper_1803_00430_amd/learn.py).  Rooms: shoeboxes and L-rooms (dims
     U[3,40] m, per-band absorption U[0.02,0.6], scattering U[0.1,0.9]).
-    Training set: `--learn-train` rooms, input = 1,024-ray trace (200 x 10 ms
-    bins x 4 bands x 16 SH coefficients + 64 trace statistics), target = the
-    estimator's output on an independent 262,144-ray trace.  Error = mean over
+    Training set: `--learn-train` rooms x `--learn-views` inputs, input = a
+    1,024-ray trace (200 x 10 ms bins x 4 bands x 16 SH coefficients + 64
+    trace statistics), target = the estimator's output on an independent
+    262,144-ray trace.  Error = mean over
     held-out rooms x bands of |RT60 - RT60_ref| / RT60_ref, RT60_ref from a
     third independent 262,144-ray trace.  Plain: the smallest ray count of a
     sweep whose error is <= 5% (N*), timed as one graph-captured batch over the
@@ -150,7 +152,8 @@ def run_learn(a):
              "eval": [R.learn_room(200000 + i) for i in range(a.learn_eval)]}
     scenes = {k: L.make_scenes(v) for k, v in rooms.items()}
     t0 = time.perf_counter()
-    data = L.make_dataset(scenes["train"], rooms["train"], chunk=1024, log=lambda m: log(m, q))
+    data = L.make_dataset(scenes["train"], rooms["train"], inputs_per_room=a.learn_views, chunk=1024,
+                          log=lambda m: log(m, q))
     t_data = time.perf_counter() - t0
     cal = L.make_dataset(scenes["cal"], rooms["cal"], chunk=1024)
     refs = {k: L.trace_rooms(scenes[k], rooms[k], n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024,
@@ -165,7 +168,7 @@ def run_learn(a):
     n_star = min(ok) if ok else max(sweep)
     model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
     t0 = time.perf_counter()
-    losses = L.train(model, data, epochs=a.learn_epochs, lr=1e-3, weight_decay=1e-2, batch=64)
+    losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     fb = L.trace_rooms(scenes["cal"], rooms["cal"], n_rays=n_star, seed_offset=L.SEED_SWEEP + n_star, chunk=1024,

@@ -383,6 +383,18 @@ int reverb_model_train_step(RprModel* model, const uint16_t* features, int64_t n
  *   params device [n], sigma device [n][B] f32 or NULL, uncertain device [n] i32 or NULL */
 int reverb_model_decode(const float* out, const float* e_in, int64_t n, int32_t n_bands, float kappa,
                         RprReverbParams* params, float* sigma, int32_t* uncertain, void* hip_stream);
+/* Input normalisation of the network, fitted on a training set of n rows of
+ * BF16 features [n][F] (device): mean[f] (FP64 accumulation) and
+ * scale[f] = gain / max(std[f], 1e-3) with the population std; gain =
+ * sqrt((F - F_hist) / F_hist) for the first F_hist features (the histogram)
+ * and 1 for the rest (the statistics), so that both groups enter with the
+ * same total variance.  mean, scale device [F] f32.  0 <= F_hist < F. */
+int reverb_model_feature_stats(const uint16_t* features, int64_t n, int32_t F, int32_t F_hist, float* mean,
+                               float* scale, void* hip_stream);
+/* In place on n rows of BF16 features [n][F] (device): x = (x - shift[f]) *
+ * scale[f], rounded to BF16 (shift, scale device [F] f32). */
+int reverb_model_normalize(uint16_t* features, int64_t n, int32_t F, const float* shift, const float* scale,
+                           void* hip_stream);
 /* dst[idx[i]] = src[i] for i < n (device arrays): merges the parameters of
  * re-traced pairs into a learned result. */
 int reverb_params_scatter(const RprReverbParams* src, const int32_t* idx, int64_t n, RprReverbParams* dst,

@@ -148,6 +148,8 @@ SIGNATURES = {
     "reverb_model_train_step": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, C.POINTER(AdamParams), _vp, _vp]),
     "reverb_model_decode": (C.c_int, [_vp, _vp, _i64, _i32, C.c_float, _vp, _vp, _vp, _vp]),
     "reverb_params_scatter": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "reverb_model_feature_stats": (C.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
+    "reverb_model_normalize": (C.c_int, [_vp, _i64, _i32, _vp, _vp, _vp]),
     "last_error": (C.c_char_p, []),
     "rpr_version": (C.c_char_p, []),
 }
@@ -402,6 +404,7 @@ class Model:
         self._h = h
         self.dims = tuple(int(d) for d in dims)
         self.max_batch = int(max_batch)
+        self.input_norm = None  # (shift, scale) device tensors, set when the model is trained
 
     def info(self) -> dict:
         mi = ModelInfo()
@@ -499,6 +502,24 @@ def decode(out, e_in, n_bands, kappa, stream=None):
     _check(lib().reverb_model_decode(_ptr(out), _ptr(e_in), n, int(n_bands), float(kappa), _ptr(params),
                                      _ptr(sigma), _ptr(unc), _stream(stream)))
     return params, sigma, unc
+
+
+def feature_stats(features, n_hist, stream=None):
+    """(mean [F], scale [F]) of the input normalisation fitted on `features`."""
+    import torch
+    n, F = features.shape
+    mean = torch.empty(F, dtype=torch.float32, device=features.device)
+    scale = torch.empty(F, dtype=torch.float32, device=features.device)
+    _check(lib().reverb_model_feature_stats(_ptr(features), n, F, int(n_hist), _ptr(mean), _ptr(scale),
+                                            _stream(stream)))
+    return mean, scale
+
+
+def normalize(features, shift, scale, stream=None):
+    """In place: features = (features - shift) * scale (BF16)."""
+    n, F = features.shape
+    _check(lib().reverb_model_normalize(_ptr(features), n, F, _ptr(shift), _ptr(scale), _stream(stream)))
+    return features
 
 
 def params_scatter(src, idx, dst, stream=None):

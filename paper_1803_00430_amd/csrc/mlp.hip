@@ -279,6 +279,41 @@ __global__ void k_to_bf16(const float* __restrict__ src, long long n, uint16_t* 
         dst[i] = f2bf(src[i]);
 }
 
+// Per-feature mean (FP64, fixed order) and scale = gain / max(std, 1e-3)
+// over n rows of BF16 features [n][F]; gain = sqrt((F - F_hist) / F_hist) for
+// the first F_hist (histogram) features and 1 for the rest.  One thread per
+// feature, two passes over the rows (mean, then squared deviations).
+__global__ void k_feature_stats(const uint16_t* __restrict__ x, long long n, int F, int F_hist,
+                                float* __restrict__ mean, float* __restrict__ scale)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= F) return;
+    double s = 0.0;
+    for (long long i = 0; i < n; ++i) s += (double)bf2f(x[(size_t)i * F + f]);
+    const double mu = s / (double)n;
+    double v = 0.0;
+    for (long long i = 0; i < n; ++i) {
+        const double d = (double)bf2f(x[(size_t)i * F + f]) - mu;
+        v += d * d;
+    }
+    const double sd = sqrt(v / (double)n);
+    const double gain = (f < F_hist && F_hist > 0) ? sqrt((double)(F - F_hist) / (double)F_hist) : 1.0;
+    mean[f] = (float)mu;
+    scale[f] = (float)(gain / fmax(sd, 1e-3));
+}
+
+// x = (x - shift[f]) * scale[f], rounded to BF16, in place.
+__global__ void k_normalize(uint16_t* __restrict__ x, long long n, int F, const float* __restrict__ shift,
+                            const float* __restrict__ scale)
+{
+    const long long total = n * (long long)F;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int f = (int)(i % F);
+        x[i] = f2bf((bf2f(x[i]) - shift[f]) * scale[f]);
+    }
+}
+
 __global__ void k_zero_f32(float* __restrict__ p, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -919,6 +954,29 @@ extern "C" int reverb_model_decode(const float* out, const float* e_in, int64_t 
     if (!out || !e_in || !params) return set_error(RPR_EINVAL, "decode: NULL buffer");
     hipLaunchKernelGGL(k_decode, dim3((unsigned)((n + 127) / 128)), dim3(128), 0, (hipStream_t)hip_stream, out, e_in,
                        (long long)n, n_bands, kappa, params, sigma, uncertain);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+extern "C" int reverb_model_feature_stats(const uint16_t* features, int64_t n, int32_t F, int32_t F_hist,
+                                          float* mean, float* scale, void* hip_stream)
+{
+    if (n < 1 || F < 1 || F_hist < 0 || F_hist >= F) return set_error(RPR_EINVAL, "feature_stats: invalid sizes");
+    if (!features || !mean || !scale) return set_error(RPR_EINVAL, "feature_stats: NULL buffer");
+    hipLaunchKernelGGL(k_feature_stats, dim3((F + 255) / 256), dim3(256), 0, (hipStream_t)hip_stream, features,
+                       (long long)n, F, F_hist, mean, scale);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+extern "C" int reverb_model_normalize(uint16_t* features, int64_t n, int32_t F, const float* shift, const float* scale,
+                                      void* hip_stream)
+{
+    if (n < 0 || F < 1) return set_error(RPR_EINVAL, "normalize: invalid sizes");
+    if (n == 0) return RPR_OK;
+    if (!features || !shift || !scale) return set_error(RPR_EINVAL, "normalize: NULL buffer");
+    hipLaunchKernelGGL(k_normalize, dim3(grid_for(n * (long long)F)), dim3(256), 0, (hipStream_t)hip_stream, features,
+                       (long long)n, F, shift, scale);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }

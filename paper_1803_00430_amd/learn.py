@@ -23,8 +23,8 @@ import time
 
 import numpy as np
 
-from . import (Batch, Model, Scene, decode, featurize, params_host, targets, LEARN_DIMS, STAT_FEATURES,
-               ST_BAD_FIT, ST_NO_ENERGY, ST_NO_RANGE)
+from . import (Batch, Model, Scene, decode, feature_stats, featurize, normalize, params_host, targets, LEARN_DIMS,
+               STAT_FEATURES, ST_BAD_FIT, ST_NO_ENERGY, ST_NO_RANGE)
 
 SH_ORDER = 3
 MAX_BOUNCES = 1000
@@ -116,12 +116,17 @@ def make_dataset(scenes, rooms, *, n_input=1024, n_target=262144, inputs_per_roo
 
 
 def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-4, seed=0, log=None):
-    """Minibatch Adam over the dataset's rows (a fresh permutation per
-    epoch), learning rate decayed by a cosine to 5% of `lr`.  Returns the
-    mean loss of each epoch."""
+    """Fit the input normalisation on the dataset's features (per-feature
+    mean and scale, the histogram group balanced against the statistics; kept
+    as model.input_norm), then minibatch Adam over the normalised rows (a
+    fresh permutation per epoch), learning rate decayed by a cosine to 5% of
+    `lr`.  Returns the mean loss of each epoch."""
     import torch
     X, t, w = data["features"], data["t"], data["w"]
-    n = X.shape[0]
+    n, F = X.shape
+    if getattr(model, "input_norm", None) is None:
+        model.input_norm = feature_stats(X, F - STAT_FEATURES)
+    Xn = normalize(X.clone(), *model.input_norm)
     steps_per_epoch = max(1, n // batch)
     total = epochs * steps_per_epoch
     gen = torch.Generator(device="cpu").manual_seed(seed)
@@ -133,7 +138,7 @@ def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-
         for i in range(steps_per_epoch):
             frac = step / max(1, total - 1)
             lr_i = lr * (0.05 + 0.95 * 0.5 * (1.0 + math.cos(math.pi * frac)))
-            model.train_step(X, t, w, perm[i * batch:(i + 1) * batch], loss[i:i + 1], lr=lr_i,
+            model.train_step(Xn, t, w, perm[i * batch:(i + 1) * batch], loss[i:i + 1], lr=lr_i,
                              weight_decay=weight_decay)
             step += 1
         losses.append(float(loss.mean().cpu()))
@@ -142,9 +147,14 @@ def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-
     return losses
 
 
-def predict(model: Model, features, e_in, n_bands, kappa):
-    """(params uint8 [n][752], sigma [n][B], uncertain [n]) on the device."""
-    out = model.forward(features)
+def predict(model: Model, features, e_in, n_bands, kappa, in_place=False):
+    """(params uint8 [n][752], sigma [n][B], uncertain [n]) on the device;
+    the features are normalised with model.input_norm first (a copy unless
+    in_place)."""
+    f = features if in_place else features.clone()
+    if getattr(model, "input_norm", None) is not None:
+        normalize(f, *model.input_norm)
+    out = model.forward(f)
     return decode(out, e_in, n_bands, kappa)
 
 
@@ -229,7 +239,7 @@ def learned_estimate(model, scenes, rooms, kappa, n_fallback, *, cheap=None, dev
                       use_graph=True, late=False, device=device)
     cheap.run()
     f, e = featurize(cheap.hist, INPUT["n_bins"], nb, nc, stats=cheap.stats)
-    params, sigma, unc = predict(model, f, e, nb, kappa)
+    params, sigma, unc = predict(model, f, e, nb, kappa, in_place=True)
     idx = torch.nonzero(unc).flatten().to(torch.int32)
     n_fb = int(idx.numel())  # synchronises
     if n_fb:

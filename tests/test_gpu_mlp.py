@@ -118,6 +118,30 @@ def test_featurize_matches_oracle(torch, T, B, NC):
     assert not fg[-1].any() and eg[-1] == 0.0
 
 
+def test_feature_stats_and_normalize(torch):
+    """Input normalisation: per-feature mean and population std (FP64), the
+    histogram group's gain sqrt(n_stats / n_hist), and the in-place affine map,
+    against numpy on the same BF16 values."""
+    g = np.random.default_rng(4)
+    n, F, F_hist = 333, 200, 136
+    X = g.normal(0, 1, (n, F)) * g.uniform(0.01, 3.0, F) + g.normal(0, 2, F)
+    X[:, 5] = 0.25  # a constant feature: std floored at 1e-3
+    Xb = f64_to_bf16_bits(X)
+    xd = torch.as_tensor(Xb, device="cuda")
+    mean, scale = P.feature_stats(xd, F_hist)
+    P.normalize(xd, mean, scale)
+    torch.cuda.synchronize()
+    Xf = bf16_bits_to_f64(Xb)
+    mu = Xf.mean(axis=0)
+    gain = np.where(np.arange(F) < F_hist, math.sqrt((F - F_hist) / F_hist), 1.0)
+    sc = gain / np.maximum(Xf.std(axis=0), 1e-3)
+    assert np.allclose(mean.cpu().numpy(), mu, rtol=1e-6, atol=1e-7)
+    assert np.allclose(scale.cpu().numpy(), sc, rtol=1e-6)
+    want = (Xf - mean.cpu().numpy().astype(np.float64)) * scale.cpu().numpy().astype(np.float64)
+    got = bf16_bits_to_f64(xd.cpu().numpy())
+    assert np.all(np.abs(got - want) <= np.abs(want) * 2.0 ** -7 + 1e-6)
+
+
 def test_targets_and_decode_match_oracle(torch):
     g = np.random.default_rng(1)
     n, B = 64, 4
