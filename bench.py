@@ -55,10 +55,13 @@ def parse():
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
                          "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
                          "learned estimator vs plain ray trace (builds its dataset and trains first)")
-    ap.add_argument("--learn-train", type=int, default=8192, help="training rooms of the learn workload")
+    ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
     ap.add_argument("--learn-views", type=int, default=4, help="1k-ray input traces per training room")
+    ap.add_argument("--learn-target-rays", type=int, default=65536, help="rays of each training target trace")
+    ap.add_argument("--learn-target-err", type=float, default=0.048,
+                    help="mean RT60 error the gate is tuned to on the calibration rooms (margin below 5%%)")
     ap.add_argument("--frames", type=int, default=8, help="frames of the hospital workload")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
@@ -132,7 +135,7 @@ def run_learn(a):
     Training set: `--learn-train` rooms x `--learn-views` inputs, input = a
     1,024-ray trace (200 x 10 ms bins x 4 bands x 16 SH coefficients + 64
     trace statistics), target = the estimator's output on an independent
-    262,144-ray trace.  Error = mean over
+    `--learn-target-rays`-ray trace.  Error = mean over
     held-out rooms x bands of |RT60 - RT60_ref| / RT60_ref, RT60_ref from a
     third independent 262,144-ray trace.  Plain: the smallest ray count of a
     sweep whose error is <= 5% (N*), timed as one graph-captured batch over the
@@ -152,8 +155,8 @@ def run_learn(a):
              "eval": [R.learn_room(200000 + i) for i in range(a.learn_eval)]}
     scenes = {k: L.make_scenes(v) for k, v in rooms.items()}
     t0 = time.perf_counter()
-    data = L.make_dataset(scenes["train"], rooms["train"], inputs_per_room=a.learn_views, chunk=1024,
-                          log=lambda m: log(m, q))
+    data = L.make_dataset(scenes["train"], rooms["train"], n_target=a.learn_target_rays,
+                          inputs_per_room=a.learn_views, chunk=1024, log=lambda m: log(m, q))
     t_data = time.perf_counter() - t0
     cal = L.make_dataset(scenes["cal"], rooms["cal"], chunk=1024)
     refs = {k: L.trace_rooms(scenes[k], rooms[k], n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024,
@@ -176,7 +179,8 @@ def run_learn(a):
     prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
     kappa, fb_frac_cal, err_cal = L.choose_kappa(sig.max(dim=1).values.cpu().numpy(),
                                                  L.rt60_error(prm, refs["cal"], 4),
-                                                 L.rt60_error(fb["params"], refs["cal"], 4))
+                                                 L.rt60_error(fb["params"], refs["cal"], 4),
+                                                 target=a.learn_target_err)
     # held-out: ungated network error, then the gated path, timed
     cheap_data = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=1024, seed_offset=L.SEED_INPUT,
                                want_features=True, chunk=1024, **L.INPUT)
@@ -202,8 +206,10 @@ def run_learn(a):
         "data": "synthetic",
         "config": {"workload": f"learn: {n_ev} held-out shoebox/L-rooms (dims U[3,40] m); step = learned estimate "
                                f"of every room (1k-ray trace + MLP + fallback at N*); "
-                               f"{a.learn_train} training rooms (100k named for this workload), 262,144-ray "
-                               f"targets and references", "train_rooms": a.learn_train, "eval_rooms": n_ev},
+                               f"{a.learn_train} training rooms x {a.learn_views} inputs (100k rooms named for this "
+                               f"workload), {a.learn_target_rays}-ray targets, 262,144-ray references",
+                   "train_rooms": a.learn_train, "eval_rooms": n_ev, "views": a.learn_views,
+                   "target_rays": a.learn_target_rays},
         "plain": {"n_star": n_star, "irs_per_s": ips_plain, "sweep": {str(k): v for k, v in sweep.items()}},
         "learned": {"irs_per_s": n_ev / t_learned, "rt60_err": err_learned, "fallback_fraction": fb_frac,
                     "kappa": kappa, "network_only_rt60_err": err_net, "cal_fallback_fraction": fb_frac_cal,
