@@ -187,8 +187,14 @@ __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float 
     const float oix = ox * ix, oiy = oy * iy, oiz = oz * iz;
     int sp = 0;
     int32_t node = sc.root;
+    // Internal nodes and leaves are handled in separate loops: every lane
+    // descends through internal nodes until it holds a leaf (or has nothing
+    // left), then the wave tests its leaves together.  A single loop that
+    // takes one node of either kind per iteration would run both code paths
+    // on every iteration of a wave whose lanes disagree on the kind.
     for (;;) {
-        if (!is_leaf(node)) {
+        bool done = false;
+        while (!is_leaf(node)) {
             const float4* nd = sc.nodes + (int64_t)kNode4 * node;
             float t[4];
             int32_t l[4];
@@ -221,22 +227,26 @@ __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float 
                 for (int j = 3; j >= 1; --j)
                     if (t[j] < inf && sp < STACK) stack[sp++ * kWave + lane] = l[j];
                 node = l[0];
-                continue;
+            } else if (sp > 0) {
+                node = stack[--sp * kWave + lane];
+            } else {
+                done = true;
+                break;
             }
-        } else {
-            const int li = leaf_index(node);
-            if (li != exclude) {
-                const float4* tr = sc.tris + 3 * (int64_t)li;
-                const float4 a = gld(tr), b = gld(tr + 1), c = gld(tr + 2);
-                if (COUNT) ++*n_tris;
-                const float th = tri_test(a, b, c, ox, oy, oz, dx, dy, dz);
-                const uint32_t id = __float_as_uint(a.w);
-                // a miss is +inf and must never win the tie-break against "no hit yet"
-                if (th < tb || (th == tb && th < inf && id < best_id)) {
-                    tb = th;
-                    best = li;
-                    best_id = id;
-                }
+        }
+        if (done) break;
+        const int li = leaf_index(node);
+        if (li != exclude) {
+            const float4* tr = sc.tris + 3 * (int64_t)li;
+            const float4 a = gld(tr), b = gld(tr + 1), c = gld(tr + 2);
+            if (COUNT) ++*n_tris;
+            const float th = tri_test(a, b, c, ox, oy, oz, dx, dy, dz);
+            const uint32_t id = __float_as_uint(a.w);
+            // a miss is +inf and must never win the tie-break against "no hit yet"
+            if (th < tb || (th == tb && th < inf && id < best_id)) {
+                tb = th;
+                best = li;
+                best_id = id;
             }
         }
         if (sp == 0) break;
