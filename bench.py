@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35812039.0,
-                 "sources_sha256": "95488d3e7a333f0792d69d219949d55b3f9392b88e6ec69e7aa067c3ed11804c"}
+TRACE_TRAFFIC = {"bytes": 36025745.0,
+                 "sources_sha256": "a030fee86706a8172284efc17645533c519b97288b26af3d2e5a1f256fabc571"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp")
 
