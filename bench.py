@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=2048, help="rays per source in the oracle sample")
+    ap.add_argument("--cpu-rays", type=int, default=8192, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital"), default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--learn-target-err", type=float, default=0.048,
                     help="mean RT60 error the gate is tuned to on the calibration rooms (margin below 5%%)")
     ap.add_argument("--frames", type=int, default=8, help="frames of the hospital workload")
+    ap.add_argument("--learned", action="store_true",
+                    help="hospital: also run the learned estimator inline (trains it first on --learn-train "
+                         "rooms), with a ray-trace fallback for uncertain sources")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
                          "(a known-size reference for the HBM byte counters)")
@@ -277,6 +280,7 @@ def run_hospital(a):
         log(f"frame {f}: {times[-1] * 1e3:.1f} ms", q)
     times = np.array(times)
     ms = times.mean() * 1e3
+    learned = run_hospital_learned(a, P, scene, cfg, sources_at, params, frame) if a.learned else None
     out = {
         "metric": "per-frame latency p50/p99 and IRs/s (plain ray trace)", "value": S / times.mean(),
         "unit": "IRs/s", "n_gpus": 1, "steps": a.frames, "warmup": a.warmup, "ms_per_step": ms,
@@ -287,8 +291,87 @@ def run_hospital(a):
         "p50_ms": float(np.percentile(times, 50) * 1e3), "p99_ms": float(np.percentile(times, 99) * 1e3),
         "build_ms": build_ms, "ray_bounces_per_s": segs / times.sum(),
     }
+    if learned:
+        out["learned"] = learned
     scene.close()
     print(json.dumps(out), flush=True)
+
+
+def run_hospital_learned(a, P, scene, cfg, sources_at, params_plain, plain_frame):
+    """The learned estimator inline in the hospital frames: per frame, every
+    source is traced with 1,024 rays (200 bins of 10 ms), its features go
+    through the network, and sources whose uncertainty exceeds kappa are
+    traced again with the full 131,072 rays and estimated by the plain method.
+    The network is trained first on shoebox / L-room data (as the learn
+    workload, with --learn-train rooms), kappa tuned on calibration rooms.
+    Accuracy: RT60 against the plain frame (131,072 rays) of the same source
+    positions."""
+    import torch
+
+    import rpr_scenes as R
+    from paper_1803_00430_amd import learn as L
+
+    q = a.quiet
+    t0 = time.perf_counter()
+    tr = [R.learn_room(10000 + i) for i in range(a.learn_train)]
+    ca = [R.learn_room(150000 + i) for i in range(512)]
+    tr_sc, ca_sc = L.make_scenes(tr), L.make_scenes(ca)
+    data = L.make_dataset(tr_sc, tr, n_target=a.learn_target_rays, inputs_per_room=a.learn_views, chunk=1024)
+    cal = L.make_dataset(ca_sc, ca, n_target=a.learn_target_rays, chunk=1024)
+    ref = L.trace_rooms(ca_sc, ca, n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024, **L.CONVERGED)
+    fb = L.trace_rooms(ca_sc, ca, n_rays=cfg["n_rays"], seed_offset=L.SEED_SWEEP + cfg["n_rays"], chunk=1024,
+                       **L.CONVERGED)
+    model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
+    prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
+    kappa, _, _ = L.choose_kappa(sig.max(dim=1).values.cpu().numpy(), L.rt60_error(prm, ref["params"], 4),
+                                 L.rt60_error(fb["params"], ref["params"], 4), target=a.learn_target_err)
+    t_prep = time.perf_counter() - t0
+    log(f"learned model ready in {t_prep:.0f} s, kappa {kappa:.3f}", q)
+    S, B, n = len(cfg["sources"]), cfg["absorption"].shape[1], cfg["sh_order"]
+    nc = (n + 1) ** 2
+    T_in, dt_in = L.INPUT["n_bins"], L.INPUT["bin_width_s"]
+    hc, lc, sc_, _ = P.alloc_trace_outputs(S, T_in, B, n, late=False)
+    # the network's input convention: 1,024 rays traced to the end of a 2 s window (bounce limit 1000)
+    prm_cheap = P.trace_params(n_rays_total=1024, max_bounces=L.MAX_BOUNCES, sh_order=n, n_bins=T_in,
+                               bin_width_s=dt_in, seed=cfg["seed"] + (1 << 32))
+    prm_full = P.trace_params(n_rays_total=cfg["n_rays"], max_bounces=cfg["max_bounces"], sh_order=n,
+                              n_bins=cfg["n_bins"], bin_width_s=cfg["bin_width_s"], seed=cfg["seed"] + (1 << 33))
+
+    def learned_frame(f):
+        src = sources_at(f)
+        P.trace_ir(scene, src, cfg["listener"], cfg["radius"], prm_cheap, hc, None, sc_)
+        feats, e = P.featurize(hc, T_in, B, nc, stats=sc_)
+        out_p, _, unc = L.predict(model, feats, e, B, kappa, in_place=True)
+        idx = torch.nonzero(unc).flatten().to(torch.int32)
+        k = int(idx.numel())
+        if k:
+            hf, lf, sf, _ = P.alloc_trace_outputs(k, cfg["n_bins"], B, n)
+            P.trace_ir(scene, src[idx.cpu().numpy()], cfg["listener"], cfg["radius"], prm_full, hf, lf, sf)
+            pf = P.alloc_params(k)
+            P.estimate_reverb(hf, lf, sf, cfg["n_bins"], B, n, cfg["bin_width_s"], pf)
+            P.params_scatter(pf, idx, out_p)
+        return out_p, k
+
+    learned_frame(-1)
+    torch.cuda.synchronize()
+    times, errs, fbs = [], [], []
+    for f in range(a.frames):
+        t1 = time.perf_counter()
+        out_p, k = learned_frame(f)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        fbs.append(k / S)
+        plain_frame(f)  # reference: the plain method at the same source positions
+        torch.cuda.synchronize()
+        errs.append(L.rt60_error(out_p, params_plain, B))
+        log(f"learned frame {f}: {times[-1] * 1e3:.1f} ms, fallback {k}/{S}", q)
+    times = np.array(times)
+    err = L.rt60_error_summary(np.concatenate(errs))
+    model.close()
+    return {"irs_per_s": S / times.mean(), "p50_ms": float(np.percentile(times, 50) * 1e3),
+            "p99_ms": float(np.percentile(times, 99) * 1e3), "fallback_fraction": float(np.mean(fbs)),
+            "rt60_err_vs_plain_frame": err, "kappa": kappa, "prep_s": t_prep}
 
 
 def main():

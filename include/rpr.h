@@ -395,6 +395,15 @@ int reverb_model_feature_stats(const uint16_t* features, int64_t n, int32_t F, i
  * scale[f], rounded to BF16 (shift, scale device [F] f32). */
 int reverb_model_normalize(uint16_t* features, int64_t n, int32_t F, const float* shift, const float* scale,
                            void* hip_stream);
+/* Input-support gate, applied after reverb_model_decode: a network's
+ * uncertainty is only meaningful for inputs like those it was trained on, so
+ * row i (features device [n][F] BF16, already normalised by
+ * reverb_model_normalize) is also marked uncertain -- uncertain[i] = 1 and
+ * RPR_ST_UNCERTAIN in params[i].status -- when any feature in columns
+ * [c0, c1) lies beyond +-zmax training standard deviations.  params device
+ * [n] or NULL, uncertain device [n] i32 or NULL (not both NULL). */
+int reverb_model_ood_gate(const uint16_t* features, int64_t n, int32_t F, int32_t c0, int32_t c1, float zmax,
+                          int32_t n_bands, RprReverbParams* params, int32_t* uncertain, void* hip_stream);
 /* dst[idx[i]] = src[i] for i < n (device arrays): merges the parameters of
  * re-traced pairs into a learned result. */
 int reverb_params_scatter(const RprReverbParams* src, const int32_t* idx, int64_t n, RprReverbParams* dst,

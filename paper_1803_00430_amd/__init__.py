@@ -150,6 +150,7 @@ SIGNATURES = {
     "reverb_params_scatter": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "reverb_model_feature_stats": (C.c_int, [_vp, _i64, _i32, _i32, _vp, _vp, _vp]),
     "reverb_model_normalize": (C.c_int, [_vp, _i64, _i32, _vp, _vp, _vp]),
+    "reverb_model_ood_gate": (C.c_int, [_vp, _i64, _i32, _i32, _i32, C.c_float, _i32, _vp, _vp, _vp]),
     "last_error": (C.c_char_p, []),
     "rpr_version": (C.c_char_p, []),
 }
@@ -520,6 +521,13 @@ def normalize(features, shift, scale, stream=None):
     n, F = features.shape
     _check(lib().reverb_model_normalize(_ptr(features), n, F, _ptr(shift), _ptr(scale), _stream(stream)))
     return features
+
+
+def ood_gate(features, c0, c1, zmax, n_bands, params=None, uncertain=None, stream=None):
+    """Mark rows whose normalised features in [c0, c1) exceed +-zmax as uncertain (in place)."""
+    n, F = features.shape
+    _check(lib().reverb_model_ood_gate(_ptr(features), n, F, int(c0), int(c1), float(zmax), int(n_bands),
+                                       _ptr(params), _ptr(uncertain), _stream(stream)))
 
 
 def params_scatter(src, idx, dst, stream=None):

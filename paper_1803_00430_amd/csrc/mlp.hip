@@ -314,6 +314,24 @@ __global__ void k_normalize(uint16_t* __restrict__ x, long long n, int F, const 
     }
 }
 
+// Input-support gate: row i is flagged uncertain (uncertain[i] = 1 and
+// RPR_ST_UNCERTAIN in every band's status) when any of its normalised features
+// in columns [c0, c1) lies beyond +-zmax.  One wave per row.
+__global__ void __launch_bounds__(64) k_ood_gate(const uint16_t* __restrict__ x, int F, int c0, int c1, float zmax,
+                                                 int n_bands, RprReverbParams* __restrict__ params,
+                                                 int32_t* __restrict__ uncertain)
+{
+    const uint16_t* r = x + (size_t)blockIdx.x * F;
+    bool out = false;
+    for (int c = c0 + threadIdx.x; c < c1; c += 64) out |= !(fabsf(bf2f(r[c])) <= zmax);
+    if (__builtin_amdgcn_ballot_w64(out) == 0) return;
+    if (threadIdx.x == 0) {
+        if (uncertain) uncertain[blockIdx.x] = 1;
+        if (params)
+            for (int b = 0; b < n_bands; ++b) params[blockIdx.x].status[b] |= RPR_ST_UNCERTAIN;
+    }
+}
+
 __global__ void k_zero_f32(float* __restrict__ p, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -977,6 +995,21 @@ extern "C" int reverb_model_normalize(uint16_t* features, int64_t n, int32_t F, 
     if (!features || !shift || !scale) return set_error(RPR_EINVAL, "normalize: NULL buffer");
     hipLaunchKernelGGL(k_normalize, dim3(grid_for(n * (long long)F)), dim3(256), 0, (hipStream_t)hip_stream, features,
                        (long long)n, F, shift, scale);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+extern "C" int reverb_model_ood_gate(const uint16_t* features, int64_t n, int32_t F, int32_t c0, int32_t c1,
+                                     float zmax, int32_t n_bands, RprReverbParams* params, int32_t* uncertain,
+                                     void* hip_stream)
+{
+    if (n < 0 || F < 1 || c0 < 0 || c1 > F || c0 >= c1 || !(zmax > 0.f) || n_bands < 1 || n_bands > RPR_MAX_BANDS)
+        return set_error(RPR_EINVAL, "ood_gate: invalid arguments");
+    if (n == 0) return RPR_OK;
+    if (n > 0x7FFFFFFF) return set_error(RPR_EUNSUPPORTED, "ood_gate: too many rows");
+    if (!features || (!params && !uncertain)) return set_error(RPR_EINVAL, "ood_gate: NULL buffer");
+    hipLaunchKernelGGL(k_ood_gate, dim3((unsigned)n), dim3(64), 0, (hipStream_t)hip_stream, features, F, c0, c1, zmax,
+                       n_bands, params, uncertain);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }

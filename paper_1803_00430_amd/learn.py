@@ -23,8 +23,8 @@ import time
 
 import numpy as np
 
-from . import (Batch, Model, Scene, decode, feature_stats, featurize, normalize, params_host, targets, LEARN_DIMS,
-               STAT_FEATURES, ST_BAD_FIT, ST_NO_ENERGY, ST_NO_RANGE)
+from . import (Batch, Model, Scene, decode, feature_stats, featurize, normalize, ood_gate, params_host, targets,
+               LEARN_DIMS, STAT_FEATURES, ST_BAD_FIT, ST_NO_ENERGY, ST_NO_RANGE)
 
 SH_ORDER = 3
 MAX_BOUNCES = 1000
@@ -35,6 +35,7 @@ SEED_TARGET = 1 << 33
 SEED_REFERENCE = 1 << 34
 SEED_SWEEP = 1 << 35  # + n_rays: the plain method's own traces in the ray-count sweep
 INVALID_FIT = ST_NO_ENERGY | ST_BAD_FIT | ST_NO_RANGE
+OOD_ZMAX = 6.0  # statistics features further than this many training std devs: outside the training support
 
 
 def room_pairs(rooms, n_rays, seed_offset, max_bounces=MAX_BOUNCES):
@@ -147,15 +148,22 @@ def train(model: Model, data, *, epochs=30, batch=256, lr=1e-3, weight_decay=1e-
     return losses
 
 
-def predict(model: Model, features, e_in, n_bands, kappa, in_place=False):
+def predict(model: Model, features, e_in, n_bands, kappa, in_place=False, zmax=OOD_ZMAX):
     """(params uint8 [n][752], sigma [n][B], uncertain [n]) on the device;
     the features are normalised with model.input_norm first (a copy unless
-    in_place)."""
+    in_place).  Rows are uncertain when any band's sigma exceeds kappa or,
+    with a fitted normalisation, when a statistics feature lies beyond zmax
+    training standard deviations (outside the inputs the network has seen)."""
     f = features if in_place else features.clone()
-    if getattr(model, "input_norm", None) is not None:
-        normalize(f, *model.input_norm)
+    norm = getattr(model, "input_norm", None)
+    if norm is not None:
+        normalize(f, *norm)
     out = model.forward(f)
-    return decode(out, e_in, n_bands, kappa)
+    params, sigma, unc = decode(out, e_in, n_bands, kappa)
+    if norm is not None and zmax is not None:
+        F = f.shape[1]
+        ood_gate(f, F - STAT_FEATURES, F, zmax, n_bands, params=params, uncertain=unc)
+    return params, sigma, unc
 
 
 def rt60_error(params, ref_params, n_bands):

@@ -142,6 +142,26 @@ def test_feature_stats_and_normalize(torch):
     assert np.all(np.abs(got - want) <= np.abs(want) * 2.0 ** -7 + 1e-6)
 
 
+def test_ood_gate_flags_rows_outside_the_training_support(torch):
+    g = np.random.default_rng(8)
+    n, F, c0 = 50, 128, 96
+    X = g.normal(0, 1, (n, F))
+    X[:, c0:] = np.clip(X[:, c0:], -5.9, 5.9)
+    X[7, c0 + 3] = 6.5     # beyond +6 in the gated columns
+    X[11, c0 + 30] = -8.0
+    X[13, 10] = 50.0       # outside the gated columns: ignored
+    xd = torch.as_tensor(f64_to_bf16_bits(X), device="cuda")
+    prm = P.alloc_params(n)
+    prm.zero_()
+    unc = torch.zeros(n, dtype=torch.int32, device="cuda")
+    P.ood_gate(xd, c0, F, 6.0, 4, params=prm, uncertain=unc)
+    torch.cuda.synchronize()
+    u = unc.cpu().numpy()
+    assert set(np.nonzero(u)[0]) == {7, 11}
+    st = P.params_host(prm)["status"]
+    assert np.all(st[[7, 11], :4] == P.ST_UNCERTAIN) and not st[np.setdiff1d(np.arange(n), [7, 11])].any()
+
+
 def test_targets_and_decode_match_oracle(torch):
     g = np.random.default_rng(1)
     n, B = 64, 4
