@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=8192, help="rays per source in the oracle sample")
+    ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital"), default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
