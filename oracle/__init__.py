@@ -60,7 +60,7 @@ class IrStats(C.Structure):
                 ("first_late_bin", C.c_int32), ("e_class", (C.c_double * MAX_BANDS) * 3),
                 ("e_escaped", C.c_double * MAX_BANDS), ("e_alive_at_stop", C.c_double * MAX_BANDS),
                 ("e_alive_at_bounce_cap", C.c_double * MAX_BANDS),
-                ("e_absorbed", C.c_double * MAX_BANDS)]
+                ("e_absorbed", C.c_double * MAX_BANDS), ("n_next_event", C.c_int64)]
 
 
 _lib = None
@@ -88,6 +88,11 @@ def lib():
                                    C.POINTER(TraceParams), dp, dp, C.POINTER(IrStats),
                                    C.POINTER(C.c_uint32)]
         L.orc_trace_ir.restype = C.c_int
+        L.orc_trace_listener.argtypes = L.orc_trace_ir.argtypes
+        L.orc_trace_listener.restype = C.c_int
+        L.orc_cone_dir.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_cone_batch.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, dp, C.c_double,
+                                     C.c_int64, dp]
         L.orc_num_threads.restype = C.c_int
         L.orc_trace_path.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp,
                                      C.c_int32, dp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_double,
@@ -184,7 +189,7 @@ def stats_to_dict(st: IrStats, nb: int) -> dict:
         e_class=np.array([[st.e_class[c][b] for b in range(nb)] for c in range(3)]),
         e_escaped=np.array(st.e_escaped[:nb]), e_alive_at_stop=np.array(st.e_alive_at_stop[:nb]),
         e_alive_at_bounce_cap=np.array(st.e_alive_at_bounce_cap[:nb]),
-        e_absorbed=np.array(st.e_absorbed[:nb]),
+        e_absorbed=np.array(st.e_absorbed[:nb]), n_next_event=int(st.n_next_event),
     )
 
 
@@ -220,6 +225,51 @@ def trace_ir(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray
         raise ValueError("oracle trace_ir: invalid arguments")
     return dict(hist=hist, hist_late=hist_late, stats=[stats_to_dict(stats[s], B) for s in range(S)],
                 ray_hash=rh)
+
+
+def trace_listener(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray_end=None,
+                   max_bounces, sh_order, n_bins, bin_width_s, seed, pair_base=0,
+                   speed_of_sound=SPEED_OF_SOUND, want_hash=False):
+    """Listener-origin trace with next-event estimation toward each source
+    ball of radius `radius` (`orc_trace_listener`).  Returns dict(hist
+    [S,T,B,NC], hist_late [S,T,B], stats [list of dict], ray_hash [R] or
+    None)."""
+    if ray_end is None:
+        ray_end = n_rays_total
+    verts = np.ascontiguousarray(scene["verts"], np.float64)
+    tris = np.ascontiguousarray(scene["tris"], np.int32)
+    tri_mat = np.ascontiguousarray(scene["tri_mat"], np.int32)
+    ab = np.ascontiguousarray(scene["absorption"], np.float64)
+    sc = np.ascontiguousarray(scene["scattering"], np.float64)
+    M, B = ab.shape
+    srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float64)
+    S = len(srcs)
+    lst = np.ascontiguousarray([*np.asarray(listener, np.float64), float(radius)], np.float64)
+    nc = (sh_order + 1) ** 2
+    R = ray_end - ray_begin
+    hist = np.zeros((S, n_bins, B, nc))
+    hist_late = np.zeros((S, n_bins, B))
+    stats = (IrStats * max(S, 1))()
+    rh = np.zeros(max(R, 0), np.uint32) if want_hash else None
+    p = TraceParams(n_rays_total, ray_begin, ray_end, max_bounces, sh_order, n_bins, pair_base,
+                    bin_width_s, speed_of_sound, seed)
+    rc = lib().orc_trace_listener(_dp(verts), len(verts), tris.ctypes.data_as(C.POINTER(C.c_int32)), len(tris),
+                                  tri_mat.ctypes.data_as(C.POINTER(C.c_int32)), _dp(ab), _dp(sc), M, B,
+                                  _dp(srcs), S, _dp(lst), C.byref(p), _dp(hist), _dp(hist_late), stats,
+                                  rh.ctypes.data_as(C.POINTER(C.c_uint32)) if rh is not None else None)
+    if rc != 0:
+        raise ValueError("oracle trace_listener: invalid arguments")
+    return dict(hist=hist, hist_late=hist_late, stats=[stats_to_dict(stats[s], B) for s in range(S)],
+                ray_hash=rh)
+
+
+def cone_batch(seed: int, pair: int, order: int, w3: int, axis, cos_half_angle: float, n: int) -> np.ndarray:
+    """Directions uniform in a cone about `axis` from counters (i, pair,
+    order, w3), i < n; [n, 3]."""
+    a = np.ascontiguousarray(axis, np.float64)
+    out = np.zeros((n, 3))
+    lib().orc_cone_batch(seed, pair, order, w3, _dp(a), float(cos_half_angle), n, _dp(out))
+    return out
 
 
 def trace_path(scene, source, *, seed, ray, pair, max_bounces, window_len, max_seg=4096):

@@ -70,6 +70,7 @@ typedef struct {
     double e_alive_at_stop[ORC_MAX_BANDS];
     double e_alive_at_bounce_cap[ORC_MAX_BANDS];
     double e_absorbed[ORC_MAX_BANDS];
+    int64_t n_next_event;      /* listener-origin trace: next-event (shadow) queries; else 0 */
 } OrcIrStats;
 
 /* ------------------------------------------------------------------ RNG */
@@ -294,36 +295,37 @@ static void atomic_min_i32(int32_t *p, int32_t v)
     }
 }
 
-/* Score one segment [o, o + t_hit d) at the listener sphere (centre pl,
- * radius r) with the track-length estimator: the part of the segment inside
- * the sphere, in propagation time, is split exactly over the histogram bins
- * it overlaps; each bin receives E_b * Y_k(-d) * (overlap in s) / V_sphere.
- * The arrival direction is -d (the notation table defines the direction as
- * pointing back toward the source along the path).  Orders 0, 1-2 and >= 3
- * are the direct, early and late classes (Section 5: the first two
- * reflection orders are early, higher orders feed the late IR). */
-static void deposit(const double o[3], const double d[3], double t_hit, double L, int order,
-                    const double *E, int nb, const double pl[3], double r, const OrcTraceParams *p,
-                    double *hist, double *hist_late, OrcIrStats *st)
+/* Chord of the ray o + t d, 0 <= t <= tmax, through the ball (centre pc,
+ * radius r): returns 1 and [*ta, *tb] when it is not empty. */
+static int ball_chord(const double o[3], const double d[3], double tmax, const double pc[3], double r,
+                      double *ta, double *tb)
 {
     double oc[3], w[3];
-    sub3(o, pl, oc);
+    sub3(o, pc, oc);
     double bq = dot3(d, oc);
     for (int i = 0; i < 3; ++i) w[i] = oc[i] - bq * d[i];
     double disc = r * r - dot3(w, w);
-    if (!(disc > 0.0)) return;
+    if (!(disc > 0.0)) return 0;
     double sq = sqrt(disc);
-    double ta = fmax(-bq - sq, 0.0);
-    double tb = fmin(-bq + sq, t_hit);
-    if (!(tb > ta)) return;
+    *ta = fmax(-bq - sq, 0.0);
+    *tb = fmin(-bq + sq, tmax);
+    return *tb > *ta;
+}
+
+/* Track-length score of the chord [ta, tb] (metres along a segment that
+ * starts at path length L) inside a ball of volume vs: the chord, in
+ * propagation time, is split exactly over the histogram bins it overlaps;
+ * each bin receives E_b * Y_k * (overlap in s) / vs.  Orders 0, 1-2 and >= 3
+ * are the direct, early and late classes (Section 5: the first two
+ * reflection orders are early, higher orders feed the late IR). */
+static void score_chord(double ta, double tb, double L, int order, const double *E, int nb, double vs,
+                        const double *Y, const OrcTraceParams *p, double *hist, double *hist_late,
+                        OrcIrStats *st)
+{
     const double c = p->speed_of_sound, dt = p->bin_width_s;
     const int T = p->n_bins;
     const int nc = (p->sh_order + 1) * (p->sh_order + 1);
     double tau_a = (L + ta) / c, tau_b = (L + tb) / c;
-    double vs = 4.0 / 3.0 * M_PI * r * r * r;
-    double md[3] = {-d[0], -d[1], -d[2]};
-    double Y[16];
-    orc_sh_eval(p->sh_order, md, Y);
     int cls = order == 0 ? 0 : (order <= 2 ? 1 : 2);
     int64_t m0 = (int64_t)floor(tau_a / dt);
     for (int64_t m = m0; m < T; ++m) {
@@ -349,6 +351,23 @@ static void deposit(const double o[3], const double d[3], double t_hit, double L
         if ((int32_t)m < st->first_arrival_bin) atomic_min_i32(&st->first_arrival_bin, (int32_t)m);
         if (order >= 3 && (int32_t)m < st->first_late_bin) atomic_min_i32(&st->first_late_bin, (int32_t)m);
     }
+}
+
+/* Score one segment [o, o + t_hit d) at the listener sphere (centre pl,
+ * radius r) with the track-length estimator.  The arrival direction is -d
+ * (the notation table defines the direction as pointing back toward the
+ * source along the path). */
+static void deposit(const double o[3], const double d[3], double t_hit, double L, int order,
+                    const double *E, int nb, const double pl[3], double r, const OrcTraceParams *p,
+                    double *hist, double *hist_late, OrcIrStats *st)
+{
+    double ta, tb;
+    if (!ball_chord(o, d, t_hit, pl, r, &ta, &tb)) return;
+    double vs = 4.0 / 3.0 * M_PI * r * r * r;
+    double md[3] = {-d[0], -d[1], -d[2]};
+    double Y[16];
+    orc_sh_eval(p->sh_order, md, Y);
+    score_chord(ta, tb, L, order, E, nb, vs, Y, p, hist, hist_late, st);
 }
 
 /* Trace rays [ray_begin, ray_end) of every source.
@@ -511,6 +530,341 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
         }
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------ listener-origin trace */
+
+/* Direction uniform in the cone of half-angle g about the unit axis a, with
+ * cg = cos g: the cosine to the axis is 1 - u0 (1 - cg), uniform in
+ * [cg, 1] (equal solid angle per unit cosine), and the azimuth is 2 pi u1 in
+ * the Duff et al. basis of a. */
+void orc_cone_dir(const double a[3], double cg, double u0, double u1, double d[3])
+{
+    double b1[3], b2[3];
+    onb(a, b1, b2);
+    double ct = 1.0 - u0 * (1.0 - cg);
+    double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+    double ph = 2.0 * M_PI * u1;
+    for (int i = 0; i < 3; ++i) d[i] = st * cos(ph) * b1[i] + st * sin(ph) * b2[i] + ct * a[i];
+}
+
+static void draw_ctr(uint64_t seed, uint32_t ray, uint32_t pair, uint32_t order, uint32_t w3, double u[4])
+{
+    uint32_t ctr[4] = {ray, pair, order, w3};
+    uint32_t key[2] = {(uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    for (int i = 0; i < 4; ++i) u[i] = orc_uniform(x[i]);
+}
+
+typedef struct {
+    const double *verts;
+    const int32_t *tris;
+    int64_t n_tris;
+    const double *srcs;
+    int n_src;
+    double r, vs;
+    int nb, nc;
+    uint64_t seed;
+    uint32_t pair;
+    const OrcTraceParams *p;
+    double *hist, *hist_late;
+    OrcIrStats *stats;
+} OrcListenerCtx;
+
+/* Next-event estimation ("diffuse rain", Section 5) from one vertex of a
+ * listener path toward every source ball.  At a reflection the vertex is the
+ * offset hit point o with facing normal nf, and band b carries
+ * f_b = E_b (1 - alpha_b) s_b, the diffuse share of the reflection; at the
+ * listener itself (nf == NULL, order 0) f_b = E_b and the lobe is the
+ * uniform emission.  For source s a direction w is drawn uniformly in the
+ * cone that the ball subtends from o (counter (ray, pair, order, 1 + s));
+ * the segment from o along w is scored like any segment with the
+ * track-length estimator, with weight f_b times
+ *     cos(nf, w) * Omega / pi     (Lambert lobe, density cos / pi), or
+ *     Omega / (4 pi)              (uniform emission, density 1 / (4 pi)),
+ * Omega = 2 pi (1 - cos g) the cone's solid angle: the expectation is the
+ * score of a lobe-sampled segment restricted to the directions that reach
+ * the ball.  The segment stops at its first hit (nearest t > 0, the vertex's
+ * own triangle excluded): a hit before the chord's entry occludes it, a hit
+ * inside it shortens it.  A vertex inside a ball samples the whole lobe
+ * instead (weight 1).  The SH row is the path's arrival direction at the
+ * listener Y0, or, for the direct sound, that of w itself.  Each query folds
+ * its outcome into the ray hash (2 clear, 3 occluded, 4 shortened). */
+static void next_event(const OrcListenerCtx *X, uint32_t ray, const double o[3], const double *nf, double L,
+                       int order, const double *f, int64_t exclude, const double *Y0, uint32_t *h,
+                       int64_t *n_query)
+{
+    const OrcTraceParams *p = X->p;
+    const double window = (double)p->n_bins * p->bin_width_s;
+    for (int s = 0; s < X->n_src; ++s) {
+        const double *ps = X->srcs + 3 * s;
+        double v[4], axis[3], w[3], g;
+        draw_ctr(X->seed, ray, X->pair, (uint32_t)order, 1u + (uint32_t)s, v);
+        sub3(ps, o, axis);
+        double rc = sqrt(dot3(axis, axis));
+        if (rc <= X->r) {
+            if (nf) orc_diffuse_dir(nf, v, w);
+            else orc_emission_dir(v, w);
+            g = 1.0;
+        } else {
+            double a[3] = {axis[0] / rc, axis[1] / rc, axis[2] / rc};
+            double cg = sqrt(1.0 - (X->r * X->r) / (rc * rc));
+            orc_cone_dir(a, cg, v[0], v[1], w);
+            double omega = 2.0 * M_PI * (1.0 - cg);
+            if (nf) {
+                double cs = dot3(nf, w);
+                if (!(cs > 0.0)) continue;
+                g = cs * omega / M_PI;
+            } else {
+                g = omega / (4.0 * M_PI);
+            }
+        }
+        double ta, tb;
+        if (!ball_chord(o, w, INFINITY, ps, X->r, &ta, &tb)) continue;
+        if ((L + ta) / p->speed_of_sound >= window) continue;
+        ++*n_query;
+        double t_occ;
+        closest_hit(X->verts, X->tris, X->n_tris, o, w, exclude, &t_occ);
+        if (t_occ <= ta) {
+            *h = fnv(*h, 3u);
+            continue;
+        }
+        if (t_occ < tb) {
+            tb = t_occ;
+            *h = fnv(*h, 4u);
+        } else {
+            *h = fnv(*h, 2u);
+        }
+        double e[ORC_MAX_BANDS], Yw[16];
+        for (int b = 0; b < X->nb; ++b) e[b] = f[b] * g;
+        const double *Y = Y0;
+        if (!Y) {
+            orc_sh_eval(p->sh_order, w, Yw);
+            Y = Yw;
+        }
+        score_chord(ta, tb, L, order, e, X->nb, X->vs, Y, p, X->hist + (size_t)s * p->n_bins * X->nb * X->nc,
+                    X->hist_late ? X->hist_late + (size_t)s * p->n_bins * X->nb : NULL, &X->stats[s]);
+    }
+}
+
+/* Listener-origin path tracing with next-event estimation toward every
+ * source (Section 5: backward path tracing from the listener, augmented with
+ * diffuse rain; one set of rays serves all sources).  Each source is a ball
+ * of radius listener[3] around its position; the listener is the point
+ * listener[0..2].  Ray i (counter (i, pair_base, k, 0)) leaves the listener
+ * uniformly on the sphere in direction w0 with 1/n_rays_total per band, and
+ * reflects exactly as in orc_trace_ir (hero-band choice, balance-heuristic
+ * band weights, Lambert or mirror direction, 1 mm offset, K and window
+ * limits).  Its contributions:
+ *   - order 0: next_event() from the listener (the direct sound; the
+ *     primary segment itself is not scored);
+ *   - at each reflection k (1 <= k <= K, before the window end):
+ *     next_event() with the diffuse share f_b = E_b (1 - alpha_b) s_b;
+ *   - each segment that follows a specular choice is scored at every source
+ *     ball with the track-length estimator (the mirror share, which no
+ *     next-event query can reach); a segment after a diffuse choice is not,
+ *     since next_event() has already accounted for that reflection's diffuse
+ *     share reaching the ball.
+ * The histogram of source s then estimates, for a source spread uniformly
+ * over its ball, the time-integrated energy density at the listener point
+ * with the SH of the arrival direction w0 (the estimator is a forward trace
+ * from the listener scored at the ball, so by the reciprocity of the room's
+ * propagation it also equals the forward trace from the listener point to a
+ * listener sphere at the source).
+ *   srcs [n_src][3]; listener[4] = point xyz, source ball radius
+ *   hist [n_src][T][nb][(n+1)^2], hist_late [n_src][T][nb] or NULL
+ *   stats [n_src]: the path statistics (segments, escapes, energies,
+ *     next-event queries) belong to the one ray set and are repeated in
+ *     every record; e_class and the first bins are per source
+ *   ray_hash [ray_end - ray_begin] or NULL: hit triangles, bounce kinds and
+ *     next-event outcomes
+ * Returns 0, or -1 on invalid arguments. */
+int orc_trace_listener(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                       const int32_t *tri_mat, const double *absorption, const double *scattering,
+                       int32_t n_materials, int32_t nb, const double *srcs, int32_t n_src, const double *listener,
+                       const OrcTraceParams *p, double *hist, double *hist_late, OrcIrStats *stats,
+                       uint32_t *ray_hash)
+{
+    if (nb < 1 || nb > ORC_MAX_BANDS || p->sh_order < 0 || p->sh_order > 3 || p->n_bins < 1 ||
+        !(p->bin_width_s > 0) || !(listener[3] > 0) || p->ray_end < p->ray_begin ||
+        p->n_rays_total < 1 || n_src < 0 || n_materials < 1)
+        return -1;
+    for (int64_t i = 0; i < 3 * n_tris; ++i)
+        if (tris[i] < 0 || tris[i] >= n_verts) return -1;
+    const int T = p->n_bins;
+    const int nc = (p->sh_order + 1) * (p->sh_order + 1);
+    const int64_t R = p->ray_end - p->ray_begin;
+    memset(hist, 0, sizeof(double) * (size_t)n_src * T * nb * nc);
+    if (hist_late) memset(hist_late, 0, sizeof(double) * (size_t)n_src * T * nb);
+    for (int s = 0; s < n_src; ++s) {
+        memset(&stats[s], 0, sizeof(OrcIrStats));
+        stats[s].first_arrival_bin = INT32_MAX;
+        stats[s].first_late_bin = INT32_MAX;
+    }
+    if (n_src == 0) return 0;
+    const double c = p->speed_of_sound;
+    const double window = (double)T * p->bin_width_s;
+    const double e0 = 1.0 / (double)p->n_rays_total;
+    const double r = listener[3];
+    OrcListenerCtx X = {verts, tris, n_tris, srcs, n_src, r, 4.0 / 3.0 * M_PI * r * r * r, nb, nc, p->seed,
+                        (uint32_t)p->pair_base, p, hist, hist_late, stats};
+    OrcIrStats rs;
+    memset(&rs, 0, sizeof(rs));
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t ri = 0; ri < R; ++ri) {
+        const uint32_t ray = (uint32_t)(p->ray_begin + ri);
+        double u[4], o[3], d[3], w0[3], Y0[16], E[ORC_MAX_BANDS], Q[ORC_MAX_BANDS], f[ORC_MAX_BANDS];
+        const int hero = (int)(ray % (uint32_t)nb);
+        draw(p->seed, ray, X.pair, 0u, u);
+        orc_emission_dir(u, w0);
+        orc_sh_eval(p->sh_order, w0, Y0);
+        for (int i = 0; i < 3; ++i) {
+            o[i] = listener[i];
+            d[i] = w0[i];
+        }
+        for (int b = 0; b < nb; ++b) {
+            E[b] = e0;
+            Q[b] = 1.0;
+        }
+        double L = 0.0;
+        int k = 0, spec = 0;
+        int64_t last = -1;
+        uint32_t h = ORC_FNV_BASIS;
+        int64_t nseg = 0, nfin = 0, nesc = 0, nq = 0;
+        double seglen = 0.0, absorbed[ORC_MAX_BANDS] = {0};
+        next_event(&X, ray, o, NULL, 0.0, 0, E, -1, NULL, &h, &nq);
+        for (;;) {
+            double t_hit;
+            int64_t tri = closest_hit(verts, tris, n_tris, o, d, last, &t_hit);
+            if (spec) {
+                for (int s = 0; s < n_src; ++s) {
+                    double ta, tb;
+                    if (ball_chord(o, d, t_hit, srcs + 3 * s, r, &ta, &tb))
+                        score_chord(ta, tb, L, k, E, nb, X.vs, Y0, p, hist + (size_t)s * T * nb * nc,
+                                    hist_late ? hist_late + (size_t)s * T * nb : NULL, &stats[s]);
+                }
+            }
+            ++nseg;
+            if (tri < 0) {
+                ++nesc;
+                h = fnv(h, ORC_HASH_ESCAPE);
+                for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+                    rs.e_escaped[b] += E[b];
+                }
+                break;
+            }
+            L += t_hit;
+            ++nfin;
+            seglen += t_hit;
+            h = fnv(h, (uint32_t)tri);
+            if (L / c >= window || k == p->max_bounces) {
+                for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+                    rs.e_alive_at_stop[b] += E[b];
+                    if (k == p->max_bounces && !(L / c >= window)) {
+#pragma omp atomic
+                        rs.e_alive_at_bounce_cap[b] += E[b];
+                    }
+                }
+                break;
+            }
+            ++k;
+            double x[3];
+            for (int i = 0; i < 3; ++i) x[i] = o[i] + t_hit * d[i];
+            const int32_t *tv = tris + 3 * tri;
+            double e1[3], e2[3], nrm[3], nf[3];
+            sub3(verts + 3 * (int64_t)tv[1], verts + 3 * (int64_t)tv[0], e1);
+            sub3(verts + 3 * (int64_t)tv[2], verts + 3 * (int64_t)tv[0], e2);
+            cross3(e1, e2, nrm);
+            double nl = sqrt(dot3(nrm, nrm));
+            for (int i = 0; i < 3; ++i) nrm[i] /= nl;
+            double sgn = dot3(d, nrm) > 0.0 ? -1.0 : 1.0; /* face the incoming ray */
+            for (int i = 0; i < 3; ++i) nf[i] = sgn * nrm[i];
+            int mat = tri_mat ? tri_mat[tri] : 0;
+            const double *al = absorption + (int64_t)mat * nb;
+            const double *sc = scattering + (int64_t)mat * nb;
+            double xo[3];
+            for (int i = 0; i < 3; ++i) xo[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
+            for (int b = 0; b < nb; ++b) f[b] = E[b] * (1.0 - al[b]) * sc[b];
+            next_event(&X, ray, xo, nf, L, k, f, tri, Y0, &h, &nq);
+            draw(p->seed, ray, X.pair, (uint32_t)k, u);
+            for (int b = 0; b < nb; ++b) absorbed[b] += al[b] * E[b];
+            const int diffuse = u[0] < sc[hero];
+            double q[ORC_MAX_BANDS], mean_q = 0.0;
+            for (int b = 0; b < nb; ++b) {
+                q[b] = diffuse ? sc[b] : 1.0 - sc[b];
+                mean_q += Q[b] * q[b];
+            }
+            mean_q /= nb;
+            for (int b = 0; b < nb; ++b) {
+                Q[b] *= q[b] / mean_q;
+                E[b] *= (1.0 - al[b]) * q[b] / mean_q;
+            }
+            if (diffuse) {
+                orc_diffuse_dir(nf, u, d);
+                h = fnv(h, 1u);
+            } else {
+                double dn = dot3(d, nf);
+                for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
+                h = fnv(h, 0u);
+            }
+            spec = !diffuse;
+            for (int i = 0; i < 3; ++i) o[i] = xo[i];
+            last = tri;
+        }
+#pragma omp atomic
+        rs.n_segments += nseg;
+#pragma omp atomic
+        rs.n_finite_segments += nfin;
+#pragma omp atomic
+        rs.n_escaped += nesc;
+#pragma omp atomic
+        rs.n_rays += 1;
+#pragma omp atomic
+        rs.seg_len_sum += seglen;
+#pragma omp atomic
+        rs.e_emitted += e0;
+#pragma omp atomic
+        rs.n_next_event += nq;
+        for (int b = 0; b < nb; ++b) {
+#pragma omp atomic
+            rs.e_absorbed[b] += absorbed[b];
+        }
+        if (ray_hash) ray_hash[ri] = h;
+    }
+    for (int s = 0; s < n_src; ++s) {
+        OrcIrStats *st = &stats[s];
+        st->n_segments = rs.n_segments;
+        st->n_finite_segments = rs.n_finite_segments;
+        st->n_escaped = rs.n_escaped;
+        st->n_rays = rs.n_rays;
+        st->seg_len_sum = rs.seg_len_sum;
+        st->e_emitted = rs.e_emitted;
+        st->n_next_event = rs.n_next_event;
+        for (int b = 0; b < ORC_MAX_BANDS; ++b) {
+            st->e_escaped[b] = rs.e_escaped[b];
+            st->e_alive_at_stop[b] = rs.e_alive_at_stop[b];
+            st->e_alive_at_bounce_cap[b] = rs.e_alive_at_bounce_cap[b];
+            st->e_absorbed[b] = rs.e_absorbed[b];
+        }
+    }
+    return 0;
+}
+
+/* Cone directions for the sampling checks: out[i] = orc_cone_dir of the
+ * uniforms of counter (i, pair, order, w3). */
+void orc_cone_batch(uint64_t seed, uint32_t pair, uint32_t order, uint32_t w3, const double a[3], double cg,
+                    int64_t n, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double u[4];
+        draw_ctr(seed, (uint32_t)i, pair, order, w3, u);
+        orc_cone_dir(a, cg, u[0], u[1], out + 3 * i);
+    }
 }
 
 /* Path of one ray for diagnostics: per segment k (up to max_seg), the
