@@ -112,6 +112,7 @@ typedef struct {
     double e_absorbed[RPR_MAX_BANDS];            /* sum over bounces of alpha_b * E_b */
     int64_t n_node_visits; /* internal BVH nodes fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
     int64_t n_tri_tests;   /* triangle records fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
+    int64_t n_next_event;  /* trace_listener: next-event (occlusion) queries of the ray set; else 0 */
 } RprIrStats;
 
 typedef struct {
@@ -166,6 +167,37 @@ int scene_info(const RprScene* scene, RprSceneInfo* out /* host */);
 int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
              const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
              uint32_t* ray_hash, void* hip_stream);
+
+/* Path tracing from the listener with next-event estimation toward every
+ * source (Section 5: backward path tracing from the listener, augmented
+ * with diffuse rain; one set of rays serves all sources).  Each source is a
+ * ball of radius lst->radius around its position; the listener is the point
+ * lst->pos.  Ray i leaves the listener uniformly on the sphere (counter
+ * (i, pair_base, 0, 0)) and reflects as in trace_ir.  Contributions, scored
+ * with the track-length estimator of trace_ir into the histogram of source s:
+ *   - at the listener and at each reflection k (1 <= k <= max_bounces, before
+ *     the window end), one query per source: a direction drawn uniformly in
+ *     the cone the ball subtends (counter (i, pair_base, k, 1 + s)), followed
+ *     to its nearest hit; weight Omega / (4 pi) at the listener, and
+ *     (1 - alpha_b) s_b cos Omega / pi times the band energy at a reflection
+ *     (Omega the cone's solid angle);
+ *   - every segment after a specular reflection, at every ball.
+ * SH are those of the ray's first direction (its arrival direction at the
+ * listener), or of the query direction for the direct sound.
+ *   srcs      host [n_src], 1 <= n_src <= 256 (0 returns at once)
+ *   lst       host: listener point, source ball radius (> 0)
+ *   p         host; flags must be 0
+ *   hist, hist_late, stats: as in trace_ir.  The path statistics (segments,
+ *             escapes, energies, n_next_event) belong to the one ray set and
+ *             are repeated in every record; e_class and the first bins are
+ *             per source.
+ *   ray_hash  device [ray_end - ray_begin] u32 (one per ray), or NULL: hit
+ *             triangles, bounce kinds and each query's outcome.
+ * Errors: RPR_EINVAL as trace_ir, or for more than 256 sources;
+ * RPR_EUNSUPPORTED if the per-wave LDS of the sources does not fit. */
+int trace_listener(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                   const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                   uint32_t* ray_hash, void* hip_stream);
 
 typedef struct {
     int32_t rt60_source; /* 0: all orders (default); 1: orders >= 3 only (hist_late) */

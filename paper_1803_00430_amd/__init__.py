@@ -104,6 +104,7 @@ IR_STATS_DTYPE = np.dtype([
     ("e_class", "<f8", (3, MAX_BANDS)), ("e_escaped", "<f8", (MAX_BANDS,)),
     ("e_alive_at_stop", "<f8", (MAX_BANDS,)), ("e_alive_at_bounce_cap", "<f8", (MAX_BANDS,)),
     ("e_absorbed", "<f8", (MAX_BANDS,)), ("n_node_visits", "<i8"), ("n_tri_tests", "<i8"),
+    ("n_next_event", "<i8"),
 ])
 REVERB_PARAMS_DTYPE = np.dtype([
     ("rt60", "<f4", (MAX_BANDS,)), ("rt60_range", "<i4", (MAX_BANDS,)), ("status", "<i4", (MAX_BANDS,)),
@@ -111,7 +112,7 @@ REVERB_PARAMS_DTYPE = np.dtype([
     ("g_reverb", "<f4", (MAX_BANDS,)), ("predelay_s", "<f4"), ("first_arrival_s", "<f4"),
     ("mean_free_path_m", "<f4"), ("reserved", "<f4"), ("dir_loudness", "<f4", (MAX_BANDS, MAX_COEFFS)),
 ])
-assert IR_STATS_DTYPE.itemsize == 520 and REVERB_PARAMS_DTYPE.itemsize == 752
+assert IR_STATS_DTYPE.itemsize == 528 and REVERB_PARAMS_DTYPE.itemsize == 752
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -124,6 +125,8 @@ SIGNATURES = {
     "scene_info": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
     "trace_ir": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp, _vp,
                            _vp, _vp, _vp]),
+    "trace_listener": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp,
+                                 _vp, _vp, _vp, _vp]),
     "estimate_reverb": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, C.c_float, C.POINTER(EstimateParams),
                                   _vp, _vp]),
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -290,6 +293,22 @@ def trace_ir(scene: Scene, sources, listener, radius, params: TraceParams, hist,
     lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
     _check(lib().trace_ir(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist), _ptr(hist_late),
                           _ptr(stats), _ptr(ray_hash), _stream(stream)))
+
+
+def trace_listener(scene: Scene, sources, listener, radius, params: TraceParams, hist, hist_late, stats,
+                   ray_hash=None, stream=None):
+    """Enqueue trace_listener (listener point, source balls of `radius`) on
+    `stream` into caller-allocated tensors; `ray_hash` is [n_rays] (one per
+    ray) or None."""
+    srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float32)
+    n = len(srcs)
+    src_arr = (Source * max(n, 1))()
+    for i in range(n):
+        src_arr[i].pos[:] = [float(x) for x in srcs[i]]
+    lp = np.asarray(listener, np.float32)
+    lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
+    _check(lib().trace_listener(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist),
+                                _ptr(hist_late), _ptr(stats), _ptr(ray_hash), _stream(stream)))
 
 
 def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width_s, out, rt60_source=0,

@@ -155,8 +155,9 @@ __device__ __forceinline__ float safe_inv(float d)
 // children are ordered by entry distance, the nearest is visited next and the
 // others are pushed farthest first.  The leaf `exclude` (sorted index) is
 // skipped: the triangle the ray just left.  Ties in t go to the lower
-// original triangle index.  Returns the sorted leaf index of the hit or -1,
-// with t in `t_hit`.
+// original triangle index.  Only hits closer than `tmax` count (an occlusion
+// query passes the distance it needs).  Returns the sorted leaf index of the
+// hit or -1, with t in `t_hit` (tmax when there is none).
 __device__ __forceinline__ void cswap(float& ta, int32_t& la, float& tb, int32_t& lb)
 {
     const bool s = tb < ta;
@@ -172,10 +173,10 @@ template <int STACK, bool COUNT = false>
 __device__ __forceinline__ int closest_hit(const SceneView& sc, float ox, float oy, float oz, float dx, float dy,
                                            float dz, int exclude, int32_t* __restrict__ stack, int lane,
                                            float& t_hit, uint32_t& hit_id, uint32_t* n_nodes = nullptr,
-                                           uint32_t* n_tris = nullptr)
+                                           uint32_t* n_tris = nullptr, float tmax = __builtin_inff())
 {
     const float inf = __builtin_inff();
-    float tb = inf;
+    float tb = tmax;
     int best = -1;
     uint32_t best_id = 0xFFFFFFFFu;
     if (sc.n_tris <= 0) {

@@ -401,7 +401,7 @@ __device__ __forceinline__ void stats_init(RprIrStats* S)
     S->e_emitted = 0.0;
     S->first_arrival_bin = INT_MAX;
     S->first_late_bin = INT_MAX;
-    S->n_node_visits = S->n_tri_tests = 0;
+    S->n_node_visits = S->n_tri_tests = S->n_next_event = 0;
     for (int b = 0; b < RPR_MAX_BANDS; ++b) {
         S->e_class[0][b] = S->e_class[1][b] = S->e_class[2][b] = 0.0;
         S->e_escaped[b] = S->e_alive_at_stop[b] = S->e_alive_at_bounce_cap[b] = S->e_absorbed[b] = 0.0;

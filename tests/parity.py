@@ -111,3 +111,59 @@ def assert_stats_close(sg, so, rel=1e-5):
         assert np.all(np.abs(sg[k] - so[k]) <= 1e-4 * scale + 1e-15), (k, sg[k], so[k])
     scale = np.abs(so["e_class"]).max(axis=0) + 1e-30
     assert np.all(np.abs(sg["e_class"] - so["e_class"]) <= HIST_TOL * scale[None]), (sg["e_class"], so["e_class"])
+
+
+def gpu_trace_listener(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray_end=None, max_bounces,
+                       sh_order, n_bins, bin_width_s, seed, pair_base=0, want_hash=True):
+    import torch
+    if ray_end is None:
+        ray_end = n_rays_total
+    srcs = np.atleast_2d(np.asarray(sources, np.float32))
+    nb = scene.n_bands
+    hist, late, stats, _ = P.alloc_trace_outputs(len(srcs), n_bins, nb, sh_order)
+    rh = torch.empty(ray_end - ray_begin, dtype=torch.int32, device="cuda") if want_hash else None
+    prm = P.trace_params(n_rays_total=n_rays_total, ray_begin=ray_begin, ray_end=ray_end,
+                         max_bounces=max_bounces, sh_order=sh_order, n_bins=n_bins, bin_width_s=bin_width_s,
+                         seed=seed, pair_base=pair_base)
+    P.trace_listener(scene, srcs, listener, radius, prm, hist, late, stats, rh)
+    torch.cuda.synchronize()
+    return dict(hist=hist.double().cpu().numpy(), hist_late=late.double().cpu().numpy(),
+                stats=P.stats_host(stats), ray_hash=None if rh is None else rh.cpu().numpy().view(np.uint32),
+                _dev=(hist, late, stats))
+
+
+_RAYSET_KEYS = ("n_segments", "n_finite_segments", "n_escaped", "n_rays", "seg_len_sum", "e_emitted",
+                "e_escaped", "e_alive_at_stop", "e_alive_at_bounce_cap", "e_absorbed")
+
+
+def traced_listener_pair(scene, sd, sources, listener, radius, **kw):
+    """trace_listener on both sides; rays whose discrete path (hit
+    triangles, bounce kinds, occlusion outcomes) differs are traced again
+    alone on both sides and removed from every source's result.  Returns
+    (gpu, oracle, divergent ray indices)."""
+    g = gpu_trace_listener(scene, sources, listener, radius, **kw)
+    okw = {k: v for k, v in kw.items() if k != "want_hash"}
+    o = oracle.trace_listener(sd, sources, listener, radius, want_hash=True, **okw)
+    srcs = np.atleast_2d(np.asarray(sources, np.float32))
+    nb = scene.n_bands
+    S = len(srcs)
+    gs = [_stats_vec(g["stats"][s], nb) for s in range(S)]
+    os_ = [_stats_vec(o["stats"][s], nb) for s in range(S)]
+    div = np.flatnonzero(g["ray_hash"] != o["ray_hash"])
+    rb = kw.get("ray_begin", 0)
+    for i in div:
+        one = dict(kw, ray_begin=rb + int(i), ray_end=rb + int(i) + 1)
+        g1 = gpu_trace_listener(scene, srcs, listener, radius, **one)
+        o1 = oracle.trace_listener(sd, srcs, listener, radius, **{k: v for k, v in one.items() if k != "want_hash"})
+        for s in range(S):
+            g["hist"][s] -= g1["hist"][s]
+            g["hist_late"][s] -= g1["hist_late"][s]
+            o["hist"][s] -= o1["hist"][s]
+            o["hist_late"][s] -= o1["hist_late"][s]
+            for side, res in ((gs, g1["stats"][s]), (os_, o1["stats"][s])):
+                v1 = _stats_vec(res, nb)
+                for key in _RAYSET_KEYS + ("e_class",):
+                    side[s][key] = side[s][key] - v1[key]
+    g["cmp_stats"] = gs
+    o["cmp_stats"] = os_
+    return g, o, div

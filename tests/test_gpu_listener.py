@@ -1,0 +1,125 @@
+"""GPU parity of the listener-origin trace with next-event estimation
+(`trace_listener`) against the FP64 oracle, through the C ABI.
+
+Tolerances as for the source-origin trace: histograms within 1e-4 of each
+bin-band-coefficient row's absolute sum, RT60 within 1%.  Rays whose
+discrete path differs between FP32 and FP64 (hit triangles, bounce kinds,
+and here also the outcome of every occlusion query) are traced again alone
+on both sides and removed; each test states the fraction it allows."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1803_00430_amd as P
+import rpr_scenes as R
+from parity import RT60_TOL, assert_hist_close, assert_stats_close, gpu_trace_listener, traced_listener_pair
+from test_gpu_trace import _cluttered_room
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return torch
+
+
+def _tiny_kw(c, **over):
+    kw = dict(n_rays_total=c["n_rays"], max_bounces=c["max_bounces"], sh_order=c["sh_order"],
+              n_bins=c["n_bins"], bin_width_s=c["bin_width_s"], seed=c["seed"])
+    kw.update(over)
+    return kw
+
+
+def test_listener_tiny_parity(torch_cuda):
+    """The tiny shoebox (4096 rays, 50 bounces, 2000 x 1 ms, SH order 2),
+    traced from the listener point with the source as a 0.5 m ball."""
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    kw = _tiny_kw(c)
+    g, o, div = traced_listener_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
+    print(f"divergent rays: {len(div)} of {c['n_rays']}")
+    assert len(div) <= 0.02 * c["n_rays"], len(div)
+    assert_hist_close(g["hist"][0], o["hist"][0])
+    assert_hist_close(g["hist_late"][0], o["hist_late"][0], what="hist_late")
+    assert_stats_close(g["cmp_stats"][0], o["cmp_stats"][0])
+    assert int(g["stats"][0]["n_next_event"]) > 0
+    out = P.alloc_params(1)
+    hist, late, stats = g["_dev"]
+    P.estimate_reverb(hist, late, stats, c["n_bins"], 4, c["sh_order"], c["bin_width_s"], out)
+    pg = P.params_host(out)[0]
+    po = oracle.estimate_reverb(o["hist"][0], o["hist_late"][0], o["stats"][0], c["bin_width_s"])
+    assert np.all(np.abs(pg["rt60"][:4] - po["rt60"]) <= RT60_TOL * po["rt60"])
+    assert np.array_equal(pg["rt60_range"][:4], po["rt60_range"])
+
+
+def test_listener_ragged_multisource_parity(torch_cuda):
+    """Cluttered room (thousands of triangles, 3 materials), three sources
+    of which boxes hide parts, a ray count that is not a multiple of the
+    wave, SH order 3, a 250 ms window."""
+    sd = _cluttered_room(7, n_boxes=25, edge=1.1)
+    sc = P.Scene.from_dict(sd)
+    srcs = np.array([[1.0, 1.0, 1.2], [6.0, 4.5, 2.0], [10.5, 8.0, 3.1]], np.float32)
+    lst = np.array([5.0, 5.0, 1.6], np.float32)
+    kw = dict(n_rays_total=1000, max_bounces=100, sh_order=3, n_bins=250, bin_width_s=1e-3, seed=78,
+              pair_base=9)
+    g, o, div = traced_listener_pair(sc, sd, srcs, lst, 0.6, **kw)
+    print(f"divergent rays: {len(div)} of 1000")
+    assert len(div) <= 0.15 * 1000, len(div)
+    for s in range(3):
+        assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
+        assert_hist_close(g["hist_late"][s], o["hist_late"][s], what=f"hist_late[{s}]")
+        assert_stats_close(g["cmp_stats"][s], o["cmp_stats"][s])
+        assert g["stats"][s]["first_arrival_bin"] == o["stats"][s]["first_arrival_bin"]
+
+
+def test_listener_subsets_and_statistics(torch_cuda):
+    """Disjoint ray ranges add up and keep their hashes; the path statistics
+    are the same in every source's record."""
+    sd = _cluttered_room(7, n_boxes=25, edge=1.1)
+    sc = P.Scene.from_dict(sd)
+    srcs = np.array([[1.0, 1.0, 1.2], [10.5, 8.0, 3.1]], np.float32)
+    lst = np.array([5.0, 5.0, 1.6], np.float32)
+    kw = dict(n_rays_total=3000, max_bounces=40, sh_order=1, n_bins=300, bin_width_s=1e-3, seed=5)
+    full = gpu_trace_listener(sc, srcs, lst, 0.6, **kw)
+    a = gpu_trace_listener(sc, srcs, lst, 0.6, ray_end=1111, **kw)
+    b = gpu_trace_listener(sc, srcs, lst, 0.6, ray_begin=1111, **kw)
+    assert np.array_equal(np.concatenate([a["ray_hash"], b["ray_hash"]]), full["ray_hash"])
+    for s in range(2):
+        assert_hist_close(a["hist"][s] + b["hist"][s], full["hist"][s], tol=1e-6)
+    st = full["stats"]
+    for k in ("n_segments", "n_escaped", "n_rays", "n_next_event", "seg_len_sum"):
+        assert st[0][k] == st[1][k], k
+    assert st[0]["n_rays"] == 3000
+
+
+@pytest.mark.parametrize("scat", [[0.5, 0.5, 0.5, 0.5], [0.05, 0.35, 0.65, 0.95]])
+def test_listener_zero_absorption_late_field(torch_cuda, scat):
+    """Closed room without absorption: dt / V per bin in every band."""
+    c = R.tiny_config()
+    sd = dict(c, absorption=np.zeros((1, 4), np.float32), scattering=np.array([scat], np.float32))
+    sc = P.Scene.from_dict(sd)
+    g = gpu_trace_listener(sc, c["sources"], c["listener"], c["radius"],
+                           **_tiny_kw(c, n_rays_total=65536, max_bounces=100000, sh_order=0), want_hash=False)
+    I = math.sqrt(4 * math.pi) * g["hist"][0][:, :, 0]
+    late = I[300:].mean(axis=0)
+    assert np.all(np.abs(late / (1e-3 / 210.0) - 1) < 0.02), late
+
+
+def test_listener_rejects_bad_arguments(torch_cuda):
+    c = R.tiny_config()
+    sc = P.Scene.from_dict(c)
+    hist, late, stats, _ = P.alloc_trace_outputs(300, 100, 4, 1)
+    prm = P.trace_params(n_rays_total=64, max_bounces=3, sh_order=1, n_bins=100, bin_width_s=1e-3, seed=0)
+    with pytest.raises(P.RprError):
+        P.trace_listener(sc, np.zeros((257, 3)), c["listener"], 0.5, prm, hist, late, stats)
+    with pytest.raises(P.RprError):
+        P.trace_listener(sc, c["sources"], c["listener"], 0.0, prm, hist, late, stats)
+    bad = P.trace_params(n_rays_total=64, max_bounces=3, sh_order=1, n_bins=100, bin_width_s=1e-3, seed=0,
+                         flags=1)
+    with pytest.raises(P.RprError):
+        P.trace_listener(sc, c["sources"], c["listener"], 0.5, bad, hist, late, stats)
