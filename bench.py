@@ -51,10 +51,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital"), default="city",
+    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms"), default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
                          "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
-                         "learned estimator vs plain ray trace (builds its dataset and trains first)")
+                         "learned estimator vs plain ray trace (builds its dataset and trains first); rooms: "
+                         "IRs/s at <= 5%% RT60 error of the plain trace from the sources vs from the listener "
+                         "with next-event estimation")
     ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
@@ -62,7 +64,19 @@ def parse():
     ap.add_argument("--learn-target-rays", type=int, default=65536, help="rays of each training target trace")
     ap.add_argument("--learn-target-err", type=float, default=0.048,
                     help="mean RT60 error the gate is tuned to on the calibration rooms (margin below 5%%)")
+    ap.add_argument("--rooms-rays", type=int, default=0,
+                    help="rooms: skip the references and sweeps, and time only --method at this ray count "
+                         "(for profiling)")
     ap.add_argument("--frames", type=int, default=8, help="frames of the hospital workload")
+    ap.add_argument("--method", choices=("source", "listener"), default="source",
+                    help="hospital: trace from every source to the listener sphere (source), or from the "
+                         "listener with next-event estimation toward every source ball (listener)")
+    ap.add_argument("--rays", type=int, default=0,
+                    help="hospital: rays per source (source method) or of the listener (listener method); "
+                         "0 = the workload's 131,072")
+    ap.add_argument("--convergence", action="store_true",
+                    help="hospital: also trace frame 0 with two more independent seeds and report their mean "
+                         "RT60 disagreement")
     ap.add_argument("--learned", action="store_true",
                     help="hospital: also run the learned estimator inline (trains it first on --learn-train "
                          "rooms), with a ray-trace fallback for uncertain sources")
@@ -226,6 +240,90 @@ def run_learn(a):
     print(json.dumps(out), flush=True)
 
 
+def run_rooms(a):
+    """The plain method traced two ways over --learn-eval held-out rooms of the
+    learn workload (shoeboxes and L-rooms, dims U[3,40] m): from the source
+    to the listener sphere, and from the listener point with next-event
+    queries toward the source ball (r = 0.5 m).  For each, the smallest ray
+    count of a sweep whose mean RT60 error against independent 262,144-ray
+    source-origin references is <= 5% (N*), then IRs/s at N* as one
+    graph-captured batch (reset, trace, estimate) over all rooms.  The
+    listener batch deals the rooms' rays round-robin in 1,024-ray chunks
+    (every reflection deposits, and the interleave spreads the atomics over
+    many histograms); the source batch keeps the rooms in order."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+    from paper_1803_00430_amd import learn as L
+
+    q = a.quiet
+    rooms = [R.learn_room(200000 + i) for i in range(a.learn_eval)]
+    scenes = L.make_scenes(rooms)
+    fixed = a.rooms_rays > 0
+    ref = None if fixed else L.trace_rooms(scenes, rooms, n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024,
+                                           **L.CONVERGED)["params"]
+    res = {}
+    plans = (("source", 0, (16384, 32768, 65536, 131072)), ("listener", 2, (4096, 8192, 16384, 32768, 65536)))
+    if fixed:
+        plans = tuple((m, o, (a.rooms_rays,)) for m, o, _ in plans if m == a.method)
+    for method, order, Ns in plans:
+        sweep = {}
+        for N in Ns:
+            if fixed:
+                break
+            tr = L.trace_rooms(scenes, rooms, n_rays=N, seed_offset=L.SEED_SWEEP + N, chunk=1024, method=method,
+                               order=order, **L.CONVERGED)
+            sweep[N] = L.rt60_error_summary(L.rt60_error(tr["params"], ref, 4))
+            log(f"{method} N={N}: {sweep[N]}", q)
+        ok = [N for N in sweep if sweep[N]["mean"] <= 0.05]
+        n_star = Ns[0] if fixed else (min(ok) if ok else max(sweep))
+        b = P.Batch(scenes, [dict(p, pair_id=k) for k, p in
+                             enumerate(L.room_pairs(rooms, n_star, L.SEED_SWEEP + n_star))],
+                    n_bins=L.CONVERGED["n_bins"], sh_order=L.SH_ORDER, bin_width_s=L.CONVERGED["bin_width_s"],
+                    autotune=False, use_graph=True, late=False, method=method, order=order)
+        for _ in range(max(1, a.warmup)):
+            b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            b.run()
+        torch.cuda.synchronize()
+        dt_step = (time.perf_counter() - t0) / a.steps
+        st = P.stats_host(b.stats)
+        err = None if fixed else L.rt60_error_summary(L.rt60_error(b.params, ref, 4))
+        res[method] = {"n_star": n_star, "irs_per_s": len(rooms) / dt_step, "ms_per_replay": dt_step * 1e3,
+                       "rt60_err_at_n_star": err, "segments_per_replay": int(st["n_segments"].sum()),
+                       "next_event_queries_per_replay": int(st["n_next_event"].sum()),
+                       "deposit_rows_per_replay": int(st["n_deposit_rows"].sum()),
+                       "sweep": {str(k): v for k, v in sweep.items()}}
+        b.close()
+        log(f"{method}: N* {n_star}, {res[method]['irs_per_s']:.1f} IRs/s", q)
+    if fixed:
+        print(json.dumps({"workload": "rooms", "method": a.method, **res[a.method]}), flush=True)
+        return
+    lst = res["listener"]
+    # the replay is reset + trace + estimate; the trace kernel is all but < 1 ms of it (rocprofv3)
+    row_bytes = 2 * 4 * 4 * (L.SH_ORDER + 1) ** 2  # read and write of one bins x coefficients row
+    achieved = lst["deposit_rows_per_replay"] * row_bytes / (lst["ms_per_replay"] * 1e-3) / 1e9
+    out = {
+        "metric": "IRs/s at <=5% RT60 error, plain ray trace from the listener (next-event estimation) "
+                  "vs from the source", "value": lst["irs_per_s"], "unit": "IRs/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": lst["ms_per_replay"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"rooms: {len(rooms)} held-out shoebox/L-rooms (dims U[3,40] m, one source, "
+                               f"r = 0.5 m); step = one graph replay over all rooms at the method's N*; "
+                               f"262,144-ray references", "rooms": len(rooms)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_trace_lstp",
+                     "bytes_counted": "histogram atomics only (read + write of each deposited row); node and "
+                                      "triangle fetches of the two traversals per reflection are not counted"},
+        "listener": lst, "source": res["source"],
+        "speedup_listener_vs_source": lst["irs_per_s"] / res["source"]["irs_per_s"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_hospital(a):
     """Large interactive scene: a hospital-like interior of ~1M triangles
     (rooms 4-12 m on a grid, corridors, doorways, clutter), 64 sources moving
@@ -247,10 +345,15 @@ def run_hospital(a):
     build_ms = (time.perf_counter() - t0) * 1e3
     S = len(cfg["sources"])
     N, K, T, n, dt = cfg["n_rays"], cfg["max_bounces"], cfg["n_bins"], cfg["sh_order"], cfg["bin_width_s"]
+    if a.rays > 0:
+        N = a.rays
     B = cfg["absorption"].shape[1]
     hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
     params = P.alloc_params(S, device=dev)
     prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+    listener = a.method == "listener"
+    if listener and a.learned:
+        raise SystemExit("--learned runs with the source method only")
     x_max = float(cfg["verts"][:, 0].max()) - 2.5
     g = np.random.default_rng(7)
     heading = np.where(g.uniform(0, 1, S) < 0.5, -1.0, 1.0)
@@ -263,8 +366,11 @@ def run_hospital(a):
         src[:, 0] = 0.5 + np.where(x <= period / 2, x, period - x)
         return src.astype(np.float32)
 
-    def frame(f):
-        P.trace_ir(scene, sources_at(f), cfg["listener"], cfg["radius"], prm, hist, late, stats)
+    def frame(f, p=prm):
+        if listener:
+            P.trace_listener(scene, sources_at(f), cfg["listener"], cfg["radius"], p, hist, late, stats)
+        else:
+            P.trace_ir(scene, sources_at(f), cfg["listener"], cfg["radius"], p, hist, late, stats)
         P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
 
     for f in range(a.warmup):
@@ -276,21 +382,49 @@ def run_hospital(a):
         frame(f)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
-        segs += int(P.stats_host(stats)["n_segments"].sum())
+        st_ = P.stats_host(stats)["n_segments"]
+        segs += int(st_[0] if listener else st_.sum())  # the listener's ray set is repeated per source
         log(f"frame {f}: {times[-1] * 1e3:.1f} ms", q)
     times = np.array(times)
     ms = times.mean() * 1e3
+    queries = int(P.stats_host(stats)["n_next_event"][0]) if listener else 0
+    conv = None
+    if a.convergence:
+        rt, el = [], []
+        for extra in (1 << 40, 2 << 40):
+            prm2 = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt,
+                                  seed=cfg["seed"] + extra)
+            frame(0, prm2)
+            torch.cuda.synchronize()
+            ph = P.params_host(params)
+            rt.append(ph["rt60"][:, :B].astype(np.float64))
+            el.append(ph["e_late"][:, :B].astype(np.float64))
+        ok = (rt[0] > 0) & (rt[1] > 0)
+        dis = np.abs(rt[0] - rt[1])[ok] / (0.5 * (rt[0] + rt[1])[ok])
+        ok_e = (el[0] + el[1]) > 0
+        dis_e = np.abs(el[0] - el[1])[ok_e] / (0.5 * (el[0] + el[1])[ok_e])
+        conv = {"mean": float(dis.mean()), "p90": float(np.quantile(dis, 0.9)), "valid": int(ok.sum()),
+                "of": int(ok.size), "e_late_mean": float(dis_e.mean()),
+                "e_late_p90": float(np.quantile(dis_e, 0.9))}
+        log(f"RT60 disagreement between two seeds: mean {conv['mean']:.4f}, p90 {conv['p90']:.4f}; "
+            f"late energy: mean {conv['e_late_mean']:.4f}, p90 {conv['e_late_p90']:.4f}", q)
     learned = run_hospital_learned(a, P, scene, cfg, sources_at, params, frame) if a.learned else None
+    how = (f"traced from the listener point with {N} rays and next-event queries toward every source ball "
+           f"(r = {cfg['radius']} m)" if listener else f"{N} rays per source to the listener sphere")
     out = {
         "metric": "per-frame latency p50/p99 and IRs/s (plain ray trace)", "value": S / times.mean(),
         "unit": "IRs/s", "n_gpus": 1, "steps": a.frames, "warmup": a.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"hospital: {len(cfg['tris'])} triangles, {S} moving sources x {N} rays, "
+        "config": {"workload": f"hospital: {len(cfg['tris'])} triangles, {S} moving sources, {how}, "
                                f"{K} bounces, SH order {n}, {B} bands, {T} x 1 ms bins; step = one frame "
-                               f"(trace + estimate of every source; BVH built once)"},
+                               f"(trace + estimate of every source; BVH built once)", "method": a.method},
         "p50_ms": float(np.percentile(times, 50) * 1e3), "p99_ms": float(np.percentile(times, 99) * 1e3),
         "build_ms": build_ms, "ray_bounces_per_s": segs / times.sum(),
     }
+    if listener:
+        out["next_event_queries_per_frame"] = queries
+    if conv:
+        out["rt60_seed_disagreement"] = conv
     if learned:
         out["learned"] = learned
     scene.close()
@@ -398,6 +532,9 @@ def main():
         return
     if a.workload == "hospital":
         run_hospital(a)
+        return
+    if a.workload == "rooms":
+        run_rooms(a)
         return
     cfg = R.city_config()
     S = len(cfg["sources"])

@@ -113,6 +113,8 @@ typedef struct {
     int64_t n_node_visits; /* internal BVH nodes fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
     int64_t n_tri_tests;   /* triangle records fetched (with RPR_TRACE_COUNT_VISITS, else 0) */
     int64_t n_next_event;  /* trace_listener: next-event (occlusion) queries of the ray set; else 0 */
+    int64_t n_deposit_rows;/* listener-origin traces: histogram bin rows (n_bands x coefficients floats)
+                              added by deposits; else 0 */
 } RprIrStats;
 
 typedef struct {
@@ -263,7 +265,11 @@ typedef struct {
     int32_t autotune;     /* 1: time the candidate launch shapes at creation and keep the fastest */
     int32_t use_graph;    /* 1: capture the run (reset, trace, estimate) into a HIP graph */
     int32_t waves_per_cu; /* launch width when autotune = 0 (0 = library default) */
-    int32_t order;        /* queue order when autotune = 0: 0 as given, 1 most rays x bounces first */
+    int32_t order;        /* queue order when autotune = 0: 0 as given, 1 most rays x bounces first,
+                             2 interleaved (pairs split into 1,024-ray chunks dealt round-robin) */
+    int32_t method;       /* 0: each pair traced from its source to the listener sphere (trace_ir);
+                             1: from its listener point with next-event queries toward its source,
+                             a ball of the pair's radius (trace_listener, one source per pair) */
 } RprBatchParams;
 
 typedef struct {

@@ -74,7 +74,10 @@ class BatchParams(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("sh_order", C.c_int32), ("bin_width_s", C.c_float),
                 ("speed_of_sound", C.c_float), ("rt60_source", C.c_int32), ("tail_iters", C.c_int32),
                 ("autotune", C.c_int32), ("use_graph", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("order", C.c_int32)]
+                ("order", C.c_int32), ("method", C.c_int32)]
+
+
+METHODS = {"source": 0, "listener": 1}
 
 
 class BatchInfo(C.Structure):
@@ -104,7 +107,7 @@ IR_STATS_DTYPE = np.dtype([
     ("e_class", "<f8", (3, MAX_BANDS)), ("e_escaped", "<f8", (MAX_BANDS,)),
     ("e_alive_at_stop", "<f8", (MAX_BANDS,)), ("e_alive_at_bounce_cap", "<f8", (MAX_BANDS,)),
     ("e_absorbed", "<f8", (MAX_BANDS,)), ("n_node_visits", "<i8"), ("n_tri_tests", "<i8"),
-    ("n_next_event", "<i8"),
+    ("n_next_event", "<i8"), ("n_deposit_rows", "<i8"),
 ])
 REVERB_PARAMS_DTYPE = np.dtype([
     ("rt60", "<f4", (MAX_BANDS,)), ("rt60_range", "<i4", (MAX_BANDS,)), ("status", "<i4", (MAX_BANDS,)),
@@ -112,7 +115,7 @@ REVERB_PARAMS_DTYPE = np.dtype([
     ("g_reverb", "<f4", (MAX_BANDS,)), ("predelay_s", "<f4"), ("first_arrival_s", "<f4"),
     ("mean_free_path_m", "<f4"), ("reserved", "<f4"), ("dir_loudness", "<f4", (MAX_BANDS, MAX_COEFFS)),
 ])
-assert IR_STATS_DTYPE.itemsize == 528 and REVERB_PARAMS_DTYPE.itemsize == 752
+assert IR_STATS_DTYPE.itemsize == 536 and REVERB_PARAMS_DTYPE.itemsize == 752
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -354,11 +357,14 @@ def debug_sh_eval(dirs, order, stream=None):
 
 class Batch:
     """A planned batch of source-listener pairs over several scenes; `run()`
-    enqueues reset + trace + estimate (a graph replay when use_graph)."""
+    enqueues reset + trace + estimate (a graph replay when use_graph).
+    method "source" traces each pair from its source to the listener sphere;
+    "listener" from its listener point with next-event queries toward its
+    source, a ball of the pair's radius."""
 
     def __init__(self, scenes, pairs, *, n_bins, sh_order, bin_width_s, speed_of_sound=343.0, rt60_source=0,
                  tail_iters=3, autotune=True, use_graph=True, waves_per_cu=0, order=0, late=True, device="cuda",
-                 stream=None):
+                 stream=None, method="source"):
         import torch
         self.scenes = list(scenes)  # kept alive for the batch's lifetime
         n = len(pairs)
@@ -378,7 +384,8 @@ class Batch:
                                                                        late=late)
         self.params = alloc_params(n, device=device)
         bp = BatchParams(int(n_bins), int(sh_order), float(bin_width_s), float(speed_of_sound), int(rt60_source),
-                         int(tail_iters), int(bool(autotune)), int(bool(use_graph)), int(waves_per_cu), int(order))
+                         int(tail_iters), int(bool(autotune)), int(bool(use_graph)), int(waves_per_cu), int(order),
+                         METHODS[method])
         handles = (C.c_void_p * len(self.scenes))(*[sc.handle.value for sc in self.scenes])
         h = C.c_void_p()
         _check(lib().batch_create(handles, len(self.scenes), arr, n, C.byref(bp), _ptr(self.hist),

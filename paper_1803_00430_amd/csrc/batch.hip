@@ -33,9 +33,12 @@ struct RprBatch {
     int64_t total = 0;
     int stack_need = 0;
     int waves_per_cu = 0, order = 0;
+    int method = 0;  // 0 source-origin, 1 listener-origin
     RprEstimateParams ep{0, 3};
     std::vector<rpr::PairDesc> pairs;  // caller order
-    rpr::PairDesc* d_pairs = nullptr;  // queue order
+    rpr::PairDesc* d_pairs = nullptr;  // queue order (pairs, or chunks of pairs when interleaved)
+    int n_table = 0;                   // descriptors in d_pairs
+    int64_t table_cap = 0;
     unsigned long long* d_queue = nullptr;
     float* hist = nullptr;
     float* hist_late = nullptr;
@@ -50,9 +53,18 @@ namespace rpr {
 namespace {
 
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
 
-// Upload the pair table in queue order `ord` (indices into b.pairs).
+constexpr int64_t kInterleaveChunk = 1024;
+
+// Upload the pair table in queue order `ord` (indices into b.pairs): 0 as
+// given, 1 most rays x bounces first, 2 interleaved -- every pair split into
+// chunks of kInterleaveChunk rays, dealt round-robin across the pairs, so
+// that the resident waves work on many pairs' histograms at once instead of
+// contending for the atomics of a few.  A chunk is a copy of its pair's
+// descriptor with its own ray range; the energy normalisation, outputs and
+// statistics stay the pair's.  The listener-origin kernel always takes a
+// table of chunks (one wave per chunk), in pair order for orders 0 and 1.
 int upload_order(RprBatch& b, int ord, hipStream_t st)
 {
     std::vector<int> idx(b.n_pairs);
@@ -64,15 +76,50 @@ int upload_order(RprBatch& b, int ord, hipStream_t st)
             return cx > cy;
         });
     }
-    std::vector<PairDesc> q(b.n_pairs);
-    int64_t off = 0;
-    for (int i = 0; i < b.n_pairs; ++i) {
-        q[i] = b.pairs[idx[i]];
-        q[i].queue_begin = off;
-        off += q[i].n_rays;
+    std::vector<PairDesc> q;
+    if (ord != 2 && b.method == 1) {
+        for (int i = 0; i < b.n_pairs; ++i) {
+            const PairDesc& P = b.pairs[idx[i]];
+            for (int64_t o = 0; o < P.n_rays; o += kInterleaveChunk) {
+                PairDesc c = P;
+                c.ray_begin = P.ray_begin + o;
+                c.n_rays = std::min(kInterleaveChunk, P.n_rays - o);
+                q.push_back(c);
+            }
+        }
+    } else if (ord == 2) {
+        std::vector<int64_t> next(b.n_pairs, 0);
+        for (bool more = true; more;) {
+            more = false;
+            for (int i = 0; i < b.n_pairs; ++i) {
+                const PairDesc& P = b.pairs[i];
+                if (next[i] >= P.n_rays) continue;
+                PairDesc c = P;
+                c.ray_begin = P.ray_begin + next[i];
+                c.n_rays = std::min(kInterleaveChunk, P.n_rays - next[i]);
+                next[i] += c.n_rays;
+                q.push_back(c);
+                more = more || next[i] < P.n_rays;
+            }
+        }
+    } else {
+        for (int i = 0; i < b.n_pairs; ++i) q.push_back(b.pairs[idx[i]]);
     }
-    RPR_HIP_TRY(hipMemcpyAsync(b.d_pairs, q.data(), sizeof(PairDesc) * b.n_pairs, hipMemcpyHostToDevice, st));
+    int64_t off = 0;
+    for (auto& d : q) {
+        d.queue_begin = off;
+        off += d.n_rays;
+    }
+    if ((int64_t)q.size() > b.table_cap) {
+        if (b.d_pairs) (void)hipFree(b.d_pairs);
+        b.d_pairs = nullptr;
+        b.table_cap = 0;
+        RPR_HIP_TRY(hipMalloc(&b.d_pairs, sizeof(PairDesc) * q.size()));
+        b.table_cap = (int64_t)q.size();
+    }
+    RPR_HIP_TRY(hipMemcpyAsync(b.d_pairs, q.data(), sizeof(PairDesc) * q.size(), hipMemcpyHostToDevice, st));
     RPR_HIP_TRY(hipStreamSynchronize(st));
+    b.n_table = (int)q.size();
     b.order = ord;
     return RPR_OK;
 }
@@ -88,7 +135,11 @@ int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t
         if (rc != RPR_OK) return rc;
     }
     if (t0) RPR_HIP_TRY(hipEventRecord(t0, st));
-    rc = launch_trace(b.d_pairs, b.n_pairs, b.d_queue, b.total, b.nb, b.stack_need, false, b.waves_per_cu, 0, st);
+    rc = b.method == 1
+             ? launch_trace_listener_pairs(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_need,
+                                           b.waves_per_cu, st)
+             : launch_trace(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_need, false, b.waves_per_cu, 0,
+                            st);
     if (rc != RPR_OK) return rc;
     if (t1) RPR_HIP_TRY(hipEventRecord(t1, st));
     return estimate_reverb(b.hist, b.hist_late, b.stats, b.n_pairs, b.T, b.nb, b.sh_order, b.dt, &b.ep, b.params,
@@ -144,9 +195,9 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     if (!scenes || n_scenes < 1 || !pairs || n_pairs < 1 || !bp || !hist || !stats || !params)
         return set_error(RPR_EINVAL, "batch_create: null or empty argument");
     if (bp->n_bins < 1 || bp->sh_order < 0 || bp->sh_order > RPR_MAX_SH_ORDER || !(bp->bin_width_s > 0.f) ||
-        !(bp->speed_of_sound > 0.f) || bp->waves_per_cu < 0 || bp->order < 0 || bp->order > 1 ||
+        !(bp->speed_of_sound > 0.f) || bp->waves_per_cu < 0 || bp->order < 0 || bp->order > 2 ||
         bp->tail_iters < 0 || bp->tail_iters > 100 || (bp->rt60_source != 0 && bp->rt60_source != 1) ||
-        (bp->rt60_source == 1 && !hist_late))
+        (bp->rt60_source == 1 && !hist_late) || (bp->method != 0 && bp->method != 1))
         return set_error(RPR_EINVAL, "batch_create: bad batch parameters");
     const int nb = scenes[0] ? scenes[0]->n_bands : 0;
     int stack_need = 1;
@@ -179,6 +230,7 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     b->dt = bp->bin_width_s;
     b->total = total;
     b->stack_need = stack_need;
+    b->method = bp->method;
     b->ep = RprEstimateParams{bp->rt60_source, bp->tail_iters};
     b->hist = hist;
     b->hist_late = hist_late;
@@ -220,18 +272,18 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         batch_free(b);
         return code;
     };
-    if (hipMalloc(&b->d_pairs, sizeof(PairDesc) * n_pairs) != hipSuccess ||
-        hipMalloc(&b->d_queue, 256) != hipSuccess)
+    if (hipMalloc(&b->d_queue, 256) != hipSuccess)
         return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
     if (device_cu_count() <= 0) return fail(set_error(RPR_EDEVICE, "batch_create: no device"));
-    const int max_wpc = trace_max_waves_per_cu(nb, stack_need);
+    const int max_wpc = bp->method == 1 ? trace_listener_max_waves_per_cu(nb, stack_need)
+                                        : trace_max_waves_per_cu(nb, stack_need);
 
     // launch shape: cached, autotuned or as requested
     int rc = RPR_OK;
     b->info.n_candidates = 0;
     if (bp->autotune) {
         const int bucket = (int)std::floor(std::log2((double)total));
-        const auto key = std::make_tuple(b->device, n_pairs, bucket, stack_need <= 32 ? 32 : 64);
+        const auto key = std::make_tuple(b->device, n_pairs, bucket, stack_need <= 32 ? 32 : 64, b->method);
         bool cached = false;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -251,7 +303,7 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
                 if (w >= 1 && std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
             float best = 1e30f, worst = 0.f;
             int best_w = max_wpc, best_o = 0;
-            for (int o = 0; o < 2; ++o) {
+            for (int o = 0; o < 3; ++o) {
                 rc = upload_order(*b, o, st);
                 if (rc != RPR_OK) return fail(rc);
                 for (int w : widths) {

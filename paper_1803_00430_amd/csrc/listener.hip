@@ -30,6 +30,7 @@
 
 #include "rpr_device.hpp"
 #include "rpr_internal.hpp"
+#include "trace_acc.hpp"
 
 namespace rpr {
 namespace {
@@ -54,14 +55,47 @@ struct LstDesc {
     int64_t hist_stride, late_stride;
 };
 
+// The 16 real SH of order <= 3 of a unit direction into row[0..15].
+__device__ __forceinline__ void sh_row(float x, float y, float z, float* __restrict__ row)
+{
+#pragma unroll
+    for (int c = 0; c < RPR_MAX_COEFFS; ++c) row[c] = sh_coeff(c, x, y, z);
+}
+
+// Value of lane l (wave-uniform) of a float.
+__device__ __forceinline__ float lane_f(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Each lane's (band, coefficient) in the two 64-float blocks of a bin row
+// (B x (n+1)^2 <= 128 floats), fixed for a launch, and 1 / bin width.
+struct RowMap {
+    int b0, c0, b1, c1;
+    float inv_dt;
+};
+
+__device__ __forceinline__ RowMap row_map(int lane, int nc, float dt)
+{
+    RowMap r;
+    r.b0 = lane / nc;
+    r.c0 = lane % nc;
+    r.b1 = (lane + kWave) / nc;
+    r.c1 = (lane + kWave) % nc;
+    r.inv_dt = 1.0f / dt;
+    return r;
+}
+
 // Deposit, for every lane with `has` set, the chord [ta, tb] (in seconds of
-// propagation time) of source s with band energies e[] and SH direction
-// (x, y, z), as the wave-cooperative row update of the source-origin trace.
+// propagation time) of source s with band energies e[] and the SH row that
+// the lane keeps in shrow (LDS, 16 per lane), as the wave-cooperative row
+// update of the source-origin trace.
 // Class energies (double) and first bins go to this wave's LDS accumulators.
 template <int NB>
 __device__ __forceinline__ void wave_deposit(const LstDesc& D, int s, bool has, float ta, float tb, const float* e,
-                                             float x, float y, float z, int order, int lane,
-                                             double* __restrict__ cls_acc, int* __restrict__ first_acc)
+                                             const float* __restrict__ shrow, int order, int lane, const RowMap& rm,
+                                             double* __restrict__ cls_acc, int* __restrict__ first_acc,
+                                             uint32_t& rows)
 {
     uint64_t dm = __ballot(has);
     if (!dm) return;
@@ -73,24 +107,24 @@ __device__ __forceinline__ void wave_deposit(const LstDesc& D, int s, bool has, 
     while (dm) {
         const int l = __ffsll((unsigned long long)dm) - 1;
         dm &= dm - 1;
-        const float a = __shfl(ta, l), b_ = __shfl(tb, l);
-        const float ax = __shfl(x, l), ay = __shfl(y, l), az = __shfl(z, l);
-        const int kk = __builtin_amdgcn_readfirstlane(__shfl(order, l));
+        const float a = lane_f(ta, l), b_ = lane_f(tb, l);
+        const int kk = __builtin_amdgcn_readlane(order, l);
         float Eb[NB];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) Eb[b] = __shfl(e[b], l);
-        int m0 = (int)floorf(a / dt);
+        for (int b = 0; b < NB; ++b) Eb[b] = lane_f(e[b], l);
+        int m0 = (int)floorf(a * rm.inv_dt);
+        if ((float)m0 * dt > a) --m0;  // never start past the chord
         m0 = m0 < 0 ? 0 : m0;
         float sum_dtau = 0.f;
-        int first_m = INT_MAX;
+        int first_m = INT_MAX, n_rows = 0;
         for (int base = 0; base < nbc; base += kWave) {
             const int j = base + lane;
             const bool act = j < nbc;
-            const int b = act ? j / nc : 0, ci = act ? j % nc : 0;
+            const int b = act ? (base ? rm.b1 : rm.b0) : 0, ci = act ? (base ? rm.c1 : rm.c0) : 0;
             float eb = 0.f;
 #pragma unroll
             for (int bb = 0; bb < NB; ++bb) eb = (bb == b) ? Eb[bb] : eb;
-            const float val = eb * sh_coeff(ci, ax, ay, az) * inv_vs;
+            const float val = eb * shrow[l * RPR_MAX_COEFFS + ci] * inv_vs;
             const bool late = act && kk >= 3 && ci == 0 && hlate != nullptr;
             for (int m = m0; m < T; ++m) {
                 const float lo = fmaxf(a, (float)m * dt);
@@ -103,10 +137,12 @@ __device__ __forceinline__ void wave_deposit(const LstDesc& D, int s, bool has, 
                     if (base == 0) {
                         sum_dtau += dtau;
                         first_m = min(first_m, m);
+                        ++n_rows;
                     }
                 }
             }
         }
+        rows += (uint32_t)n_rows;
         const int cls = kk == 0 ? 0 : (kk <= 2 ? 1 : 2);
 #pragma unroll
         for (int b = 0; b < NB; ++b)
@@ -133,10 +169,81 @@ __device__ __forceinline__ bool ball_chord(float ox, float oy, float oz, float d
     return tb > ta;
 }
 
+// Occlusion query of a next-event segment: the nearest hit in (0, tb) of
+// o + t d, except that any hit at t <= ta (before the ball's chord begins)
+// ends the search at once, since the segment is then occluded whatever lies
+// nearer.  The excluded leaf is the vertex's own triangle.  Returns that
+// first blocking t (<= ta), else the nearest hit in (ta, tb), else tb: the
+// same three outcomes as the nearest-hit definition.  Traversal as
+// closest_hit (4-wide nodes, per-lane LDS stack, internal and leaf loops).
+template <int STACK>
+__device__ __forceinline__ float occlusion_query(const SceneView& sc, float ox, float oy, float oz, float dx,
+                                                 float dy, float dz, float ta, float tb, int exclude,
+                                                 int32_t* __restrict__ stack, int lane)
+{
+    const float inf = __builtin_inff();
+    if (sc.n_tris <= 0) return tb;
+    const float ix = safe_inv(dx), iy = safe_inv(dy), iz = safe_inv(dz);
+    const float oix = ox * ix, oiy = oy * iy, oiz = oz * iz;
+    int sp = 0;
+    int32_t node = sc.root;
+    float tcur = tb;
+    for (;;) {
+        bool done = false;
+        while (!is_leaf(node)) {
+            const float4* nd = sc.nodes + (int64_t)kNode4 * node;
+            float t[4];
+            int32_t l[4];
+            float4 na[4], nb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                na[j] = gld(nd + 2 * j);
+                nb[j] = gld(nd + 2 * j + 1);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 a = na[j], b = nb[j];
+                float tn;
+                const bool h = slab(a.x, a.y, a.z, b.x, b.y, b.z, oix, oiy, oiz, ix, iy, iz, tcur, tn);
+                t[j] = h ? tn : inf;
+                l[j] = __float_as_int(a.w);
+            }
+            cswap(t[0], l[0], t[1], l[1]);
+            cswap(t[2], l[2], t[3], l[3]);
+            cswap(t[0], l[0], t[2], l[2]);
+            cswap(t[1], l[1], t[3], l[3]);
+            cswap(t[1], l[1], t[2], l[2]);
+            if (t[0] < inf) {
+#pragma unroll
+                for (int j = 3; j >= 1; --j)
+                    if (t[j] < inf && sp < STACK) stack[sp++ * kWave + lane] = l[j];
+                node = l[0];
+            } else if (sp > 0) {
+                node = stack[--sp * kWave + lane];
+            } else {
+                done = true;
+                break;
+            }
+        }
+        if (done) break;
+        const int li = leaf_index(node);
+        if (li != exclude) {
+            const float4* tr = sc.tris + 3 * (int64_t)li;
+            const float th = tri_test(gld(tr), gld(tr + 1), gld(tr + 2), ox, oy, oz, dx, dy, dz);
+            if (th <= ta) return th;
+            if (th < tcur) tcur = th;
+        }
+        if (sp == 0) break;
+        node = stack[--sp * kWave + lane];
+    }
+    return tcur;
+}
+
 template <int NB, int STACK>
 __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned long long* __restrict__ queue)
 {
     __shared__ int32_t stk[STACK * kWave];
+    __shared__ float shrow[kWave * RPR_MAX_COEFFS];  // SH of each lane's arrival direction
     extern __shared__ double dyn[];
     double* cls_acc = dyn;                                     // [n_src][3][NB]
     int* first_acc = (int*)(dyn + (size_t)D.n_src * 3 * NB);   // [n_src][2]
@@ -149,6 +256,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
     const SceneView& sc = D.scene;
     const int nbr = sc.n_bands;
     const long long total = D.n_rays;
+    const RowMap rm = row_map(lane, D.n_coeffs, D.dt);
     bool alive = false, spec = false, nee = false, nee_lst = false;
     uint32_t ray = 0;
     long long rl = 0;
@@ -165,7 +273,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
     float F[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) E[b] = Q[b] = F[b] = 0.f;
-    uint32_t a_seg = 0, a_fin = 0, a_esc = 0, a_rays = 0, a_nq = 0;
+    uint32_t a_seg = 0, a_fin = 0, a_esc = 0, a_rays = 0, a_nq = 0, a_rows = 0;  // a_rows: wave-uniform
     double a_len = 0.0;
     float a_esc_e[NB], a_alive[NB], a_cap[NB], a_absb[NB];
 #pragma unroll
@@ -193,6 +301,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                         ax = dx;
                         ay = dy;
                         az = dz;
+                        sh_row(ax, ay, az, shrow + lane * RPR_MAX_COEFFS);
                         ox = vx = D.lst[0];
                         oy = vy = D.lst[1];
                         oz = vz = D.lst[2];
@@ -267,10 +376,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                     if (g > 0.f && ball_chord(vx, vy, vz, wx, wy, wz, __builtin_inff(), ps, D.r2, ta, tb) &&
                         vL + ta < D.l_window) {
                         ++a_nq;
-                        float t_occ;
-                        uint32_t id;
-                        closest_hit<STACK>(sc, vx, vy, vz, wx, wy, wz, vexcl, stk, lane, t_occ, id, nullptr, nullptr,
-                                           tb);
+                        const float t_occ = occlusion_query<STACK>(sc, vx, vy, vz, wx, wy, wz, ta, tb, vexcl, stk, lane);
                         if (t_occ <= ta) {
                             h = fnv1a(h, 3u);
                         } else {
@@ -288,9 +394,13 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                         }
                     }
                 }
-                const bool own = nee && nee_lst;
-                wave_deposit<NB>(D, s, has, ta, tb, e, own ? wx : ax, own ? wy : ay, own ? wz : az, vk, lane,
-                                 cls_acc, first_acc);
+                // the direct sound arrives from the query direction itself
+                const bool own = has && nee_lst;
+                if (own) sh_row(wx, wy, wz, shrow + lane * RPR_MAX_COEFFS);
+                __syncthreads();
+                wave_deposit<NB>(D, s, has, ta, tb, e, shrow, vk, lane, rm, cls_acc, first_acc, a_rows);
+                __syncthreads();
+                if (own) sh_row(ax, ay, az, shrow + lane * RPR_MAX_COEFFS);
             }
             if (nee && !nee_lst) h = fnv1a(h, vkind);
             nee = false;
@@ -313,7 +423,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                     tb = (L + tb) / D.c;
                     has = ta < D.t_window;
                 }
-                wave_deposit<NB>(D, s, has, ta, tb, E, ax, ay, az, k, lane, cls_acc, first_acc);
+                wave_deposit<NB>(D, s, has, ta, tb, E, shrow, k, lane, rm, cls_acc, first_acc, a_rows);
             }
         }
 
@@ -430,6 +540,7 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
         atomicAdd((unsigned long long*)&S->n_escaped, (unsigned long long)esc);
         atomicAdd((unsigned long long*)&S->n_rays, (unsigned long long)rays);
         atomicAdd((unsigned long long*)&S->n_next_event, (unsigned long long)nq);
+        atomicAdd((unsigned long long*)&S->n_deposit_rows, (unsigned long long)a_rows);
         unsafeAtomicAdd(&S->seg_len_sum, len);
         unsafeAtomicAdd(&S->e_emitted, (double)rays * (double)D.e0);
     }
@@ -461,6 +572,387 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
     }
 }
 
+// ---------------------------------------------------------------- batched pairs
+// Wave-cooperative deposit of every lane with `has` set into the histogram of
+// its own pair (as the source-origin trace's deposit), with the lane's SH row
+// in shrow and the class of `order`; class energies and first bins
+// go to the per-pair accumulator `dep`.
+template <int NB>
+__device__ __forceinline__ void pair_deposit(const PairDesc* __restrict__ pairs, bool has, int p, float ta, float tb,
+                                             const float* e, const float* __restrict__ shrow, int order, int lane,
+                                             const RowMap& rm, DepAcc& dep)
+{
+    uint64_t dm = __ballot(has);
+    while (dm) {
+        const int l = __ffsll((unsigned long long)dm) - 1;
+        dm &= dm - 1;
+        const int q = __builtin_amdgcn_readlane(p, l);
+        const float a = lane_f(ta, l), b_ = lane_f(tb, l);
+        const int kk = __builtin_amdgcn_readlane(order, l);
+        float Eb[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) Eb[b] = lane_f(e[b], l);
+        const PairDesc& P = pairs[q];
+        const int T = P.n_bins, nc = P.n_coeffs, nb = P.scene.n_bands;
+        const float dt = P.dt, inv_vs = P.inv_vs;
+        float* __restrict__ hist = P.hist;
+        float* __restrict__ hlate = P.hist_late;
+        const int nbc = nb * nc;
+        int m0 = (int)floorf(a * rm.inv_dt);
+        if ((float)m0 * dt > a) --m0;  // never start past the chord
+        m0 = m0 < 0 ? 0 : m0;
+        float sum_dtau = 0.f;
+        int first_m = INT_MAX, n_rows = 0;
+        for (int base = 0; base < nbc; base += kWave) {
+            const int j = base + lane;
+            const bool act = j < nbc;
+            const int b = act ? (base ? rm.b1 : rm.b0) : 0, ci = act ? (base ? rm.c1 : rm.c0) : 0;
+            float eb = 0.f;
+#pragma unroll
+            for (int bb = 0; bb < NB; ++bb) eb = (bb == b) ? Eb[bb] : eb;
+            const float val = eb * shrow[l * RPR_MAX_COEFFS + ci] * inv_vs;
+            const bool late = act && kk >= 3 && ci == 0 && hlate != nullptr;
+            for (int m = m0; m < T; ++m) {
+                const float lo = fmaxf(a, (float)m * dt);
+                const float hi = fminf(b_, (float)(m + 1) * dt);
+                if (lo >= b_) break;
+                const float dtau = hi - lo;
+                if (dtau > 0.f) {
+                    if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * dtau);
+                    if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * dtau * inv_vs);
+                    if (base == 0) {
+                        sum_dtau += dtau;
+                        first_m = min(first_m, m);
+                        ++n_rows;
+                    }
+                }
+            }
+        }
+        if (q != dep.p) {
+            dep_acc_flush<NB>(dep, pairs, lane);
+            dep.p = q;
+        }
+        dep.rows += (uint32_t)n_rows;
+        const int cls = kk == 0 ? 0 : (kk <= 2 ? 1 : 2);
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            if (lane == cls * NB + b) dep.e += (double)(Eb[b] * sum_dtau * inv_vs);
+        if (first_m != INT_MAX) {
+            dep.fa = min(dep.fa, first_m);
+            if (kk >= 3) dep.fl = min(dep.fl, first_m);
+        }
+    }
+}
+
+// The listener-origin trace over a table of chunks of pairs (one source
+// each; a chunk is a pair's descriptor with a ray range of its own).  A wave
+// takes a whole chunk from the queue with one atomic and fills its lanes from
+// that chunk alone, so its lanes hold rays of one or two chunks at a time and
+// the per-pair statistics are flushed about once per chunk, while the chunks
+// of different pairs, dealt to different waves, spread the histogram atomics
+// over many pairs.  Each pair's rays leave its listener point and query its
+// source's ball.
+template <int NB, int STACK>
+__global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict__ pairs, int n_table,
+                                                      unsigned long long* __restrict__ queue)
+{
+    __shared__ int32_t stk[STACK * kWave];
+    __shared__ float shrow[kWave * RPR_MAX_COEFFS];  // SH of each lane's arrival direction
+    const int lane = threadIdx.x;
+    const uint64_t lt = lanemask_lt(lane);
+    bool alive = false, spec = false, nee = false, nee_lst = false;
+    int p = -1;
+    uint32_t ray = 0;
+    long long rl = 0;
+    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f, L = 0.f;
+    float ax = 0.f, ay = 0.f, az = 1.f;
+    int k = 0, last = -1;
+    uint32_t h = 0;
+    float E[NB], Q[NB], F[NB];
+    float vx = 0.f, vy = 0.f, vz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f, vL = 0.f;
+    int vk = 0, vexcl = -1;
+    uint32_t vkind = 0;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) E[b] = Q[b] = F[b] = 0.f;
+    SceneView sc{};
+    LaneAcc<NB> acc;
+    lane_acc_zero(acc);
+    DepAcc dep{-1, 0.0, INT_MAX, INT_MAX, 0u};
+    bool exhausted = false;
+    int ch = -1;                      // the wave's current chunk (wave-uniform)
+    long long ch_off = 0, ch_len = 0; // next ray of the chunk, its ray count
+    // bands, coefficients and bin width are the same for every pair of a batch
+    const RowMap rm = row_map(lane, pairs[0].n_coeffs, pairs[0].dt);
+
+    for (;;) {
+        if (!exhausted) {
+            uint64_t dead = __ballot(!alive);
+            int np = -1;
+            long long rr = 0;
+            while (dead) {
+                if (ch_off >= ch_len) {
+                    unsigned long long c = 0;
+                    if (lane == 0) c = atomicAdd(queue, 1ull);
+                    c = __shfl(c, 0);
+                    if (c >= (unsigned long long)n_table) {
+                        exhausted = true;
+                        break;
+                    }
+                    ch = (int)c;
+                    ch_off = 0;
+                    ch_len = pairs[ch].n_rays;
+                }
+                const long long avail = ch_len - ch_off;
+                const int nd = __popcll(dead);
+                const int take = (int)(avail < (long long)nd ? avail : (long long)nd);
+                const int rank = __popcll(dead & lt);
+                const bool mine = ((dead >> lane) & 1ull) && rank < take;
+                if (mine) {
+                    np = ch;
+                    rr = ch_off + rank;
+                }
+                dead &= ~__ballot(mine);
+                ch_off += take;
+            }
+            if (__ballot(np >= 0 && acc.p >= 0 && acc.p != np)) lane_acc_flush<NB, false, true>(acc, pairs, lane);
+            if (np >= 0) {
+                const PairDesc& P = pairs[np];
+                p = np;
+                rl = rr;
+                ray = (uint32_t)(P.ray_begin + rl);
+                const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, 0u, 0u), P.key0, P.key1);
+                sphere_dir(u01(x.x), u01(x.y), dx, dy, dz);
+                ax = dx;
+                ay = dy;
+                az = dz;
+                sh_row(ax, ay, az, shrow + lane * RPR_MAX_COEFFS);
+                ox = vx = P.lst[0];
+                oy = vy = P.lst[1];
+                oz = vz = P.lst[2];
+                L = vL = 0.f;
+                k = vk = 0;
+                last = vexcl = -1;
+                h = 2166136261u;
+                sc = P.scene;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    E[b] = b < sc.n_bands ? P.e0 : 0.f;
+                    Q[b] = b < sc.n_bands ? 1.f : 0.f;
+                    F[b] = E[b];
+                }
+                spec = false;
+                nee = true;
+                nee_lst = true;
+                alive = true;
+            }
+        }
+        if (__ballot(alive) == 0) break;
+
+        // ------------------------------------------------ next-event query toward the pair's source
+        if (__ballot(nee)) {
+            bool has = false;
+            float ta = 0.f, tb = 0.f, wx = 0.f, wy = 0.f, wz = 1.f;
+            float e[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) e[b] = 0.f;
+            if (nee) {
+                const PairDesc& P = pairs[p];
+                const float4 ps = make_float4(P.src[0], P.src[1], P.src[2], 0.f);
+                const float r2 = P.radius * P.radius;
+                const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, (uint32_t)vk, 1u), P.key0, P.key1);
+                const float px = ps.x - vx, py = ps.y - vy, pz = ps.z - vz;
+                const float rc2 = px * px + py * py + pz * pz;
+                float g = 0.f;
+                if (rc2 <= r2) {
+                    if (nee_lst) sphere_dir(u01(x.x), u01(x.y), wx, wy, wz);
+                    else lambert_dir(nx, ny, nz, u01(x.y), u01(x.z), wx, wy, wz);
+                    g = 1.f;
+                } else {
+                    const float irc = 1.0f / sqrtf(rc2);
+                    const float qx = px * irc, qy = py * irc, qz = pz * irc;
+                    const float hq = r2 / rc2;
+                    const float omc = hq / (1.0f + sqrtf(1.0f - hq));
+                    const float w1 = u01(x.x) * omc;
+                    const float ct = 1.0f - w1;
+                    const float st = sqrtf(w1 * (2.0f - w1));
+                    const float sg = qz >= 0.0f ? 1.0f : -1.0f;
+                    const float aa = -1.0f / (sg + qz);
+                    const float bb = qx * qy * aa;
+                    const float b1x = 1.0f + sg * qx * qx * aa, b1y = sg * bb, b1z = -sg * qx;
+                    const float b2x = bb, b2y = sg + qy * qy * aa, b2z = -qy;
+                    float sn, cs;
+                    sincospif(2.0f * u01(x.y), &sn, &cs);
+                    wx = st * cs * b1x + st * sn * b2x + ct * qx;
+                    wy = st * cs * b1y + st * sn * b2y + ct * qy;
+                    wz = st * cs * b1z + st * sn * b2z + ct * qz;
+                    const float omega = 2.0f * (float)M_PI * omc;
+                    if (nee_lst) {
+                        g = omega * (float)(0.25 / M_PI);
+                    } else {
+                        const float cw = nx * wx + ny * wy + nz * wz;
+                        g = cw > 0.f ? cw * omega * (float)(1.0 / M_PI) : 0.f;
+                    }
+                }
+                if (g > 0.f && ball_chord(vx, vy, vz, wx, wy, wz, __builtin_inff(), ps, r2, ta, tb) &&
+                    vL + ta < P.l_window) {
+                    ++acc.nq;
+                    const float t_occ = occlusion_query<STACK>(sc, vx, vy, vz, wx, wy, wz, ta, tb, vexcl, stk, lane);
+                    if (t_occ <= ta) {
+                        h = fnv1a(h, 3u);
+                    } else {
+                        if (t_occ < tb) {
+                            tb = t_occ;
+                            h = fnv1a(h, 4u);
+                        } else {
+                            h = fnv1a(h, 2u);
+                        }
+                        has = true;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) e[b] = F[b] * g;
+                        ta = (vL + ta) / P.c;
+                        tb = (vL + tb) / P.c;
+                    }
+                }
+                if (!nee_lst) h = fnv1a(h, vkind);
+            }
+            // the direct sound arrives from the query direction itself
+            const bool own = has && nee_lst;
+            if (own) sh_row(wx, wy, wz, shrow + lane * RPR_MAX_COEFFS);
+            __syncthreads();
+            pair_deposit<NB>(pairs, has, p, ta, tb, e, shrow, vk, lane, rm, dep);
+            __syncthreads();
+            if (own) sh_row(ax, ay, az, shrow + lane * RPR_MAX_COEFFS);
+            nee = false;
+        }
+
+        // ------------------------------------------------ closest hit
+        float t_hit = __builtin_inff();
+        uint32_t hit_id = 0xFFFFFFFFu;
+        int hit = -1;
+        if (alive) hit = closest_hit<STACK>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, t_hit, hit_id);
+
+        // ------------------------------------------------ mirror share at the source ball
+        if (__ballot(alive && spec)) {
+            float ta = 0.f, tb = 0.f;
+            bool has = false;
+            if (alive && spec) {
+                const PairDesc& P = pairs[p];
+                const float4 ps = make_float4(P.src[0], P.src[1], P.src[2], 0.f);
+                if (ball_chord(ox, oy, oz, dx, dy, dz, t_hit, ps, P.radius * P.radius, ta, tb)) {
+                    ta = (L + ta) / P.c;
+                    tb = (L + tb) / P.c;
+                    has = ta < (float)P.n_bins * P.dt;
+                }
+            }
+            pair_deposit<NB>(pairs, has, p, ta, tb, E, shrow, k, lane, rm, dep);
+        }
+
+        // ------------------------------------------------ bounce or terminate
+        if (alive) {
+            const PairDesc& P = pairs[p];
+            if (acc.p < 0) acc.p = p;
+            ++acc.seg;
+            bool term = false;
+            if (hit < 0) {
+                ++acc.esc;
+                h = fnv1a(h, 0xFFFFFFFFu);
+#pragma unroll
+                for (int b = 0; b < NB; ++b) acc.esc_e[b] += E[b];
+                term = true;
+            } else {
+                L += t_hit;
+                ++acc.fin;
+                acc.len += (double)t_hit;
+                h = fnv1a(h, hit_id);
+                const bool win = L >= P.l_window;
+                if (win || k == P.max_bounces) {
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        acc.alive[b] += E[b];
+                        if (!win) acc.cap[b] += E[b];
+                    }
+                    term = true;
+                } else {
+                    ++k;
+                    ox += t_hit * dx;
+                    oy += t_hit * dy;
+                    oz += t_hit * dz;
+                    const float4* tr = sc.tris + 3 * (int64_t)hit;
+                    const float4 e1 = tr[1], e2 = tr[2];
+                    float mx = e1.y * e2.z - e1.z * e2.y, my = e1.z * e2.x - e1.x * e2.z,
+                          mz = e1.x * e2.y - e1.y * e2.x;
+                    const float inl = 1.0f / sqrtf(mx * mx + my * my + mz * mz);
+                    mx *= inl;
+                    my *= inl;
+                    mz *= inl;
+                    if (dx * mx + dy * my + dz * mz > 0.f) {
+                        mx = -mx;
+                        my = -my;
+                        mz = -mz;
+                    }
+                    const float* __restrict__ mr = sc.mats + (int64_t)__float_as_int(e1.w) * kMatStride;
+                    ox = fmaf(kSurfaceOffset, mx, ox);
+                    oy = fmaf(kSurfaceOffset, my, oy);
+                    oz = fmaf(kSurfaceOffset, mz, oz);
+                    vx = ox;
+                    vy = oy;
+                    vz = oz;
+                    nx = mx;
+                    ny = my;
+                    nz = mz;
+                    vL = L;
+                    vk = k;
+                    vexcl = hit;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) F[b] = E[b] * mr[kMatKeep + b] * mr[kMatS + b];
+                    nee = true;
+                    nee_lst = false;
+                    const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, (uint32_t)k, 0u), P.key0, P.key1);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) acc.absb[b] += mr[kMatAlpha + b] * E[b];
+                    const int nbr = sc.n_bands;
+                    const bool diffuse = u01(x.x) < mr[kMatS + (int)(ray % (uint32_t)nbr)];
+                    float q[NB], mean_q = 0.f;
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        q[b] = diffuse ? mr[kMatS + b] : 1.f - mr[kMatS + b];
+                        mean_q += Q[b] * q[b];
+                    }
+                    const float inv_mean = (float)nbr / fmaxf(mean_q, 1e-30f);
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const float r = q[b] * inv_mean;
+                        Q[b] *= r;
+                        E[b] *= mr[kMatKeep + b] * r;
+                    }
+                    if (diffuse) {
+                        lambert_dir(mx, my, mz, u01(x.y), u01(x.z), dx, dy, dz);
+                    } else {
+                        const float dn = 2.0f * (dx * mx + dy * my + dz * mz);
+                        dx -= dn * mx;
+                        dy -= dn * my;
+                        dz -= dn * mz;
+                        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+                        dx *= il;
+                        dy *= il;
+                        dz *= il;
+                    }
+                    vkind = diffuse ? 1u : 0u;
+                    spec = !diffuse;
+                    last = hit;
+                }
+            }
+            if (term) {
+                ++acc.rays;
+                if (P.ray_hash) P.ray_hash[rl] = h;
+                alive = false;
+            }
+        }
+    }
+    lane_acc_flush<NB, false, true>(acc, pairs, lane);
+    dep_acc_flush<NB>(dep, pairs, lane);
+}
+
 // ---------------------------------------------------------------- setup / finalize
 struct LstSetupArgs {
     int s0, ns;
@@ -481,7 +973,7 @@ __global__ void k_lst_setup(LstSetupArgs a, float4* __restrict__ src, RprIrStats
     S->e_emitted = 0.0;
     S->first_arrival_bin = INT_MAX;
     S->first_late_bin = INT_MAX;
-    S->n_node_visits = S->n_tri_tests = S->n_next_event = 0;
+    S->n_node_visits = S->n_tri_tests = S->n_next_event = S->n_deposit_rows = 0;
     for (int b = 0; b < RPR_MAX_BANDS; ++b) {
         S->e_class[0][b] = S->e_class[1][b] = S->e_class[2][b] = 0.0;
         S->e_escaped[b] = S->e_alive_at_stop[b] = S->e_alive_at_bounce_cap[b] = S->e_absorbed[b] = 0.0;
@@ -502,6 +994,7 @@ __global__ void k_lst_finalize(RprIrStats* __restrict__ stats, int n_src)
     S.seg_len_sum = A.seg_len_sum;
     S.e_emitted = A.e_emitted;
     S.n_next_event = A.n_next_event;
+    S.n_deposit_rows = A.n_deposit_rows;
     for (int b = 0; b < RPR_MAX_BANDS; ++b) {
         S.e_escaped[b] = A.e_escaped[b];
         S.e_alive_at_stop[b] = A.e_alive_at_stop[b];
@@ -543,7 +1036,54 @@ int ensure_lst_variants()
     return RPR_OK;
 }
 
+using LstpFn = void (*)(const PairDesc*, int, unsigned long long*);
+
+std::mutex g_pmu;
+LstpFn g_pfn[2][2];
+int g_pper[2][2];
+bool g_p_init = false;
+
+int ensure_lstp_variants()
+{
+    std::lock_guard<std::mutex> lk(g_pmu);
+    if (g_p_init) return RPR_OK;
+    g_pfn[0][0] = k_trace_lstp<4, 32>;
+    g_pfn[0][1] = k_trace_lstp<4, 64>;
+    g_pfn[1][0] = k_trace_lstp<8, 32>;
+    g_pfn[1][1] = k_trace_lstp<8, 64>;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            int nb = 0;
+            RPR_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)g_pfn[a][b], kWave, 0));
+            g_pper[a][b] = nb > 0 ? nb : 1;
+        }
+    g_p_init = true;
+    return RPR_OK;
+}
+
 }  // namespace
+
+int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned long long* d_queue, int64_t total_rays,
+                                int nb, int stack_need, int waves_per_cu, hipStream_t stream)
+{
+    if (total_rays <= 0 || n_chunks <= 0) return RPR_OK;
+    int rc = ensure_lstp_variants();
+    if (rc != RPR_OK) return rc;
+    const int bi = nb <= 4 ? 0 : 1, si = stack_need <= 32 ? 0 : 1;
+    const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, g_pper[bi][si]) : g_pper[bi][si];
+    long long grid = (long long)device_cu_count() * per_cu;
+    grid = std::max(1ll, std::min(grid, (long long)n_chunks));
+    hipLaunchKernelGGL(g_pfn[bi][si], dim3((unsigned)grid), dim3(kWave), 0, stream, d_chunks, n_chunks, d_queue);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+int trace_listener_max_waves_per_cu(int nb, int stack_need)
+{
+    if (ensure_lstp_variants() != RPR_OK) return 1;
+    return g_pper[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1];
+}
+
 }  // namespace rpr
 
 using namespace rpr;

@@ -119,6 +119,12 @@ void workspace_free(Workspace& ws);
 // Launch the persistent trace over `n_pairs` descriptors already in device memory.
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
                  int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream);
+// Launch the listener-origin trace (next-event queries toward each pair's
+// source ball) over `n_chunks` chunk descriptors already in device memory
+// (the queue counts chunks; each is traced by one wave).
+int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned long long* d_queue, int64_t total_rays,
+                                int nb, int stack_need, int waves_per_cu, hipStream_t stream);
+int trace_listener_max_waves_per_cu(int nb, int stack_need);
 int device_cu_count();
 // Largest resident waves per CU of the trace variant for (nb, stack_need).
 int trace_max_waves_per_cu(int nb, int stack_need);

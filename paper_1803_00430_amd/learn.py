@@ -45,10 +45,12 @@ def room_pairs(rooms, n_rays, seed_offset, max_bounces=MAX_BOUNCES):
 
 
 def trace_rooms(scenes, rooms, *, n_rays, n_bins, bin_width_s, seed_offset, want_features=False, chunk=512,
-                device="cuda", log=None):
-    """Trace every room once (one pair each) in chunks of `chunk` pairs.
-    Returns dict(params uint8 [n][752] on the device, features int16 [n][F]
-    (BF16 bits) and e_in [n] if want_features, segments, seconds)."""
+                device="cuda", log=None, method="source", order=0):
+    """Trace every room once (one pair each) in chunks of `chunk` pairs, from
+    the source (method "source") or from the listener with next-event
+    queries toward the source ("listener").  Returns dict(params uint8
+    [n][752] on the device, features int16 [n][F] (BF16 bits) and e_in [n]
+    if want_features, segments, seconds)."""
     import torch
     n = len(rooms)
     out = dict(params=torch.empty((n, 752), dtype=torch.uint8, device=device), segments=0, seconds=0.0)
@@ -63,7 +65,7 @@ def trace_rooms(scenes, rooms, *, n_rays, n_bins, bin_width_s, seed_offset, want
         sub = [dict(p, scene=p["scene"] - c0, pair_id=k) for k, p in enumerate(pairs[c0:c1])]
         t0 = time.perf_counter()
         b = Batch(scenes[c0:c1], sub, n_bins=n_bins, sh_order=SH_ORDER, bin_width_s=bin_width_s, autotune=False,
-                  use_graph=False, late=False, device=device)
+                  use_graph=False, late=False, device=device, method=method, order=order)
         b.run()
         if want_features:
             f, e = featurize(b.hist, n_bins, nb, nc, stats=b.stats)
@@ -211,14 +213,14 @@ def choose_kappa(sigma_max, err_learned, err_fallback, target=0.05):
     return best
 
 
-def timed_plain(scenes, rooms, n_rays, *, steps=3, device="cuda"):
+def timed_plain(scenes, rooms, n_rays, *, steps=3, device="cuda", method="source", order=0):
     """IRs per second of the plain method at n_rays per pair: one graph-
     captured batch (reset, trace, estimate) over all rooms, replayed `steps`
     times after one warm-up.  Returns (IRs/s, params of the last replay)."""
     import torch
     b = Batch(scenes, [dict(p, pair_id=k) for k, p in enumerate(room_pairs(rooms, n_rays, SEED_SWEEP + n_rays))],
               n_bins=CONVERGED["n_bins"], sh_order=SH_ORDER, bin_width_s=CONVERGED["bin_width_s"], autotune=False,
-              use_graph=True, late=False, device=device)
+              use_graph=True, late=False, device=device, method=method, order=order)
     b.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -123,3 +123,40 @@ def test_listener_rejects_bad_arguments(torch_cuda):
                          flags=1)
     with pytest.raises(P.RprError):
         P.trace_listener(sc, c["sources"], c["listener"], 0.5, bad, hist, late, stats)
+
+
+def test_listener_batch_matches_single_pairs(torch_cuda):
+    """A batch with method "listener" (one persistent launch over pairs in
+    several scenes, replayed from a graph) gives every pair the histogram of
+    trace_listener on that pair alone, up to the order of the FP32 atomic
+    additions; one pair is also checked against the oracle."""
+    rooms = [R.learn_room(200000 + i) for i in range(4)]
+    scenes = [P.Scene.from_dict(r) for r in rooms]
+    pairs = []
+    for i, r in enumerate(rooms):
+        for j in range(2 if i < 2 else 1):
+            pairs.append(dict(scene=i, pair_id=10 + len(pairs), source=r["sources"][0] + 0.1 * j,
+                              listener=r["listener"], radius=0.5, max_bounces=100 + 50 * j,
+                              n_rays=333 + 250 * len(pairs), seed=(1 << 33) + 7 * len(pairs)))
+    T, dt, n = 300, 1e-3, 3
+    b = P.Batch(scenes, pairs, n_bins=T, sh_order=n, bin_width_s=dt, autotune=False, use_graph=True,
+                method="listener")
+    for _ in range(2):
+        b.run()
+    torch_cuda.cuda.synchronize()
+    Hb = b.hist.double().cpu().numpy()
+    stb = P.stats_host(b.stats)
+    for k, p in enumerate(pairs):
+        g = gpu_trace_listener(scenes[p["scene"]], p["source"][None], p["listener"], p["radius"],
+                               n_rays_total=p["n_rays"], max_bounces=p["max_bounces"], sh_order=n, n_bins=T,
+                               bin_width_s=dt, seed=p["seed"], pair_base=p["pair_id"], want_hash=False)
+        assert_hist_close(Hb[k], g["hist"][0], tol=1e-5, what=f"pair {k}")
+        for key in ("n_segments", "n_escaped", "n_rays", "n_next_event", "first_arrival_bin"):
+            assert stb[k][key] == g["stats"][0][key], (k, key)
+    p = pairs[0]
+    kw = dict(n_rays_total=p["n_rays"], max_bounces=p["max_bounces"], sh_order=n, n_bins=T, bin_width_s=dt,
+              seed=p["seed"], pair_base=p["pair_id"])
+    g, o, div = traced_listener_pair(scenes[0], rooms[0], p["source"][None], p["listener"], p["radius"], **kw)
+    assert len(div) <= 0.02 * p["n_rays"]
+    assert_hist_close(g["hist"][0], o["hist"][0])
+    b.close()
