@@ -28,10 +28,10 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 36025745.0,
-                 "sources_sha256": "a030fee86706a8172284efc17645533c519b97288b26af3d2e5a1f256fabc571"}
+TRACE_TRAFFIC = {"bytes": 35804128.0,
+                 "sources_sha256": "5aefb568bda5657b8a8c5dedc216b05d96f847bc0f9eb1913196ba9114f32907"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
-                 "paper_1803_00430_amd/csrc/rpr_internal.hpp")
+                 "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 
 
 def trace_sources_sha256():

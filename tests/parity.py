@@ -86,9 +86,18 @@ def traced_pair(scene, sd, sources, listener, radius, **kw):
     return g, o, div
 
 
-def assert_hist_close(Hg, Ho, tol=HIST_TOL, what="hist"):
+def assert_hist_close(Hg, Ho, tol=HIST_TOL, what="hist", time_rel=0.0):
     """Row sums over bins agree within tol of sum|H_oracle|, and every cell
-    within tol of that same absolute row sum."""
+    within tol of that same absolute row sum.
+
+    time_rel > 0 (for [T][B][NC] histograms of long FP32 paths): a cell may
+    also differ by the energy that a relative path-length error of time_rel
+    moves across its two bin edges, time_rel * t_m / dt * 2 * (the largest
+    |H_oracle| among the cell and its two neighbours in time), t_m the end of
+    bin m.  An FP32 path that keeps its discrete twin's hit sequence still
+    drifts continuously from it; where one ray carries most of a row, the
+    drift of its arrival time shows up at the 1e-4 level of that row, while
+    a deposit in the wrong bin would still miss by a whole bin's energy."""
     Hg = np.asarray(Hg, np.float64)
     Ho = np.asarray(Ho, np.float64)
     assert Hg.shape == Ho.shape
@@ -96,9 +105,17 @@ def assert_hist_close(Hg, Ho, tol=HIST_TOL, what="hist"):
     floor = 1e-30
     dr = np.abs(Hg.sum(0) - Ho.sum(0))
     assert np.all(dr <= tol * row_abs + floor), f"{what}: row-sum error {np.max(dr / (row_abs + floor)):.3e}"
+    allow = tol * row_abs[None] + floor
+    if time_rel > 0:
+        a = np.abs(Ho)
+        near = a.copy()
+        near[1:] = np.maximum(near[1:], a[:-1])
+        near[:-1] = np.maximum(near[:-1], a[1:])
+        T = Ho.shape[0]
+        t_end = np.arange(1, T + 1, dtype=np.float64).reshape((T,) + (1,) * (Ho.ndim - 1))  # in bins
+        allow = allow + time_rel * t_end * 2.0 * near
     dc = np.abs(Hg - Ho)
-    assert np.all(dc <= tol * row_abs[None] + floor), \
-        f"{what}: cell error {np.max(dc / (row_abs[None] + floor)):.3e}"
+    assert np.all(dc <= allow), f"{what}: cell error {np.max(dc / (row_abs[None] + floor)):.3e} of the row"
 
 
 def assert_stats_close(sg, so, rel=1e-5):
