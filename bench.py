@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--rays", type=int, default=0,
                     help="hospital: rays per source (source method) or of the listener (listener method); "
                          "0 = the workload's 131,072")
+    ap.add_argument("--temporal", action="store_true",
+                    help="hospital: smooth across frames (IR caches with tau 1 s / 3 s and Eq. 4 on the RT60) "
+                         "and report the frame-to-frame RT60 jitter")
     ap.add_argument("--convergence", action="store_true",
                     help="hospital: also trace frame 0 with two more independent seeds and report their mean "
                          "RT60 disagreement")
@@ -354,6 +357,8 @@ def run_hospital(a):
     listener = a.method == "listener"
     if listener and a.learned:
         raise SystemExit("--learned runs with the source method only")
+    if a.temporal and (a.learned or a.convergence):
+        raise SystemExit("--temporal runs without --learned and --convergence")
     x_max = float(cfg["verts"][:, 0].max()) - 2.5
     g = np.random.default_rng(7)
     heading = np.where(g.uniform(0, 1, S) < 0.5, -1.0, 1.0)
@@ -366,28 +371,53 @@ def run_hospital(a):
         src[:, 0] = 0.5 + np.where(x <= period / 2, x, period - x)
         return src.astype(np.float32)
 
+    frame_dt = 0.1  # seconds of source motion per frame
+    temporal = a.temporal
+    if temporal:
+        # IR caches (all orders with tau_ER = 1 s, late with tau_LR = 3 s) and Eq. 4
+        a_er, a_lr = P.temporal_alpha(frame_dt, 1.0), P.temporal_alpha(frame_dt, 3.0)
+        hist_c, late_c = torch.empty_like(hist), torch.empty_like(late)
+        params_f = P.alloc_params(S, device=dev)
+    n_done = [0]
+
     def frame(f, p=prm):
         if listener:
             P.trace_listener(scene, sources_at(f), cfg["listener"], cfg["radius"], p, hist, late, stats)
         else:
             P.trace_ir(scene, sources_at(f), cfg["listener"], cfg["radius"], p, hist, late, stats)
-        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+        if temporal:
+            first = n_done[0] == 0
+            P.ir_cache_update(hist_c, hist, a_er, first)
+            P.ir_cache_update(late_c, late, a_lr, first)
+            P.estimate_reverb(hist_c, late_c, stats, T, B, n, dt, params_f)
+            P.reverb_params_smooth(params, params_f, B, a_er, a_lr, first)
+        else:
+            P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+        n_done[0] += 1
 
     for f in range(a.warmup):
         frame(-1 - f)
     torch.cuda.synchronize()
-    times, segs = [], 0
+    times, segs, rt_frames = [], 0, []
     for f in range(a.frames):
         t1 = time.perf_counter()
         frame(f)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t1)
+        rt_frames.append(params.clone())
         st_ = P.stats_host(stats)["n_segments"]
         segs += int(st_[0] if listener else st_.sum())  # the listener's ray set is repeated per source
         log(f"frame {f}: {times[-1] * 1e3:.1f} ms", q)
     times = np.array(times)
     ms = times.mean() * 1e3
     queries = int(P.stats_host(stats)["n_next_event"][0]) if listener else 0
+    rts = [P.params_host(x)["rt60"][:, :B].astype(np.float64) for x in rt_frames]
+    jit = []
+    for r0, r1 in zip(rts[:-1], rts[1:]):
+        ok = (r0 > 0) & (r1 > 0)
+        jit.append(np.abs(r1 - r0)[ok] / (0.5 * (r0 + r1)[ok]))
+    jit = np.concatenate(jit) if jit else np.zeros(0)
+    jitter = {"mean": float(jit.mean()), "p90": float(np.quantile(jit, 0.9))} if jit.size else None
     conv = None
     if a.convergence:
         rt, el = [], []
@@ -411,6 +441,8 @@ def run_hospital(a):
     learned = run_hospital_learned(a, P, scene, cfg, sources_at, params, frame) if a.learned else None
     how = (f"traced from the listener point with {N} rays and next-event queries toward every source ball "
            f"(r = {cfg['radius']} m)" if listener else f"{N} rays per source to the listener sphere")
+    if temporal:
+        how += ", smoothed across frames (IR caches tau 1 s / 3 s, Eq. 4 RT60 smoothing, 0.1 s frames)"
     out = {
         "metric": "per-frame latency p50/p99 and IRs/s (plain ray trace)", "value": S / times.mean(),
         "unit": "IRs/s", "n_gpus": 1, "steps": a.frames, "warmup": a.warmup, "ms_per_step": ms,
@@ -421,6 +453,8 @@ def run_hospital(a):
         "p50_ms": float(np.percentile(times, 50) * 1e3), "p99_ms": float(np.percentile(times, 99) * 1e3),
         "build_ms": build_ms, "ray_bounces_per_s": segs / times.sum(),
     }
+    out["rt60_frame_jitter"] = jitter
+    out["config"]["temporal"] = bool(temporal)
     if listener:
         out["next_event_queries_per_frame"] = queries
     if conv:

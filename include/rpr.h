@@ -235,6 +235,39 @@ int estimate_reverb(const float* hist, const float* hist_late, const RprIrStats*
                     int32_t n_bins, int32_t n_bands, int32_t sh_order, float bin_width_s,
                     const RprEstimateParams* ep, RprReverbParams* out, void* hip_stream);
 
+/* ---------------------------------------------------------- temporal coherence
+ * Smoothing across frames (Section 4.2, Eq. 4: the RT60 of each frame is
+ * blended into a cached value; Section 5: early- and late-reflection caches
+ * with time constants tau_ER = 1 s and tau_LR = 3 s).  With frame length dt,
+ * alpha = 1 - exp(-dt / tau), so a step is covered to 1 - exp(-t / tau)
+ * after time t. */
+
+/* alpha = 1 - exp(-frame_dt_s / tau_s); 1 when tau_s <= 0 (no smoothing). */
+float temporal_alpha(float frame_dt_s, float tau_s);
+
+/* IR cache: cache[i] = alpha * fresh[i] + (1 - alpha) * cache[i] for
+ * i < n, or cache[i] = fresh[i] when first != 0 (the first frame or a reset).
+ * Use it on the all-orders histogram with the early factor and on hist_late
+ * with the late factor, then estimate from the caches.
+ *   cache, fresh  device f32, 16-byte aligned, n floats each (the caller owns both)
+ * Errors: RPR_EINVAL for a null or misaligned buffer or alpha outside [0, 1]. */
+int ir_cache_update(float* cache, const float* fresh, int64_t n, float alpha, int32_t first, void* hip_stream);
+
+/* Parameter smoothing of n_ir IRs, in place in `cache` (the output of the
+ * frame and the cache of the next, as in Eq. 4):
+ *   rt60[b]      Eq. 4 with alpha_late; a frame whose fit is invalid (status
+ *                NO_ENERGY, BAD_FIT or NO_RANGE) keeps the cached value, and
+ *                a valid frame after an invalid cache takes its own value;
+ *                status and rt60_range follow the frame whose RT60 was used
+ *   e_direct, e_early  smoothed with alpha_early; e_late with alpha_late
+ *   g_reverb     sqrt(e_late * 6 ln 10 / rt60) of the smoothed values (Eq. 5, Eq. 8)
+ *   all other fields: the fresh frame's
+ * first != 0 copies fresh into cache.
+ *   cache, fresh  device [n_ir]
+ * Errors: RPR_EINVAL for bad sizes, null buffers or alphas outside [0, 1]. */
+int reverb_params_smooth(RprReverbParams* cache, const RprReverbParams* fresh, int32_t n_ir, int32_t n_bands,
+                         float alpha_early, float alpha_late, int32_t first, void* hip_stream);
+
 /* ------------------------------------------------------------------ batches
  * Many source-listener pairs over several scenes traced by one persistent
  * launch (the paper traces every source of a frame; Section 5 "Sound

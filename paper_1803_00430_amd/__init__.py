@@ -132,6 +132,9 @@ SIGNATURES = {
                                  _vp, _vp, _vp, _vp]),
     "estimate_reverb": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, C.c_float, C.POINTER(EstimateParams),
                                   _vp, _vp]),
+    "temporal_alpha": (C.c_float, [C.c_float, C.c_float]),
+    "ir_cache_update": (C.c_int, [_vp, _vp, _i64, C.c_float, _i32, _vp]),
+    "reverb_params_smooth": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, C.c_float, _i32, _vp]),
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "debug_philox": (C.c_int, [_vp, _i64, _vp, _vp]),
     "debug_sh_eval": (C.c_int, [_vp, _i64, _i32, _vp, _vp]),
@@ -321,6 +324,27 @@ def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width
     ep = EstimateParams(int(rt60_source), int(tail_iters))
     _check(lib().estimate_reverb(_ptr(hist), _ptr(hist_late), _ptr(stats), n_ir, int(n_bins), int(n_bands),
                                  int(sh_order), float(bin_width_s), C.byref(ep), _ptr(out), _stream(stream)))
+
+
+def temporal_alpha(frame_dt_s: float, tau_s: float) -> float:
+    """Smoothing factor of one frame: 1 - exp(-dt / tau) (1 when tau <= 0)."""
+    return float(lib().temporal_alpha(float(frame_dt_s), float(tau_s)))
+
+
+def ir_cache_update(cache, fresh, alpha: float, first: bool, stream=None):
+    """cache = alpha * fresh + (1 - alpha) * cache over all cells (fresh on
+    the first frame); both float32 device tensors of the same size."""
+    assert cache.numel() == fresh.numel() and cache.dtype == fresh.dtype
+    _check(lib().ir_cache_update(_ptr(cache), _ptr(fresh), int(cache.numel()), float(alpha), int(bool(first)),
+                                 _stream(stream)))
+
+
+def reverb_params_smooth(cache, fresh, n_bands, alpha_early: float, alpha_late: float, first: bool, stream=None):
+    """Eq. 4 and the energy smoothing, in place in `cache` ([n_ir, 752] uint8)."""
+    n_ir = int(cache.shape[0])
+    assert int(fresh.shape[0]) == n_ir
+    _check(lib().reverb_params_smooth(_ptr(cache), _ptr(fresh), n_ir, int(n_bands), float(alpha_early),
+                                      float(alpha_late), int(bool(first)), _stream(stream)))
 
 
 def alloc_params(n_ir, device="cuda"):

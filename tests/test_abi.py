@@ -95,3 +95,12 @@ def test_binding_has_no_cpu_path():
     # the binding module must not import the oracle
     src = open(os.path.join(ROOT, "paper_1803_00430_amd", "__init__.py")).read()
     assert "oracle" not in src.replace("no fallback", "")
+
+
+def test_temporal_alpha_is_host_side_and_matches_oracle():
+    """temporal_alpha is plain host arithmetic (no device call)."""
+    import math
+    from oracle import temporal as TC
+    for dt, tau in ((0.1, 1.0), (0.1, 3.0), (0.02, 0.5)):
+        assert math.isclose(P.temporal_alpha(dt, tau), TC.smoothing_alpha(dt, tau), rel_tol=1e-6)
+    assert P.temporal_alpha(0.1, 0.0) == 1.0 and P.temporal_alpha(0.1, -2.0) == 1.0
