@@ -101,11 +101,17 @@ __global__ void k_materials(const float* __restrict__ absorption, const float* _
 // Triangle bounds, centroids and validation; reduces the centroid bounds.
 __global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
                        const int32_t* __restrict__ tri_mat, int nm, float4* __restrict__ cent,
-                       BuildFlags* f)
+                       uint32_t* __restrict__ seen, uint32_t* __restrict__ refs, BuildFlags* f)
 {
     __shared__ int32_t s_lo[3][kBuildBlock / kWave], s_hi[3][kBuildBlock / kWave];
     __shared__ int32_t s_blo[3][kBuildBlock / kWave], s_bhi[3][kBuildBlock / kWave];
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nt) {
+        // clear the counters of later kernels: seen [nt], refs [2 nt - 1]
+        seen[t] = 0u;
+        refs[t] = 0u;
+        if (t > 0) refs[nt - 1 + t] = 0u;
+    }
     float c[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float cm[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
@@ -513,15 +519,55 @@ __device__ __forceinline__ void node_box(int n, int32_t link, const float4* __re
     }
 }
 
-// Depth of every internal node of the binary tree (the root has depth 0).
-__global__ void k_node_depth(int n, const int32_t* __restrict__ parent, uint32_t* __restrict__ even, BuildFlags* f)
+// Depth of every internal node of the binary tree (the root has depth 0), its
+// parity for the 4-wide collapse (written to even and idx4, the scan's input),
+// and the sizes of the 4-wide traversal.  On the path from the root to a
+// leaf, every binary node at even depth becomes a 4-wide node that pushes at
+// most its slot count minus one entries.  Walking up from node i, the push
+// counts of the ancestors at even and at odd distance from i are summed
+// apart; once the walk gives i's depth d, the ancestors at even depth are
+// those whose distance has the parity of d.  A node with a leaf child ends
+// that leaf's path: its depth + 1 and its sum give the tree depth and the
+// stack bound (maxima over such nodes, reduced over the wave first).
+__global__ void k_node_depth(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
+                             uint32_t* __restrict__ even, uint32_t* __restrict__ idx4, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    int d = 0;
-    for (int node = i; node != 0 && d <= 4 * kMaxStack; ++d) node = parent[node];
-    even[i] = (d % 2 == 0) ? 1u : 0u;
-    if (d % 2 == 0) atomicAdd(&f->n_nodes4, 1u);
+    int depth_leaf = 0, need = 0;
+    uint32_t is_even = 0;
+    if (i < n - 1) {
+        int d = 0, sum[2] = {0, 0};
+        int node = i;
+        for (;;) {
+            const int2 c = child[node];
+            sum[d & 1] += (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1;
+            if (node == 0 || d > 4 * kMaxStack) break;
+            node = parent[node];
+            if (node < 0) break;
+            ++d;
+        }
+        is_even = (d % 2 == 0) ? 1u : 0u;
+        even[i] = is_even;
+        idx4[i] = is_even;
+        const int2 c = child[i];
+        if (is_leaf(c.x) || is_leaf(c.y)) {
+            depth_leaf = d + 1;
+            need = sum[d & 1];
+        }
+    }
+    // wave maxima and count, one set of atomics per wave
+    uint32_t cnt = is_even;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        depth_leaf = max(depth_leaf, __shfl_xor(depth_leaf, o, kWave));
+        need = max(need, __shfl_xor(need, o, kWave));
+        cnt += __shfl_xor(cnt, o, kWave);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        if (depth_leaf > 0) atomicMax(&f->max_depth, depth_leaf);
+        if (need > 0) atomicMax(&f->max_stack, need);
+        if (cnt) atomicAdd(&f->n_nodes4, cnt);
+    }
 }
 
 // Collapse of the binary tree into 4-wide nodes: every internal node at an
@@ -566,28 +612,6 @@ __global__ void k_collapse4(int n, const int2* __restrict__ child, const float4*
         o[2 * j] = make_float4(lo[j].x, lo[j].y, lo[j].z, __int_as_float(links[j]));
         o[2 * j + 1] = make_float4(hi[j].x, hi[j].y, hi[j].z, 0.0f);
     }
-}
-
-// Depth of every leaf (edges to the root) and the stack the 4-wide traversal
-// can need on its path: each 4-wide ancestor (an even-depth binary node)
-// pushes at most its slot count minus one.
-__global__ void k_depth(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
-                        const uint32_t* __restrict__ even, BuildFlags* f)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int d = 0, need = 0;
-    int node = parent[(n - 1) + i];
-    while (node >= 0 && d <= 4 * kMaxStack) {
-        ++d;
-        if (even[node]) {
-            const int2 c = child[node];
-            need += (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1;
-        }
-        node = node == 0 ? -1 : parent[node];
-    }
-    atomicMax(&f->max_depth, d);
-    atomicMax(&f->max_stack, need);
 }
 
 // Build temporaries come from one grow-only device arena per device, reused
@@ -737,10 +761,8 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     TRY(hipGetLastError());
 
     if (n > 0) {
-        TRY(hipMemsetAsync(seen.p, 0, sizeof(uint32_t) * n, st));
-        TRY(hipMemsetAsync(refs.p, 0, sizeof(uint32_t) * (2 * (size_t)n - 1), st));
         hipLaunchKernelGGL(k_prep, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts, n_verts, tris,
-                           n_tris, tri_material, n_materials, cent.p, flags.p);
+                           n_tris, tri_material, n_materials, cent.p, seen.p, refs.p, flags.p);
         hipLaunchKernelGGL(k_morton, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent.p, n_tris,
                            flags.p, k0.p, v0.p);
         uint32_t *ki = k0.p, *vi = v0.p, *ko = k1.p, *vo = v1.p;
@@ -770,13 +792,10 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
             hipLaunchKernelGGL(k_refit, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p, box.p,
                                ibox.p);
             hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
-                               parent.p, even.p, flags.p);
-            TRY(hipMemcpyAsync(idx4.p, even.p, sizeof(uint32_t) * (n - 1), hipMemcpyDeviceToDevice, st));
+                               parent.p, child.p, even.p, idx4.p, flags.p);
             scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
             hipLaunchKernelGGL(k_collapse4, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
                                box.p, ibox.p, even.p, idx4.p, sc->nodes);
-            hipLaunchKernelGGL(k_depth, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,
-                               child.p, even.p, flags.p);
         }
         TRY(hipGetLastError());
         BuildFlags hf;
