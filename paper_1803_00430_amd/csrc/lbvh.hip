@@ -379,7 +379,7 @@ __device__ __forceinline__ int delta(const uint32_t* __restrict__ k, int n, int 
 // the common prefix of the range ends.  parent[] indexes internal nodes
 // 0..n-2 then leaves n-1..2n-2.
 __global__ void k_karras(const uint32_t* __restrict__ keys, int n, int2* __restrict__ child,
-                         int32_t* __restrict__ parent, BuildFlags* f)
+                         int32_t* __restrict__ parent, int2* __restrict__ range, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
@@ -404,8 +404,10 @@ __global__ void k_karras(const uint32_t* __restrict__ keys, int n, int2* __restr
         // cannot happen for a correct split search; keep every index in range
         atomicOr(&f->flags, (uint32_t)kBadTree);
         child[i] = make_int2(leaf_link(0), leaf_link(0));
+        range[i] = make_int2(0, 0);
         return;
     }
+    range[i] = make_int2(lo, hi);
     const int c0 = (lo == g) ? leaf_link(g) : g;
     const int c1 = (hi == g + 1) ? leaf_link(g + 1) : g + 1;
     child[i] = make_int2(c0, c1);
@@ -449,36 +451,107 @@ __global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const
     box[2 * b + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
 }
 
-// Bottom-up bounds without ordering: internal boxes are kept as
-// order-preserving integer keys and widened with atomic min/max.  Each leaf
-// walks towards the root and stops at the first ancestor that none of its six
-// bounds widened: that ancestor already holds bounds at least as wide, set by
-// a leaf that is itself still propagating them upwards.  No fences are needed
-// because min and max commute.
-__global__ void k_box_init(int64_t n6, int32_t* __restrict__ ibox)
+// Internal boxes from leaf ranges.  Every internal node of the LBVH covers a
+// contiguous range [lo, hi] of the Morton-sorted leaves (known to k_karras),
+// so its box is the union of the leaf boxes over that range.  A pyramid of
+// unions over aligned blocks (level L, entry m covers leaves
+// [m 2^L, (m + 1) 2^L)) answers each range with at most two blocks per level,
+// as a segment tree does; no atomics and no ordering between nodes.
+constexpr int kPyrMaxLevels = 32;
+struct PyrLevels {
+    int64_t off[kPyrMaxLevels + 1];  // first entry of level L >= 1 in pyr (off[0] unused)
+    int64_t len[kPyrMaxLevels + 1];  // entries of level L, ceil(n / 2^L)
+    int top;                         // highest level (1 entry)
+};
+
+__device__ __forceinline__ void box_union(float4& lo, float4& hi, const float4 l, const float4 h)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n6) return;
-    ibox[i] = (i % 6) < 3 ? ordered(__builtin_inff()) : ordered(-__builtin_inff());
+    lo = make_float4(fminf(lo.x, l.x), fminf(lo.y, l.y), fminf(lo.z, l.z), 0.0f);
+    hi = make_float4(fmaxf(hi.x, h.x), fmaxf(hi.y, h.y), fmaxf(hi.z, h.z), 0.0f);
 }
 
-__global__ void k_refit(int n, const int32_t* __restrict__ parent, const float4* __restrict__ box,
-                        int32_t* __restrict__ ibox)
+// Levels 1..8 of the pyramid: each workgroup reduces its 256 leaves in LDS.
+__global__ void __launch_bounds__(kBuildBlock) k_pyr_low(int n, const float4* __restrict__ box, PyrLevels pl,
+                                                         float4* __restrict__ pyr)
+{
+    __shared__ float4 s_lo[kBuildBlock], s_hi[kBuildBlock];
+    const int t = threadIdx.x;
+    const int64_t leaf = (int64_t)blockIdx.x * kBuildBlock + t;
+    const float inf = __builtin_inff();
+    float4 lo = make_float4(inf, inf, inf, 0.0f), hi = make_float4(-inf, -inf, -inf, 0.0f);
+    if (leaf < n) {
+        lo = box[2 * ((int64_t)(n - 1) + leaf)];
+        hi = box[2 * ((int64_t)(n - 1) + leaf) + 1];
+    }
+    s_lo[t] = lo;
+    s_hi[t] = hi;
+    __syncthreads();
+    for (int L = 1, w = kBuildBlock / 2; w >= 1 && L <= pl.top; ++L, w >>= 1) {
+        if (t < w) {
+            float4 a = s_lo[2 * t], b = s_hi[2 * t];
+            box_union(a, b, s_lo[2 * t + 1], s_hi[2 * t + 1]);
+            const int64_t m = (int64_t)blockIdx.x * w + t;
+            if (m < pl.len[L]) {
+                pyr[2 * (pl.off[L] + m)] = a;
+                pyr[2 * (pl.off[L] + m) + 1] = b;
+            }
+            lo = a;
+            hi = b;
+        }
+        __syncthreads();
+        if (t < w) {
+            s_lo[t] = lo;
+            s_hi[t] = hi;
+        }
+        __syncthreads();
+    }
+}
+
+// Levels 9 and up, by one workgroup (their entries number n / 256 and fewer).
+__global__ void __launch_bounds__(1024) k_pyr_high(PyrLevels pl, float4* __restrict__ pyr)
+{
+    for (int L = 9; L <= pl.top; ++L) {
+        for (int64_t m = threadIdx.x; m < pl.len[L]; m += blockDim.x) {
+            const int64_t a = 2 * m, b = 2 * m + 1;
+            float4 lo = pyr[2 * (pl.off[L - 1] + a)], hi = pyr[2 * (pl.off[L - 1] + a) + 1];
+            if (b < pl.len[L - 1]) box_union(lo, hi, pyr[2 * (pl.off[L - 1] + b)], pyr[2 * (pl.off[L - 1] + b) + 1]);
+            pyr[2 * (pl.off[L] + m)] = lo;
+            pyr[2 * (pl.off[L] + m) + 1] = hi;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_refit(int n, const int2* __restrict__ range, const float4* __restrict__ box,
+                        const float4* __restrict__ pyr, PyrLevels pl, int32_t* __restrict__ ibox)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t lb = (int64_t)(n - 1) + i;
-    const float4 lo = box[2 * lb], hi = box[2 * lb + 1];
-    const int32_t v[6] = {ordered(lo.x), ordered(lo.y), ordered(lo.z), ordered(hi.x), ordered(hi.y), ordered(hi.z)};
-    int node = parent[lb];
-    for (int guard = 0; node >= 0 && guard < 4 * kMaxStack; ++guard) {
-        int32_t* b = ibox + 6 * (int64_t)node;
-        bool widened = false;
-        for (int k = 0; k < 3; ++k) widened |= atomicMin(&b[k], v[k]) > v[k];
-        for (int k = 3; k < 6; ++k) widened |= atomicMax(&b[k], v[k]) < v[k];
-        if (!widened) break;
-        node = node == 0 ? -1 : parent[node];
+    if (i >= n - 1) return;
+    const int2 r = range[i];
+    const float inf = __builtin_inff();
+    float4 lo = make_float4(inf, inf, inf, 0.0f), hi = make_float4(-inf, -inf, -inf, 0.0f);
+    int64_t a = r.x, b = r.y;
+    for (int L = 0; a <= b && L <= pl.top; ++L) {
+        if (a & 1) {
+            const int64_t e = L == 0 ? 2 * ((int64_t)(n - 1) + a) : 2 * (pl.off[L] + a);
+            box_union(lo, hi, L == 0 ? box[e] : pyr[e], L == 0 ? box[e + 1] : pyr[e + 1]);
+            ++a;
+        }
+        if (!(b & 1) && a <= b) {
+            const int64_t e = L == 0 ? 2 * ((int64_t)(n - 1) + b) : 2 * (pl.off[L] + b);
+            box_union(lo, hi, L == 0 ? box[e] : pyr[e], L == 0 ? box[e + 1] : pyr[e + 1]);
+            --b;
+        }
+        a >>= 1;
+        b >>= 1;
     }
+    int32_t* q = ibox + 6 * (int64_t)i;
+    q[0] = ordered(lo.x);
+    q[1] = ordered(lo.y);
+    q[2] = ordered(lo.z);
+    q[3] = ordered(hi.x);
+    q[4] = ordered(hi.y);
+    q[5] = ordered(hi.z);
 }
 
 // Structure check: every link in range, and every node except the root
@@ -734,7 +807,8 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     DevBuf<float4> cent, box;
     DevBuf<uint32_t> k0, v0, k1, v1, counts, seen, refs, even, idx4, scan_sums;
     DevBuf<int32_t> ibox, parent;
-    DevBuf<int2> child;
+    DevBuf<int2> child, range;
+    DevBuf<float4> pyr;
     const int n_tiles = (int)blocks(n > 0 ? n : 1, kSortTile);
     if (n > 0) {
         TRY(cent.alloc(n));
@@ -745,6 +819,9 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(counts.alloc((size_t)256 * n_tiles));
         TRY(box.alloc(2 * (size_t)(2 * n - 1)));
         TRY(child.alloc(n > 1 ? n - 1 : 1));
+        TRY(range.alloc(n > 1 ? n - 1 : 1));
+        // sum over levels of ceil(n / 2^L) <= n - 1 + levels
+        TRY(pyr.alloc(2 * ((size_t)n + kPyrMaxLevels + 1)));
         TRY(parent.alloc(2 * (size_t)n - 1));
         TRY(ibox.alloc(6 * (size_t)(n > 1 ? n - 1 : 1)));
         TRY(seen.alloc(n));
@@ -754,7 +831,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(scan_sums.alloc(std::max<size_t>(blocks((int64_t)256 * n_tiles, kSortTile), blocks(n, kSortTile))));
     }
     TRY(arena_place(arena, flags, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, ibox, parent, child,
-                    scan_sums));
+                    range, pyr, scan_sums));
     hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
     hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
                        n_materials, n_bands, sc->mats, flags.p);
@@ -782,15 +859,26 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                            n_verts, tris, tri_material, vi, n, sc->tris, box.p, seen.p, flags.p);
         if (n > 1) {
             hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, ki, n,
-                               child.p, parent.p, flags.p);
+                               child.p, parent.p, range.p, flags.p);
             hipLaunchKernelGGL(k_check_links, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
                                child.p, refs.p, flags.p);
             hipLaunchKernelGGL(k_check_refs, dim3(blocks(2 * (int64_t)n - 1, kBuildBlock)), dim3(kBuildBlock), 0,
                                st, n, refs.p, flags.p);
-            hipLaunchKernelGGL(k_box_init, dim3(blocks(6 * (int64_t)(n - 1), kBuildBlock)), dim3(kBuildBlock), 0,
-                               st, 6 * (int64_t)(n - 1), ibox.p);
-            hipLaunchKernelGGL(k_refit, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p, box.p,
-                               ibox.p);
+            PyrLevels pl;
+            std::memset(&pl, 0, sizeof(pl));
+            int64_t off = 0, len = n;
+            pl.top = 0;
+            while (len > 1 && pl.top < kPyrMaxLevels) {
+                len = (len + 1) / 2;
+                ++pl.top;
+                pl.off[pl.top] = off;
+                pl.len[pl.top] = len;
+                off += len;
+            }
+            hipLaunchKernelGGL(k_pyr_low, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, box.p, pl, pyr.p);
+            if (pl.top > 8) hipLaunchKernelGGL(k_pyr_high, dim3(1), dim3(1024), 0, st, pl, pyr.p);
+            hipLaunchKernelGGL(k_refit, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, range.p, box.p,
+                               pyr.p, pl, ibox.p);
             hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
                                parent.p, child.p, even.p, idx4.p, flags.p);
             scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
