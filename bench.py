@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="city: run the steps one after another on one stream (default: two streams, pipelined)")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms"), default="city",
@@ -604,41 +606,51 @@ def main():
         f"{vn:.1f} nodes + {vt:.1f} triangles per segment",
         a.quiet)
 
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    t_build, t_trace, t_est = [], [], []
+    # Steps are independent (same scene, same rays), so consecutive steps are
+    # pipelined on two streams with their own outputs: step i+1's BVH build
+    # (scene_create waits for its own stream only) and trace start while the
+    # longest rays of step i are still bouncing.  Every step does all of its
+    # own work; --serial runs them one after another on one stream.
+    n_pipe = 1 if a.serial else 2
+    streams = [stream] if a.serial else [torch.cuda.Stream(device=dev) for _ in range(n_pipe)]
+    outs = [(hist, late, stats, params)] + [(*P.alloc_trace_outputs(S, T, B, n, device=dev)[:3],
+                                             P.alloc_params(S, device=dev)) for _ in range(n_pipe - 1)]
+    rec = []  # per timed step: (build ms, trace events, estimate events)
 
-    def step(record):
-        e0 = time.perf_counter()
-        sc = P.Scene(verts, tris, tmat, absb, scat, device=dev)  # synchronises after the build
-        b_ms = (time.perf_counter() - e0) * 1e3
-        ev[1].record(stream)
-        P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
-        ev[2].record(stream)
-        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
-        ev[3].record(stream)
+    def step(i, record):
+        st_, (h_, l_, s_, p_) = streams[i % n_pipe], outs[i % n_pipe]
+        with torch.cuda.stream(st_):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            ev[3].record(st_)
+            sc = P.Scene(verts, tris, tmat, absb, scat, device=dev)  # waits for this stream only
+            ev[0].record(st_)
+            P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, h_, l_, s_)
+            ev[1].record(st_)
+            P.estimate_reverb(h_, l_, s_, T, B, n, dt, p_)
+            ev[2].record(st_)
         if record:
-            torch.cuda.synchronize()
-            t_build.append(b_ms)
-            t_trace.append(ev[1].elapsed_time(ev[2]))
-            t_est.append(ev[2].elapsed_time(ev[3]))
+            rec.append(ev)
         return sc
 
-    for _ in range(a.warmup):
-        step(False).close()
+    keep = []
+    for i in range(a.warmup):
+        keep.append(step(i, False))
     torch.cuda.synchronize()
+    for s_ in keep:
+        s_.close()
     # timed region: exactly `steps` steps, synchronised on both sides
     scenes = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(a.steps):
-        scenes.append(step(False))
+    for i in range(a.steps):
+        scenes.append(step(i, True))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for s_ in scenes:
         s_.close()
-    # per-phase timing in a separate pass (phases synchronised one by one)
-    for _ in range(min(a.steps, 10)):
-        step(True).close()
+    t_build = [ev[3].elapsed_time(ev[0]) for ev in rec]
+    t_trace = [ev[0].elapsed_time(ev[1]) for ev in rec]
+    t_est = [ev[1].elapsed_time(ev[2]) for ev in rec]
 
     st = P.stats_host(stats)
     segs = int(st["n_segments"].sum())
@@ -655,7 +667,9 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "city: procedural city of 99,996 triangles (extruded boxes, tessellated), "
                                "8 sources x 32,768 rays, 100 bounces, 4 bands, SH order 3, 3000 x 1 ms bins; "
-                               "step = BVH build + trace + estimate",
+                               "step = BVH build + trace + estimate" +
+                               ("" if a.serial else "; consecutive steps pipelined on two streams"),
+                   "pipelined_streams": n_pipe,
                    "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
                    "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -663,6 +677,8 @@ def main():
                      "kernel": "k_trace", "bytes_per_ray_bounce": bytes_per_seg,
                      "node_visits_per_ray_bounce": vn, "tri_tests_per_ray_bounce": vt,
                      "kernel_ms": trace_ms},
+        # per timed step, by events on the step's stream (with two streams the phases overlap the
+        # neighbouring steps, so they do not add up to ms_per_step)
         "breakdown_ms": {"build": float(np.mean(t_build)), "trace": trace_ms, "estimate": float(np.mean(t_est))},
         "trace_ray_bounces_per_s": segs / (trace_ms * 1e-3),
         "irs_per_s": S / (ms_step * 1e-3),
