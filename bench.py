@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true",
-                    help="city: run the steps one after another on one stream (default: two streams, pipelined)")
+                    help="city: run the steps one after another on one stream (default: pipelined streams)")
+    ap.add_argument("--streams", type=int, default=3, help="city: streams the consecutive steps rotate over")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms"), default="city",
@@ -611,7 +612,7 @@ def main():
     # (scene_create waits for its own stream only) and trace start while the
     # longest rays of step i are still bouncing.  Every step does all of its
     # own work; --serial runs them one after another on one stream.
-    n_pipe = 1 if a.serial else 2
+    n_pipe = 1 if a.serial else max(1, a.streams)
     streams = [stream] if a.serial else [torch.cuda.Stream(device=dev) for _ in range(n_pipe)]
     outs = [(hist, late, stats, params)] + [(*P.alloc_trace_outputs(S, T, B, n, device=dev)[:3],
                                              P.alloc_params(S, device=dev)) for _ in range(n_pipe - 1)]
@@ -668,7 +669,7 @@ def main():
         "config": {"workload": "city: procedural city of 99,996 triangles (extruded boxes, tessellated), "
                                "8 sources x 32,768 rays, 100 bounces, 4 bands, SH order 3, 3000 x 1 ms bins; "
                                "step = BVH build + trace + estimate" +
-                               ("" if a.serial else "; consecutive steps pipelined on two streams"),
+                               ("" if n_pipe == 1 else f"; consecutive steps pipelined on {n_pipe} streams"),
                    "pipelined_streams": n_pipe,
                    "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
                    "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt},
