@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--learn-epochs", type=int, default=16)
     ap.add_argument("--learn-views", type=int, default=4, help="1k-ray input traces per training room")
     ap.add_argument("--learn-target-rays", type=int, default=65536, help="rays of each training target trace")
+    ap.add_argument("--learn-fallback", choices=("source", "listener"), default="listener",
+                    help="learn: plain method that traces the uncertain rooms again (at its own N*)")
     ap.add_argument("--learn-target-err", type=float, default=0.048,
                     help="mean RT60 error the gate is tuned to on the calibration rooms (margin below 5%%)")
     ap.add_argument("--rooms-rays", type=int, default=0,
@@ -184,21 +186,27 @@ def run_learn(a):
     cal = L.make_dataset(scenes["cal"], rooms["cal"], chunk=1024)
     refs = {k: L.trace_rooms(scenes[k], rooms[k], n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024,
                              **L.CONVERGED)["params"] for k in ("cal", "eval")}
-    sweep = {}
-    for N in (1024, 4096, 16384, 32768, 65536, 131072, 262144):
-        tr = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=N, seed_offset=L.SEED_SWEEP + N, chunk=1024,
-                           **L.CONVERGED)
-        sweep[N] = L.rt60_error_summary(L.rt60_error(tr["params"], refs["eval"], 4))
-        log(f"plain N={N}: {sweep[N]}", q)
-    ok = [N for N in sweep if sweep[N]["mean"] <= 0.05]
-    n_star = min(ok) if ok else max(sweep)
+    def plain_sweep(method, Ns):
+        sw = {}
+        for N in Ns:
+            tr = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=N, seed_offset=L.SEED_SWEEP + N, chunk=1024,
+                               method=method, order=2 if method == "listener" else 0, **L.CONVERGED)
+            sw[N] = L.rt60_error_summary(L.rt60_error(tr["params"], refs["eval"], 4))
+            log(f"plain ({method}) N={N}: {sw[N]}", q)
+        ok = [N for N in sw if sw[N]["mean"] <= 0.05]
+        return sw, (min(ok) if ok else max(sw))
+
+    sweep, n_star = plain_sweep("source", (1024, 4096, 16384, 32768, 65536, 131072, 262144))
+    sweep_l, n_star_l = plain_sweep("listener", (4096, 8192, 16384, 32768, 65536))
+    fbm = a.learn_fallback
+    n_fb = n_star_l if fbm == "listener" else n_star
     model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
     t0 = time.perf_counter()
     losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    fb = L.trace_rooms(scenes["cal"], rooms["cal"], n_rays=n_star, seed_offset=L.SEED_SWEEP + n_star, chunk=1024,
-                       **L.CONVERGED)
+    fb = L.trace_rooms(scenes["cal"], rooms["cal"], n_rays=n_fb, seed_offset=L.SEED_SWEEP + n_fb, chunk=1024,
+                       method=fbm, order=2 if fbm == "listener" else 0, **L.CONVERGED)
     prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
     kappa, fb_frac_cal, err_cal = L.choose_kappa(sig.max(dim=1).values.cpu().numpy(),
                                                  L.rt60_error(prm, refs["cal"], 4),
@@ -209,18 +217,20 @@ def run_learn(a):
                                want_features=True, chunk=1024, **L.INPUT)
     prm, _, _ = L.predict(model, cheap_data["features"], cheap_data["e_in"], 4, 1e9)
     err_net = L.rt60_error_summary(L.rt60_error(prm, refs["eval"], 4))
-    prm, unc, cheap = L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star)
+    prm, unc, cheap = L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, fallback=fbm)
     err_learned = L.rt60_error_summary(L.rt60_error(prm, refs["eval"], 4))
     fb_frac = float(unc.float().mean())
     for _ in range(a.warmup):
-        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star, cheap=cheap)
+        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, cheap=cheap, fallback=fbm)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_star, cheap=cheap)
+        L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, cheap=cheap, fallback=fbm)
     torch.cuda.synchronize()
     t_learned = (time.perf_counter() - t0) / a.steps
     ips_plain, _ = L.timed_plain(scenes["eval"], rooms["eval"], n_star, steps=a.steps)
+    ips_plain_l, _ = L.timed_plain(scenes["eval"], rooms["eval"], n_star_l, steps=a.steps, method="listener",
+                                   order=2)
     n_ev = len(rooms["eval"])
     out = {
         "metric": "IRs/s at <=5% RT60 error, learned vs plain ray trace", "value": n_ev / t_learned,
@@ -228,16 +238,20 @@ def run_learn(a):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32 trace, bf16 mlp",
         "data": "synthetic",
         "config": {"workload": f"learn: {n_ev} held-out shoebox/L-rooms (dims U[3,40] m); step = learned estimate "
-                               f"of every room (1k-ray trace + MLP + fallback at N*); "
+                               f"of every room (1k-ray trace + MLP + {fbm}-origin fallback at its N*); "
                                f"{a.learn_train} training rooms x {a.learn_views} inputs (100k rooms named for this "
                                f"workload), {a.learn_target_rays}-ray targets, 262,144-ray references",
                    "train_rooms": a.learn_train, "eval_rooms": n_ev, "views": a.learn_views,
                    "target_rays": a.learn_target_rays},
         "plain": {"n_star": n_star, "irs_per_s": ips_plain, "sweep": {str(k): v for k, v in sweep.items()}},
+        "plain_listener": {"n_star": n_star_l, "irs_per_s": ips_plain_l,
+                           "sweep": {str(k): v for k, v in sweep_l.items()}},
         "learned": {"irs_per_s": n_ev / t_learned, "rt60_err": err_learned, "fallback_fraction": fb_frac,
+                    "fallback_method": fbm, "fallback_rays": n_fb,
                     "kappa": kappa, "network_only_rt60_err": err_net, "cal_fallback_fraction": fb_frac_cal,
                     "cal_rt60_err": err_cal},
         "speedup_learned_vs_plain": (n_ev / t_learned) / ips_plain,
+        "speedup_learned_vs_best_plain": (n_ev / t_learned) / max(ips_plain, ips_plain_l),
         "training": {"dataset_s": t_data, "dataset_segments": data["segments"], "train_s": t_train,
                      "epochs": a.learn_epochs, "final_loss": losses[-1]},
         "total_s": time.perf_counter() - t_all,

@@ -233,13 +233,13 @@ def timed_plain(scenes, rooms, n_rays, *, steps=3, device="cuda", method="source
     return len(rooms) / dt, params
 
 
-def learned_estimate(model, scenes, rooms, kappa, n_fallback, *, cheap=None, device="cuda"):
+def learned_estimate(model, scenes, rooms, kappa, n_fallback, *, cheap=None, device="cuda", fallback="source"):
     """The learned path for a set of rooms: a 1k-ray trace (one graph replay
     of `cheap`, a planned Batch over the rooms at INPUT bins, built here when
     None), features, network, decoding; rooms whose uncertainty exceeds kappa
-    are traced again at n_fallback rays by the plain method and their
-    parameters replace the network's.  Returns (params, uncertain mask,
-    cheap batch)."""
+    are traced again at n_fallback rays by the plain method (`fallback`:
+    "source", or "listener" with next-event queries) and their parameters
+    replace the network's.  Returns (params, uncertain mask, cheap batch)."""
     import torch
     nb = scenes[0].n_bands
     nc = (SH_ORDER + 1) ** 2
@@ -258,7 +258,8 @@ def learned_estimate(model, scenes, rooms, kappa, n_fallback, *, cheap=None, dev
         pairs = [dict(p, scene=k, pair_id=k) for k, p in
                  enumerate(room_pairs([rooms[i] for i in sel], n_fallback, SEED_SWEEP + n_fallback))]
         fb = Batch(sub_scenes, pairs, n_bins=CONVERGED["n_bins"], sh_order=SH_ORDER,
-                   bin_width_s=CONVERGED["bin_width_s"], autotune=False, use_graph=False, late=False, device=device)
+                   bin_width_s=CONVERGED["bin_width_s"], autotune=False, use_graph=False, late=False, device=device,
+                   method=fallback, order=2 if fallback == "listener" else 0)
         fb.run()
         from . import params_scatter
         params_scatter(fb.params, idx, params)

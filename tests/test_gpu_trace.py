@@ -374,3 +374,34 @@ def test_bvh_at_one_million_triangles(torch_cuda):
     assert np.mean((tri >= 0) != (trir >= 0)) <= 1 / 256
     both = (tri >= 0) & (trir >= 0)
     assert np.quantile(np.abs(t[both] - tr[both]) / np.maximum(tr[both], 1e-3), 0.99) < 1e-4
+
+
+def test_concurrent_streams_match_serial(torch_cuda):
+    """Steps of the benchmark rotate over several streams: scenes built and
+    traced on three streams at once give each trace the result it has alone
+    (up to the order of FP32 atomic additions), with identical statistics."""
+    torch = torch_cuda
+    c = R.city_config()
+    kw = dict(n_rays_total=4096, max_bounces=c["max_bounces"], sh_order=c["sh_order"], n_bins=c["n_bins"],
+              bin_width_s=c["bin_width_s"], seed=c["seed"])
+    prm = P.trace_params(**kw)
+    ref = gpu_trace(P.Scene.from_dict(c), c["sources"], c["listener"], c["radius"], want_hash=False, **kw)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    outs, scenes = [], []
+    for st in streams:
+        with torch.cuda.stream(st):
+            sc = P.Scene.from_dict(c)  # synchronises its own stream only
+            o = P.alloc_trace_outputs(8, c["n_bins"], 4, c["sh_order"])[:3]
+            P.trace_ir(sc, c["sources"], c["listener"], c["radius"], prm, *o)
+            scenes.append(sc)
+            outs.append(o)
+    torch.cuda.synchronize()
+    for hist, late, stats in outs:
+        H = hist.double().cpu().numpy()
+        st = P.stats_host(stats)
+        for s in range(8):
+            assert_hist_close(H[s], ref["hist"][s], tol=1e-5, what=f"hist[{s}]")
+            assert st[s]["n_segments"] == ref["stats"][s]["n_segments"]
+            assert st[s]["first_arrival_bin"] == ref["stats"][s]["first_arrival_bin"]
+    for sc in scenes:
+        sc.close()
