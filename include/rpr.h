@@ -245,6 +245,17 @@ int estimate_reverb(const float* hist, const float* hist_late, const RprIrStats*
 /* alpha = 1 - exp(-frame_dt_s / tau_s); 1 when tau_s <= 0 (no smoothing). */
 float temporal_alpha(float frame_dt_s, float tau_s);
 
+/* Rays of the next frame under a segment budget (Section 5: every frame
+ * traces the same number of ray segments; rays that escape early leave budget
+ * for more primary rays).  A parallel trace cannot stop at the ray where the
+ * budget runs out, so the frame traces N' rays with 1/N' of the energy each,
+ * N' = clamp(floor(budget_segments * prev_rays / prev_segments), min_rays,
+ * max_rays) from the previous frame's measured segments and rays (summed over
+ * the sources traced together), or clamp(nominal) when there is no previous
+ * frame (prev_segments or prev_rays <= 0).  Host arithmetic; no device call. */
+int64_t budget_ray_count(int64_t budget_segments, int64_t prev_segments, int64_t prev_rays, int64_t min_rays,
+                         int64_t max_rays, int64_t nominal);
+
 /* IR cache: cache[i] = alpha * fresh[i] + (1 - alpha) * cache[i] for
  * i < n, or cache[i] = fresh[i] when first != 0 (the first frame or a reset).
  * Use it on the all-orders histogram with the early factor and on hist_late

@@ -133,6 +133,7 @@ SIGNATURES = {
     "estimate_reverb": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, C.c_float, C.POINTER(EstimateParams),
                                   _vp, _vp]),
     "temporal_alpha": (C.c_float, [C.c_float, C.c_float]),
+    "budget_ray_count": (_i64, [_i64, _i64, _i64, _i64, _i64, _i64]),
     "ir_cache_update": (C.c_int, [_vp, _vp, _i64, C.c_float, _i32, _vp]),
     "reverb_params_smooth": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, C.c_float, _i32, _vp]),
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
@@ -324,6 +325,12 @@ def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width
     ep = EstimateParams(int(rt60_source), int(tail_iters))
     _check(lib().estimate_reverb(_ptr(hist), _ptr(hist_late), _ptr(stats), n_ir, int(n_bins), int(n_bands),
                                  int(sh_order), float(bin_width_s), C.byref(ep), _ptr(out), _stream(stream)))
+
+
+def budget_ray_count(budget_segments, prev_segments, prev_rays, min_rays, max_rays, nominal) -> int:
+    """Rays of the next frame under a segment budget (see include/rpr.h)."""
+    return int(lib().budget_ray_count(int(budget_segments), int(prev_segments), int(prev_rays), int(min_rays),
+                                      int(max_rays), int(nominal)))
 
 
 def temporal_alpha(frame_dt_s: float, tau_s: float) -> float:

@@ -1,5 +1,6 @@
 // Temporal coherence across frames (Section 4.2, Eq. 4; Section 5, the
-// early- and late-reflection caches with their own time constants).
+// early- and late-reflection caches with their own time constants), and the
+// frame's ray count under a segment budget (Section 5).
 //
 // ir_cache_update: every histogram cell of the cache becomes
 // alpha * fresh + (1 - alpha) * cache (the fresh value on the first frame).
@@ -74,6 +75,18 @@ __global__ void k_params_smooth(RprReverbParams* __restrict__ cache, const RprRe
 }  // namespace rpr
 
 using namespace rpr;
+
+extern "C" int64_t budget_ray_count(int64_t budget_segments, int64_t prev_segments, int64_t prev_rays,
+                                    int64_t min_rays, int64_t max_rays, int64_t nominal)
+{
+    int64_t n = nominal;
+    if (prev_segments > 0 && prev_rays > 0) {
+        // floor(budget * prev_rays / prev_segments) without overflowing 64 bits
+        const __int128 q = (__int128)budget_segments * (__int128)prev_rays / (__int128)prev_segments;
+        n = q > (__int128)INT64_MAX ? INT64_MAX : (int64_t)q;
+    }
+    return std::max(min_rays, std::min(n, max_rays));
+}
 
 extern "C" float temporal_alpha(float frame_dt_s, float tau_s)
 {

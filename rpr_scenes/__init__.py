@@ -197,8 +197,40 @@ def city_config(seed=1, target_tris=100_000, extent=500.0, cell=36.0, n_material
         absorption=absorption, scattering=scattering,
         sources=np.array(srcs, np.float32), listener=lp.astype(np.float32), radius=radius,
         n_rays=32768, max_bounces=100, n_bins=3000, bin_width_s=1e-3, sh_order=3, seed=1,
-        panel_edge=edge, n_buildings=len(bld),
+        panel_edge=edge, n_buildings=len(bld), buildings=bld,
     )
+
+
+def city_source_walk(cfg, n_frames, step=3.0, seed=7, clear=0.5):
+    """Street-level random walks of the city's sources: each frame a source
+    moves `step` metres in its current heading, turning to a random heading
+    whenever the move would enter a building (with `clear` metres margin) or
+    leave the ground plane.  Returns [n_frames][n_sources][3] float32."""
+    g = rng(seed)
+    bld = cfg["buildings"]
+    extent = float(cfg["verts"][:, 0].max())
+
+    def free(p):
+        if not (clear <= p[0] <= extent - clear and clear <= p[1] <= extent - clear):
+            return False
+        for (x0, y0, fx, fy, _) in bld:
+            if x0 - clear <= p[0] <= x0 + fx + clear and y0 - clear <= p[1] <= y0 + fy + clear:
+                return False
+        return True
+
+    pos = cfg["sources"].astype(np.float64).copy()
+    head = g.uniform(0, 2 * math.pi, len(pos))
+    out = []
+    for _ in range(n_frames):
+        out.append(pos.copy())
+        for i in range(len(pos)):
+            for _try in range(64):
+                q = pos[i] + step * np.array([math.cos(head[i]), math.sin(head[i]), 0.0])
+                if free(q):
+                    pos[i] = q
+                    break
+                head[i] = g.uniform(0, 2 * math.pi)
+    return np.array(out, np.float32)
 
 
 def lroom(dims, notch, edge=None):

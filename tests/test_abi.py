@@ -104,3 +104,12 @@ def test_temporal_alpha_is_host_side_and_matches_oracle():
     for dt, tau in ((0.1, 1.0), (0.1, 3.0), (0.02, 0.5)):
         assert math.isclose(P.temporal_alpha(dt, tau), TC.smoothing_alpha(dt, tau), rel_tol=1e-6)
     assert P.temporal_alpha(0.1, 0.0) == 1.0 and P.temporal_alpha(0.1, -2.0) == 1.0
+
+
+def test_budget_ray_count_is_host_side_and_matches_oracle():
+    from oracle.budget import budget_ray_count as ref
+    g = np.random.default_rng(0)
+    for _ in range(200):
+        args = (int(g.integers(1, 10**12)), int(g.integers(0, 10**10)), int(g.integers(0, 10**7)),
+                int(g.integers(1, 1000)), int(g.integers(1000, 10**9)), int(g.integers(1, 10**6)))
+        assert P.budget_ray_count(*args) == ref(*args), args
