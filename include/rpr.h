@@ -491,6 +491,96 @@ int reverb_model_ood_gate(const uint16_t* features, int64_t n, int32_t F, int32_
 int reverb_params_scatter(const RprReverbParams* src, const int32_t* idx, int64_t n, RprReverbParams* dst,
                           void* hip_stream);
 
+/* ------------------------------------------------------------ SH reverberator
+ * The reverberator that renders the late reverberation from the estimated
+ * parameters (Section 4.1 "Sound Rendering"; Section 4.2 for the comb gains
+ * of Eq. 7, the comb delays and the predelay; Section 5 "Auralization" for 8
+ * combs and 4 all-passes).  Per source and band, 8 feedback combs in parallel
+ * take the band audio x_b, each comb i with delay M_i, input gains a_i (the
+ * real SH of its input direction over 8) and feedback matrix g_b,i J_i (an SH
+ * rotation times the Eq. 7 gain):  y_i[n] = a_i x_b[n - M_i] + g_b,i J_i
+ * y_i[n - M_i].  Their sum passes 4 Schroeder all-passes per SH channel
+ * (delays 4.9, 4.1, 3.4, 2.9 ms, gain 0.7), then the directional-loudness
+ * matrix D_b and the gain g_reverb,b; the bands are summed into
+ * (sh_order+1)^2 output channels.  The input is the band audio read at the
+ * predelay tap of the caller's delay line. */
+#define RPR_REVERB_COMBS 8
+#define RPR_REVERB_ALLPASS 4
+
+typedef struct {
+    int32_t n_bands;        /* 1..RPR_MAX_BANDS */
+    int32_t sh_order;       /* 0..RPR_MAX_SH_ORDER */
+    float sample_rate;      /* Hz, 8000..192000 */
+    float speed_of_sound;   /* m/s, > 0 */
+    float max_comb_delay_s; /* comb delay capacity of the state, 0.005..2 s; longer delays are clamped */
+    int32_t reserved;
+} RprReverbDesc;
+
+/* Parameters of one source's reverberator (device, written by reverb_setup). */
+typedef struct {
+    float t_comb[RPR_REVERB_COMBS];  /* seconds: mean free path / c (1 + z / 3), z clamped to [-2.7, 3],
+                                        then clamped to [1 ms, max_comb_delay_s] */
+    int32_t m_comb[RPR_REVERB_COMBS];/* samples: floor(t fs + 1/2) >= 1 */
+    float mfp_drawn;                 /* mean free path of the last draw (m); 0 = none yet */
+    int32_t predelay_samples;        /* floor(t_first fs + 1/2): the caller's input tap */
+    int32_t n_bands;
+    int32_t sh_order;
+    float g_comb[RPR_MAX_BANDS][RPR_REVERB_COMBS]; /* Eq. 7: 10^(-3 t / RT60); 0 if RT60 <= 0 */
+    float g_reverb[RPR_MAX_BANDS];                 /* Eq. 5 with Eq. 8 */
+    float dir[RPR_REVERB_COMBS][4];                /* input direction (x, y, z, 1), or (0, 0, 0, 0) */
+    float a[RPR_REVERB_COMBS][RPR_MAX_COEFFS];     /* comb input gains */
+    float J[RPR_REVERB_COMBS][RPR_MAX_COEFFS][RPR_MAX_COEFFS]; /* SH rotation of each comb's feedback */
+    float D[RPR_MAX_BANDS][RPR_MAX_COEFFS][RPR_MAX_COEFFS];   /* directional loudness */
+} RprReverbSetup;
+
+/* Bytes of rendering state one source needs (comb and all-pass delay lines
+ * plus a 64-byte header), for the given description.  Returns RPR_EINVAL for
+ * a description out of range. */
+int reverb_state_bytes(const RprReverbDesc* desc /* host */, int64_t* bytes_per_source /* host */);
+
+/* Zero the state of n_src sources (device, n_src * bytes_per_source bytes,
+ * 16-byte aligned), e.g. before the first render or to silence them. */
+int reverb_state_reset(void* state, int32_t n_src, const RprReverbDesc* desc, void* hip_stream);
+
+/* Reverberator parameters of n_ir sources from their reverb estimates
+ * (Section 4.1, Section 4.2):
+ *   - comb delays drawn from the caller's standard normals z (device
+ *     [n_ir][8] f32) around mean_free_path_m / c with sigma a third of that;
+ *     with first = 0 the delays in setup[i] are kept while mean_free_path_m /
+ *     c stays within 2 sigma of the mean of their draw, and also when
+ *     mean_free_path_m <= 0;
+ *   - Eq. 7 gains per band from rt60; g_reverb copied;
+ *   - input direction of comb i from hist (device [n_ir][n_bins][n_bands]
+ *     [(sh_order+1)^2] f32, the all-orders histogram) at t_first + t_comb,i,
+ *     t_first = predelay_s (first_arrival_s if that is < 0, else 0): the
+ *     band-summed first-order coefficients, linear between bin starts, zero
+ *     past the last bin; direction (-X_11, -X_1-1, X_10) normalised; a zero
+ *     vector (or sh_order 0) gives an omnidirectional input a_i = Y_00 e_0 / 8;
+ *   - J_i, the SH rotation of R_i = Rz(c) Ry(b) Rx(a) with angles (a, b, c)
+ *     from the caller (device [n_ir][8][3] f32, radians), built by exact
+ *     quadrature of Y_k(R v) Y_k'(v) over the sphere;
+ *   - D_b = sum_q w_q g_b(v_q) Y(v_q) Y(v_q)^T, g_b = sqrt(max(0, 4 pi
+ *     dir_loudness_b . Y)), over 8 Gauss-Legendre nodes in cos(theta) x 16
+ *     azimuths; the identity where dir_loudness_b,00 <= 0.
+ *   params device [n_ir]; setup device [n_ir], read (first = 0) and written.
+ *   The histogram's SH order and band count are desc's. */
+int reverb_setup(const RprReverbParams* params, const float* hist, int32_t n_ir, int32_t n_bins, float bin_width_s,
+                 const float* z, const float* angles, int32_t first, const RprReverbDesc* desc,
+                 RprReverbSetup* setup, void* hip_stream);
+
+/* Render n samples of n_src reverberators.
+ *   setup device [n_src] (from reverb_setup with the same desc)
+ *   x     device [n_src][n_bands][n] f32: band audio at each source's predelay tap
+ *   state device [n_src] x bytes_per_source, 16-byte aligned: delay lines and
+ *         their positions, carried from call to call (zeroed by
+ *         reverb_state_reset); one source's state must not be rendered by two
+ *         calls at once
+ *   out   device [n_src][(sh_order+1)^2][n] f32, overwritten
+ * Consecutive calls continue the same output stream.  A comb whose delay
+ * changes between calls keeps the contents of its delay line.  n >= 0. */
+int reverb_render(const RprReverbSetup* setup, int32_t n_src, const float* x, int32_t n, void* state, float* out,
+                  const RprReverbDesc* desc, void* hip_stream);
+
 /* Closest hit of arbitrary rays against the scene's BVH, with the same
  * traversal and triangle test as trace_ir (no triangle excluded).
  *   orig, dir device [n][3] f32;  t_out device [n] f32 (INFINITY on a miss);

@@ -87,6 +87,11 @@ class BatchInfo(C.Structure):
 
 
 # Host views of the device structs (same layout as include/rpr.h).
+class ReverbDesc(C.Structure):
+    _fields_ = [("n_bands", C.c_int32), ("sh_order", C.c_int32), ("sample_rate", C.c_float),
+                ("speed_of_sound", C.c_float), ("max_comb_delay_s", C.c_float), ("reserved", C.c_int32)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("n_params", C.c_int64), ("n_layers", C.c_int32), ("dims", C.c_int32 * 9), ("max_batch", C.c_int32),
                 ("step", C.c_int64)]
@@ -115,7 +120,17 @@ REVERB_PARAMS_DTYPE = np.dtype([
     ("g_reverb", "<f4", (MAX_BANDS,)), ("predelay_s", "<f4"), ("first_arrival_s", "<f4"),
     ("mean_free_path_m", "<f4"), ("reserved", "<f4"), ("dir_loudness", "<f4", (MAX_BANDS, MAX_COEFFS)),
 ])
+REVERB_COMBS = 8
+REVERB_ALLPASS = 4
+REVERB_SETUP_DTYPE = np.dtype([
+    ("t_comb", "<f4", (REVERB_COMBS,)), ("m_comb", "<i4", (REVERB_COMBS,)), ("mfp_drawn", "<f4"),
+    ("predelay_samples", "<i4"), ("n_bands", "<i4"), ("sh_order", "<i4"),
+    ("g_comb", "<f4", (MAX_BANDS, REVERB_COMBS)), ("g_reverb", "<f4", (MAX_BANDS,)),
+    ("dir", "<f4", (REVERB_COMBS, 4)), ("a", "<f4", (REVERB_COMBS, MAX_COEFFS)),
+    ("J", "<f4", (REVERB_COMBS, MAX_COEFFS, MAX_COEFFS)), ("D", "<f4", (MAX_BANDS, MAX_COEFFS, MAX_COEFFS)),
+])
 assert IR_STATS_DTYPE.itemsize == 536 and REVERB_PARAMS_DTYPE.itemsize == 752
+assert REVERB_SETUP_DTYPE.itemsize == 17392
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -136,6 +151,10 @@ SIGNATURES = {
     "budget_ray_count": (_i64, [_i64, _i64, _i64, _i64, _i64, _i64]),
     "ir_cache_update": (C.c_int, [_vp, _vp, _i64, C.c_float, _i32, _vp]),
     "reverb_params_smooth": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, C.c_float, _i32, _vp]),
+    "reverb_state_bytes": (C.c_int, [C.POINTER(ReverbDesc), C.POINTER(_i64)]),
+    "reverb_state_reset": (C.c_int, [_vp, _i32, C.POINTER(ReverbDesc), _vp]),
+    "reverb_setup": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, _vp, _vp, _i32, C.POINTER(ReverbDesc), _vp, _vp]),
+    "reverb_render": (C.c_int, [_vp, _i32, _vp, _i32, _vp, _vp, C.POINTER(ReverbDesc), _vp]),
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "debug_philox": (C.c_int, [_vp, _i64, _vp, _vp]),
     "debug_sh_eval": (C.c_int, [_vp, _i64, _i32, _vp, _vp]),
@@ -589,6 +608,73 @@ def ood_gate(features, c0, c1, zmax, n_bands, params=None, uncertain=None, strea
 
 def params_scatter(src, idx, dst, stream=None):
     _check(lib().reverb_params_scatter(_ptr(src), _ptr(idx), idx.shape[0], _ptr(dst), _stream(stream)))
+
+
+def reverb_desc(n_bands=4, sh_order=1, sample_rate=44100.0, speed_of_sound=343.0, max_comb_delay_s=0.3):
+    return ReverbDesc(int(n_bands), int(sh_order), float(sample_rate), float(speed_of_sound),
+                      float(max_comb_delay_s), 0)
+
+
+def reverb_state_bytes(desc: ReverbDesc) -> int:
+    """Bytes of rendering state per source (delay lines + header)."""
+    b = _i64(0)
+    _check(lib().reverb_state_bytes(C.byref(desc), C.byref(b)))
+    return int(b.value)
+
+
+def reverb_state(n_src, desc: ReverbDesc, device="cuda", stream=None):
+    """Zeroed rendering state of n_src sources ([n_src, bytes] uint8)."""
+    import torch
+    st = torch.empty((n_src, reverb_state_bytes(desc)), dtype=torch.uint8, device=device)
+    reverb_state_reset(st, desc, stream)
+    return st
+
+
+def reverb_state_reset(state, desc: ReverbDesc, stream=None):
+    _check(lib().reverb_state_reset(_ptr(state), int(state.shape[0]), C.byref(desc), _stream(stream)))
+
+
+def alloc_reverb_setup(n, device="cuda"):
+    import torch
+    return torch.zeros((n, REVERB_SETUP_DTYPE.itemsize), dtype=torch.uint8, device=device)
+
+
+def reverb_setup(params, hist, bin_width_s, z, angles, desc: ReverbDesc, setup=None, first=True, stream=None):
+    """Reverberator parameters of each IR (see include/rpr.h).  params [n, 752]
+    uint8 (REVERB_PARAMS_DTYPE), hist [n, T, B, NC] f32, z [n, 8] f32 standard
+    normals, angles [n, 8, 3] f32 radians; setup [n, 17392] uint8 (read when
+    first is False).  Returns setup."""
+    n = int(params.shape[0])
+    assert hist.shape[0] == n and hist.dtype.is_floating_point and hist.is_contiguous()
+    assert hist.shape[2] == desc.n_bands and hist.shape[3] == (desc.sh_order + 1) ** 2
+    assert tuple(z.shape) == (n, REVERB_COMBS) and tuple(angles.shape) == (n, REVERB_COMBS, 3)
+    if setup is None:
+        setup = alloc_reverb_setup(n, params.device)
+    assert setup.shape[0] == n and setup.shape[1] == REVERB_SETUP_DTYPE.itemsize
+    _check(lib().reverb_setup(_ptr(params), _ptr(hist), n, int(hist.shape[1]), float(bin_width_s), _ptr(z),
+                              _ptr(angles), int(bool(first)), C.byref(desc), _ptr(setup), _stream(stream)))
+    return setup
+
+
+def reverb_render(setup, x, state, desc: ReverbDesc, out=None, stream=None):
+    """Render x [n_src, n_bands, n] f32 (band audio at the predelay tap) into
+    out [n_src, (sh_order+1)^2, n] f32, continuing each source's state."""
+    import torch
+    n_src, nb, n = x.shape
+    nc = (desc.sh_order + 1) ** 2
+    assert nb == desc.n_bands and x.dtype == torch.float32 and x.is_contiguous()
+    assert setup.shape[0] >= n_src and state.shape[0] >= n_src
+    assert state.shape[1] == reverb_state_bytes(desc)
+    if out is None:
+        out = torch.empty((n_src, nc, n), dtype=torch.float32, device=x.device)
+    assert tuple(out.shape) == (n_src, nc, n) and out.is_contiguous()
+    _check(lib().reverb_render(_ptr(setup), n_src, _ptr(x), n, _ptr(state), _ptr(out), C.byref(desc),
+                               _stream(stream)))
+    return out
+
+
+def reverb_setup_host(setup) -> np.ndarray:
+    return setup.cpu().numpy().view(REVERB_SETUP_DTYPE).reshape(-1)
 
 
 def header_functions(path: str = HEADER) -> list[str]:

@@ -472,3 +472,60 @@ def random_rays(seed: int, n: int, lo, hi):
     d = g.normal(size=(n, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     return o.astype(np.float32), d.astype(np.float32)
+
+
+def reverb_inputs(seed: int, n_ir: int, n_bands: int, sh_order: int, n_bins: int = 80, bin_width_s: float = 0.01,
+                  mfp_range=(2.0, 40.0)):
+    """Seeded inputs of the SH reverberator, shaped like the estimates of
+    rooms and outdoor scenes: RT60 U(0.2, 3) s per band, g_reverb U(0.01,
+    0.5), mean free path U(mfp_range) m, a predelay (first late bin) 2..12
+    bins after t = 0 and a first arrival one to two bins earlier, an
+    all-orders histogram [n_ir][n_bins][n_bands][(n+1)^2] whose energy decays
+    from the first arrival while its dominant direction turns from bin to
+    bin, a directional distribution per band (coefficient 0 = 1/sqrt(4 pi),
+    the others uniform in +-0.3 of it), the standard normals of the comb
+    delays and the rotation angles in [pi/2, 3pi/2].  Plain random numbers and
+    shapes only: returns a dict of numpy arrays."""
+    g = rng(seed)
+    nc = (sh_order + 1) ** 2
+    B, T = n_bands, n_bins
+    fa = g.integers(0, 10, size=n_ir)
+    pre = fa + g.integers(1, 3, size=n_ir)
+    hist = np.zeros((n_ir, T, B, nc), np.float32)
+    for i in range(n_ir):
+        tau = g.uniform(3.0, 25.0)
+        env = np.zeros(T)
+        env[fa[i]:] = np.exp(-np.arange(T - fa[i]) / tau)
+        a0 = g.normal(size=3)
+        a1 = g.normal(size=3)
+        for t in range(fa[i], T):
+            s = (t - fa[i]) / max(T - fa[i] - 1, 1)
+            u = (1 - s) * a0 + s * a1
+            u = u / (np.linalg.norm(u) + 1e-30)
+            for b in range(B):
+                e = env[t] * g.uniform(0.5, 1.0) / (b + 1)
+                hist[i, t, b, 0] = e * 0.28209479177387814
+                if nc >= 4:
+                    k = 0.4886025119029199 * e * g.uniform(0.3, 0.9)
+                    hist[i, t, b, 1:4] = (-k * u[1], k * u[2], -k * u[0])
+                if nc > 4:
+                    hist[i, t, b, 4:] = e * g.uniform(-0.05, 0.05, size=nc - 4)
+    xbar = np.zeros((n_ir, 8, 16), np.float32)
+    xbar[:, :B, 0] = 1 / math.sqrt(4 * math.pi)
+    xbar[:, :B, 1:nc] = g.uniform(-0.3, 0.3, size=(n_ir, B, nc - 1)) / math.sqrt(4 * math.pi)
+    rt = np.zeros((n_ir, 8), np.float32)
+    rt[:, :B] = g.uniform(0.2, 3.0, size=(n_ir, B))
+    gr = np.zeros((n_ir, 8), np.float32)
+    gr[:, :B] = g.uniform(0.01, 0.5, size=(n_ir, B))
+    return dict(
+        rt60=rt, g_reverb=gr, dir_loudness=xbar,
+        mean_free_path_m=g.uniform(*mfp_range, size=n_ir).astype(np.float32),
+        predelay_s=(pre * bin_width_s).astype(np.float32), first_arrival_s=(fa * bin_width_s).astype(np.float32),
+        hist=hist, bin_width_s=bin_width_s,
+        z=g.normal(size=(n_ir, 8)).astype(np.float32),
+        angles=g.uniform(math.pi / 2, 1.5 * math.pi, size=(n_ir, 8, 3)).astype(np.float32))
+
+
+def band_audio(seed: int, n_src: int, n_bands: int, n: int, scale: float = 0.1):
+    """Seeded band audio [n_src][n_bands][n] f32: white noise, scale rms."""
+    return (rng(seed).normal(size=(n_src, n_bands, n)) * scale).astype(np.float32)
