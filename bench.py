@@ -54,12 +54,13 @@ def parse():
     ap.add_argument("--streams", type=int, default=3, help="city: streams the consecutive steps rotate over")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms"), default="city",
+    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb"), default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
                          "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
                          "learned estimator vs plain ray trace (builds its dataset and trains first); rooms: "
                          "IRs/s at <= 5%% RT60 error of the plain trace from the sources vs from the listener "
-                         "with next-event estimation")
+                         "with next-event estimation; reverb: audio-rate rendering of the SH reverberator for "
+                         "many sources")
     ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
@@ -93,6 +94,9 @@ def parse():
     ap.add_argument("--learned", action="store_true",
                     help="hospital: also run the learned estimator inline (trains it first on --learn-train "
                          "rooms), with a ray-trace fallback for uncertain sources")
+    ap.add_argument("--reverb-sources", type=int, default=4096, help="reverb: sources rendered per step")
+    ap.add_argument("--reverb-block", type=int, default=1024, help="reverb: samples per source per step")
+    ap.add_argument("--reverb-order", type=int, default=1, help="reverb: SH order of the rendered channels")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
                          "(a known-size reference for the HBM byte counters)")
@@ -347,6 +351,109 @@ def run_rooms(a):
         "speedup_listener_vs_source": lst["irs_per_s"] / res["source"]["irs_per_s"],
     }
     print(json.dumps(out), flush=True)
+
+
+def run_reverb(a):
+    """Audio-rate rendering of the SH reverberator (Section 4.1; 8 combs and 4
+    all-passes, Section 5): every step renders the next block of band audio
+    for all sources, their delay lines carried from step to step; the
+    parameters (reverb_setup) are built once before, as at a propagation
+    update, and timed on their own."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+    dev = torch.device("cuda:0")
+    S, n, order, B, fs = a.reverb_sources, a.reverb_block, a.reverb_order, 4, 44100.0
+    nc = (order + 1) ** 2
+    desc = P.reverb_desc(B, order, fs, 343.0, 0.3)
+    log(f"reverb: {S} sources x {n} samples, {B} bands, SH order {order}, {fs:.0f} Hz", a.quiet)
+    inp = R.reverb_inputs(5, S, B, order, n_bins=40)
+    prm = np.zeros(S, P.REVERB_PARAMS_DTYPE)
+    for k in ("rt60", "g_reverb", "dir_loudness", "mean_free_path_m", "predelay_s", "first_arrival_s"):
+        prm[k] = inp[k]
+    params = torch.from_numpy(prm.view(np.uint8).reshape(S, -1).copy()).to(dev)
+    hist = torch.from_numpy(inp["hist"]).to(dev)
+    z = torch.from_numpy(inp["z"]).to(dev)
+    ang = torch.from_numpy(inp["angles"]).to(dev)
+    setup = P.alloc_reverb_setup(S, dev)
+    state = P.reverb_state(S, desc, dev)
+    x = torch.from_numpy(R.band_audio(6, S, B, n)).to(dev)
+    out = torch.empty((S, nc, n), dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    P.reverb_setup(params, hist, inp["bin_width_s"], z, ang, desc, setup=setup, first=True)
+    e1.record()
+    torch.cuda.synchronize()
+    setup_ms = e0.elapsed_time(e1)
+    sh = P.reverb_setup_host(setup)
+    for _ in range(a.warmup):
+        P.reverb_render(setup, x, state, desc, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(a.steps):
+        ev[i][0].record()
+        P.reverb_render(setup, x, state, desc, out=out)
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    ms_step = wall * 1e3 / a.steps
+    value = S * n * a.steps / wall
+    ap_m = [int(np.floor(t * fs + 0.5)) for t in (4.9e-3, 4.1e-3, 3.4e-3, 2.9e-3)]
+    # algorithmic HBM bytes per launch: each comb line read and written once per sample, the band
+    # input read and the channels written once, the all-pass lines (short, cache-resident within a
+    # launch) read and written once, the setup rows read once
+    per_src = (n * B * 8 * nc * 8 + n * B * 4 + n * nc * 4 + 2 * B * nc * 4 * sum(ap_m)
+               + 4 * (8 * nc * nc + B * nc * nc + 8 * nc + 8 * B + B + 8) + 64)
+    bytes_launch = S * per_src
+    achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    res = {
+        "metric": "reverb source-samples/s", "value": value, "unit": "source-samples/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"reverb: {S} sources x {n}-sample blocks at {fs:.0f} Hz, {B} bands, SH order "
+                               f"{order} ({nc} channels), 8 combs with SH rotations + 4 all-passes + loudness "
+                               f"matrix; parameters from seeded estimates (RT60 U(0.2,3) s, mean free path "
+                               f"U(2,40) m); step = one block for every source",
+                   "sources": S, "block": n, "bands": B, "sh_order": order, "sample_rate": fs},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_reverb_render",
+                     "bytes_per_source_sample": per_src / n, "kernel_ms": k_ms},
+        "realtime_sources": value / fs,
+        "setup_ms": setup_ms,
+        "mean_comb_delay_ms": float(sh["t_comb"][:S].mean() * 1e3),
+    }
+    if not a.no_cpu_baseline:
+        import oracle  # noqa: F401  (the oracle's SH basis is loaded through it)
+        from oracle import reverb as RV
+        ns, nsamp = 4, 16384
+        xs = R.band_audio(7, ns, B, nsamp).astype(np.float64)
+        c0 = time.perf_counter()
+        for s_ in range(ns):
+            po = dict(rt60=inp["rt60"][s_, :B].astype(np.float64), g_reverb=inp["g_reverb"][s_, :B].astype(np.float64),
+                      dir_loudness=inp["dir_loudness"][s_, :B, :nc].astype(np.float64),
+                      predelay_s=float(inp["predelay_s"][s_]), first_arrival_s=float(inp["first_arrival_s"][s_]),
+                      mean_free_path_m=float(inp["mean_free_path_m"][s_]))
+            so = RV.setup(po, inp["hist"][s_].astype(np.float64), inp["bin_width_s"], inp["z"][s_].astype(np.float64),
+                          inp["angles"][s_].astype(np.float64), order=order, n_bands=B, fs=fs, c=343.0, t_max=0.3)
+            RV.render(xs[s_], so, order)
+        c_wall = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": ns * nsamp / c_wall, "unit": "source-samples/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"sources 0..{ns - 1}, {nsamp} samples each ({c_wall:.1f} s), FP64 "
+                                         f"per-sample loops, setup included"}
+    if a.calib_copy_mib > 0:
+        m = a.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(m, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = 4 * m
+    print(json.dumps(res), flush=True)
 
 
 def run_city_frames(a):
@@ -660,6 +767,9 @@ def main():
         return
     if a.workload == "rooms":
         run_rooms(a)
+        return
+    if a.workload == "reverb":
+        run_reverb(a)
         return
     if a.segment_budget > 0:
         run_city_frames(a)

@@ -14,11 +14,12 @@
 // sample n holds the line's value from n - M, so a sample reads its slot and
 // writes it back, and a run of up to min(M) consecutive samples touches
 // distinct slots.  The block is walked in such sub-steps, the samples of a
-// sub-step in parallel (one thread per band and sample), with one barrier
-// between sub-steps.  Comb lines hold w[n] = a x[n] + G y[n] (so that
-// y[n] = w[n - M]), all-pass lines w[n] = u[n] + g w[n - M] with output
-// v[n] = -g w[n] + w[n - M].  The delay lines are read and written once per
-// sample, so the render is bound by HBM traffic.
+// sub-step in parallel (one wave per band and run of 64 samples), with a
+// barrier between sub-steps.  Comb lines hold w[n] = a x[n] + G y[n] (so
+// that y[n] = w[n - M]), all-pass lines w[n] = u[n] + g w[n - M] with output
+// v[n] = -g w[n] + w[n - M].  The comb lines are read and written once per
+// sample and dominate the traffic, so the render is bound by HBM; the short
+// all-pass lines stay in LDS for the launch where they fit.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,8 +39,10 @@ constexpr double kApDelayS[kAllpass] = {4.9e-3, 4.1e-3, 3.4e-3, 2.9e-3};
 constexpr float kApGain = 0.7f;
 constexpr double kMinCombS = 1e-3;
 constexpr int kHeaderBytes = 64;
-constexpr int kRenderThreads = 256;
-constexpr int kOutStage = 4096;  // floats of LDS for the per-band outputs of one sub-step
+constexpr int kRenderThreads = 512;
+constexpr int kRenderWaves = kRenderThreads / 64;
+constexpr int kOutStage = 2048;  // floats of LDS for the per-band outputs of one sub-step
+constexpr int kLdsLimit = 65536; // bytes of LDS a render workgroup may use
 constexpr int kQuadZ = 8, kQuadPhi = 16, kQuad = kQuadZ * kQuadPhi;
 
 struct Geometry {
@@ -64,7 +67,8 @@ int geometry(const RprReverbDesc* d, Geometry* g)
         g->ap_m[j] = std::max(1, samples_of(kApDelayS[j], (double)d->sample_rate));
         g->a_cap = std::max(g->a_cap, g->ap_m[j]);
     }
-    const int64_t floats = (int64_t)g->nb * g->nc * ((int64_t)kCombs * g->m_cap + (int64_t)kAllpass * g->a_cap);
+    const int64_t pad = g->nc == 1 ? 1 : (g->nc + 3) / 4 * 4;  // channels of a comb-line slot
+    const int64_t floats = (int64_t)g->nb * ((int64_t)kCombs * g->m_cap * pad + (int64_t)kAllpass * g->nc * g->a_cap);
     g->bytes = (kHeaderBytes + floats * 4 + 255) / 256 * 256;
     return RPR_OK;
 }
@@ -270,21 +274,71 @@ __global__ __launch_bounds__(256) void k_reverb_setup(const RprReverbParams* __r
 // ------------------------------------------------------------------ render
 struct ApArgs {
     int m[kAllpass];
+    int pref[kAllpass];  // offset of each all-pass line in the LDS copy (prefix sums of m)
+    int sum;
 };
 
+// Static LDS of the render kernel, an upper bound for the budget of the
+// all-pass lines (which take the rest when they fit).
+constexpr int render_static_lds(int nc)
+{
+    return 4 * (kOutStage + kCombs * nc * nc + RPR_MAX_BANDS * nc * nc + kCombs * nc + RPR_MAX_BANDS * kCombs +
+                RPR_MAX_BANDS + 2 * (kCombs + kAllpass)) + 256;
+}
+
+// Comb line layout [band][comb][slot][channel]: the channels of a sample are
+// contiguous, padded to a multiple of 4 from order 1 on, and move as float4.
+// kGroup combs have their loads in flight together.
 template <int NC>
-__global__ __launch_bounds__(kRenderThreads) void k_reverb_render(const RprReverbSetup* __restrict__ setup,
+struct CombLine {
+    static constexpr int kPad = NC == 1 ? 1 : (NC + 3) / 4 * 4;
+    static constexpr int kGroup = NC == 1 ? kCombs : std::max(1, 32 / kPad);
+    __device__ static void load(const float* p, float (&y)[kPad])
+    {
+        if constexpr (NC == 1) {
+            y[0] = *p;
+        } else {
+#pragma unroll
+            for (int v = 0; v < kPad / 4; ++v) {
+                const float4 t = reinterpret_cast<const float4*>(p)[v];
+                y[4 * v] = t.x;
+                y[4 * v + 1] = t.y;
+                y[4 * v + 2] = t.z;
+                y[4 * v + 3] = t.w;
+            }
+        }
+    }
+    __device__ static void store(float* p, const float (&w)[kPad])
+    {
+        if constexpr (NC == 1) {
+            *p = w[0];
+        } else {
+#pragma unroll
+            for (int v = 0; v < kPad / 4; ++v)
+                reinterpret_cast<float4*>(p)[v] = make_float4(w[4 * v], w[4 * v + 1], w[4 * v + 2], w[4 * v + 3]);
+        }
+    }
+};
+
+// AP_LDS: the all-pass lines are copied into LDS for the launch (loaded at
+// the start, stored at the end).  They are short (a few ms) and touched
+// every few sub-steps; in global memory the streaming comb lines evict them
+// from L2 between touches.
+template <int NC, bool AP_LDS>
+__global__ __launch_bounds__(kRenderThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_reverb_render(const RprReverbSetup* __restrict__ setup,
                                                                    const float* __restrict__ x, int n,
                                                                    char* __restrict__ state, int64_t stride,
                                                                    float* __restrict__ out, int nb, int m_cap,
                                                                    int a_cap, ApArgs ap)
 {
-    const int src = blockIdx.x, tid = threadIdx.x;
+    extern __shared__ float s_apl[];
+    const int src = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const RprReverbSetup& S = setup[src];
     char* st = state + (size_t)src * stride;
     int* header = reinterpret_cast<int*>(st);
     float* comb = reinterpret_cast<float*>(st + kHeaderBytes);
-    float* apl = comb + (size_t)nb * kCombs * NC * m_cap;
+    float* apl = comb + (size_t)nb * kCombs * CombLine<NC>::kPad * m_cap;
 
     __shared__ float s_J[kCombs][NC][NC];
     __shared__ float s_a[kCombs][NC];
@@ -312,57 +366,97 @@ __global__ __launch_bounds__(kRenderThreads) void k_reverb_render(const RprRever
     } else if (tid < kCombs + kAllpass) {
         s_ph[tid] = (int)((unsigned)header[tid] % (unsigned)ap.m[tid - kCombs]);
     }
+    if constexpr (AP_LDS) {  // [b][k][all-pass lines one after another]
+        for (int e = tid; e < nb * NC * ap.sum; e += kRenderThreads) {
+            const int bk = e / ap.sum, q = e - bk * ap.sum, b = bk / NC, k = bk - b * NC;
+            const int s = (q >= ap.pref[1]) + (q >= ap.pref[2]) + (q >= ap.pref[3]);
+            s_apl[e] = apl[((size_t)(b * kAllpass + s) * NC + k) * a_cap + (q - ap.pref[s])];
+        }
+    }
     __syncthreads();
 
     int M[kCombs], base[kCombs + kAllpass];
     int step = std::min(kOutStage / (nb * NC), 256);
+    // uniform across the workgroup: kept in scalar registers
     for (int i = 0; i < kCombs; ++i) {
-        M[i] = s_M[i];
-        base[i] = s_ph[i];
+        M[i] = __builtin_amdgcn_readfirstlane(s_M[i]);
+        base[i] = __builtin_amdgcn_readfirstlane(s_ph[i]);
         step = std::min(step, M[i]);
     }
     for (int j = 0; j < kAllpass; ++j) {
-        base[kCombs + j] = s_ph[kCombs + j];
+        base[kCombs + j] = __builtin_amdgcn_readfirstlane(s_ph[kCombs + j]);
         step = std::min(step, ap.m[j]);
     }
 
     for (int n1 = 0; n1 < n; n1 += step) {
         const int sc = std::min(step, n - n1);
-        for (int it = tid; it < nb * sc; it += kRenderThreads) {
-            const int b = it / sc, j = it - b * sc, nn = n1 + j;
+        // one wave per band and run of 64 samples: the band, and with it every line base, is uniform
+        const int nj = (sc + 63) >> 6;
+        for (int grp = wave; grp < nb * nj; grp += kRenderWaves) {
+            const int b = grp / nj, j = ((grp - b * nj) << 6) + lane;
+            if (j >= sc) continue;
+            // keeps the LDS reads of J and D inside the loop: hoisted, they would hold
+            // 8 NC^2 + NC^2 registers for the whole loop and spill
+            __asm__ volatile("" ::: "memory");
+            const int nn = n1 + j;
             const float xv = x[((size_t)src * nb + b) * n + nn];
             float u[NC];
 #pragma unroll
             for (int k = 0; k < NC; ++k) u[k] = 0.f;
+            // all loads of a group of combs are issued before its stores (a comb's line
+            // may alias another's as far as the compiler knows)
 #pragma unroll
-            for (int i = 0; i < kCombs; ++i) {
-                int pos = base[i] + j;
-                if (pos >= M[i]) pos -= M[i];
-                float* line = comb + ((size_t)(b * kCombs + i) * NC) * m_cap + pos;
-                float y[NC];
+            for (int i0 = 0; i0 < kCombs; i0 += CombLine<NC>::kGroup) {
+                constexpr int G = CombLine<NC>::kGroup, NP = CombLine<NC>::kPad;
+                float y[G][NP];
+                float* line[G];
 #pragma unroll
-                for (int k = 0; k < NC; ++k) y[k] = line[(size_t)k * m_cap];
-                const float g = s_g[b][i];
+                for (int gi = 0; gi < G; ++gi) {
+                    const int i = i0 + gi;
+                    int pos = base[i] + j;
+                    if (pos >= M[i]) pos -= M[i];
+                    line[gi] = comb + ((size_t)(b * kCombs + i) * m_cap + pos) * NP;
+                    CombLine<NC>::load(line[gi], y[gi]);
+                }
 #pragma unroll
-                for (int k = 0; k < NC; ++k) {
-                    float r = 0.f;
+                for (int gi = 0; gi < G; ++gi) {
+                    const int i = i0 + gi;
+                    const float g = s_g[b][i];
+                    float w[NP];
 #pragma unroll
-                    for (int kk = 0; kk < NC; ++kk) r = fmaf(s_J[i][k][kk], y[kk], r);
-                    line[(size_t)k * m_cap] = fmaf(s_a[i][k], xv, g * r);
-                    u[k] += y[k];
+                    for (int k = 0; k < NP; ++k) w[k] = 0.f;
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) {
+                        float r = 0.f;
+#pragma unroll
+                        for (int kk = 0; kk < NC; ++kk) r = fmaf(s_J[i][k][kk], y[gi][kk], r);
+                        w[k] = fmaf(s_a[i][k], xv, g * r);
+                        u[k] += y[gi][k];
+                    }
+                    CombLine<NC>::store(line[gi], w);
                 }
             }
 #pragma unroll
             for (int s = 0; s < kAllpass; ++s) {
                 int pos = base[kCombs + s] + j;
                 if (pos >= ap.m[s]) pos -= ap.m[s];
-                float* line = apl + ((size_t)(b * kAllpass + s) * NC) * a_cap + pos;
+                float* line;
+                int ks;
+                if constexpr (AP_LDS) {
+                    line = s_apl + (size_t)b * NC * ap.sum + ap.pref[s] + pos;
+                    ks = ap.sum;
+                } else {
+                    line = apl + ((size_t)(b * kAllpass + s) * NC) * a_cap + pos;
+                    ks = a_cap;
+                }
+                float wh[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) wh[k] = line[(size_t)k * ks];  // all loads before the stores
 #pragma unroll
                 for (int k = 0; k < NC; ++k) {
-                    const float wh = line[(size_t)k * a_cap];
-                    const float w = fmaf(kApGain, wh, u[k]);
-                    line[(size_t)k * a_cap] = w;
-                    u[k] = fmaf(-kApGain, w, wh);
+                    const float w = fmaf(kApGain, wh[k], u[k]);
+                    line[(size_t)k * ks] = w;
+                    u[k] = fmaf(-kApGain, w, wh[k]);
                 }
             }
             const float gr = s_gr[b];
@@ -392,6 +486,13 @@ __global__ __launch_bounds__(kRenderThreads) void k_reverb_render(const RprRever
         __syncthreads();
     }
     __syncthreads();
+    if constexpr (AP_LDS) {
+        for (int e = tid; e < nb * NC * ap.sum; e += kRenderThreads) {
+            const int bk = e / ap.sum, q = e - bk * ap.sum, b = bk / NC, k = bk - b * NC;
+            const int s = (q >= ap.pref[1]) + (q >= ap.pref[2]) + (q >= ap.pref[3]);
+            apl[((size_t)(b * kAllpass + s) * NC + k) * a_cap + (q - ap.pref[s])] = s_apl[e];
+        }
+    }
     if (tid < kCombs + kAllpass) header[tid] = base[tid];
 }
 
@@ -460,16 +561,34 @@ extern "C" int reverb_render(const RprReverbSetup* setup, int32_t n_src, const f
     if (reinterpret_cast<uintptr_t>(state) & 15u) return set_error(RPR_EINVAL, "reverb_render: state must be 16-byte aligned");
     if (n_src == 0) return RPR_OK;
     ApArgs ap;
-    for (int j = 0; j < kAllpass; ++j) ap.m[j] = g.ap_m[j];
+    ap.sum = 0;
+    for (int j = 0; j < kAllpass; ++j) {
+        ap.m[j] = g.ap_m[j];
+        ap.pref[j] = ap.sum;
+        ap.sum += g.ap_m[j];
+    }
+    const size_t ap_lds = (size_t)g.nb * g.nc * ap.sum * sizeof(float);
+    const bool in_lds = ap_lds + (size_t)render_static_lds(g.nc) <= (size_t)kLdsLimit;
     const dim3 grid((unsigned)n_src), block(kRenderThreads);
     hipStream_t s = (hipStream_t)hip_stream;
     char* st = reinterpret_cast<char*>(state);
+    const size_t dyn = in_lds ? ap_lds : 0;
+#define RPR_RENDER(NCV)                                                                                    \
+    do {                                                                                                   \
+        if (in_lds)                                                                                        \
+            hipLaunchKernelGGL((k_reverb_render<NCV, true>), grid, block, dyn, s, setup, x, n, st, g.bytes, out, \
+                               g.nb, g.m_cap, g.a_cap, ap);                                                \
+        else                                                                                               \
+            hipLaunchKernelGGL((k_reverb_render<NCV, false>), grid, block, 0, s, setup, x, n, st, g.bytes, out,  \
+                               g.nb, g.m_cap, g.a_cap, ap);                                                \
+    } while (0)
     switch (g.nc) {
-    case 1: hipLaunchKernelGGL(k_reverb_render<1>, grid, block, 0, s, setup, x, n, st, g.bytes, out, g.nb, g.m_cap, g.a_cap, ap); break;
-    case 4: hipLaunchKernelGGL(k_reverb_render<4>, grid, block, 0, s, setup, x, n, st, g.bytes, out, g.nb, g.m_cap, g.a_cap, ap); break;
-    case 9: hipLaunchKernelGGL(k_reverb_render<9>, grid, block, 0, s, setup, x, n, st, g.bytes, out, g.nb, g.m_cap, g.a_cap, ap); break;
-    default: hipLaunchKernelGGL(k_reverb_render<16>, grid, block, 0, s, setup, x, n, st, g.bytes, out, g.nb, g.m_cap, g.a_cap, ap); break;
+    case 1: RPR_RENDER(1); break;
+    case 4: RPR_RENDER(4); break;
+    case 9: RPR_RENDER(9); break;
+    default: RPR_RENDER(16); break;
     }
+#undef RPR_RENDER
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }
