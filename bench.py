@@ -34,10 +34,19 @@ TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/cs
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 
 
-def trace_sources_sha256():
+# HBM bytes per k_reverb_render launch on the default reverb workload (4096 sources x
+# 1024 samples, 4 bands, order 1), from FETCH_SIZE / WRITE_SIZE passes scaled by the same
+# copy kernel (profiles/k_reverb_render_hbm_counters.md); null once the sources change.
+REVERB_TRAFFIC = {"bytes": 4862583808.0,
+                  "sources_sha256": "a0375314380329927e05226474f3ca1ccb747b4014fc39e079cba59432c91d6c"}
+REVERB_SOURCES = ("paper_1803_00430_amd/csrc/reverb.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
+                  "paper_1803_00430_amd/csrc/rpr_internal.hpp")
+
+
+def trace_sources_sha256(sources=TRACE_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for rel in TRACE_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -410,6 +419,9 @@ def run_reverb(a):
                + 4 * (8 * nc * nc + B * nc * nc + 8 * nc + 8 * B + B + 8) + 64)
     bytes_launch = S * per_src
     achieved = bytes_launch / (k_ms * 1e-3) / 1e9
+    default = (S, n, order) == (4096, 1024, 1)
+    traffic = (REVERB_TRAFFIC["bytes"] if default and REVERB_TRAFFIC["sources_sha256"] ==
+               trace_sources_sha256(REVERB_SOURCES) else None)
     res = {
         "metric": "reverb source-samples/s", "value": value, "unit": "source-samples/s", "n_gpus": 1,
         "steps": a.steps, "warmup": a.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
@@ -420,7 +432,7 @@ def run_reverb(a):
                                f"U(2,40) m); step = one block for every source",
                    "sources": S, "block": n, "bands": B, "sh_order": order, "sample_rate": fs},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_reverb_render",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "k_reverb_render",
                      "bytes_per_source_sample": per_src / n, "kernel_ms": k_ms},
         "realtime_sources": value / fs,
         "setup_ms": setup_ms,

@@ -136,14 +136,19 @@ def test_setup_keep_rule_across_frames():
     assert g[0]["mfp_drawn"] == 10.0 and g[1]["mfp_drawn"] == 17.0 and g[2]["mfp_drawn"] == 10.0
 
 
-@pytest.mark.parametrize("nb,order,fs,seed", CASES)
-def test_render_matches_oracle(nb, order, fs, seed):
-    """Three consecutive calls of ragged lengths against one oracle run."""
+# plus order 1 with 8 bands, and order 1 with comb delays of a few ms (sub-steps shorter
+# than a wave's 64 samples)
+RENDER_CASES = [c + ((2.0, 8.0),) for c in CASES] + [(8, 1, 44100.0, 15, (2.0, 8.0)), (4, 1, 44100.0, 16, (0.5, 1.0))]
+
+
+@pytest.mark.parametrize("nb,order,fs,seed,mfp", RENDER_CASES)
+def test_render_matches_oracle(nb, order, fs, seed, mfp):
+    """Four consecutive calls of ragged lengths against one oracle run."""
     from oracle import reverb as RV
     P = _P()
     desc = P.reverb_desc(nb, order, fs, 343.0, 0.3)
     n_src = 3
-    inp = R.reverb_inputs(seed, n_src, nb, order, mfp_range=(2.0, 8.0))
+    inp = R.reverb_inputs(seed, n_src, nb, order, mfp_range=mfp)
     setup = _gpu_setup(P, inp, desc)
     N = 2600 if nb < 8 else 1400
     x = R.band_audio(seed + 100, n_src, nb, N)
