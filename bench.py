@@ -897,7 +897,15 @@ def main():
         "trace_ray_bounces_per_s": segs / (trace_ms * 1e-3),
         "irs_per_s": S / (ms_step * 1e-3),
         "segments_per_step": segs,
-        "rt60_s_source0": [float(x) for x in pg["rt60"][0][:B]],
+        # the fit needs a decay range: in the open city most listener spheres catch only a few
+        # bins of energy from 32,768 source rays, and those estimates come back invalid (RT60 0)
+        "estimates": {
+            "valid_sources": int(sum(((pg["status"][i][:B] & 7) == 0).all() for i in range(S))),
+            "no_energy_sources": int(sum(((pg["status"][i][:B] & 1) != 0).any() for i in range(S))),
+            "no_range_sources": int(sum(((pg["status"][i][:B] & 4) != 0).any() for i in range(S))),
+            "rt60_s_valid": [[float(x) for x in pg["rt60"][i][:B]] for i in range(S)
+                             if ((pg["status"][i][:B] & 7) == 0).all()],
+        },
     }
     if not a.no_cpu_baseline:
         import oracle
