@@ -12,7 +12,10 @@
  * direction per time sample (Section 4.2, first paragraph).  Reverb
  * parameters -- RT60 per band, direct/early/late energies, reverb gain
  * (Eq. 5-8), predelay, mean free path and the energy-weighted directivity of
- * Eq. 1 -- are then estimated from that histogram (Section 4.2).
+ * Eq. 1 -- are then estimated from that histogram (Section 4.2).  The
+ * spherical-harmonic reverberator that those parameters drive (Section 4.1)
+ * is built and rendered at audio rate by the reverb_setup / reverb_render
+ * group.
  *
  * Conventions for every entry point
  *  - Return value: RPR_OK (0) or a negative RPR_E* code; last_error() then
@@ -577,7 +580,8 @@ int reverb_setup(const RprReverbParams* params, const float* hist, int32_t n_ir,
  *         calls at once
  *   out   device [n_src][(sh_order+1)^2][n] f32, overwritten
  * Consecutive calls continue the same output stream.  A comb whose delay
- * changes between calls keeps the contents of its delay line.  n >= 0. */
+ * changes between calls keeps the contents of its delay line.  n >= 0; n = 0
+ * (or n_src = 0) does nothing. */
 int reverb_render(const RprReverbSetup* setup, int32_t n_src, const float* x, int32_t n, void* state, float* out,
                   const RprReverbDesc* desc, void* hip_stream);
 

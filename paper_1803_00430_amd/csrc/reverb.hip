@@ -559,7 +559,7 @@ extern "C" int reverb_render(const RprReverbSetup* setup, int32_t n_src, const f
     if (n_src < 0 || n < 0 || (n_src > 0 && n > 0 && (!setup || !x || !state || !out)))
         return set_error(RPR_EINVAL, "reverb_render: bad argument");
     if (reinterpret_cast<uintptr_t>(state) & 15u) return set_error(RPR_EINVAL, "reverb_render: state must be 16-byte aligned");
-    if (n_src == 0) return RPR_OK;
+    if (n_src == 0 || n == 0) return RPR_OK;  // nothing to render: the state is left as it is
     ApArgs ap;
     ap.sum = 0;
     for (int j = 0; j < kAllpass; ++j) {

@@ -59,6 +59,9 @@ int main(void) {
   printf("RprPair %zu\nRprBatchParams %zu\nRprBatchInfo %zu\n", sizeof(RprPair), sizeof(RprBatchParams),
          sizeof(RprBatchInfo));
   printf("RprModelInfo %zu\nRprAdamParams %zu\n", sizeof(RprModelInfo), sizeof(RprAdamParams));
+  printf("RprReverbDesc %zu\nRprReverbSetup %zu\n", sizeof(RprReverbDesc), sizeof(RprReverbSetup));
+  P(RprReverbSetup, g_comb); P(RprReverbSetup, dir); P(RprReverbSetup, J); P(RprReverbSetup, D);
+  P(RprReverbDesc, max_comb_delay_s);
   P(RprModelInfo, max_batch); P(RprModelInfo, step); P(RprAdamParams, weight_decay);
   P(RprPair, n_rays); P(RprPair, seed); P(RprBatchInfo, best_ms);
   P(RprIrStats, seg_len_sum); P(RprIrStats, first_arrival_bin); P(RprIrStats, e_class);
@@ -87,6 +90,11 @@ int main(void) {
         assert int(got[f"RprIrStats.{name}"]) == P.IR_STATS_DTYPE.fields[name][1], name
     for name in ("g_reverb", "predelay_s", "dir_loudness"):
         assert int(got[f"RprReverbParams.{name}"]) == P.REVERB_PARAMS_DTYPE.fields[name][1], name
+    assert int(got["RprReverbDesc"]) == C.sizeof(P.ReverbDesc)
+    assert int(got["RprReverbDesc.max_comb_delay_s"]) == P.ReverbDesc.max_comb_delay_s.offset
+    assert int(got["RprReverbSetup"]) == P.REVERB_SETUP_DTYPE.itemsize
+    for name in ("g_comb", "dir", "J", "D"):
+        assert int(got[f"RprReverbSetup.{name}"]) == P.REVERB_SETUP_DTYPE.fields[name][1], name
     assert int(got["RprTraceParams.bin_width_s"]) == P.TraceParams.bin_width_s.offset
     assert int(got["RprTraceParams.seed"]) == P.TraceParams.seed.offset
 
@@ -113,3 +121,38 @@ def test_budget_ray_count_is_host_side_and_matches_oracle():
         args = (int(g.integers(1, 10**12)), int(g.integers(0, 10**10)), int(g.integers(0, 10**7)),
                 int(g.integers(1, 1000)), int(g.integers(1000, 10**9)), int(g.integers(1, 10**6)))
         assert P.budget_ray_count(*args) == ref(*args), args
+
+
+def test_reverb_state_bytes_and_description_checks_are_host_side():
+    """The reverberator's state size (header, comb lines with channels padded
+    to 4 from order 1 on, all-pass lines) and its description checks need no
+    GPU."""
+    import math
+    for nb, order, fs, tmax in ((4, 1, 44100.0, 0.3), (1, 0, 8000.0, 0.005), (8, 3, 192000.0, 2.0),
+                                (3, 2, 48000.0, 0.1)):
+        nc = (order + 1) ** 2
+        pad = 1 if nc == 1 else (nc + 3) // 4 * 4
+        m_cap = math.floor(float(np.float32(tmax)) * float(np.float32(fs)) + 0.5)
+        a_cap = max(math.floor(t * float(np.float32(fs)) + 0.5) for t in (4.9e-3, 4.1e-3, 3.4e-3, 2.9e-3))
+        want = 64 + 4 * nb * (8 * m_cap * pad + 4 * nc * a_cap)
+        got = P.reverb_state_bytes(P.reverb_desc(nb, order, fs, 343.0, tmax))
+        assert got == (want + 255) // 256 * 256, (nb, order, fs, tmax, got, want)
+    for bad in (P.reverb_desc(0, 1), P.reverb_desc(9, 1), P.reverb_desc(4, -1), P.reverb_desc(4, 4),
+                P.reverb_desc(4, 1, 7999.0), P.reverb_desc(4, 1, 200000.0), P.reverb_desc(4, 1, 44100.0, 0.0),
+                P.reverb_desc(4, 1, 44100.0, 343.0, 0.004), P.reverb_desc(4, 1, 44100.0, 343.0, 2.5),
+                P.reverb_desc(4, 1, float("nan"))):
+        with pytest.raises(P.RprError):
+            P.reverb_state_bytes(bad)
+    L = P.lib()
+    d = P.reverb_desc()
+    # bad arguments are refused before any launch; empty calls are no-ops
+    assert L.reverb_setup(None, None, 1, 10, 0.01, None, None, 1, C.byref(d), None, None) == -1
+    assert L.reverb_setup(None, None, 1, 0, 0.01, None, None, 1, C.byref(d), None, None) == -1
+    assert L.reverb_setup(None, None, 0, 10, 0.01, None, None, 1, C.byref(d), None, None) == 0
+    assert L.reverb_render(None, 2, None, 16, None, None, C.byref(d), None) == -1
+    assert L.reverb_render(None, -1, None, 0, None, None, C.byref(d), None) == -1
+    assert L.reverb_render(None, 0, None, 0, None, None, C.byref(d), None) == 0
+    assert L.reverb_render(None, 2, None, 0, None, None, C.byref(d), None) == 0  # no samples: no launch
+    assert L.reverb_state_reset(None, 3, C.byref(d), None) == -1
+    assert L.reverb_state_reset(None, 0, C.byref(d), None) == 0
+    assert L.reverb_state_reset(C.c_void_p(16), 1, None, None) == -1
