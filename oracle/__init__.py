@@ -88,6 +88,8 @@ def lib():
                                    C.POINTER(TraceParams), dp, dp, C.POINTER(IrStats),
                                    C.POINTER(C.c_uint32)]
         L.orc_trace_ir.restype = C.c_int
+        L.orc_trace_ir_paths.argtypes = L.orc_trace_ir.argtypes[:-1] + [dp]
+        L.orc_trace_ir_paths.restype = C.c_int
         L.orc_trace_listener.argtypes = L.orc_trace_ir.argtypes
         L.orc_trace_listener.restype = C.c_int
         L.orc_cone_dir.argtypes = [dp, C.c_double, C.c_double, C.c_double, dp]

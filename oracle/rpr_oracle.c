@@ -42,6 +42,11 @@
  * segment starts 1 mm off the surface along the normal that faces the
  * incoming ray, and the triangle just hit is excluded from the next query. */
 #define ORC_SURFACE_OFFSET 1e-3
+/* early-reflection path record: [valid, order, tri1, tri2, e[8], t, d[16]] */
+#define ORC_REC_W 29
+#define ORC_REC_E 4
+#define ORC_REC_T 12
+#define ORC_REC_D 13
 
 typedef struct {
     int64_t n_rays_total; /* energy normalisation: each ray starts with 1/n_rays_total per band */
@@ -359,7 +364,7 @@ static void score_chord(double ta, double tb, double L, int order, const double 
  * source along the path). */
 static void deposit(const double o[3], const double d[3], double t_hit, double L, int order,
                     const double *E, int nb, const double pl[3], double r, const OrcTraceParams *p,
-                    double *hist, double *hist_late, OrcIrStats *st)
+                    double *hist, double *hist_late, OrcIrStats *st, double *rec)
 {
     double ta, tb;
     if (!ball_chord(o, d, t_hit, pl, r, &ta, &tb)) return;
@@ -368,6 +373,23 @@ static void deposit(const double o[3], const double d[3], double t_hit, double L
     double Y[16];
     orc_sh_eval(p->sh_order, md, Y);
     score_chord(ta, tb, L, order, E, nb, vs, Y, p, hist, hist_late, st);
+    if (rec) {
+        /* early-reflection path record (orders 1-2, Section 5): the intensity the
+         * histogram received within the window, the midpoint of the chord's time
+         * interval clipped to the window, and the SH directivity e_total Y */
+        const double c = p->speed_of_sound, W = (double)p->n_bins * p->bin_width_s;
+        double tau_a = (L + ta) / c, tau_b = fmin((L + tb) / c, W);
+        if (!(tau_b > tau_a)) return;
+        double et = 0.0;
+        for (int b = 0; b < nb; ++b) {
+            rec[ORC_REC_E + b] = E[b] * (tau_b - tau_a) / vs;
+            et += rec[ORC_REC_E + b];
+        }
+        rec[ORC_REC_T] = 0.5 * (tau_a + tau_b);
+        const int nc = (p->sh_order + 1) * (p->sh_order + 1);
+        for (int k = 0; k < nc; ++k) rec[ORC_REC_D + k] = et * Y[k];
+        rec[0] = 1.0;
+    }
 }
 
 /* Trace rays [ray_begin, ray_end) of every source.
@@ -393,11 +415,45 @@ static void deposit(const double o[3], const double d[3], double t_hit, double L
  *     hit triangle ids and bounce kinds, for finding rays whose discrete path
  *     differs between implementations.
  * Returns 0, or -1 on invalid arguments. */
+static int trace_core(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                      const int32_t *tri_mat, const double *absorption, const double *scattering,
+                      int32_t n_materials, int32_t nb, const double *srcs,
+                      int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
+                      double *hist_late, OrcIrStats *stats, uint32_t *ray_hash, double *records);
+
 int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
                  const int32_t *tri_mat, const double *absorption, const double *scattering,
                  int32_t n_materials, int32_t nb, const double *srcs,
                  int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
                  double *hist_late, OrcIrStats *stats, uint32_t *ray_hash)
+{
+    return trace_core(verts, n_verts, tris, n_tris, tri_mat, absorption, scattering, n_materials, nb, srcs, n_src,
+                      listener, p, hist, hist_late, stats, ray_hash, NULL);
+}
+
+/* orc_trace_ir that also writes the early-reflection path records (Section 5:
+ * reflection orders 1 and 2 are the early reflections): records
+ * [n_src][ray_end - ray_begin][2][ORC_REC_W], slot o-1 for the deposit of the
+ * ray's order-o segment: [0] 1 if the segment deposited (else all zero),
+ * [1] order, [2] triangle of the first reflection, [3] of the second (-1 for
+ * order 1), [4..4+nb) band intensity, [12] arrival time, [13..13+nc) SH
+ * directivity. */
+int orc_trace_ir_paths(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                       const int32_t *tri_mat, const double *absorption, const double *scattering,
+                       int32_t n_materials, int32_t nb, const double *srcs,
+                       int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
+                       double *hist_late, OrcIrStats *stats, double *records)
+{
+    if (!records) return -1;
+    return trace_core(verts, n_verts, tris, n_tris, tri_mat, absorption, scattering, n_materials, nb, srcs, n_src,
+                      listener, p, hist, hist_late, stats, NULL, records);
+}
+
+static int trace_core(const double *verts, int64_t n_verts, const int32_t *tris, int64_t n_tris,
+                      const int32_t *tri_mat, const double *absorption, const double *scattering,
+                      int32_t n_materials, int32_t nb, const double *srcs,
+                      int32_t n_src, const double *listener, const OrcTraceParams *p, double *hist,
+                      double *hist_late, OrcIrStats *stats, uint32_t *ray_hash, double *records)
 {
     if (nb < 1 || nb > ORC_MAX_BANDS || p->sh_order < 0 || p->sh_order > 3 || p->n_bins < 1 ||
         !(p->bin_width_s > 0) || !(listener[3] > 0) || p->ray_end < p->ray_begin ||
@@ -410,6 +466,7 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
     const int64_t R = p->ray_end - p->ray_begin;
     memset(hist, 0, sizeof(double) * (size_t)n_src * T * nb * nc);
     if (hist_late) memset(hist_late, 0, sizeof(double) * (size_t)n_src * T * nb);
+    if (records) memset(records, 0, sizeof(double) * (size_t)n_src * R * 2 * ORC_REC_W);
     for (int s = 0; s < n_src; ++s) {
         memset(&stats[s], 0, sizeof(OrcIrStats));
         stats[s].first_arrival_bin = INT32_MAX;
@@ -438,14 +495,22 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
             }
             double L = 0.0;
             int k = 0;
-            int64_t last = -1;
+            int64_t last = -1, tri1 = -1, tri2 = -1;
             uint32_t h = ORC_FNV_BASIS;
             int64_t nseg = 0, nfin = 0, nesc = 0;
             double seglen = 0.0, absorbed[ORC_MAX_BANDS] = {0};
             for (;;) {
                 double t_hit;
                 int64_t tri = closest_hit(verts, tris, n_tris, o, d, last, &t_hit);
-                deposit(o, d, t_hit, L, k, E, nb, listener, listener[3], p, H, HL, st);
+                double *rec = NULL;
+                if (records && (k == 1 || k == 2)) {
+                    rec = records + (((size_t)s * R + ri) * 2 + (k - 1)) * ORC_REC_W;
+                    rec[1] = k;
+                    rec[2] = (double)tri1;
+                    rec[3] = (double)tri2;
+                }
+                deposit(o, d, t_hit, L, k, E, nb, listener, listener[3], p, H, HL, st, rec);
+                if (rec && rec[0] == 0.0) memset(rec, 0, sizeof(double) * ORC_REC_W);
                 ++nseg;
                 if (tri < 0) {
                     ++nesc;
@@ -472,6 +537,8 @@ int orc_trace_ir(const double *verts, int64_t n_verts, const int32_t *tris, int6
                     break;
                 }
                 ++k;
+                if (k == 1) tri1 = tri;
+                if (k == 2) tri2 = tri;
                 double x[3];
                 for (int i = 0; i < 3; ++i) x[i] = o[i] + t_hit * d[i];
                 const int32_t *tv = tris + 3 * tri;
