@@ -494,6 +494,80 @@ int reverb_model_ood_gate(const uint16_t* features, int64_t n, int32_t F, int32_
 int reverb_params_scatter(const RprReverbParams* src, const int32_t* idx, int64_t n, RprReverbParams* dst,
                           void* hip_stream);
 
+/* ------------------------------------------------------- early-reflection paths
+ * The early reflections as individual paths (Section 5): the first two
+ * reflection orders, kept across frames in a diffuse path cache with SH
+ * directivity per path, and prioritised for rendering -- paths below the
+ * threshold of hearing discarded, the N_ER = 100 strongest among all sources
+ * rendered, the others added to the late IR before it is analysed. */
+#define RPR_PATH_RECORD_WORDS 32
+
+/* trace_ir, plus one record per deposit of an order-1 or order-2 segment at
+ * the listener sphere, in records (device [max_records][32] f32, in no
+ * particular order): words 0-1 the 64-bit path key (little-endian words:
+ * source << 48 | order << 46 | tri1 << 23 | tri2, triangles as original
+ * indices, 0x7FFFFF for none), 2-9 the band intensity the histogram received
+ * within the window (zero past n_bands), 10 the midpoint of the chord's
+ * arrival-time interval clipped to the window (s), 11-26 the SH directivity
+ * e_total Y_k(arrival direction) (zero past (sh_order+1)^2).  n_records
+ * (device, 1 u32) is zeroed, then counts every record; those past
+ * max_records are dropped (n_records > max_records tells).  Up to 65535
+ * sources and 2^23 - 2 triangles (else RPR_EUNSUPPORTED); no
+ * RPR_TRACE_COUNT_VISITS. */
+int trace_ir_paths(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                   const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats, float* records,
+                   uint32_t* n_records, int32_t max_records, void* hip_stream);
+
+typedef struct RprPathCache RprPathCache;
+
+/* A path for rendering (device). */
+typedef struct {
+    int32_t source;
+    int32_t order;                /* 1 or 2 */
+    int32_t tri[2];               /* triangles of the reflections (original indices), -1 for none */
+    float e[RPR_MAX_BANDS];       /* band intensity */
+    float t;                      /* intensity-weighted mean arrival time, s */
+    float d[RPR_MAX_COEFFS];      /* SH directivity: sum of e_total Y_k(arrival direction) */
+    float reserved[3];
+} RprEarlyPath;
+
+typedef struct {
+    int32_t max_paths;
+    int32_t n_paths;     /* paths in the cache now */
+    int32_t overflow;    /* 1 once a frame's paths exceeded the capacity (sticky) */
+    int32_t table_size;  /* hash-table slots (a power of two >= 4 max_paths) */
+} RprPathCacheInfo;
+
+/* A cache of up to max_paths (1..2^20) paths on the current device.
+ * Allocates; synchronises the device. */
+int path_cache_create(int32_t max_paths, RprPathCache** out);
+int path_cache_destroy(RprPathCache* cache);
+/* One frame of the cache (the diffuse path cache, Section 5, with the
+ * early-reflection time constant): per path key, P <- (1 - alpha) P +
+ * alpha F, F the sum of the frame's records of that key (0 if none), with P
+ * the band intensities, the intensity-weighted arrival time (as a sum of
+ * e_total t) and the SH directivity; first != 0 takes F alone.  Paths whose
+ * total intensity falls below min_energy leave the cache.  records and
+ * n_records as written by trace_ir_paths (the first min(*n_records,
+ * max_records) are read).  Calls on one cache must be ordered on one
+ * stream. */
+int path_cache_update(RprPathCache* cache, const float* records, const uint32_t* n_records, int32_t max_records,
+                      float alpha, int32_t first, float min_energy, void* hip_stream);
+/* Prioritization of the cache's paths (Section 5): paths with total
+ * intensity below threshold are discarded; the others are ranked by
+ * decreasing total intensity over all sources (ties by key), the first n_er
+ * written to out (device [n_er], strongest first) and their number to n_out
+ * (device, 1 i32); every other path joins the late class of its source:
+ * its band intensity is added to hist_late (device [n_src][n_bins][n_bands]
+ * f32, or NULL) at the bin of its mean arrival time and moved from
+ * stats[source].e_class[1] to e_class[2] (device [n_src], or NULL).  The
+ * cache is not changed.  The ranking compares every pair of paths. */
+int path_cache_select(RprPathCache* cache, float threshold, int32_t n_er, RprEarlyPath* out, int32_t* n_out,
+                      float* hist_late, RprIrStats* stats, int32_t n_src, int32_t n_bins, int32_t n_bands,
+                      float bin_width_s, void* hip_stream);
+/* Counts and flags of the cache (host out); synchronises the device. */
+int path_cache_info(const RprPathCache* cache, RprPathCacheInfo* out);
+
 /* ------------------------------------------------------------ SH reverberator
  * The reverberator that renders the late reverberation from the estimated
  * parameters (Section 4.1 "Sound Rendering"; Section 4.2 for the comb gains

@@ -92,6 +92,10 @@ class ReverbDesc(C.Structure):
                 ("speed_of_sound", C.c_float), ("max_comb_delay_s", C.c_float), ("reserved", C.c_int32)]
 
 
+class PathCacheInfo(C.Structure):
+    _fields_ = [("max_paths", C.c_int32), ("n_paths", C.c_int32), ("overflow", C.c_int32), ("table_size", C.c_int32)]
+
+
 class ModelInfo(C.Structure):
     _fields_ = [("n_params", C.c_int64), ("n_layers", C.c_int32), ("dims", C.c_int32 * 9), ("max_batch", C.c_int32),
                 ("step", C.c_int64)]
@@ -131,6 +135,12 @@ REVERB_SETUP_DTYPE = np.dtype([
 ])
 assert IR_STATS_DTYPE.itemsize == 536 and REVERB_PARAMS_DTYPE.itemsize == 752
 assert REVERB_SETUP_DTYPE.itemsize == 17392
+PATH_RECORD_WORDS = 32
+EARLY_PATH_DTYPE = np.dtype([
+    ("source", "<i4"), ("order", "<i4"), ("tri", "<i4", (2,)), ("e", "<f4", (MAX_BANDS,)), ("t", "<f4"),
+    ("d", "<f4", (MAX_COEFFS,)), ("reserved", "<f4", (3,)),
+])
+assert EARLY_PATH_DTYPE.itemsize == 128
 
 _vp = C.c_void_p
 _i64 = C.c_int64
@@ -151,6 +161,13 @@ SIGNATURES = {
     "budget_ray_count": (_i64, [_i64, _i64, _i64, _i64, _i64, _i64]),
     "ir_cache_update": (C.c_int, [_vp, _vp, _i64, C.c_float, _i32, _vp]),
     "reverb_params_smooth": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, C.c_float, _i32, _vp]),
+    "trace_ir_paths": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp,
+                                 _vp, _vp, _vp, _vp, _i32, _vp]),
+    "path_cache_create": (C.c_int, [_i32, C.POINTER(_vp)]),
+    "path_cache_destroy": (C.c_int, [_vp]),
+    "path_cache_update": (C.c_int, [_vp, _vp, _vp, _i32, C.c_float, _i32, C.c_float, _vp]),
+    "path_cache_select": (C.c_int, [_vp, C.c_float, _i32, _vp, _vp, _vp, _vp, _i32, _i32, _i32, C.c_float, _vp]),
+    "path_cache_info": (C.c_int, [_vp, C.POINTER(PathCacheInfo)]),
     "reverb_state_bytes": (C.c_int, [C.POINTER(ReverbDesc), C.POINTER(_i64)]),
     "reverb_state_reset": (C.c_int, [_vp, _i32, C.POINTER(ReverbDesc), _vp]),
     "reverb_setup": (C.c_int, [_vp, _vp, _i32, _i32, C.c_float, _vp, _vp, _i32, C.POINTER(ReverbDesc), _vp, _vp]),
@@ -608,6 +625,63 @@ def ood_gate(features, c0, c1, zmax, n_bands, params=None, uncertain=None, strea
 
 def params_scatter(src, idx, dst, stream=None):
     _check(lib().reverb_params_scatter(_ptr(src), _ptr(idx), idx.shape[0], _ptr(dst), _stream(stream)))
+
+
+def trace_ir_paths(scene: Scene, sources, listener, radius, params: TraceParams, hist, hist_late, stats, records,
+                   n_records, stream=None):
+    """trace_ir plus the early-reflection path records: records
+    [max_records, 32] float32, n_records [1] int32/uint32 (device)."""
+    srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float32)
+    n = len(srcs)
+    src_arr = (Source * max(n, 1))()
+    for i in range(n):
+        src_arr[i].pos[:] = [float(x) for x in srcs[i]]
+    lp = np.asarray(listener, np.float32)
+    lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
+    assert records.shape[1] == PATH_RECORD_WORDS and records.is_contiguous()
+    _check(lib().trace_ir_paths(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist),
+                                _ptr(hist_late), _ptr(stats), _ptr(records), _ptr(n_records), int(records.shape[0]),
+                                _stream(stream)))
+
+
+class PathCache:
+    """The diffuse path cache and the prioritization of early paths (see
+    include/rpr.h)."""
+
+    def __init__(self, max_paths=65536):
+        h = _vp()
+        _check(lib().path_cache_create(int(max_paths), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            lib().path_cache_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, records, n_records, alpha, first, min_energy=0.0, stream=None):
+        _check(lib().path_cache_update(self._h, _ptr(records), _ptr(n_records), int(records.shape[0]), float(alpha),
+                                       int(bool(first)), float(min_energy), _stream(stream)))
+
+    def select(self, threshold, n_er, out, n_out, hist_late=None, stats=None, n_src=0, n_bins=1, n_bands=4,
+               bin_width_s=1e-3, stream=None):
+        _check(lib().path_cache_select(self._h, float(threshold), int(n_er), _ptr(out), _ptr(n_out), _ptr(hist_late),
+                                       _ptr(stats), int(n_src), int(n_bins), int(n_bands), float(bin_width_s),
+                                       _stream(stream)))
+
+    def info(self):
+        i = PathCacheInfo()
+        _check(lib().path_cache_info(self._h, C.byref(i)))
+        return dict(max_paths=i.max_paths, n_paths=i.n_paths, overflow=i.overflow, table_size=i.table_size)
+
+
+def early_paths_host(out, n) -> np.ndarray:
+    return out.cpu().numpy().view(EARLY_PATH_DTYPE).reshape(-1)[:n]
 
 
 def reverb_desc(n_bands=4, sh_order=1, sample_rate=44100.0, speed_of_sound=343.0, max_comb_delay_s=0.3):

@@ -118,7 +118,15 @@ int workspace_reserve(Workspace& ws, size_t pairs);
 void workspace_free(Workspace& ws);
 // Launch the persistent trace over `n_pairs` descriptors already in device memory.
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
-                 int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream);
+                 int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
+                 float* rec = nullptr, unsigned* rec_count = nullptr, int rec_cap = 0);
+
+// Early-reflection path records (trace_ir_paths, path_cache_*): 32 words each,
+// words 0-1 the key (source << 48 | order << 46 | tri1 << 23 | tri2, 23-bit
+// triangle fields, kRecNoTri for none), 2-9 band intensity, 10 arrival time,
+// 11-26 SH directivity.
+constexpr int kRecWords = 32;
+constexpr uint32_t kRecNoTri = 0x7FFFFFu;
 // Launch the listener-origin trace (next-event queries toward each pair's
 // source ball) over `n_chunks` chunk descriptors already in device memory
 // (the queue counts chunks; each is traced by one wave).

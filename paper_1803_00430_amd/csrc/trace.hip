@@ -25,9 +25,13 @@ namespace {
 
 constexpr int kSetupChunk = 64;
 
-template <int NB, int STACK, bool COUNT>
+// REC: every deposit of an order-1 or order-2 segment also writes one early-reflection
+// path record of kRecWords words (see trace_ir_paths) at rec[slot], slot from *rec_count.
+template <int NB, int STACK, bool COUNT, bool REC>
 __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pairs, int n_pairs,
-                                                 unsigned long long* __restrict__ queue, long long total)
+                                                 unsigned long long* __restrict__ queue, long long total,
+                                                 float* __restrict__ rec, unsigned* __restrict__ rec_count,
+                                                 int rec_cap)
 {
     __shared__ int32_t stk[STACK * kWave];
     const int lane = threadIdx.x;
@@ -39,6 +43,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     long long rl = 0;
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f, L = 0.f;
     int k = 0, last = -1;
+    uint32_t tri1 = kRecNoTri, tri2 = kRecNoTri;  // triangles of the first two reflections (REC)
     uint32_t h = 0;
     // E[b]: band energy; Q[b]: the path's probability under band b's choice
     // rule relative to the mean over the bands (see the bounce below).
@@ -182,6 +187,37 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 dep.fa = min(dep.fa, first_m);
                 if (kk >= 3) dep.fl = min(dep.fl, first_m);
             }
+            if constexpr (REC) {
+                // one record per early deposit: lane w writes word w (a 128-byte store)
+                if ((kk == 1 || kk == 2) && sum_dtau > 0.f) {
+                    unsigned slot = 0;
+                    if (lane == 0) slot = atomicAdd(rec_count, 1u);
+                    slot = __shfl(slot, 0);
+                    if (slot < (unsigned)rec_cap) {
+                        const uint32_t t1 = __shfl(tri1, src), t2 = kk == 2 ? __shfl(tri2, src) : kRecNoTri;
+                        const uint64_t key = ((uint64_t)q << 48) | ((uint64_t)kk << 46) |
+                                             ((uint64_t)(t1 & kRecNoTri) << 23) | (uint64_t)(t2 & kRecNoTri);
+                        float et = 0.f;
+#pragma unroll
+                        for (int b = 0; b < NB; ++b) et += b < nb ? Eb[b] * sum_dtau * inv_vs : 0.f;
+                        float v = 0.f;
+                        if (lane == 0) v = __uint_as_float((uint32_t)key);
+                        else if (lane == 1) v = __uint_as_float((uint32_t)(key >> 32));
+                        else if (lane < 2 + RPR_MAX_BANDS) {
+                            const int b = lane - 2;
+#pragma unroll
+                            for (int bb = 0; bb < NB; ++bb)
+                                if (bb == b && bb < nb) v = Eb[bb] * sum_dtau * inv_vs;
+                        } else if (lane == 10) {
+                            v = 0.5f * (ta + fminf(tb, (float)T * dt));
+                        } else if (lane >= 11 && lane < 11 + RPR_MAX_COEFFS) {
+                            const int ci = lane - 11;
+                            v = ci < nc ? et * sh_coeff(ci, ax, ay, az) : 0.f;
+                        }
+                        if (lane < kRecWords) rec[(size_t)slot * kRecWords + lane] = v;
+                    }
+                }
+            }
         }
 
         // ------------------------------------------------ bounce or terminate
@@ -211,6 +247,10 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                     term = true;
                 } else {
                     ++k;
+                    if constexpr (REC) {
+                        if (k == 1) tri1 = hit_id;
+                        else if (k == 2) tri2 = hit_id;
+                    }
                     ox += t_hit * dx;
                     oy += t_hit * dy;
                     oz += t_hit * dz;
@@ -381,12 +421,12 @@ __global__ void k_debug_sh(const float* __restrict__ dirs, long long n, int orde
 }
 
 // ---------------------------------------------------------------- launch helpers
-using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long);
+using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long, float*, unsigned*, int);
 
-template <int NB, int STACK, bool COUNT>
+template <int NB, int STACK, bool COUNT, bool REC = false>
 TraceFn trace_fn()
 {
-    return k_trace<NB, STACK, COUNT>;
+    return k_trace<NB, STACK, COUNT, REC>;
 }
 
 struct Variant {
@@ -396,6 +436,7 @@ struct Variant {
 
 std::mutex g_mu;
 Variant g_var[2][2][2];  // [bands 4/8][stack 32/64][count visits]
+Variant g_rec[2][2];     // [bands 4/8][stack 32/64], with early-path records
 bool g_var_init = false;
 int g_cus = 0;
 
@@ -418,6 +459,14 @@ int ensure_variants()
                     hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fns[a][b][c], kWave, 0));
                 g_var[a][b][c] = Variant{fns[a][b][c], nb > 0 ? nb : 1};
             }
+    TraceFn rfns[2][2] = {{trace_fn<4, 32, false, true>(), trace_fn<4, 64, false, true>()},
+                          {trace_fn<8, 32, false, true>(), trace_fn<8, 64, false, true>()}};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            int nb = 0;
+            RPR_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)rfns[a][b], kWave, 0));
+            g_rec[a][b] = Variant{rfns[a][b], nb > 0 ? nb : 1};
+        }
     g_var_init = true;
     return RPR_OK;
 }
@@ -476,18 +525,20 @@ int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hip
 }
 
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,
-                 int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream)
+                 int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
+                 float* rec, unsigned* rec_count, int rec_cap)
 {
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
     int rc = ensure_variants();
     if (rc != RPR_OK) return rc;
-    const Variant& v = g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][count_visits ? 1 : 0];
+    const Variant& v = rec ? g_rec[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1]
+                           : g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][count_visits ? 1 : 0];
     const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, v.blocks_per_cu) : v.blocks_per_cu;
     long long grid = grid_override > 0 ? grid_override : (long long)g_cus * per_cu;
     const long long need = (total_rays + kWave - 1) / kWave;
     grid = std::max(1ll, std::min(grid, need));
     hipLaunchKernelGGL(v.fn, dim3((unsigned)grid), dim3(kWave), 0, stream, d_pairs, n_pairs, d_queue,
-                       (long long)total_rays);
+                       (long long)total_rays, rec, rec_count, rec_cap);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }
@@ -496,9 +547,13 @@ int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_que
 
 using namespace rpr;
 
-extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
-                        const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
-                        uint32_t* ray_hash, void* hip_stream)
+namespace {
+
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                 const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats, uint32_t* ray_hash,
+                 void* hip_stream, float* rec, unsigned* rec_count, int rec_cap)
 {
     if (!scene || !p || !lst || (n_src > 0 && (!srcs || !hist || !stats)))
         return set_error(RPR_EINVAL, "trace_ir: null argument");
@@ -523,6 +578,10 @@ extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_
     for (int s = 0; s < n_src; ++s)
         for (int a = 0; a < 3; ++a)
             if (!std::isfinite(srcs[s].pos[a])) return set_error(RPR_EINVAL, "trace_ir: non-finite source %d", s);
+    if (rec_count) {  // after the argument checks, before anything else
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, (hipStream_t)hip_stream, rec_count);
+        RPR_HIP_TRY(hipGetLastError());
+    }
     if (n_src == 0) return RPR_OK;
     const double window = (double)p->n_bins * (double)p->bin_width_s;
     if ((double)p->max_bounces > 1e7) return set_error(RPR_EINVAL, "trace_ir: max_bounces too large");
@@ -589,7 +648,31 @@ extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_
     }
     RPR_HIP_TRY(hipGetLastError());
     return launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need,
-                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0, p->waves_per_cu, 0, st);
+                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec, p->waves_per_cu, 0, st, rec, rec_count,
+                        rec_cap);
+}
+
+}  // namespace
+
+extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                        const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                        uint32_t* ray_hash, void* hip_stream)
+{
+    return trace_common(scene, srcs, n_src, lst, p, hist, hist_late, stats, ray_hash, hip_stream, nullptr, nullptr,
+                        0);
+}
+
+extern "C" int trace_ir_paths(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                              const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                              float* records, uint32_t* n_records, int32_t max_records, void* hip_stream)
+{
+    if (!records || !n_records || max_records < 1) return set_error(RPR_EINVAL, "trace_ir_paths: bad record buffer");
+    if (n_src > 0xFFFF) return set_error(RPR_EUNSUPPORTED, "trace_ir_paths: more than 65535 sources");
+    if (scene && scene->n_tris >= (int64_t)kRecNoTri)
+        return set_error(RPR_EUNSUPPORTED, "trace_ir_paths: more than %u triangles", kRecNoTri - 1);
+    if (p && (p->flags & RPR_TRACE_COUNT_VISITS)) return set_error(RPR_EINVAL, "trace_ir_paths: no visit counting");
+    return trace_common(scene, srcs, n_src, lst, p, hist, hist_late, stats, nullptr, hip_stream, records,
+                        n_records, max_records);
 }
 
 extern "C" int scene_closest_hit(const RprScene* scene, const float* orig, const float* dir, int64_t n,

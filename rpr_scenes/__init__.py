@@ -529,3 +529,23 @@ def reverb_inputs(seed: int, n_ir: int, n_bands: int, sh_order: int, n_bins: int
 def band_audio(seed: int, n_src: int, n_bands: int, n: int, scale: float = 0.1):
     """Seeded band audio [n_src][n_bands][n] f32: white noise, scale rms."""
     return (rng(seed).normal(size=(n_src, n_bands, n)) * scale).astype(np.float32)
+
+
+def path_records(seed: int, n: int, n_src: int, n_keys: int, n_bands: int = 4, n_coeffs: int = 4,
+                 n_tris: int = 5000, t_max: float = 0.2):
+    """Seeded early-path records: n records over about n_keys distinct paths
+    (source, order 1 or 2, one or two triangles), band intensities
+    log-uniform over five decades, arrival times uniform in [0, t_max) and
+    directivities uniform in +-1 of the intensity.  Plain random numbers:
+    returns dict(src, order, tri1, tri2 (-1 for none), e [n][n_bands],
+    t [n], d [n][n_coeffs])."""
+    g = rng(seed)
+    ks = g.integers(0, n_src, size=n_keys)
+    ko = g.integers(1, 3, size=n_keys)
+    k1 = g.integers(0, n_tris, size=n_keys)
+    k2 = np.where(ko == 2, g.integers(0, n_tris, size=n_keys), -1)
+    pick = g.integers(0, n_keys, size=n)
+    e = (10.0 ** g.uniform(-9, -4, size=(n, 1)) * g.uniform(0.2, 1.0, size=(n, n_bands))).astype(np.float32)
+    t = g.uniform(0, t_max, size=n).astype(np.float32)
+    d = (e.sum(axis=1, keepdims=True) * g.uniform(-1, 1, size=(n, n_coeffs))).astype(np.float32)
+    return dict(src=ks[pick], order=ko[pick], tri1=k1[pick], tri2=k2[pick], e=e, t=t, d=d)
