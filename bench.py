@@ -63,13 +63,15 @@ def parse():
     ap.add_argument("--streams", type=int, default=3, help="city: streams the consecutive steps rotate over")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb"), default="city",
+    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb", "paths"),
+                    default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
                          "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
                          "learned estimator vs plain ray trace (builds its dataset and trains first); rooms: "
                          "IRs/s at <= 5%% RT60 error of the plain trace from the sources vs from the listener "
                          "with next-event estimation; reverb: audio-rate rendering of the SH reverberator for "
-                         "many sources")
+                         "many sources; paths: early-reflection paths per frame (records, path cache, "
+                         "prioritization) on the city")
     ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
@@ -468,6 +470,121 @@ def run_reverb(a):
     print(json.dumps(res), flush=True)
 
 
+def run_paths(a):
+    """Early-reflection paths per frame (Section 5: the first two reflection
+    orders with the diffuse path cache, the N_ER = 100 strongest paths over
+    all sources rendered and the rest added to the late IR).  The city's 8
+    sources, static, are traced every 0.1 s frame with fresh rays: each frame
+    runs trace_ir_paths, the path cache update (tau_ER = 1 s), the
+    prioritization and the late-IR estimate, against trace_ir + estimate
+    alone.  The frame-to-frame change of every source's rendered early energy
+    is measured with the cache and without it (alpha = 1)."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+    dev = torch.device("cuda:0")
+    cfg = R.city_config()
+    S, K, T, n, dt = len(cfg["sources"]), cfg["max_bounces"], cfg["n_bins"], cfg["sh_order"], cfg["bin_width_s"]
+    B = cfg["absorption"].shape[1]
+    N = a.rays or cfg["n_rays"]
+    n_er, thr, emin, max_rec = 100, 1e-12, 1e-14, 1 << 18
+    alpha = P.temporal_alpha(0.1, 1.0)
+    scene = P.Scene.from_dict(cfg, device=dev)
+    hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
+    params = P.alloc_params(S, device=dev)
+    rec = torch.zeros((max_rec, P.PATH_RECORD_WORDS), dtype=torch.float32, device=dev)
+    n_rec = torch.zeros(1, dtype=torch.int32, device=dev)
+    out = torch.zeros((n_er, 128), dtype=torch.uint8, device=dev)
+    n_out = torch.zeros(1, dtype=torch.int32, device=dev)
+    out2 = torch.zeros((n_er, 128), dtype=torch.uint8, device=dev)
+    n_out2 = torch.zeros(1, dtype=torch.int32, device=dev)
+    cache, nocache = P.PathCache(65536), P.PathCache(65536)
+    log(f"paths: city, {S} static sources x {N} rays, K={K}, N_ER={n_er}, alpha={alpha:.4f}", a.quiet)
+    frames = a.frames if a.frames != 8 else 30
+    ev_names = ("trace_paths", "cache_update", "select", "estimate")
+    times = {k: [] for k in ev_names}
+    plain_ms, walls, recs, cached, e_on, e_off = [], [], [], [], [], []
+    for f in range(a.warmup + frames):
+        prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt,
+                             seed=cfg["seed"] + 1000 + f)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record()
+        P.trace_ir_paths(scene, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats, rec, n_rec)
+        ev[1].record()
+        cache.update(rec, n_rec, alpha, f == 0, emin)
+        ev[2].record()
+        cache.select(thr, n_er, out, n_out, hist_late=late, stats=stats, n_src=S, n_bins=T, n_bands=B,
+                     bin_width_s=dt)
+        ev[3].record()
+        P.estimate_reverb(hist, late, stats, T, B, n, dt, params, rt60_source=1)
+        ev[4].record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        nocache.update(rec, n_rec, 1.0, True, emin)
+        nocache.select(thr, n_er, out2, n_out2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        P.trace_ir(scene, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
+        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+        torch.cuda.synchronize()
+        pl = time.perf_counter() - t1
+        if f < a.warmup:
+            continue
+        for i, k in enumerate(ev_names):
+            times[k].append(ev[i].elapsed_time(ev[i + 1]))
+        walls.append(wall * 1e3)
+        plain_ms.append(pl * 1e3)
+        recs.append(int(n_rec.item()))
+        cached.append(cache.info()["n_paths"])
+        for dst, o_, no_ in ((e_on, out, n_out), (e_off, out2, n_out2)):
+            pth = P.early_paths_host(o_, int(no_.item()))
+            e = np.zeros(S)
+            for p_ in pth:
+                e[p_["source"]] += float(p_["e"][:B].sum())
+            dst.append(e)
+
+    def jitter(es):
+        es = np.array(es)
+        m = es.mean(axis=0)
+        ok = m > 0
+        return float(np.mean(np.abs(np.diff(es[:, ok], axis=0)) / m[ok]))
+
+    # traversal bytes per segment from one visit-counting trace of the same rays
+    prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"] + 1000,
+                         flags=P.TRACE_COUNT_VISITS)
+    P.trace_ir(scene, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
+    torch.cuda.synchronize()
+    st = P.stats_host(stats)
+    segs = int(st["n_segments"].sum())
+    bps = (128.0 * float(st["n_node_visits"].sum()) + 48.0 * float(st["n_tri_tests"].sum())) / segs
+    tr_ms = float(np.mean(times["trace_paths"]))
+    achieved = segs * bps / (tr_ms * 1e-3) / 1e9
+    ms = float(np.mean(walls))
+    res = {
+        "metric": "early-path frames/s (trace with path records + path cache + prioritization + late-IR estimate)",
+        "value": 1e3 / ms, "unit": "frames/s", "n_gpus": 1, "steps": frames, "warmup": a.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"paths: city of {len(cfg['tris'])} triangles, {S} static sources x {N} rays, "
+                               f"{K} bounces, SH order {n}, {T} x 1 ms bins, 0.1 s frames, tau_ER 1 s, N_ER {n_er} "
+                               f"over all sources", "sources": S, "rays_per_source": N, "n_er": n_er,
+                   "frames": frames},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_trace (path-record variant)",
+                     "bytes_per_ray_bounce": bps, "kernel_ms": tr_ms},
+        "breakdown_ms": {k: float(np.mean(v)) for k, v in times.items()},
+        "plain_trace_estimate_ms": float(np.mean(plain_ms)),
+        "records_per_frame": float(np.mean(recs)), "cached_paths": float(np.mean(cached)),
+        "early_energy_jitter": {"with_cache": jitter(e_on), "without_cache": jitter(e_off)},
+    }
+    cache.close()
+    nocache.close()
+    scene.close()
+    print(json.dumps(res), flush=True)
+
+
 def run_city_frames(a):
     """City frames with moving sources: the 8 sources walk through the streets
     (3 m per 0.1 s frame, turning away from buildings), the listener stays.
@@ -782,6 +899,9 @@ def main():
         return
     if a.workload == "reverb":
         run_reverb(a)
+        return
+    if a.workload == "paths":
+        run_paths(a)
         return
     if a.segment_budget > 0:
         run_city_frames(a)
