@@ -12,6 +12,7 @@ Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -28,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35804128.0,
-                 "sources_sha256": "5aefb568bda5657b8a8c5dedc216b05d96f847bc0f9eb1913196ba9114f32907"}
+TRACE_TRAFFIC = {"bytes": 35832896.0,
+                 "sources_sha256": "26605d8c167ec7ee25c8a9d0952aba7201a6f8f5aee33abfd11c5e7b22e0236e"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 
@@ -37,8 +38,8 @@ TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/cs
 # HBM bytes per k_reverb_render launch on the default reverb workload (4096 sources x
 # 1024 samples, 4 bands, order 1), from FETCH_SIZE / WRITE_SIZE passes scaled by the same
 # copy kernel (profiles/k_reverb_render_hbm_counters.md); null once the sources change.
-REVERB_TRAFFIC = {"bytes": 4862583808.0,
-                  "sources_sha256": "a0375314380329927e05226474f3ca1ccb747b4014fc39e079cba59432c91d6c"}
+REVERB_TRAFFIC = {"bytes": 4863029675.0,
+                  "sources_sha256": "4908398ff6a22659b2d5684116d9d6e7fa7b304c881150bc1ae06c0a8121f8e2"}
 REVERB_SOURCES = ("paper_1803_00430_amd/csrc/reverb.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                   "paper_1803_00430_amd/csrc/rpr_internal.hpp")
 
@@ -885,6 +886,14 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # Python's cyclic garbage collector is kept out of the timed regions (as timeit does): a
+    # collection walks every live object (torch's included) and, when one lands in a step, adds
+    # about 2 ms of host time that belongs to no GPU work.  The objects alive now are frozen out
+    # of later collections and the collector stays off for this short-lived process; the steps
+    # create no reference cycles, so reference counting frees everything they allocate.
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     if a.workload == "batch":
         run_batch(a)
         return

@@ -694,8 +694,34 @@ struct Arena {
     std::mutex mu;
     char* base = nullptr;
     size_t cap = 0, used = 0;
+    BuildFlags* host = nullptr;   // pinned host copy of the build's flags
+    hipEvent_t done = nullptr;    // marks the copy's completion on the build's stream
 };
 Arena g_arena[16];
+
+// Read the build's flags back: the copy lands in pinned host memory (one
+// direct DMA instead of a staged pageable copy) and the host polls the copy's
+// event rather than blocking on the stream, returning as soon as it is done.
+// Called with the arena's lock held, which also guards `host` and `done`.
+hipError_t read_flags(Arena& a, const BuildFlags* dev_flags, hipStream_t st, BuildFlags* out)
+{
+    if (!a.host) {
+        hipError_t e = hipHostMalloc((void**)&a.host, sizeof(BuildFlags), hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+    }
+    if (!a.done) {
+        hipError_t e = hipEventCreateWithFlags(&a.done, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMemcpyAsync(a.host, dev_flags, sizeof(BuildFlags), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(a.done, st);
+    if (e != hipSuccess) return e;
+    while ((e = hipEventQuery(a.done)) == hipErrorNotReady) __builtin_ia32_pause();
+    if (e != hipSuccess) return e;
+    *out = *a.host;
+    return hipSuccess;
+}
 
 template <class T>
 struct DevBuf {
@@ -887,8 +913,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         }
         TRY(hipGetLastError());
         BuildFlags hf;
-        TRY(hipMemcpyAsync(&hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, st));
-        TRY(hipStreamSynchronize(st));
+        TRY(read_flags(arena, flags.p, st, &hf));
         if (hf.flags & kBadIndex) return fail(set_error(RPR_EINVAL, "scene_create: vertex index out of range"));
         if (hf.flags & kBadVertex) return fail(set_error(RPR_EINVAL, "scene_create: non-finite vertex"));
         if (hf.flags & kBadMaterial) return fail(set_error(RPR_EINVAL, "scene_create: material index out of range"));
@@ -909,8 +934,7 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                                   sc->max_depth, sc->stack_need, kMaxStack));
     } else {
         BuildFlags hf;
-        TRY(hipMemcpyAsync(&hf, flags.p, sizeof(hf), hipMemcpyDeviceToHost, st));
-        TRY(hipStreamSynchronize(st));
+        TRY(read_flags(arena, flags.p, st, &hf));
         if (hf.flags & kBadCoeff)
             return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
     }
