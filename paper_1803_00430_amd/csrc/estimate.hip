@@ -64,8 +64,9 @@ __device__ __forceinline__ double I_fit(const EstArgs& a, const float* H, const 
 // A tree-shaped suffix sum would round such plateaus up or down by an ulp
 // and drop some of them from the fit.  Every use of S -- its value at 0 and
 // at the range-test bin, and the decay curve -- is formed from the same Sb.
-// With LDS, Sb is computed once and kept (T <= kLdsBins); otherwise it is
-// recomputed by every pass.
+// With LDS, Sb is computed once and kept (T <= kLdsBins), from the
+// intensities that the kernel's first pass staged there (so the serial scan
+// waits on no memory load); otherwise it is recomputed by every pass.
 constexpr int kLdsBins = 8192;
 
 template <bool LDS>
@@ -80,21 +81,30 @@ struct SbSource {
     __device__ __forceinline__ double scan(F&& visit) const
     {
         double carry = 0.0;
-        const int n_chunks = (m_last + kWave) / kWave;
+        const int last = __builtin_amdgcn_readfirstlane(m_last);  // uniform: keeps the loops scalar
+        const int n_chunks = (last + kWave) / kWave;
         for (int ch = n_chunks - 1; ch >= 0; --ch) {
             const int m = ch * kWave + lane;
-            const double v = m <= m_last ? I_fit(a, H, HL, m, b) : 0.0;
-            const int top = min(kWave - 1, m_last - ch * kWave);
+            // with LDS, the first pass has left I[m] in sS (overwritten here by Sb[m])
+            const double v = m <= last ? (LDS ? sS[m] : I_fit(a, H, HL, m, b)) : 0.0;
+            const int top = min(kWave - 1, last - ch * kWave);
             // each lane's value in turn, read as a scalar (no LDS round trip per step)
             const uint64_t vb = (uint64_t)__double_as_longlong(v);
             const uint32_t lo = (uint32_t)vb, hi = (uint32_t)(vb >> 32);
             double mine = 0.0;
-            for (int j = top; j >= 0; --j) {
+            auto step = [&](int j) {
                 const uint32_t l = __builtin_amdgcn_readlane(lo, j), h = __builtin_amdgcn_readlane(hi, j);
                 carry += __longlong_as_double((long long)(((uint64_t)h << 32) | l));
-                if (lane == j) mine = carry;
+                mine = lane == j ? carry : mine;
+            };
+            if (top == kWave - 1) {
+                // a full chunk: constant lane indices, no loop control between the adds
+#pragma unroll
+                for (int j = kWave - 1; j >= 0; --j) step(j);
+            } else {
+                for (int j = top; j >= 0; --j) step(j);
             }
-            if (m <= m_last) visit(m, mine);
+            if (m <= last) visit(m, mine);
         }
         return carry;
     }
@@ -132,26 +142,37 @@ __device__ Fit fit_once(const SbSource<LDS>& src, double dt, int m_last, int W, 
     const double y_top = 10.0 * log10(S_top / S0);
     const double his[4] = {-5.0, -5.0, -5.0, 0.0};
     const double los[4] = {-35.0, -25.0, -15.0, -10.0};
-    for (int r = 0; r < 4; ++r) {
-        const double hi = his[r], lo = los[r];
-        if (!(y_top <= lo)) continue;
-        double n = 0, s_t = 0, s_y = 0, s_tt = 0, s_ty = 0;
-        src.each([&](int m, double Sb) {
-            const double y = 10.0 * log10((C + Sb) / S0);
-            if (y <= hi && y >= lo) {
-                const double t = (double)m * dt;
-                n += 1.0;
-                s_t += t;
-                s_y += y;
-                s_tt += t * t;
-                s_ty += t * y;
+    // One pass over the decay curve gathers the sums of every range that the
+    // curve reaches (each lane adds its bins in the same order as a pass per
+    // range would, so the sums are the same); the ranges are then tried in turn.
+    bool want[4];
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) any |= (want[r] = y_top <= los[r]);
+    if (!any) return f;
+    double acc[4][5];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int q = 0; q < 5; ++q) acc[r][q] = 0.0;
+    src.each([&](int m, double Sb) {
+        const double y = 10.0 * log10((C + Sb) / S0);
+        const double t = (double)m * dt;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (want[r] && y <= his[r] && y >= los[r]) {
+                acc[r][0] += 1.0;
+                acc[r][1] += t;
+                acc[r][2] += y;
+                acc[r][3] += t * t;
+                acc[r][4] += t * y;
             }
-        });
-        n = wsum(n);
-        s_t = wsum(s_t);
-        s_y = wsum(s_y);
-        s_tt = wsum(s_tt);
-        s_ty = wsum(s_ty);
+        }
+    });
+    for (int r = 0; r < 4; ++r) {
+        if (!want[r]) continue;
+        const double n = wsum(acc[r][0]), s_t = wsum(acc[r][1]), s_y = wsum(acc[r][2]);
+        const double s_tt = wsum(acc[r][3]), s_ty = wsum(acc[r][4]);
         if (n < 3.0) continue;
         const double den = n * s_tt - s_t * s_t;
         if (!(den > 0.0)) continue;
@@ -183,11 +204,12 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
     for (int c = 0; c < RPR_MAX_COEFFS; ++c) dsum[c] = 0.0;
     if (a.vec4) {
         // 16 coefficients per (bin, band): four 16-byte loads per row
-#pragma unroll 2
+#pragma unroll 4
         for (int m = lane; m < T; m += kWave) {
             const float4* row = reinterpret_cast<const float4*>(H + ((size_t)m * nb + b) * 16);
             const float4 q[4] = {row[0], row[1], row[2], row[3]};
             const double v = a.rt60_source == 1 ? (double)HL[(size_t)m * nb + b] : 3.5449077018110318 * (double)q[0].x;
+            if (LDS) sS[m] = v;
             if (v > 0.0) m_last = m;
             tot_all += 3.5449077018110318 * (double)q[0].x;
 #pragma unroll
@@ -201,6 +223,7 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
     } else {
         for (int m = lane; m < T; m += kWave) {
             const double v = I_fit(a, H, HL, m, b);
+            if (LDS) sS[m] = v;
             if (v > 0.0) m_last = m;
             const float* row = H + ((size_t)m * nb + b) * nc;
             tot_all += 3.5449077018110318 * (double)row[0];
@@ -209,6 +232,7 @@ __global__ void __launch_bounds__(kWave) k_estimate(EstArgs a)
                 if (c < nc) dsum[c] += (double)row[c];
         }
     }
+    if (LDS) __syncthreads();
     m_last = wmax(m_last);
     tot_all = wsum(tot_all);
 #pragma unroll
