@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--serial", action="store_true",
                     help="city: run the steps one after another on one stream (default: pipelined streams)")
     ap.add_argument("--streams", type=int, default=3, help="city: streams the consecutive steps rotate over")
+    ap.add_argument("--waves-per-cu", type=int, default=0,
+                    help="city: resident trace waves per CU (0: as many as fit); fewer waves refill their lanes")
     ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb", "paths"),
@@ -929,7 +931,8 @@ def main():
     scat = torch.as_tensor(cfg["scattering"], device=dev)
     hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
     params = P.alloc_params(S, device=dev)
-    prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+    prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"],
+                         waves_per_cu=a.waves_per_cu)
     stream = torch.cuda.current_stream()
 
     # one counting pass (untimed): nodes and triangles fetched per ray-bounce
@@ -950,7 +953,7 @@ def main():
         a.quiet)
 
     # Steps are independent (same scene, same rays), so consecutive steps are
-    # pipelined on two streams with their own outputs: step i+1's BVH build
+    # pipelined on several streams (--streams) with their own outputs: step i+1's BVH build
     # (scene_create waits for its own stream only) and trace start while the
     # longest rays of step i are still bouncing.  Every step does all of its
     # own work; --serial runs them one after another on one stream.
@@ -1014,13 +1017,14 @@ def main():
                                ("" if n_pipe == 1 else f"; consecutive steps pipelined on {n_pipe} streams"),
                    "pipelined_streams": n_pipe,
                    "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
-                   "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt},
+                   "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt,
+                   **({"waves_per_cu": a.waves_per_cu} if a.waves_per_cu else {})},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_trace", "bytes_per_ray_bounce": bytes_per_seg,
                      "node_visits_per_ray_bounce": vn, "tri_tests_per_ray_bounce": vt,
                      "kernel_ms": trace_ms},
-        # per timed step, by events on the step's stream (with two streams the phases overlap the
+        # per timed step, by events on the step's stream (with several streams the phases overlap the
         # neighbouring steps, so they do not add up to ms_per_step)
         "breakdown_ms": {"build": float(np.mean(t_build)), "trace": trace_ms, "estimate": float(np.mean(t_est))},
         "trace_ray_bounces_per_s": segs / (trace_ms * 1e-3),
