@@ -230,6 +230,52 @@ def test_estimate_exact_on_plateaus(torch_cuda):
     assert n_edt > 10  # the EDT range (top at 0 dB) is exercised
 
 
+@pytest.mark.parametrize("sh_order", [0, 3])
+def test_estimate_long_window_without_lds(torch_cuda, sh_order):
+    """Windows longer than the estimator keeps in LDS (9,000 bins): the
+    backward integral is recomputed by every pass instead of kept.  Decays
+    that end at ragged bins (partial 64-bin chunks), decays cut by the window
+    end (tail compensation) and sparse gaps; 16 coefficients take the
+    vectorised row loads, one coefficient the scalar ones.  Same range, status
+    and RT60 as the oracle, and the Eq. 1 directivity."""
+    import torch
+    g = np.random.default_rng(11)
+    n, T, B, dt = 12, 9000, 4, 1e-3
+    nc = (sh_order + 1) ** 2
+    t = np.arange(T) * dt
+    H = np.zeros((n, T, B, nc))
+    for i in range(n):
+        for b in range(B):
+            rt = g.uniform(0.3, 12.0)
+            start = int(g.integers(0, 300))
+            end = T if i % 3 == 0 else int(g.integers(start + 200, T))  # every third IR reaches the window end
+            I = np.exp(-6.0 * np.log(10.0) * t / rt) * (t >= start * dt) * (np.arange(T) < end)
+            I *= g.uniform(0.5, 1.5, T)
+            I[g.uniform(0, 1, T) < 0.2] = 0.0
+            H[i, :, b, 0] = I / math.sqrt(4 * math.pi)
+            if nc > 1:
+                H[i, :, b, 1:] = I[:, None] * g.uniform(-0.2, 0.2, (T, nc - 1))
+    H = H.astype(np.float32)
+    st = np.zeros(n, P.IR_STATS_DTYPE)
+    st["e_emitted"] = 1.0
+    st["first_arrival_bin"] = st["first_late_bin"] = P.INT32_MAX
+    hist = torch.as_tensor(H, device="cuda")
+    stats = torch.as_tensor(st.view(np.uint8).reshape(n, -1), device="cuda")
+    out = P.alloc_params(n)
+    P.estimate_reverb(hist, None, stats, T, B, sh_order, dt, out)
+    pg = P.params_host(out)
+    n_tail = 0
+    for i in range(n):
+        sd = {k: st[i][k] for k in st.dtype.names}
+        po = oracle.estimate_reverb(H[i].astype(np.float64), None, sd, dt)
+        assert np.array_equal(pg["rt60_range"][i][:B], po["rt60_range"]), i
+        assert np.array_equal(pg["status"][i][:B], po["status"]), i
+        assert np.allclose(pg["rt60"][i][:B], po["rt60"], rtol=1e-6), i
+        assert np.allclose(pg["dir_loudness"][i][:B, :nc], po["dir_loudness"], rtol=1e-5, atol=1e-7), i
+        n_tail += int(np.sum((po["status"] & P.ST_TAIL_COMPENSATED) != 0))
+    assert n_tail > 0  # the tail compensation ran on the recomputed integral
+
+
 def test_zero_absorption_invariants(torch_cuda):
     c = R.tiny_config()
     sd = dict(c, absorption=np.zeros((1, 4), np.float32))
