@@ -14,7 +14,7 @@ RT60_TOL = 0.01   # relative
 
 
 def gpu_trace(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray_end=None, max_bounces,
-              sh_order, n_bins, bin_width_s, seed, pair_base=0, want_hash=True):
+              sh_order, n_bins, bin_width_s, seed, pair_base=0, want_hash=True, waves_per_cu=0):
     import torch
     if ray_end is None:
         ray_end = n_rays_total
@@ -24,7 +24,7 @@ def gpu_trace(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ra
                                                   want_hash=want_hash)
     prm = P.trace_params(n_rays_total=n_rays_total, ray_begin=ray_begin, ray_end=ray_end,
                          max_bounces=max_bounces, sh_order=sh_order, n_bins=n_bins, bin_width_s=bin_width_s,
-                         seed=seed, pair_base=pair_base)
+                         seed=seed, pair_base=pair_base, waves_per_cu=waves_per_cu)
     P.trace_ir(scene, srcs, listener, radius, prm, hist, late, stats, rh)
     torch.cuda.synchronize()
     return dict(hist=hist.double().cpu().numpy(), hist_late=late.double().cpu().numpy(),
