@@ -592,6 +592,27 @@ __device__ __forceinline__ void node_box(int n, int32_t link, const float4* __re
     }
 }
 
+// Push count of binary node i in the 4-wide traversal: its slot count
+// (a leaf child fills one slot, an internal child two) minus the one taken.
+__device__ __forceinline__ int push_weight(int2 c) { return (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1; }
+
+// One record per internal node for the upward walk of k_node_depth: parent,
+// grandparent (-1 past the root, which is node 0), and the push counts of the
+// node and of its parent, so that the walk climbs two levels per load.
+__global__ void k_node_up(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
+                          int4* __restrict__ up)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    const int p = i == 0 ? -1 : parent[i];
+    int gp = -1, wp = 0;
+    if (p >= 0) {
+        gp = p == 0 ? -1 : parent[p];
+        wp = push_weight(child[p]);
+    }
+    up[i] = make_int4(p, gp, push_weight(child[i]), wp);
+}
+
 // Depth of every internal node of the binary tree (the root has depth 0), its
 // parity for the 4-wide collapse (written to even and idx4, the scan's input),
 // and the sizes of the 4-wide traversal.  On the path from the root to a
@@ -601,8 +622,10 @@ __device__ __forceinline__ void node_box(int n, int32_t link, const float4* __re
 // apart; once the walk gives i's depth d, the ancestors at even depth are
 // those whose distance has the parity of d.  A node with a leaf child ends
 // that leaf's path: its depth + 1 and its sum give the tree depth and the
-// stack bound (maxima over such nodes, reduced over the wave first).
-__global__ void k_node_depth(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
+// stack bound (maxima over such nodes, reduced over the wave first).  The
+// walk reads one k_node_up record per two levels; it stops past 4 kMaxStack
+// levels (such a tree is rejected by its stack bound).
+__global__ void k_node_depth(int n, const int4* __restrict__ up, const int2* __restrict__ child,
                              uint32_t* __restrict__ even, uint32_t* __restrict__ idx4, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -612,11 +635,13 @@ __global__ void k_node_depth(int n, const int32_t* __restrict__ parent, const in
         int d = 0, sum[2] = {0, 0};
         int node = i;
         for (;;) {
-            const int2 c = child[node];
-            sum[d & 1] += (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1;
-            if (node == 0 || d > 4 * kMaxStack) break;
-            node = parent[node];
-            if (node < 0) break;
+            const int4 u = up[node];
+            sum[d & 1] += u.z;
+            if (u.x < 0 || d > 4 * kMaxStack) break;
+            sum[(d + 1) & 1] += u.w;
+            ++d;
+            if (u.y < 0 || d > 4 * kMaxStack) break;
+            node = u.y;
             ++d;
         }
         is_even = (d % 2 == 0) ? 1u : 0u;
@@ -628,7 +653,8 @@ __global__ void k_node_depth(int n, const int32_t* __restrict__ parent, const in
             need = sum[d & 1];
         }
     }
-    // wave maxima and count, one set of atomics per wave
+    // maxima and count over the wave, then over the block: one set of
+    // atomics per block (every block updates the same three words)
     uint32_t cnt = is_even;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -636,7 +662,21 @@ __global__ void k_node_depth(int n, const int32_t* __restrict__ parent, const in
         need = max(need, __shfl_xor(need, o, kWave));
         cnt += __shfl_xor(cnt, o, kWave);
     }
+    __shared__ int s_depth[kBuildBlock / kWave], s_need[kBuildBlock / kWave];
+    __shared__ uint32_t s_cnt[kBuildBlock / kWave];
+    const int w = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
+        s_depth[w] = depth_leaf;
+        s_need[w] = need;
+        s_cnt[w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 1; j < kBuildBlock / kWave; ++j) {
+            depth_leaf = max(depth_leaf, s_depth[j]);
+            need = max(need, s_need[j]);
+            cnt += s_cnt[j];
+        }
         if (depth_leaf > 0) atomicMax(&f->max_depth, depth_leaf);
         if (need > 0) atomicMax(&f->max_stack, need);
         if (cnt) atomicAdd(&f->n_nodes4, cnt);
@@ -905,8 +945,12 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
             if (pl.top > 8) hipLaunchKernelGGL(k_pyr_high, dim3(1), dim3(1024), 0, st, pl, pyr.p);
             hipLaunchKernelGGL(k_refit, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, range.p, box.p,
                                pyr.p, pl, ibox.p);
-            hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
-                               parent.p, child.p, even.p, idx4.p, flags.p);
+            // the centroids are dead after the Morton codes: their n float4 hold the n - 1 walk records
+            int4* up = reinterpret_cast<int4*>(cent.p);
+            hipLaunchKernelGGL(k_node_up, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,
+                               child.p, up);
+            hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, up,
+                               child.p, even.p, idx4.p, flags.p);
             scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
             hipLaunchKernelGGL(k_collapse4, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
                                box.p, ibox.p, even.p, idx4.p, sc->nodes);
