@@ -20,6 +20,7 @@ namespace rpr {
 namespace {
 
 constexpr int kBuildBlock = 256;
+constexpr int kPrepBlocks = 128;  // k_prep's grid cap (it strides over the triangles)
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kBuildBlock * kSortItems;
 
@@ -105,18 +106,18 @@ __global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_
 {
     __shared__ int32_t s_lo[3][kBuildBlock / kWave], s_hi[3][kBuildBlock / kWave];
     __shared__ int32_t s_blo[3][kBuildBlock / kWave], s_bhi[3][kBuildBlock / kWave];
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nt) {
-        // clear the counters of later kernels: seen [nt], refs [2 nt - 1]
-        seen[t] = 0u;
-        refs[t] = 0u;
-        if (t > 0) refs[nt - 1 + t] = 0u;
-    }
     float c[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float cm[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    if (t < nt) {
+    // grid-stride over the triangles: fewer blocks, so fewer of the atomics
+    // below, which all land on the same flag words
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
+        // clear the counters of later kernels: seen [nt], refs [2 nt - 1]
+        seen[t] = 0u;
+        refs[t] = 0u;
+        if (t > 0) refs[nt - 1 + t] = 0u;
         uint32_t flags = 0;
         int32_t idx[3];
         for (int k = 0; k < 3; ++k) {
@@ -141,12 +142,17 @@ __global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_
         const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
         if (nx == 0.0f && ny == 0.0f && nz == 0.0f) atomicAdd(&f->n_degenerate, 1u);
         if (flags) atomicOr(&f->flags, flags);
+        float cen[3];
         for (int a = 0; a < 3; ++a) {
-            lo[a] = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
-            hi[a] = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
-            c[a] = cm[a] = 0.5f * (lo[a] + hi[a]);
+            const float l = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
+            const float h = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
+            cen[a] = 0.5f * (l + h);
+            lo[a] = fminf(lo[a], l);
+            hi[a] = fmaxf(hi[a], h);
+            c[a] = fminf(c[a], cen[a]);
+            cm[a] = fmaxf(cm[a], cen[a]);
         }
-        cent[t] = make_float4(c[0], c[1], c[2], 0.0f);
+        cent[t] = make_float4(cen[0], cen[1], cen[2], 0.0f);
     }
     // wave then block reduction of the bounds
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -904,7 +910,8 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     TRY(hipGetLastError());
 
     if (n > 0) {
-        hipLaunchKernelGGL(k_prep, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts, n_verts, tris,
+        hipLaunchKernelGGL(k_prep, dim3(std::min(blocks(n, kBuildBlock), (unsigned)kPrepBlocks)), dim3(kBuildBlock), 0, st,
+                           verts, n_verts, tris,
                            n_tris, tri_material, n_materials, cent.p, seen.p, refs.p, flags.p);
         hipLaunchKernelGGL(k_morton, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent.p, n_tris,
                            flags.p, k0.p, v0.p);
