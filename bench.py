@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35832896.0,
-                 "sources_sha256": "26605d8c167ec7ee25c8a9d0952aba7201a6f8f5aee33abfd11c5e7b22e0236e"}
+TRACE_TRAFFIC = {"bytes": 35531872.0,
+                 "sources_sha256": "99b481f4f7c0bbdda120f01c637e34c27a60ed65c564afcdc4610c91b091216f"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 

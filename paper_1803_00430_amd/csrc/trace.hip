@@ -2,7 +2,8 @@
 //
 // One wave per workgroup.  Each lane owns one ray at a time; lanes whose ray
 // has terminated are refilled from a global queue of (pair, ray) slots with
-// one atomic per wave, so waves stay full while ray lifetimes differ (an
+// one atomic per wave (each wave's first 64 slots are fixed by its index), so
+// waves stay full while ray lifetimes differ (an
 // escape after one segment vs. a hundred bounces).  Closest hits use the
 // scene's 4-wide BVH with a per-lane node stack in LDS.  Listener-sphere
 // deposits are gathered over the wave and issued as coalesced atomics: for
@@ -55,6 +56,11 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     lane_acc_zero(acc);
     DepAcc dep{-1, 0.0, INT_MAX, INT_MAX};
     bool exhausted = false;
+    // Each wave's first 64 slots are fixed (slot blockIdx.x * 64 + lane); the
+    // queue counter hands out the slots after the first gridDim.x * 64, so the
+    // launch does not start with every wave's atomic on the same counter.
+    const unsigned long long n_static = (unsigned long long)gridDim.x * kWave;
+    bool first = true;
 
     for (;;) {
         // ------------------------------------------------ refill dead lanes
@@ -64,9 +70,16 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 const int nd = __popcll(dead);
                 const int leader = __ffsll((unsigned long long)dead) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(queue, (unsigned long long)nd);
-                base = __shfl(base, leader);
-                if (base + (unsigned long long)nd >= (unsigned long long)total) exhausted = true;
+                if (first) {
+                    // every lane is dead before the first fill: nd = 64
+                    base = (unsigned long long)blockIdx.x * kWave;
+                    first = false;
+                    if (n_static >= (unsigned long long)total) exhausted = true;
+                } else {
+                    if (lane == leader) base = atomicAdd(queue, (unsigned long long)nd);
+                    base = n_static + __shfl(base, leader);
+                    if (base + (unsigned long long)nd >= (unsigned long long)total) exhausted = true;
+                }
                 int np = -1;
                 long long r = -1;
                 if (!alive) {
