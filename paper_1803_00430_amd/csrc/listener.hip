@@ -279,6 +279,10 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
 #pragma unroll
     for (int b = 0; b < NB; ++b) a_esc_e[b] = a_alive[b] = a_cap[b] = a_absb[b] = 0.f;
     bool exhausted = false;
+    // each wave's first 64 slots are fixed by its index; the counter hands
+    // out the slots after gridDim.x * 64 (no burst of atomics at the start)
+    const unsigned long long n_static = (unsigned long long)gridDim.x * kWave;
+    bool first = true;
 
     for (;;) {
         // ------------------------------------------------ refill dead lanes
@@ -288,9 +292,16 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                 const int nd = __popcll(dead);
                 const int leader = __ffsll((unsigned long long)dead) - 1;
                 unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(queue, (unsigned long long)nd);
-                base = __shfl(base, leader);
-                if (base + (unsigned long long)nd >= (unsigned long long)total) exhausted = true;
+                if (first) {
+                    // every lane is dead before the first fill: nd = 64
+                    base = (unsigned long long)blockIdx.x * kWave;
+                    first = false;
+                    if (n_static >= (unsigned long long)total) exhausted = true;
+                } else {
+                    if (lane == leader) base = atomicAdd(queue, (unsigned long long)nd);
+                    base = n_static + __shfl(base, leader);
+                    if (base + (unsigned long long)nd >= (unsigned long long)total) exhausted = true;
+                }
                 if (!alive) {
                     const long long r = (long long)(base + (unsigned long long)__popcll(dead & lt));
                     if (r < total) {
@@ -691,9 +702,16 @@ __global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict
             long long rr = 0;
             while (dead) {
                 if (ch_off >= ch_len) {
+                    // the first chunk of each wave is fixed by its index (the
+                    // grid has at most one wave per chunk); the counter hands
+                    // out the chunks after gridDim.x
                     unsigned long long c = 0;
-                    if (lane == 0) c = atomicAdd(queue, 1ull);
-                    c = __shfl(c, 0);
+                    if (ch < 0) {
+                        c = blockIdx.x;
+                    } else {
+                        if (lane == 0) c = atomicAdd(queue, 1ull);
+                        c = (unsigned long long)gridDim.x + __shfl(c, 0);
+                    }
                     if (c >= (unsigned long long)n_table) {
                         exhausted = true;
                         break;
