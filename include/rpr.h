@@ -173,6 +173,20 @@ int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const 
              const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
              uint32_t* ray_hash, void* hip_stream);
 
+/* trace_ir for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as trace_ir, but the queue counter and the
+ * pair table live in a static device array of the library (256 + 1,024 x 176
+ * bytes, one per GPU, held until the process ends) instead of the scene's
+ * workspace, so the call allocates nothing on the host or the device.
+ * Limit: n_src <= 1024 (RPR_EINVAL above).  Every call on one GPU shares that
+ * array and leaves its contents behind (each call rewrites what it reads):
+ * calls that overlap on one GPU -- on different streams or from different
+ * threads -- race and must be ordered by the caller. */
+int trace_ir_noalloc(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                     const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                     uint32_t* ray_hash, void* hip_stream);
+
 /* Path tracing from the listener with next-event estimation toward every
  * source (Section 5: backward path tracing from the listener, augmented
  * with diffuse rain; one set of rays serves all sources).  Each source is a

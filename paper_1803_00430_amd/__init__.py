@@ -153,6 +153,8 @@ SIGNATURES = {
     "scene_info": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
     "trace_ir": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp, _vp,
                            _vp, _vp, _vp]),
+    "trace_ir_noalloc": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp,
+                                   _vp, _vp, _vp, _vp]),
     "trace_listener": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp,
                                  _vp, _vp, _vp, _vp]),
     "estimate_reverb": (C.c_int, [_vp, _vp, _vp, _i32, _i32, _i32, _i32, C.c_float, C.POINTER(EstimateParams),
@@ -336,6 +338,21 @@ def trace_ir(scene: Scene, sources, listener, radius, params: TraceParams, hist,
     lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
     _check(lib().trace_ir(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist), _ptr(hist_late),
                           _ptr(stats), _ptr(ray_hash), _stream(stream)))
+
+
+def trace_ir_noalloc(scene: Scene, sources, listener, radius, params: TraceParams, hist, hist_late, stats,
+                     ray_hash=None, stream=None):
+    """Enqueue trace_ir_noalloc (trace_ir with the library's static scratch,
+    no allocation; at most 1024 sources) on `stream`."""
+    srcs = np.ascontiguousarray(np.atleast_2d(sources), np.float32)
+    n = len(srcs)
+    src_arr = (Source * max(n, 1))()
+    for i in range(n):
+        src_arr[i].pos[:] = [float(x) for x in srcs[i]]
+    lp = np.asarray(listener, np.float32)
+    lst = Listener((C.c_float * 3)(*[float(x) for x in lp]), float(radius))
+    _check(lib().trace_ir_noalloc(scene.handle, src_arr, n, C.byref(lst), C.byref(params), _ptr(hist),
+                                  _ptr(hist_late), _ptr(stats), _ptr(ray_hash), _stream(stream)))
 
 
 def trace_listener(scene: Scene, sources, listener, radius, params: TraceParams, hist, hist_late, stats,

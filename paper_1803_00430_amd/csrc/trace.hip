@@ -564,9 +564,41 @@ namespace {
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
+// Scratch of trace_ir_noalloc: the queue counter (first 256 bytes) and the
+// pair table, in place of the scene's workspace.  Each GPU the library runs
+// on holds its own copy until the process ends.
+constexpr int kNoAllocMaxSources = 1024;
+constexpr size_t kNoAllocScratchBytes = 256 + (size_t)kNoAllocMaxSources * sizeof(PairDesc);
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device.  The array's name is a
+// host-side stand-in in host code, so kernels get this address instead; it is
+// looked up once per device, with that device current.
+int noalloc_scratch(void** out)
+{
+    int dev = 0;
+    RPR_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(RPR_EUNSUPPORTED, "trace_ir_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        RPR_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return set_error(RPR_EDEVICE, "trace_ir_noalloc: no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RPR_OK;
+}
+
+// ws: device workspace of 256 bytes (queue counter) + n_src pair descriptors,
+// or null for the scene's own (grown on demand).
 int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
                  const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats, uint32_t* ray_hash,
-                 void* hip_stream, float* rec, unsigned* rec_count, int rec_cap)
+                 void* hip_stream, float* rec, unsigned* rec_count, int rec_cap, void* ws = nullptr)
 {
     if (!scene || !p || !lst || (n_src > 0 && (!srcs || !hist || !stats)))
         return set_error(RPR_EINVAL, "trace_ir: null argument");
@@ -601,11 +633,14 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     (void)window;
 
     hipStream_t st = (hipStream_t)hip_stream;
-    RprScene* sc = const_cast<RprScene*>(scene);
-    int rc = workspace_reserve(sc->ws, (size_t)n_src);
-    if (rc != RPR_OK) return rc;
-    unsigned long long* d_queue = (unsigned long long*)sc->ws.dev;
-    PairDesc* d_pairs = (PairDesc*)((char*)sc->ws.dev + 256);
+    if (!ws) {
+        RprScene* sc = const_cast<RprScene*>(scene);
+        const int rc = workspace_reserve(sc->ws, (size_t)n_src);
+        if (rc != RPR_OK) return rc;
+        ws = sc->ws.dev;
+    }
+    unsigned long long* d_queue = (unsigned long long*)ws;
+    PairDesc* d_pairs = (PairDesc*)((char*)ws + 256);
 
     const int nb = scene->n_bands;
     const int nc = (p->sh_order + 1) * (p->sh_order + 1);
@@ -673,6 +708,22 @@ extern "C" int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_
 {
     return trace_common(scene, srcs, n_src, lst, p, hist, hist_late, stats, ray_hash, hip_stream, nullptr, nullptr,
                         0);
+}
+
+extern "C" int trace_ir_noalloc(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
+                                const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
+                                uint32_t* ray_hash, void* hip_stream)
+{
+    if (n_src > kNoAllocMaxSources)
+        return set_error(RPR_EINVAL, "trace_ir_noalloc: n_src=%d exceeds the static scratch's %d sources", n_src,
+                         kNoAllocMaxSources);
+    void* ws = nullptr;
+    if (n_src > 0) {
+        const int rc = noalloc_scratch(&ws);
+        if (rc != RPR_OK) return rc;
+    }
+    return trace_common(scene, srcs, n_src, lst, p, hist, hist_late, stats, ray_hash, hip_stream, nullptr, nullptr, 0,
+                        ws);
 }
 
 extern "C" int trace_ir_paths(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
