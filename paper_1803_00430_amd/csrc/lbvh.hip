@@ -444,13 +444,29 @@ __global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const
     }
     const int32_t m = tri_mat ? tri_mat[t] : 0;
     recs[3 * (int64_t)i + 0] = make_float4(v[0][0], v[0][1], v[0][2], __uint_as_float(t));
-    recs[3 * (int64_t)i + 1] =
-        make_float4(v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2], __int_as_float(m));
-    recs[3 * (int64_t)i + 2] = make_float4(v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2], 0.0f);
+    recs[3 * (int64_t)i + 1] = make_float4(v[1][0], v[1][1], v[1][2], __int_as_float(m));
+    recs[3 * (int64_t)i + 2] = make_float4(v[2][0], v[2][1], v[2][2], 0.0f);
+    // The traversal tests boxes in FP32 against the ray rounded to FP32, which
+    // moves it by a few units in the last place of the coordinates and of the
+    // distance travelled (about 2^-24 x (|origin| + t) each).  Padding each leaf
+    // box by 2^-22 x (largest |coordinate| + diagonal) of the scene keeps every
+    // box that the exact ray enters within reach of the rounded one, for
+    // origins inside the scene's bounds (grazing rays excepted), so the FP64
+    // triangle tests see every candidate.  The pad stays well below the 1 mm
+    // by which a reflected segment starts off its surface (0.3 mm for a
+    // 500 m scene), so a new origin is not inside the boxes of the coplanar
+    // neighbours of the triangle it leaves.
+    float m_abs = 0.0f, diag2 = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+        const float bl = unordered(f->blo[a]), bh = unordered(f->bhi[a]);
+        m_abs = fmaxf(m_abs, fmaxf(fabsf(bl), fabsf(bh)));
+        diag2 += (bh - bl) * (bh - bl);
+    }
+    const float pad = 0x1p-22f * (m_abs + sqrtf(diag2));
     float lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-        lo[a] = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
-        hi[a] = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
+        lo[a] = fminf(fminf(v[0][a], v[1][a]), v[2][a]) - pad;
+        hi[a] = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]) + pad;
     }
     const int64_t b = (int64_t)(n - 1) + i;
     box[2 * b + 0] = make_float4(lo[0], lo[1], lo[2], 0.0f);

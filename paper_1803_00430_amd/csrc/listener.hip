@@ -421,7 +421,11 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
         float t_hit = __builtin_inff();
         uint32_t hit_id = 0xFFFFFFFFu;
         int hit = -1;
-        if (alive) hit = closest_hit<STACK>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, t_hit, hit_id);
+        if (alive) {
+            double th;
+            hit = closest_hit<STACK>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, th, hit_id);
+            t_hit = (float)th;
+        }
 
         // ------------------------------------------------ mirror share at the source balls
         if (__ballot(alive && spec)) {
@@ -467,7 +471,9 @@ __global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned l
                     oy += t_hit * dy;
                     oz += t_hit * dz;
                     const float4* tr = sc.tris + 3 * (int64_t)hit;
-                    const float4 e1 = tr[1], e2 = tr[2];
+                    const float4 v0 = tr[0], v1 = tr[1], v2 = tr[2];
+                    const float4 e1 = make_float4(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z, v1.w);
+                    const float4 e2 = make_float4(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z, 0.0f);
                     float mx = e1.y * e2.z - e1.z * e2.y, my = e1.z * e2.x - e1.x * e2.z,
                           mz = e1.x * e2.y - e1.y * e2.x;
                     const float inl = 1.0f / sqrtf(mx * mx + my * my + mz * mz);
@@ -847,7 +853,11 @@ __global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict
         float t_hit = __builtin_inff();
         uint32_t hit_id = 0xFFFFFFFFu;
         int hit = -1;
-        if (alive) hit = closest_hit<STACK>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, t_hit, hit_id);
+        if (alive) {
+            double th;
+            hit = closest_hit<STACK>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, th, hit_id);
+            t_hit = (float)th;
+        }
 
         // ------------------------------------------------ mirror share at the source ball
         if (__ballot(alive && spec)) {
@@ -869,7 +879,6 @@ __global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict
         if (alive) {
             const PairDesc& P = pairs[p];
             if (acc.p < 0) acc.p = p;
-            ++acc.seg;
             bool term = false;
             if (hit < 0) {
                 ++acc.esc;
@@ -896,7 +905,9 @@ __global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict
                     oy += t_hit * dy;
                     oz += t_hit * dz;
                     const float4* tr = sc.tris + 3 * (int64_t)hit;
-                    const float4 e1 = tr[1], e2 = tr[2];
+                    const float4 v0 = tr[0], v1 = tr[1], v2 = tr[2];
+                    const float4 e1 = make_float4(v1.x - v0.x, v1.y - v0.y, v1.z - v0.z, v1.w);
+                    const float4 e2 = make_float4(v2.x - v0.x, v2.y - v0.y, v2.z - v0.z, 0.0f);
                     float mx = e1.y * e2.z - e1.z * e2.y, my = e1.z * e2.x - e1.x * e2.z,
                           mz = e1.x * e2.y - e1.y * e2.x;
                     const float inl = 1.0f / sqrtf(mx * mx + my * my + mz * mz);

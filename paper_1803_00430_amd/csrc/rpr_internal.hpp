@@ -34,6 +34,7 @@ constexpr int kMatStride = 32;      // floats per material record
 // the shared edge of two coplanar triangles can meet the neighbour at t ~ 0 and
 // alternate between the two.  1 mm is >= 30 ulps for coordinates up to 500 m.
 constexpr float kSurfaceOffset = 1e-3f;
+constexpr double kSurfaceOffset64 = 1e-3;
 // Material record: [1 + b] alpha_b, [9 + b] scattering s_b, [17 + b] 1 - alpha_b.
 constexpr int kMatAlpha = 1, kMatS = 9, kMatKeep = 17;
 
@@ -47,8 +48,9 @@ __host__ __device__ inline int32_t leaf_link(int32_t i) { return ~i; }
 //     slots, slot j = float4 (lo.x, lo.y, lo.z, link bits), float4 (hi.x,
 //     hi.y, hi.z, 0).  An empty slot has the box lo = hi = +inf, whose entry
 //     distance is never finite, and a leaf link.
-//   tris: 3 float4 per triangle in Morton (leaf) order:
-//     (v0.xyz, original index bits), (e1.xyz, material bits), (e2.xyz, 0)
+//   tris: 3 float4 per triangle in Morton (leaf) order, the input vertices
+//     unchanged: (v0.xyz, original index bits), (v1.xyz, material bits),
+//     (v2.xyz, 0)
 struct SceneView {
     const float4* nodes;
     const float4* tris;

@@ -41,17 +41,24 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     bool alive = false;
     int p = -1;
     uint32_t ray = 0;
-    long long rl = 0;
-    float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = 1.f, L = 0.f;
+    // The ray's origin, direction and path length are FP64: every hit point,
+    // reflection and listener chord is formed from them in FP64, so the path
+    // does not drift from the one the definition traces; only the box tests
+    // of the traversal round the ray to FP32 (see closest_hit).
+    double ox = 0.0, oy = 0.0, oz = 0.0, dx = 0.0, dy = 0.0, dz = 1.0, L = 0.0;
     int k = 0, last = -1;
     uint32_t tri1 = kRecNoTri, tri2 = kRecNoTri;  // triangles of the first two reflections (REC)
     uint32_t h = 0;
-    // E[b]: band energy; Q[b]: the path's probability under band b's choice
-    // rule relative to the mean over the bands (see the bounce below).
-    float E[NB], Q[NB];
+    // E(b): band energy; Q(b): the path's probability under band b's choice
+    // rule relative to the mean over the bands (see the bounce below).  With
+    // up to four bands and the 32-entry stack they live in LDS, where the
+    // 2 KB per wave still fit 16 waves per CU beside the stacks (in registers
+    // they would cost a wave per SIMD); otherwise in registers.
+    using Bands = BandState<NB, (NB <= 4 && STACK <= 32)>;
+    __shared__ float eq_lds[Bands::kLdsWords];
+    Bands eq(eq_lds, lane);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) E[b] = Q[b] = 0.f;
-    SceneView sc{};
+    for (int b = 0; b < NB; ++b) eq.E(b) = eq.Q(b) = 0.f;
     LaneAcc<NB> acc;
     lane_acc_zero(acc);
     DepAcc dep{-1, 0.0, INT_MAX, INT_MAX};
@@ -90,22 +97,20 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 if (np >= 0) {
                     const PairDesc& P = pairs[np];
                     p = np;
-                    rl = r - P.queue_begin;
-                    ray = (uint32_t)(P.ray_begin + rl);
+                    ray = (uint32_t)(P.ray_begin + (r - P.queue_begin));
                     const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, 0u, 0u), P.key0, P.key1);
-                    sphere_dir(u01(x.x), u01(x.y), dx, dy, dz);
+                    sphere_dir_f64((double)u01(x.x), (double)u01(x.y), dx, dy, dz);
                     ox = P.src[0];
                     oy = P.src[1];
                     oz = P.src[2];
-                    L = 0.f;
+                    L = 0.0;
                     k = 0;
                     last = -1;
                     h = 2166136261u;
-                    sc = P.scene;
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        E[b] = P.e0;
-                        Q[b] = b < sc.n_bands ? 1.f : 0.f;
+                        eq.E(b) = P.e0;
+                        eq.Q(b) = b < P.scene.n_bands ? 1.f : 0.f;
                     }
                     alive = true;
                 }
@@ -114,30 +119,33 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
         if (__ballot(alive) == 0) break;
 
         // ------------------------------------------------ closest hit
-        float t_hit = __builtin_inff();
+        double t_hit = __builtin_inf();
         uint32_t hit_id = 0xFFFFFFFFu;
         int hit = -1;
-        if (alive)
+        if (alive) {
+            const SceneView sc = pairs[p].scene;
             hit = closest_hit<STACK, COUNT>(sc, ox, oy, oz, dx, dy, dz, last, stk, lane, t_hit, hit_id, &acc.nodes,
                                             &acc.tris);
+        }
 
         // ------------------------------------------------ listener sphere
         bool has_dep = false;
-        float tau_a = 0.f, tau_b = 0.f;
+        double tau_a = 0.0, tau_b = 0.0;
         if (alive) {
             const PairDesc& P = pairs[p];
-            const float cx = ox - P.lst[0], cy = oy - P.lst[1], cz = oz - P.lst[2];
-            const float bq = dx * cx + dy * cy + dz * cz;
-            const float wx = cx - bq * dx, wy = cy - bq * dy, wz = cz - bq * dz;
-            const float disc = P.radius * P.radius - (wx * wx + wy * wy + wz * wz);
-            if (disc > 0.f) {
-                const float sq = sqrtf(disc);
-                const float ta = fmaxf(-bq - sq, 0.f);
-                const float tb = fminf(-bq + sq, t_hit);
+            const double r = P.radius, c = P.c;
+            const double cx = ox - (double)P.lst[0], cy = oy - (double)P.lst[1], cz = oz - (double)P.lst[2];
+            const double bq = dx * cx + dy * cy + dz * cz;
+            const double wx = cx - bq * dx, wy = cy - bq * dy, wz = cz - bq * dz;
+            const double disc = r * r - (wx * wx + wy * wy + wz * wz);
+            if (disc > 0.0) {
+                const double sq = sqrt(disc);
+                const double ta = fmax(-bq - sq, 0.0);
+                const double tb = fmin(-bq + sq, t_hit);
                 if (tb > ta) {
-                    tau_a = (L + ta) / P.c;
-                    tau_b = (L + tb) / P.c;
-                    has_dep = tau_a < (float)P.n_bins * P.dt;
+                    tau_a = (L + ta) / c;
+                    tau_b = (L + tb) / c;
+                    has_dep = tau_a < (double)P.n_bins * (double)P.dt;
                 }
             }
         }
@@ -147,22 +155,24 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
         while (dm) {
             const int src = __ffsll((unsigned long long)dm) - 1;
             dm &= dm - 1;
-            const int q = __builtin_amdgcn_readfirstlane(__shfl(p, src));
-            const float ta = __shfl(tau_a, src), tb = __shfl(tau_b, src);
-            const float ax = -__shfl(dx, src), ay = -__shfl(dy, src), az = -__shfl(dz, src);
-            const int kk = __shfl(k, src);
+            // the depositing lane's values, as wave-uniform scalars
+            const int q = rdlane(p, src);
+            const double ta = rdlane(tau_a, src), tb = rdlane(tau_b, src);
+            const float ax = -rdlane((float)dx, src), ay = -rdlane((float)dy, src), az = -rdlane((float)dz, src);
+            const int kk = rdlane(k, src);
             float Eb[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) Eb[b] = __shfl(E[b], src);
+            for (int b = 0; b < NB; ++b) Eb[b] = rdlane(eq.E(b), src);
             const PairDesc& P = pairs[q];
             const int T = P.n_bins, nc = P.n_coeffs, nb = P.scene.n_bands;
-            const float dt = P.dt, inv_vs = P.inv_vs;
+            const double dt = P.dt;
+            const float inv_vs = P.inv_vs;
             float* __restrict__ hist = P.hist;
             float* __restrict__ hlate = P.hist_late;
             const int nbc = nb * nc;
-            int m0 = (int)floorf(ta / dt);
+            int m0 = (int)floor(ta / dt);
             m0 = m0 < 0 ? 0 : m0;
-            float sum_dtau = 0.f;
+            double sum_dtau = 0.0;
             int first_m = INT_MAX;
             for (int base = 0; base < nbc; base += kWave) {
                 const int j = base + lane;
@@ -174,13 +184,14 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 const float val = eb * sh_coeff(ci, ax, ay, az) * inv_vs;
                 const bool late = act && kk >= 3 && ci == 0 && hlate != nullptr;
                 for (int m = m0; m < T; ++m) {
-                    const float lo = fmaxf(ta, (float)m * dt);
-                    const float hi = fminf(tb, (float)(m + 1) * dt);
+                    const double lo = fmax(ta, (double)m * dt);
+                    const double hi = fmin(tb, (double)(m + 1) * dt);
                     if (lo >= tb) break;
-                    const float dtau = hi - lo;
-                    if (dtau > 0.f) {
-                        if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * dtau);
-                        if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * dtau * inv_vs);
+                    const double dtau = hi - lo;
+                    if (dtau > 0.0) {
+                        const float fd = (float)dtau;
+                        if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * fd);
+                        if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * fd * inv_vs);
                         if (base == 0) {
                             sum_dtau += dtau;
                             first_m = min(first_m, m);
@@ -195,14 +206,14 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
             const int cls = kk == 0 ? 0 : (kk <= 2 ? 1 : 2);
 #pragma unroll
             for (int b = 0; b < NB; ++b)
-                if (lane == cls * NB + b) dep.e += (double)(Eb[b] * sum_dtau * inv_vs);
+                if (lane == cls * NB + b) dep.e += (double)(Eb[b] * (float)sum_dtau * inv_vs);
             if (first_m != INT_MAX) {
                 dep.fa = min(dep.fa, first_m);
                 if (kk >= 3) dep.fl = min(dep.fl, first_m);
             }
             if constexpr (REC) {
                 // one record per early deposit: lane w writes word w (a 128-byte store)
-                if ((kk == 1 || kk == 2) && sum_dtau > 0.f) {
+                if ((kk == 1 || kk == 2) && sum_dtau > 0.0) {
                     unsigned slot = 0;
                     if (lane == 0) slot = atomicAdd(rec_count, 1u);
                     slot = __shfl(slot, 0);
@@ -212,7 +223,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                                              ((uint64_t)(t1 & kRecNoTri) << 23) | (uint64_t)(t2 & kRecNoTri);
                         float et = 0.f;
 #pragma unroll
-                        for (int b = 0; b < NB; ++b) et += b < nb ? Eb[b] * sum_dtau * inv_vs : 0.f;
+                        for (int b = 0; b < NB; ++b) et += b < nb ? Eb[b] * (float)sum_dtau * inv_vs : 0.f;
                         float v = 0.f;
                         if (lane == 0) v = __uint_as_float((uint32_t)key);
                         else if (lane == 1) v = __uint_as_float((uint32_t)(key >> 32));
@@ -220,9 +231,9 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                             const int b = lane - 2;
 #pragma unroll
                             for (int bb = 0; bb < NB; ++bb)
-                                if (bb == b && bb < nb) v = Eb[bb] * sum_dtau * inv_vs;
+                                if (bb == b && bb < nb) v = Eb[bb] * (float)sum_dtau * inv_vs;
                         } else if (lane == 10) {
-                            v = 0.5f * (ta + fminf(tb, (float)T * dt));
+                            v = (float)(0.5 * (ta + fmin(tb, (double)T * dt)));
                         } else if (lane >= 11 && lane < 11 + RPR_MAX_COEFFS) {
                             const int ci = lane - 11;
                             v = ci < nc ? et * sh_coeff(ci, ax, ay, az) : 0.f;
@@ -236,26 +247,27 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
         // ------------------------------------------------ bounce or terminate
         if (alive) {
             const PairDesc& P = pairs[p];
+            const SceneView sc = P.scene;
             if (acc.p < 0) acc.p = p;
-            ++acc.seg;
             bool term = false;
             if (hit < 0) {
                 ++acc.esc;
                 h = fnv1a(h, 0xFFFFFFFFu);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) acc.esc_e[b] += E[b];
+                for (int b = 0; b < NB; ++b) acc.esc_e[b] += eq.E(b);
                 term = true;
             } else {
                 L += t_hit;
                 ++acc.fin;
-                acc.len += (double)t_hit;
+                acc.len += t_hit;
                 h = fnv1a(h, hit_id);
-                const bool win = L >= P.l_window;
+                const bool win = L / (double)P.c >= (double)P.n_bins * (double)P.dt;
                 if (win || k == P.max_bounces) {
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
-                        acc.alive[b] += E[b];
-                        if (!win) acc.cap[b] += E[b];
+                        const float e = eq.E(b);
+                        acc.alive[b] += e;
+                        if (!win) acc.cap[b] += e;
                     }
                     term = true;
                 } else {
@@ -264,26 +276,26 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                         if (k == 1) tri1 = hit_id;
                         else if (k == 2) tri2 = hit_id;
                     }
-                    ox += t_hit * dx;
-                    oy += t_hit * dy;
-                    oz += t_hit * dz;
+                    const double hx = ox + t_hit * dx, hy = oy + t_hit * dy, hz = oz + t_hit * dz;
+                    // unit normal of the exact triangle, turned to face the incoming ray
                     const float4* tr = sc.tris + 3 * (int64_t)hit;
-                    const float4 e1 = tr[1], e2 = tr[2];
-                    float nx = e1.y * e2.z - e1.z * e2.y, ny = e1.z * e2.x - e1.x * e2.z,
-                          nz = e1.x * e2.y - e1.y * e2.x;
-                    const float inl = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
+                    const float4 v0 = tr[0], v1 = tr[1], v2 = tr[2];
+                    const double e1x = (double)v1.x - v0.x, e1y = (double)v1.y - v0.y, e1z = (double)v1.z - v0.z;
+                    const double e2x = (double)v2.x - v0.x, e2y = (double)v2.y - v0.y, e2z = (double)v2.z - v0.z;
+                    double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+                    const double inl = 1.0 / sqrt(nx * nx + ny * ny + nz * nz);
                     nx *= inl;
                     ny *= inl;
                     nz *= inl;
-                    if (dx * nx + dy * ny + dz * nz > 0.f) {
+                    if (dx * nx + dy * ny + dz * nz > 0.0) {
                         nx = -nx;
                         ny = -ny;
                         nz = -nz;
                     }
-                    const float* __restrict__ mr = sc.mats + (int64_t)__float_as_int(e1.w) * kMatStride;
+                    const float* __restrict__ mr = sc.mats + (int64_t)__float_as_int(v1.w) * kMatStride;
                     const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, (uint32_t)k, 0u), P.key0, P.key1);
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) acc.absb[b] += mr[kMatAlpha + b] * E[b];
+                    for (int b = 0; b < NB; ++b) acc.absb[b] += mr[kMatAlpha + b] * eq.E(b);
                     // The ray's hero band (ray id mod bands) picks the kind of
                     // reflection with its own scattering coefficient; each band
                     // is weighted by its rule's path probability over the mean
@@ -296,7 +308,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         q[b] = diffuse ? mr[kMatS + b] : 1.f - mr[kMatS + b];
-                        mean_q += Q[b] * q[b];
+                        mean_q += eq.Q(b) * q[b];
                     }
                     // mean_q >= Q_hero q_hero / bands > 0 in exact arithmetic; the
                     // floor only guards an FP32 underflow of every term
@@ -304,33 +316,29 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
 #pragma unroll
                     for (int b = 0; b < NB; ++b) {
                         const float r = q[b] * inv_mean;
-                        Q[b] *= r;
-                        E[b] *= mr[kMatKeep + b] * r;
+                        eq.Q(b) *= r;
+                        eq.E(b) *= mr[kMatKeep + b] * r;
                     }
                     if (diffuse) {
-                        lambert_dir(nx, ny, nz, u01(x.y), u01(x.z), dx, dy, dz);
+                        lambert_dir_f64(nx, ny, nz, (double)u01(x.y), (double)u01(x.z), dx, dy, dz);
                         h = fnv1a(h, 1u);
                     } else {
-                        const float dn = 2.0f * (dx * nx + dy * ny + dz * nz);
+                        const double dn = 2.0 * (dx * nx + dy * ny + dz * nz);
                         dx -= dn * nx;
                         dy -= dn * ny;
                         dz -= dn * nz;
-                        const float il = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
-                        dx *= il;
-                        dy *= il;
-                        dz *= il;
                         h = fnv1a(h, 0u);
                     }
                     // the reflected segment starts just off the surface, on its facing side
-                    ox = fmaf(kSurfaceOffset, nx, ox);
-                    oy = fmaf(kSurfaceOffset, ny, oy);
-                    oz = fmaf(kSurfaceOffset, nz, oz);
+                    ox = hx + kSurfaceOffset64 * nx;
+                    oy = hy + kSurfaceOffset64 * ny;
+                    oz = hz + kSurfaceOffset64 * nz;
                     last = hit;
                 }
             }
             if (term) {
                 ++acc.rays;
-                if (P.ray_hash) P.ray_hash[rl] = h;
+                if (P.ray_hash) P.ray_hash[(int64_t)ray - P.ray_begin] = h;
                 alive = false;
             }
         }
@@ -404,11 +412,11 @@ __global__ void __launch_bounds__(kWave) k_closest(SceneView sc, const float* __
     __shared__ int32_t stk[kMaxStack * kWave];
     const long long i = (long long)blockIdx.x * kWave + threadIdx.x;
     if (i >= n) return;
-    float t;
+    double t;
     uint32_t id;
     const int hit = closest_hit<kMaxStack>(sc, orig[3 * i], orig[3 * i + 1], orig[3 * i + 2], dir[3 * i],
                                            dir[3 * i + 1], dir[3 * i + 2], -1, stk, threadIdx.x, t, id);
-    t_out[i] = t;
+    t_out[i] = (float)t;
     tri_out[i] = hit >= 0 ? (int32_t)id : -1;
 }
 

@@ -13,11 +13,37 @@
 namespace rpr {
 namespace {
 
-// Per-lane statistics of the rays one lane traced for pair `p`.
+// Per-lane band state of a ray (energy E and choice weight Q per band), in
+// LDS (band b of lane l at word b * 64 + l: no bank conflicts) or in
+// registers.
+template <int NB, bool LDS>
+struct BandState;
+
+template <int NB>
+struct BandState<NB, true> {
+    static constexpr int kLdsWords = 2 * NB * kWave;
+    float* p;
+    __device__ BandState(float* lds, int lane) : p(lds + lane) {}
+    __device__ float& E(int b) { return p[b * kWave]; }
+    __device__ float& Q(int b) { return p[(NB + b) * kWave]; }
+};
+
+template <int NB>
+struct BandState<NB, false> {
+    static constexpr int kLdsWords = 1;
+    float e[NB], q[NB];
+    __device__ BandState(float*, int) {}
+    __device__ float& E(int b) { return e[b]; }
+    __device__ float& Q(int b) { return q[b]; }
+};
+
+// Per-lane statistics of the rays one lane traced for pair `p`.  Every
+// closest-hit query either escapes or ends on a surface, so the segment count
+// is fin + esc.
 template <int NB>
 struct LaneAcc {
     int p;
-    uint32_t seg, fin, esc, rays, nodes, tris, nq;
+    uint32_t fin, esc, rays, nodes, tris, nq;
     double len;
     float esc_e[NB], alive[NB], cap[NB], absb[NB];
 };
@@ -26,7 +52,7 @@ template <int NB>
 __device__ __forceinline__ void lane_acc_zero(LaneAcc<NB>& a)
 {
     a.p = -1;
-    a.seg = a.fin = a.esc = a.rays = a.nodes = a.tris = a.nq = 0;
+    a.fin = a.esc = a.rays = a.nodes = a.tris = a.nq = 0;
     a.len = 0.0;
 #pragma unroll
     for (int b = 0; b < NB; ++b) a.esc_e[b] = a.alive[b] = a.cap[b] = a.absb[b] = 0.0f;
@@ -46,9 +72,9 @@ __device__ __forceinline__ void lane_acc_flush(LaneAcc<NB>& a, const PairDesc* _
         RprIrStats* S = pairs[q].stats;
         const int nb = pairs[q].scene.n_bands;
         const float e0 = pairs[q].e0;
-        const uint32_t seg = wave_sum_u32(in ? a.seg : 0u);
         const uint32_t fin = wave_sum_u32(in ? a.fin : 0u);
         const uint32_t esc = wave_sum_u32(in ? a.esc : 0u);
+        const uint32_t seg = fin + esc;
         const uint32_t rays = wave_sum_u32(in ? a.rays : 0u);
         const double len = wave_sum(in ? a.len : 0.0);
         if (lane == 0) {

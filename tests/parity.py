@@ -32,8 +32,22 @@ def gpu_trace(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ra
                 _dev=(hist, late, stats))
 
 
+def f32(x):
+    """The value the C ABI carries for a scalar parameter (FP32)."""
+    return float(np.float32(x))
+
+
+def oracle_kw(kw):
+    """Oracle arguments for the same inputs as the HIP path: the ABI passes the
+    bin width as FP32, so the oracle gets that FP32 value (exact in FP64)."""
+    o = {k: v for k, v in kw.items() if k not in ("want_hash", "waves_per_cu")}
+    if "bin_width_s" in o:
+        o["bin_width_s"] = f32(o["bin_width_s"])
+    return o
+
+
 def orc_trace(sd, sources, listener, radius, **kw):
-    return oracle.trace_ir(sd, sources, listener, radius, want_hash=True, **kw)
+    return oracle.trace_ir(sd, sources, listener, f32(radius), want_hash=True, **oracle_kw(kw))
 
 
 def _stats_vec(st, nb):
@@ -55,35 +69,65 @@ def _stats_vec(st, nb):
     )
 
 
+def _removed_totals(side, one, s, nb):
+    """Add ray `one`'s class energies (per class and band) to side[s]."""
+    side[s] = side[s] + np.asarray(one["stats"][0]["e_class"])[:, :nb]
+
+
 def traced_pair(scene, sd, sources, listener, radius, **kw):
     """Trace on both sides; rays whose discrete path (hit triangles and bounce
-    kinds) differs between FP32 and FP64 are traced again one by one on both
-    sides and removed from both results.  Returns (gpu, oracle, divergent)."""
+    kinds) differs between the HIP path and the oracle are traced again one
+    by one on both sides and removed from both results.  Returns (gpu,
+    oracle, divergent); gpu["removed"] and oracle["removed"] hold the class
+    energies [source][class][band] of the removed rays on each side, and
+    gpu["removed_sq"] their per-ray squares summed (for a Monte Carlo bound,
+    see assert_removed_close)."""
     g = gpu_trace(scene, sources, listener, radius, **kw)
-    okw = {k: v for k, v in kw.items() if k != "want_hash"}
-    o = orc_trace(sd, sources, listener, radius, **okw)
+    o = orc_trace(sd, sources, listener, radius, **kw)
     srcs = np.atleast_2d(np.asarray(sources, np.float32))
     nb = scene.n_bands
-    gs = [_stats_vec(g["stats"][s], nb) for s in range(len(srcs))]
-    os_ = [_stats_vec(o["stats"][s], nb) for s in range(len(srcs))]
+    S = len(srcs)
+    gs = [_stats_vec(g["stats"][s], nb) for s in range(S)]
+    os_ = [_stats_vec(o["stats"][s], nb) for s in range(S)]
     div = np.argwhere(g["ray_hash"] != o["ray_hash"])
     rb = kw.get("ray_begin", 0)
+    rem_g = [np.zeros((3, nb)) for _ in range(S)]
+    rem_o = [np.zeros((3, nb)) for _ in range(S)]
+    rem_sq = [np.zeros((3, nb)) for _ in range(S)]
     for (s, i) in div:
         one = dict(kw, ray_begin=rb + int(i), ray_end=rb + int(i) + 1, pair_base=kw.get("pair_base", 0) + int(s))
         g1 = gpu_trace(scene, srcs[s:s + 1], listener, radius, **one)
-        o1 = orc_trace(sd, srcs[s:s + 1], listener, radius, **{k: v for k, v in one.items() if k != "want_hash"})
+        o1 = orc_trace(sd, srcs[s:s + 1], listener, radius, **one)
         g["hist"][s] -= g1["hist"][0]
         g["hist_late"][s] -= g1["hist_late"][0]
         o["hist"][s] -= o1["hist"][0]
         o["hist_late"][s] -= o1["hist_late"][0]
-        for side, one_res, lst_ in ((gs, g1["stats"][0], None), (os_, o1["stats"][0], None)):
+        _removed_totals(rem_g, g1, s, nb)
+        _removed_totals(rem_o, o1, s, nb)
+        eg = np.asarray(g1["stats"][0]["e_class"])[:, :nb]
+        eo = np.asarray(o1["stats"][0]["e_class"])[:, :nb]
+        rem_sq[s] = rem_sq[s] + eg ** 2 + eo ** 2
+        for side, one_res in ((gs, g1["stats"][0]), (os_, o1["stats"][0])):
             v1 = _stats_vec(one_res, nb)
             for key in ("n_segments", "n_finite_segments", "n_escaped", "n_rays", "seg_len_sum", "e_emitted",
                         "e_class", "e_escaped", "e_alive_at_stop", "e_alive_at_bounce_cap", "e_absorbed"):
                 side[s][key] = side[s][key] - v1[key]
     g["cmp_stats"] = gs
     o["cmp_stats"] = os_
+    g["removed"], o["removed"], g["removed_sq"] = rem_g, rem_o, rem_sq
+    print(f"[parity] {len(div)} of {g['ray_hash'].size} rays took another discrete path on the two sides")
     return g, o, div
+
+
+def assert_removed_close(g, o, sigmas=5.0):
+    """The rays removed from the comparison (a different discrete path on the
+    two sides) are two independent-looking samples of the same estimator:
+    their summed class energies agree within `sigmas` Monte Carlo standard
+    deviations, estimated from the removed rays' own contributions."""
+    for s in range(len(g["removed"])):
+        d = np.abs(g["removed"][s] - o["removed"][s])
+        sd = np.sqrt(g["removed_sq"][s])
+        assert np.all(d <= sigmas * sd + 1e-300), (s, d, sd)
 
 
 def assert_hist_close(Hg, Ho, tol=HIST_TOL, what="hist", time_rel=0.0):
@@ -159,19 +203,19 @@ def traced_listener_pair(scene, sd, sources, listener, radius, **kw):
     alone on both sides and removed from every source's result.  Returns
     (gpu, oracle, divergent ray indices)."""
     g = gpu_trace_listener(scene, sources, listener, radius, **kw)
-    okw = {k: v for k, v in kw.items() if k != "want_hash"}
-    o = oracle.trace_listener(sd, sources, listener, radius, want_hash=True, **okw)
+    o = oracle.trace_listener(sd, sources, listener, f32(radius), want_hash=True, **oracle_kw(kw))
     srcs = np.atleast_2d(np.asarray(sources, np.float32))
     nb = scene.n_bands
     S = len(srcs)
     gs = [_stats_vec(g["stats"][s], nb) for s in range(S)]
     os_ = [_stats_vec(o["stats"][s], nb) for s in range(S)]
     div = np.flatnonzero(g["ray_hash"] != o["ray_hash"])
+    print(f"[parity] {len(div)} of {g['ray_hash'].size} listener rays took another discrete path on the two sides")
     rb = kw.get("ray_begin", 0)
     for i in div:
         one = dict(kw, ray_begin=rb + int(i), ray_end=rb + int(i) + 1)
         g1 = gpu_trace_listener(scene, srcs, listener, radius, **one)
-        o1 = oracle.trace_listener(sd, srcs, listener, radius, **{k: v for k, v in one.items() if k != "want_hash"})
+        o1 = oracle.trace_listener(sd, srcs, listener, f32(radius), **oracle_kw(one))
         for s in range(S):
             g["hist"][s] -= g1["hist"][s]
             g["hist_late"][s] -= g1["hist_late"][s]
