@@ -219,7 +219,8 @@ int trace_listener(const RprScene* scene, const RprSource* srcs, int32_t n_src, 
                    uint32_t* ray_hash, void* hip_stream);
 
 typedef struct {
-    int32_t rt60_source; /* 0: all orders (default); 1: orders >= 3 only (hist_late) */
+    int32_t rt60_source; /* 1: orders >= 3 only (hist_late), the IR Section 4.2 estimates the
+                            parameters from; 0: all orders */
     int32_t tail_iters;  /* refits with the missing tail added when the window cut the decay (3) */
 } RprEstimateParams;
 
@@ -246,7 +247,7 @@ typedef struct {
  *   hist      device [n_ir][n_bins][n_bands][(sh_order+1)^2] f32
  *   hist_late device [n_ir][n_bins][n_bands] f32, or NULL (then rt60_source must be 0)
  *   stats     device [n_ir]
- *   ep        host, or NULL for {0, 3}
+ *   ep        host, or NULL for {1, 3} ({0, 3} when hist_late is NULL)
  *   out       device [n_ir] */
 int estimate_reverb(const float* hist, const float* hist_late, const RprIrStats* stats, int32_t n_ir,
                     int32_t n_bins, int32_t n_bands, int32_t sh_order, float bin_width_s,

@@ -367,13 +367,18 @@ def rt60_schroeder(I, dt, tail_iters=3):
     return rt, rng_, st
 
 
-def estimate_reverb(hist, hist_late, stats, bin_width_s, rt60_source=0, tail_iters=3):
+def estimate_reverb(hist, hist_late, stats, bin_width_s, rt60_source=None, tail_iters=3):
     """Reverb parameters of one IR (Section 4.2).
       hist      [T, B, NC]  SH x band histogram, I[m] = sqrt(4 pi) H[m][b][0]
-      hist_late [T, B]      orders >= 3 only (used when rt60_source = 1: the
-                            parameter IR holds only higher-order reflections)
+      hist_late [T, B]      orders >= 3 only, or None
+      rt60_source  1: RT60 from hist_late (Section 4.2: the IR the parameters
+                   are estimated from holds only the higher-order
+                   reflections); 0: from the all-orders intensity.  Default:
+                   1 when hist_late is given, else 0.
       stats     dict from trace_ir
     Returns a dict of per-band arrays and scalars."""
+    if rt60_source is None:
+        rt60_source = 0 if hist_late is None else 1
     H = np.asarray(hist, np.float64)
     T, B, NC = H.shape
     dt = float(bin_width_s)

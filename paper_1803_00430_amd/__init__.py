@@ -371,10 +371,14 @@ def trace_listener(scene: Scene, sources, listener, radius, params: TraceParams,
                                 _ptr(hist_late), _ptr(stats), _ptr(ray_hash), _stream(stream)))
 
 
-def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width_s, out, rt60_source=0,
+def estimate_reverb(hist, hist_late, stats, n_bins, n_bands, sh_order, bin_width_s, out, rt60_source=None,
                     tail_iters=3, stream=None):
-    """Enqueue estimate_reverb; `out` is a uint8 tensor [n_ir, 752]."""
+    """Enqueue estimate_reverb; `out` is a uint8 tensor [n_ir, 752].
+    rt60_source: 1 late-only (orders >= 3), 0 all orders; default 1 when
+    hist_late is given."""
     n_ir = int(stats.shape[0])
+    if rt60_source is None:
+        rt60_source = 0 if hist_late is None else 1
     ep = EstimateParams(int(rt60_source), int(tail_iters))
     _check(lib().estimate_reverb(_ptr(hist), _ptr(hist_late), _ptr(stats), n_ir, int(n_bins), int(n_bands),
                                  int(sh_order), float(bin_width_s), C.byref(ep), _ptr(out), _stream(stream)))
@@ -446,10 +450,12 @@ class Batch:
     "listener" from its listener point with next-event queries toward its
     source, a ball of the pair's radius."""
 
-    def __init__(self, scenes, pairs, *, n_bins, sh_order, bin_width_s, speed_of_sound=343.0, rt60_source=0,
+    def __init__(self, scenes, pairs, *, n_bins, sh_order, bin_width_s, speed_of_sound=343.0, rt60_source=None,
                  tail_iters=3, autotune=True, use_graph=True, waves_per_cu=0, order=0, late=True, device="cuda",
                  stream=None, method="source"):
         import torch
+        if rt60_source is None:
+            rt60_source = 1 if late else 0
         self.scenes = list(scenes)  # kept alive for the batch's lifetime
         n = len(pairs)
         arr = (Pair * n)()

@@ -302,7 +302,7 @@ extern "C" int estimate_reverb(const float* hist, const float* hist_late, const 
                                int32_t n_bins, int32_t n_bands, int32_t sh_order, float bin_width_s,
                                const RprEstimateParams* ep, RprReverbParams* out, void* hip_stream)
 {
-    const RprEstimateParams def{0, 3};
+    const RprEstimateParams def{hist_late ? 1 : 0, 3};
     const RprEstimateParams e = ep ? *ep : def;
     if (n_ir < 0) return set_error(RPR_EINVAL, "estimate_reverb: n_ir < 0");
     if (n_ir == 0) return RPR_OK;

@@ -4,13 +4,17 @@ Tolerances: histograms within 1e-4 relative per bin-band-coefficient row sum
 (cells within 1e-4 of that row's absolute sum), RT60 within 1%.  Integer
 outputs (Philox words) bit-exact.
 
-A ray whose discrete path (sequence of hit triangles and bounce kinds)
-differs between the FP32 kernel and the FP64 oracle is traced again alone on
-both sides and removed from both results before the comparison.  Such
-splits are inherent: the rounding difference of a hit position grows by the
-grazing-incidence factor of every bounce until the two paths land on
-different sides of a triangle edge.  Each test states the fraction of rays it
-allows to split (a few times what was measured)."""
+The kernel keeps each ray's origin, direction and path length in FP64 and
+decides every hit with an FP64 triangle test, so a ray follows the oracle's
+path.  The two sides still round differently in the last bit (fused
+multiply-adds, a sin/cos within a few ulps), and a grazing hit multiplies a
+position difference by 1 / cos(incidence); over a couple of hundred bounces
+in a closed interior a few rays end up on a neighbouring triangle.  A ray
+whose discrete path (sequence of hit triangles and bounce kinds) differs is
+traced again alone on both sides and removed from both results before the
+comparison, and the removed rays' class energies must agree within Monte
+Carlo error.  Each test states the fraction of rays it allows to split and
+what was measured."""
 import math
 
 import numpy as np
@@ -19,7 +23,8 @@ import pytest
 import oracle
 import paper_1803_00430_amd as P
 import rpr_scenes as R
-from parity import RT60_TOL, assert_hist_close, assert_stats_close, gpu_trace, orc_trace, traced_pair
+from parity import (RT60_TOL, assert_hist_close, assert_removed_close, assert_stats_close, f32, gpu_trace, orc_trace,
+                    traced_pair)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,7 +124,8 @@ def test_tiny_config_parity(torch_cuda):
     sc = P.Scene.from_dict(c)
     kw = _tiny_kw(c)
     g, o, div = traced_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
-    assert len(div) <= 0.01 * c["n_rays"], len(div)  # measured 8 of 4096 (splits after bounce 44)
+    assert len(div) <= 1e-3 * c["n_rays"], len(div)  # measured 0 of 4096
+    assert_removed_close(g, o)
     assert_hist_close(g["hist"][0], o["hist"][0])
     assert_hist_close(g["hist_late"][0], o["hist_late"][0], what="hist_late")
     assert_stats_close(g["cmp_stats"][0], o["cmp_stats"][0])
@@ -144,7 +150,8 @@ def test_ragged_multisource_parity(torch_cuda):
     kw = dict(n_rays_total=1000, max_bounces=100, sh_order=3, n_bins=250, bin_width_s=1e-3, seed=77,
               pair_base=5)
     g, o, div = traced_pair(sc, sd, srcs, lst, 0.6, **kw)
-    assert len(div) <= 0.10 * 3000, len(div)
+    assert len(div) <= 1e-3 * 3000, len(div)  # measured 0 of 3000
+    assert_removed_close(g, o)
     assert any(st["e_alive_at_bounce_cap"].sum() < st["e_alive_at_stop"].sum() for st in o["stats"])
     for s in range(3):
         assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
@@ -357,34 +364,58 @@ def test_city_full_size_ray_subset(torch_cuda):
     subset of absolute ray ids that the brute-force oracle can follow."""
     c = R.city_config()
     sc = P.Scene.from_dict(c)
-    kw = dict(n_rays_total=c["n_rays"], ray_begin=1000, ray_end=1192, max_bounces=c["max_bounces"],
+    kw = dict(n_rays_total=c["n_rays"], ray_begin=1000, ray_end=2024, max_bounces=c["max_bounces"],
               sh_order=c["sh_order"], n_bins=c["n_bins"], bin_width_s=c["bin_width_s"], seed=c["seed"])
     g, o, div = traced_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
-    assert len(div) <= 0.02 * 8 * 192, len(div)
+    assert len(div) <= 1e-3 * 8 * 1024, len(div)  # measured 0 of 8192
+    assert_removed_close(g, o)
     for s in range(8):
         assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
         assert_stats_close(g["cmp_stats"][s], o["cmp_stats"][s])
 
 
-@pytest.mark.parametrize("K,max_div", [(25, 0.15), (200, 0.95)])
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("K,max_div", [(25, 1e-3), (200, 0.01)])
 def test_hospital_full_size_ray_subset(torch_cuda, K, max_div):
     """The hospital interior at full size (999,956 triangles, SH order 3, 3000
-    bins) for two of its 64 sources, on a subset of absolute ray ids that the
-    brute-force oracle can follow.  In this closed, cluttered interior every
-    ray lives to the bounce limit, so at the workload's 200 bounces most FP32
-    paths split from their FP64 twins somewhere along the way (measured 39 of
-    48); those are detected by the path hash and removed from both sides, and
-    the rest must agree.  At 25 bounces nearly all paths stay together."""
+    bins) for two of its 64 sources, 1,024 absolute ray ids each, at 25 and at
+    the workload's 200 bounces.  In this closed, cluttered interior every ray
+    lives to the bounce limit; at 200 bounces a few paths split from their
+    oracle twins after grazing hits (measured 5 of 2,048), and those are
+    removed from both sides and checked statistically.  The remaining
+    histograms agree cell by cell, and at 200 bounces the RT60 that each side
+    estimates from its own remaining late histogram agrees within 1%, from
+    the same fit range (measured: all 8 band fits of the two sources; at 25
+    bounces the late decay is cut before any fit range is reached)."""
     c = R.hospital_config()
     sc = P.Scene.from_dict(c)
     srcs = c["sources"][:2]
-    kw = dict(n_rays_total=c["n_rays"], ray_begin=5000, ray_end=5024, max_bounces=K,
+    radius, rays = c["radius"], 1024
+    kw = dict(n_rays_total=c["n_rays"], ray_begin=5000, ray_end=5000 + rays, max_bounces=K,
               sh_order=c["sh_order"], n_bins=c["n_bins"], bin_width_s=c["bin_width_s"], seed=c["seed"])
-    g, o, div = traced_pair(sc, c, srcs, c["listener"], c["radius"], **kw)
-    assert len(div) <= max_div * 2 * 24, len(div)
+    g, o, div = traced_pair(sc, c, srcs, c["listener"], radius, **kw)
+    assert len(div) <= max_div * 2 * rays, len(div)
+    print(f"[parity] hospital K={K} r={radius}: {2 * rays - len(div)} of {2 * rays} rays compared")
+    assert_removed_close(g, o)
+    torch = torch_cuda
+    hist = torch.as_tensor(g["hist"], dtype=torch.float32, device="cuda")
+    late = torch.as_tensor(g["hist_late"], dtype=torch.float32, device="cuda")
+    out = P.alloc_params(2)
+    P.estimate_reverb(hist, late, g["_dev"][2], c["n_bins"], 4, c["sh_order"], c["bin_width_s"], out)
+    pg = P.params_host(out)
+    n_valid = 0
     for s in range(2):
         assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
         assert_stats_close(g["cmp_stats"][s], o["cmp_stats"][s])
+        po = oracle.estimate_reverb(o["hist"][s], o["hist_late"][s], o["stats"][s], f32(c["bin_width_s"]))
+        ok = po["rt60"] > 0
+        n_valid += int(ok.sum())
+        assert np.array_equal(pg[s]["rt60_range"][:4][ok], po["rt60_range"][ok]), (s, pg[s]["rt60_range"], po)
+        assert np.all(np.abs(pg[s]["rt60"][:4][ok] - po["rt60"][ok]) <= RT60_TOL * po["rt60"][ok]), \
+            (s, pg[s]["rt60"][:4], po["rt60"])
+    print(f"[parity] hospital K={K} r={radius}: {n_valid} of 8 band RT60 fits compared")
+    if K == 200:
+        assert n_valid >= 4  # fits exist to compare
 
 
 def test_city_full_trace_invariants(torch_cuda):
