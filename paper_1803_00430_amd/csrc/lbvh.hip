@@ -75,9 +75,10 @@ __global__ void k_init_flags(BuildFlags* f)
     }
 }
 
-// Material record per material (see kMat* offsets): p_d = mean_b s_b computed
-// in FP64 and rounded to FP32, and the per-band weights applied on a diffuse
-// or specular bounce.
+// Material record per material (see kMat* offsets): per band the absorption
+// alpha_b, the scattering coefficient s_b (the hero band's s_b is the diffuse
+// probability of a bounce; every band's s_b or 1 - s_b enters the band
+// weights) and 1 - alpha_b, formed in FP64 and rounded to FP32.
 __global__ void k_materials(const float* __restrict__ absorption, const float* __restrict__ scattering, int nm,
                             int nb, float* __restrict__ mats, BuildFlags* f)
 {
