@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35531872.0,
-                 "sources_sha256": "99b481f4f7c0bbdda120f01c637e34c27a60ed65c564afcdc4610c91b091216f"}
+TRACE_TRAFFIC = {"bytes": 35562516.5,
+                 "sources_sha256": "829abc1799f05caff4035248d9df4eb5aafbb91b8adcec4fb1b259ef8be88a94"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 
@@ -64,9 +64,9 @@ def parse():
     ap.add_argument("--streams", type=int, default=3, help="city: streams the consecutive steps rotate over")
     ap.add_argument("--waves-per-cu", type=int, default=0,
                     help="city: resident trace waves per CU (0: as many as fit); fewer waves refill their lanes")
-    ap.add_argument("--cpu-rays", type=int, default=16384, help="rays per source in the oracle sample")
+    ap.add_argument("--cpu-rays", type=int, default=8192, help="rays per source in the oracle sample")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb", "paths"),
+    ap.add_argument("--workload", choices=("city", "batch", "learn", "hospital", "rooms", "reverb", "paths", "probe"),
                     default="city",
                     help="city: the single-scene frame (default, the headline line); batch: 256 pairs over "
                          "16 scenes in one persistent graph-captured launch; learn: IRs/s at <= 5%% RT60 error, "
@@ -115,6 +115,81 @@ def parse():
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
                          "(a known-size reference for the HBM byte counters)")
     return ap.parse_args()
+
+
+def probe_rate(P, torch, nbytes, pattern, *, grid, block, iters, reps=5):
+    """Median rate of `reps` memory-probe launches over a working set of
+    `nbytes` (include/rpr.h memory_probe), timed with events on the current
+    stream: (GB/s, ms per launch, bytes per launch)."""
+    nbytes = max(128, (int(nbytes) + 127) // 128 * 128)
+    buf = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    sink = torch.empty(grid * block, dtype=torch.float32, device="cuda")
+    P.memory_probe(buf, pattern, iters, grid, block, sink)  # first touch: the data enters the caches
+    ms = []
+    nb = 0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nb = P.memory_probe(buf, pattern, iters, grid, block, sink)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    m = float(np.median(ms))
+    del buf, sink
+    return nb / (m * 1e-3) / 1e9, m, nb
+
+
+def trace_roof(P, torch, work_bytes, cus):
+    """The measured roof of the traversal at its working set: 128-byte lines
+    gathered at scattered addresses by the trace's launch shape (one-wave
+    workgroups, 16 per compute unit)."""
+    grid = cus * 16
+    gbs, ms, nb = probe_rate(P, torch, work_bytes, 1, grid=grid, block=64, iters=256)
+    return {"gather_gbs": gbs, "working_set_bytes": int(work_bytes), "probe_ms": ms, "probe_bytes": nb,
+            "launch": f"{grid} x 64 threads, 256 lines of 128 B per thread"}
+
+
+def run_probe(a):
+    """The bandwidth-vs-working-set curve of the memory hierarchy for the
+    traversal's read patterns (memory_probe): streaming reads, independent
+    128-byte line gathers (throughput) and dependent line chases (latency),
+    from 1 MiB to 8 GiB."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    cus = P.device_cus()
+    sizes = [1 << k for k in range(20, 34)]  # 1 MiB .. 8 GiB
+    rows = []
+    for ws in sizes:
+        it_stream = max(1, (4 << 30) // ws)
+        s_gbs, s_ms, _ = probe_rate(P, torch, ws, 0, grid=cus * 8, block=256, iters=it_stream, reps=3)
+        g_gbs, g_ms, _ = probe_rate(P, torch, ws, 1, grid=cus * 16, block=64, iters=256, reps=3)
+        c_gbs, c_ms, _ = probe_rate(P, torch, ws, 2, grid=cus * 16, block=64, iters=64, reps=3)
+        c1_gbs, c1_ms, _ = probe_rate(P, torch, ws, 2, grid=cus, block=64, iters=64, reps=3)
+        row = {"working_set_bytes": ws, "stream_gbs": s_gbs, "gather_gbs": g_gbs,
+               "chase_ns_loaded": c_ms * 1e6 / 64, "chase_ns_one_wave_per_cu": c1_ms * 1e6 / 64}
+        rows.append(row)
+        log(f"{ws / 2**20:8.0f} MiB: stream {s_gbs:9.0f} GB/s, gather {g_gbs:9.0f} GB/s, "
+            f"chase {row['chase_ns_loaded']:7.0f} ns loaded / {row['chase_ns_one_wave_per_cu']:6.0f} ns alone",
+            a.quiet)
+    out = {"metric": "memory bandwidth vs working set", "value": max(r["gather_gbs"] for r in rows), "unit": "GB/s",
+           "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "memory_probe over 1 MiB .. 8 GiB: streaming reads (grid CUs x 8 x 256), "
+                                  "128-byte line gathers and chases (grid CUs x 16 x 64, the trace's shape)"},
+           "curve": rows}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or '' where there is none."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return ""
 
 
 def log(msg, quiet=False):
@@ -914,6 +989,9 @@ def main():
     if a.workload == "paths":
         run_paths(a)
         return
+    if a.workload == "probe":
+        run_probe(a)
+        return
     if a.segment_budget > 0:
         run_city_frames(a)
         return
@@ -1003,9 +1081,29 @@ def main():
     ms_step = wall * 1e3 / a.steps
     value = segs * a.steps / wall
     trace_ms = float(np.mean(t_trace))
-    achieved = segs * bytes_per_seg / (trace_ms * 1e-3) / 1e9
     traffic = TRACE_TRAFFIC["bytes"] if TRACE_TRAFFIC["sources_sha256"] == trace_sources_sha256() else None
     pg = P.params_host(params)
+
+    # After the timed region: the trace alone, launch after launch on one stream
+    # (the duration a profiler reports for k_trace under --serial), and the
+    # memory probe at the traversal's working set (the roof it runs under).
+    sc = P.Scene(verts, tris, tmat, absb, scat, device=dev)
+    s_ms = []
+    for i in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
+        e1.record()
+        e1.synchronize()
+        if i > 0:
+            s_ms.append(e0.elapsed_time(e1))
+    sc.close()
+    serial_ms = float(np.median(s_ms))
+    work_bytes = 128 * int(info["n_nodes"]) + 48 * int(info["n_tris"])
+    roof = trace_roof(P, torch, work_bytes, P.device_cus())
+    alg_bytes = segs * bytes_per_seg  # algorithmic bytes of one step's trace
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9  # over the step time the job sustains
+    achieved_serial = alg_bytes / (serial_ms * 1e-3) / 1e9
 
     out = {
         "metric": "ray-bounces/s", "value": value, "unit": "ray-bounces/s", "n_gpus": 1, "steps": a.steps,
@@ -1019,11 +1117,21 @@ def main():
                    "n_tris": int(info["n_tris"]), "sources": S, "rays_per_source": N, "max_bounces": K,
                    "sh_order": n, "bands": B, "bins": T, "bin_width_s": dt,
                    **({"waves_per_cu": a.waves_per_cu} if a.waves_per_cu else {})},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_trace", "bytes_per_ray_bounce": bytes_per_seg,
+        # k_trace's algorithmic bytes (nodes and triangle records fetched) per step over the
+        # pipelined step time, against the measured rate at which the chip serves scattered
+        # 128-byte lines from a working set of the tree's size (L2 + Infinity Cache: the tree is
+        # far below HBM, whose traffic `traffic` is ~1% of these bytes); `serial` is the trace
+        # launched alone, one launch after another
+        "roofline": {"bound": "cache", "achieved": achieved, "peak": roof["gather_gbs"], "unit": "GB/s",
+                     "frac": achieved / roof["gather_gbs"], "traffic": traffic,
+                     "kernel": "k_trace", "kernel_ms": ms_step, "algorithmic_bytes": alg_bytes,
+                     "bytes_per_ray_bounce": bytes_per_seg,
                      "node_visits_per_ray_bounce": vn, "tri_tests_per_ray_bounce": vt,
-                     "kernel_ms": trace_ms},
+                     "peak_source": "memory_probe gather at the tree's working set", "probe": roof,
+                     "hbm_peak": HBM_PEAK_GBS, "hbm_frac": achieved / HBM_PEAK_GBS,
+                     "serial": {"kernel_ms": serial_ms, "achieved": achieved_serial,
+                                "frac": achieved_serial / roof["gather_gbs"]},
+                     "per_launch_overlapped_ms": trace_ms},
         # per timed step, by events on the step's stream (with several streams the phases overlap the
         # neighbouring steps, so they do not add up to ms_per_step)
         "breakdown_ms": {"build": float(np.mean(t_build)), "trace": trace_ms, "estimate": float(np.mean(t_est))},
@@ -1043,15 +1151,19 @@ def main():
     if not a.no_cpu_baseline:
         import oracle
         R_s = a.cpu_rays
-        c0 = time.perf_counter()
-        o = oracle.trace_ir(cfg, cfg["sources"], cfg["listener"], cfg["radius"], n_rays_total=N, ray_begin=0,
-                            ray_end=R_s, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
-        c_wall = time.perf_counter() - c0
+        runs = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            o = oracle.trace_ir(cfg, cfg["sources"], cfg["listener"], cfg["radius"], n_rays_total=N, ray_begin=0,
+                                ray_end=R_s, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=cfg["seed"])
+            runs.append(time.perf_counter() - c0)
+        c_wall = float(np.median(runs))
         osegs = sum(x["n_segments"] for x in o["stats"])
         out["cpu_baseline"] = {"value": osegs / c_wall, "unit": "ray-bounces/s", "cores": oracle.num_threads(),
-                               "kind": "oracle",
-                               "sample": f"city, rays 0..{R_s - 1} of each of the 8 sources ({osegs} ray-bounces, "
-                                         f"{c_wall:.1f} s), FP64 brute force"}
+                               "kind": "oracle", "cpu": cpu_model(),
+                               "sample": f"city, rays 0..{R_s - 1} of each of the 8 sources ({osegs} ray-bounces), "
+                                         f"FP64 brute force; median of 3 runs "
+                                         f"({', '.join(f'{r:.1f}' for r in runs)} s)"}
     if a.calib_copy_mib > 0:
         n = a.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)

@@ -681,6 +681,26 @@ int reverb_render(const RprReverbSetup* setup, int32_t n_src, const float* x, in
 int scene_closest_hit(const RprScene* scene, const float* orig, const float* dir, int64_t n,
                       float* t_out, int32_t* tri_out, void* hip_stream);
 
+/* Memory-hierarchy probe: one launch that reads a working set the way the
+ * BVH traversal does, to measure the roof the traversal runs under (Table 1:
+ * ray tracing is nearly all of the propagation update, and its bytes are
+ * node lines and triangle records read from the cache hierarchy).
+ *   buf      device, `bytes` bytes (a multiple of 128, 16-byte aligned): the
+ *            working set; its contents are only summed
+ *   pattern  0 streaming: coalesced 16-byte reads, grid-stride, `iters` passes
+ *            over the buffer (bytes read: iters x bytes);
+ *            1 gather: each thread reads `iters` whole 128-byte lines at
+ *            pseudo-random line indices, independent of the data (bytes read:
+ *            grid x block x iters x 128);
+ *            2 chase: as 1, each index depending on the previous line's data
+ *            (one line in flight per thread: latency)
+ *   grid, block  launch shape; block a multiple of 64, at most 1024
+ *   sink     device [grid x block] f32, overwritten (keeps the reads alive)
+ * Enqueues one kernel on the stream; the caller times it (events on that
+ * stream).  Errors: RPR_EINVAL for a bad size, pattern or shape. */
+int memory_probe(const void* buf, int64_t bytes, int32_t pattern, int32_t iters, int32_t grid, int32_t block,
+                 float* sink, void* hip_stream);
+
 /* Device implementations of the shared primitives, exposed for unit checks.
  * debug_philox: in device [n][6] u32 = ctr0..3, key0..1; out device [n][4].
  * debug_sh_eval: dirs device [n][3] f32 (unit), out device [n][16] f32 (the

@@ -177,6 +177,7 @@ SIGNATURES = {
     "scene_closest_hit": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
     "debug_philox": (C.c_int, [_vp, _i64, _vp, _vp]),
     "debug_sh_eval": (C.c_int, [_vp, _i64, _i32, _vp, _vp]),
+    "memory_probe": (C.c_int, [_vp, _i64, _i32, _i32, _i32, _i32, _vp, _vp]),
     "batch_create": (C.c_int, [C.POINTER(_vp), _i32, C.POINTER(Pair), _i32, C.POINTER(BatchParams), _vp, _vp,
                                _vp, _vp, _vp, C.POINTER(_vp)]),
     "batch_run": (C.c_int, [_vp, _vp]),
@@ -433,6 +434,21 @@ def debug_philox(ctr_key, stream=None):
     out = torch.empty((a.shape[0], 4), dtype=torch.int32, device="cuda")
     _check(lib().debug_philox(_ptr(t), a.shape[0], _ptr(out), _stream(stream)))
     return out
+
+
+def memory_probe(buf, pattern, iters, grid, block, sink, stream=None):
+    """Enqueue one memory-probe launch over the device tensor `buf` (see
+    include/rpr.h); returns the bytes it reads."""
+    nbytes = buf.numel() * buf.element_size()
+    _check(lib().memory_probe(_ptr(buf), int(nbytes), int(pattern), int(iters), int(grid), int(block), _ptr(sink),
+                              _stream(stream)))
+    return int(iters) * nbytes if pattern == 0 else int(grid) * int(block) * int(iters) * 128
+
+
+def device_cus():
+    """Compute units of the current device."""
+    import torch
+    return int(torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count)
 
 
 def debug_sh_eval(dirs, order, stream=None):

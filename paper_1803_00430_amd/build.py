@@ -20,7 +20,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librpr.so")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "lbvh.hip", "trace.hip", "listener.hip", "estimate.hip", "temporal.hip", "reverb.hip", "paths.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "lbvh.hip", "trace.hip", "listener.hip", "estimate.hip", "temporal.hip", "reverb.hip", "paths.hip", "batch.hip", "mlp.hip", "probe.hip"]
 
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = [
