@@ -328,10 +328,13 @@ typedef struct {
     int32_t use_graph;    /* 1: capture the run (reset, trace, estimate) into a HIP graph */
     int32_t waves_per_cu; /* launch width when autotune = 0 (0 = library default) */
     int32_t order;        /* queue order when autotune = 0: 0 as given, 1 most rays x bounces first,
-                             2 interleaved (pairs split into 1,024-ray chunks dealt round-robin) */
+                             2 interleaved (pairs split into chunks of chunk_rays rays dealt
+                             round-robin) */
     int32_t method;       /* 0: each pair traced from its source to the listener sphere (trace_ir);
                              1: from its listener point with next-event queries toward its source,
                              a ball of the pair's radius (trace_listener, one source per pair) */
+    int32_t chunk_rays;   /* rays per chunk of the interleaved order and of the listener method's
+                             chunk table when autotune = 0: 256, 1024 or 4096 (0 = 1024) */
 } RprBatchParams;
 
 typedef struct {
@@ -341,9 +344,12 @@ typedef struct {
     int32_t order;         /* chosen queue order */
     int32_t stack_need;
     int32_t graph;         /* 1 if runs replay a captured graph */
-    int32_t n_candidates;  /* launch shapes timed by the autotuner (0 without autotune) */
+    int32_t n_candidates;  /* launch shapes timed by the autotuner (0 without autotune or when the
+                              shape came from the tuning cache) */
     float best_ms;         /* autotuner's best trace time */
     float worst_ms;        /* autotuner's worst trace time */
+    int32_t chunk_rays;    /* chosen chunk size (interleaved order, listener method) */
+    int32_t from_cache;    /* 1 if the shape came from the tuning cache (in memory or file) */
 } RprBatchInfo;
 
 /* Plan a batch.
@@ -355,7 +361,15 @@ typedef struct {
  *   params     device [n_pairs]
  * The caller keeps the scenes and output buffers alive until batch_destroy.
  * Synchronises hip_stream (uploads the pair table; the autotuner runs the
- * batch once per candidate shape). */
+ * batch a few times per candidate shape).
+ * Autotuning times resident waves per CU (4 widths) x queue order (as given,
+ * longest first, interleaved) x chunk size (256, 1,024, 4,096 rays; for the
+ * interleaved order and the listener method) and keeps the fastest.  The
+ * choice is cached per (GPU architecture, CU count, method, bands, bins, SH
+ * coefficients, stack variant, and the log2 buckets of pairs, total rays,
+ * mean bounces and largest scene); when the environment variable
+ * RPR_AUTOTUNE_CACHE names a file, the cache is read from it at the first
+ * batch_create and every new choice is written back (one line per key). */
 int batch_create(const RprScene* const* scenes, int32_t n_scenes, const RprPair* pairs, int32_t n_pairs,
                  const RprBatchParams* bp, float* hist, float* hist_late, RprIrStats* stats,
                  RprReverbParams* params, void* hip_stream, RprBatch** out);

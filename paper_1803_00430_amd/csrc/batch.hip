@@ -7,20 +7,25 @@
 // the histograms, trace every ray of every pair through the shared queue,
 // estimate every pair -- which can be captured into a HIP graph and replayed.
 //
-// Launch shape: the resident waves per compute unit and the order in which
-// pairs enter the queue (as given, or most rays x bounces first so that the
-// longest pairs start early and the tail is shorter).  The autotuner times
-// every candidate shape on the batch itself and keeps the fastest; the choice
-// is cached per (device, pairs, total-ray bucket, stack variant).  Results do
+// Launch shape: the resident waves per compute unit, the order in which
+// pairs enter the queue (as given; most rays x bounces first, so that the
+// longest pairs start early and the tail is shorter; or interleaved chunks)
+// and the chunk size of the interleaved order and of the listener method's
+// chunk table.  The autotuner times every candidate shape on the batch
+// itself and keeps the fastest; the choice is cached per key (see tune_key),
+// in memory and, when RPR_AUTOTUNE_CACHE names a file, on disk.  Results do
 // not depend on the shape: every ray is a function of (pair, ray id).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -33,7 +38,8 @@ struct RprBatch {
     int64_t total = 0;
     int stack_need = 0;
     int waves_per_cu = 0, order = 0;
-    int method = 0;  // 0 source-origin, 1 listener-origin
+    int64_t chunk = 1024;  // rays per chunk (interleaved order, listener chunk table)
+    int method = 0;        // 0 source-origin, 1 listener-origin
     RprEstimateParams ep{0, 3};
     std::vector<rpr::PairDesc> pairs;  // caller order
     rpr::PairDesc* d_pairs = nullptr;  // queue order (pairs, or chunks of pairs when interleaved)
@@ -52,15 +58,73 @@ struct RprBatch {
 namespace rpr {
 namespace {
 
+// The tuning cache: key -> (waves per CU, queue order, chunk rays).
+struct TuneChoice {
+    int waves_per_cu, order, chunk;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int>, std::pair<int, int>> g_tune_cache;
+std::map<std::string, TuneChoice> g_tune_cache;
+bool g_tune_file_read = false;
 
-constexpr int64_t kInterleaveChunk = 1024;
+constexpr int kChunkChoices[3] = {256, 1024, 4096};
+
+int ilog2(double x) { return x >= 1.0 ? (int)std::floor(std::log2(x)) : 0; }
+
+// What a launch shape's speed depends on: the device (architecture, CUs), the
+// kernel variant (method, bands, stack variant), the per-ray work (bins, SH
+// coefficients, mean bounces, scene size) and the amount of work (pairs,
+// total rays), the continuous ones as log2 buckets.
+std::string tune_key(int device, const RprBatch& b, int64_t max_tris)
+{
+    hipDeviceProp_t prop;
+    const char* arch = hipGetDeviceProperties(&prop, device) == hipSuccess ? prop.gcnArchName : "unknown";
+    double bounces = 0.0;
+    for (const auto& d : b.pairs) bounces += (double)d.n_rays * (d.max_bounces + 1);
+    bounces /= (double)std::max<int64_t>(1, b.total);
+    char buf[256];
+    std::snprintf(buf, sizeof(buf), "%s/cu%d/m%d/nb%d/T%d/nc%d/st%d/p%d/r%d/k%d/t%d", arch, device_cu_count(),
+                  b.method, b.nb, b.T, b.nc, b.stack_need <= 32 ? 32 : 64, ilog2(b.n_pairs), ilog2((double)b.total),
+                  ilog2(bounces), ilog2((double)max_tris));
+    std::string k(buf);
+    for (char& c : k)
+        if (c == ' ') c = '_';
+    return k;
+}
+
+// Read the file cache once (lines: key waves order chunk); called with g_tune_mu held.
+void tune_file_read()
+{
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const char* path = std::getenv("RPR_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int w, o, c;
+    while (std::fscanf(f, "%255s %d %d %d", key, &w, &o, &c) == 4)
+        if (w >= 1 && o >= 0 && o <= 2 && (c == 256 || c == 1024 || c == 4096)) g_tune_cache[key] = TuneChoice{w, o, c};
+    std::fclose(f);
+}
+
+// Rewrite the file cache with every known choice; called with g_tune_mu held.
+void tune_file_write()
+{
+    const char* path = std::getenv("RPR_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto& kv : g_tune_cache)
+        std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.waves_per_cu, kv.second.order, kv.second.chunk);
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
+}
 
 // Upload the pair table in queue order `ord` (indices into b.pairs): 0 as
 // given, 1 most rays x bounces first, 2 interleaved -- every pair split into
-// chunks of kInterleaveChunk rays, dealt round-robin across the pairs, so
-// that the resident waves work on many pairs' histograms at once instead of
+// chunks of b.chunk rays, dealt round-robin across the pairs, so that the
+// resident waves work on many pairs' histograms at once instead of
 // contending for the atomics of a few.  A chunk is a copy of its pair's
 // descriptor with its own ray range; the energy normalisation, outputs and
 // statistics stay the pair's.  The listener-origin kernel always takes a
@@ -80,10 +144,10 @@ int upload_order(RprBatch& b, int ord, hipStream_t st)
     if (ord != 2 && b.method == 1) {
         for (int i = 0; i < b.n_pairs; ++i) {
             const PairDesc& P = b.pairs[idx[i]];
-            for (int64_t o = 0; o < P.n_rays; o += kInterleaveChunk) {
+            for (int64_t o = 0; o < P.n_rays; o += b.chunk) {
                 PairDesc c = P;
                 c.ray_begin = P.ray_begin + o;
-                c.n_rays = std::min(kInterleaveChunk, P.n_rays - o);
+                c.n_rays = std::min(b.chunk, P.n_rays - o);
                 q.push_back(c);
             }
         }
@@ -96,7 +160,7 @@ int upload_order(RprBatch& b, int ord, hipStream_t st)
                 if (next[i] >= P.n_rays) continue;
                 PairDesc c = P;
                 c.ray_begin = P.ray_begin + next[i];
-                c.n_rays = std::min(kInterleaveChunk, P.n_rays - next[i]);
+                c.n_rays = std::min(b.chunk, P.n_rays - next[i]);
                 next[i] += c.n_rays;
                 q.push_back(c);
                 more = more || next[i] < P.n_rays;
@@ -197,14 +261,17 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     if (bp->n_bins < 1 || bp->sh_order < 0 || bp->sh_order > RPR_MAX_SH_ORDER || !(bp->bin_width_s > 0.f) ||
         !(bp->speed_of_sound > 0.f) || bp->waves_per_cu < 0 || bp->order < 0 || bp->order > 2 ||
         bp->tail_iters < 0 || bp->tail_iters > 100 || (bp->rt60_source != 0 && bp->rt60_source != 1) ||
-        (bp->rt60_source == 1 && !hist_late) || (bp->method != 0 && bp->method != 1))
+        (bp->rt60_source == 1 && !hist_late) || (bp->method != 0 && bp->method != 1) ||
+        (bp->chunk_rays != 0 && bp->chunk_rays != 256 && bp->chunk_rays != 1024 && bp->chunk_rays != 4096))
         return set_error(RPR_EINVAL, "batch_create: bad batch parameters");
     const int nb = scenes[0] ? scenes[0]->n_bands : 0;
     int stack_need = 1;
+    int64_t max_tris = 0;
     for (int i = 0; i < n_scenes; ++i) {
         if (!scenes[i]) return set_error(RPR_EINVAL, "batch_create: scene %d is null", i);
         if (scenes[i]->n_bands != nb) return set_error(RPR_EINVAL, "batch_create: scenes differ in band count");
         stack_need = std::max(stack_need, scenes[i]->stack_need);
+        max_tris = std::max(max_tris, scenes[i]->n_tris);
     }
     const int nc = (bp->sh_order + 1) * (bp->sh_order + 1);
     int64_t total = 0;
@@ -281,20 +348,23 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     // launch shape: cached, autotuned or as requested
     int rc = RPR_OK;
     b->info.n_candidates = 0;
+    b->info.from_cache = 0;
     if (bp->autotune) {
-        const int bucket = (int)std::floor(std::log2((double)total));
-        const auto key = std::make_tuple(b->device, n_pairs, bucket, stack_need <= 32 ? 32 : 64, b->method);
+        const std::string key = tune_key(b->device, *b, max_tris);
         bool cached = false;
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
+            tune_file_read();
             auto it = g_tune_cache.find(key);
             if (it != g_tune_cache.end()) {
-                b->waves_per_cu = it->second.first;
-                b->order = it->second.second;
+                b->waves_per_cu = std::min(it->second.waves_per_cu, max_wpc);
+                b->order = it->second.order;
+                b->chunk = it->second.chunk;
                 cached = true;
             }
         }
         if (cached) {
+            b->info.from_cache = 1;
             rc = upload_order(*b, b->order, st);
             if (rc != RPR_OK) return fail(rc);
         } else {
@@ -302,34 +372,41 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
             for (int w : {max_wpc / 4, max_wpc / 2, (3 * max_wpc) / 4, max_wpc})
                 if (w >= 1 && std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
             float best = 1e30f, worst = 0.f;
-            int best_w = max_wpc, best_o = 0;
+            TuneChoice pick{max_wpc, 0, 1024};
             for (int o = 0; o < 3; ++o) {
-                rc = upload_order(*b, o, st);
-                if (rc != RPR_OK) return fail(rc);
-                for (int w : widths) {
-                    b->waves_per_cu = w;
-                    float ms = 0.f;
-                    rc = time_shape(*b, st, 3, ms);
+                // the chunk size matters to the interleaved order and to the listener method's chunk table
+                const bool chunked = o == 2 || b->method == 1;
+                for (int ci = 0; ci < (chunked ? 3 : 1); ++ci) {
+                    b->chunk = chunked ? kChunkChoices[ci] : 1024;
+                    rc = upload_order(*b, o, st);
                     if (rc != RPR_OK) return fail(rc);
-                    ++b->info.n_candidates;
-                    worst = std::max(worst, ms);
-                    if (ms < best) {
-                        best = ms;
-                        best_w = w;
-                        best_o = o;
+                    for (int w : widths) {
+                        b->waves_per_cu = w;
+                        float ms = 0.f;
+                        rc = time_shape(*b, st, 3, ms);
+                        if (rc != RPR_OK) return fail(rc);
+                        ++b->info.n_candidates;
+                        worst = std::max(worst, ms);
+                        if (ms < best) {
+                            best = ms;
+                            pick = TuneChoice{w, o, (int)b->chunk};
+                        }
                     }
                 }
             }
             b->info.best_ms = best;
             b->info.worst_ms = worst;
-            b->waves_per_cu = best_w;
-            rc = upload_order(*b, best_o, st);
+            b->waves_per_cu = pick.waves_per_cu;
+            b->chunk = pick.chunk;
+            rc = upload_order(*b, pick.order, st);
             if (rc != RPR_OK) return fail(rc);
             std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tune_cache[key] = {best_w, best_o};
+            g_tune_cache[key] = pick;
+            tune_file_write();
         }
     } else {
         b->waves_per_cu = bp->waves_per_cu > 0 ? std::min(bp->waves_per_cu, max_wpc) : max_wpc;
+        b->chunk = bp->chunk_rays > 0 ? bp->chunk_rays : 1024;
         rc = upload_order(*b, bp->order, st);
         if (rc != RPR_OK) return fail(rc);
     }
@@ -359,6 +436,7 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     b->info.order = b->order;
     b->info.stack_need = stack_need;
     b->info.graph = b->exec ? 1 : 0;
+    b->info.chunk_rays = (int32_t)b->chunk;
     *out = b;
     return RPR_OK;
 }

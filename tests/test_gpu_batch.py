@@ -48,12 +48,12 @@ def _host(b):
             P.params_host(b.params))
 
 
-@pytest.mark.parametrize("order,wpc", [(0, 0), (1, 2)])
-def test_batch_equals_pairs_alone(setup, order, wpc):
+@pytest.mark.parametrize("order,wpc,chunk", [(0, 0, 0), (1, 2, 0), (2, 0, 256), (2, 5, 4096)])
+def test_batch_equals_pairs_alone(setup, order, wpc, chunk):
     import torch
     scenes, pairs = setup
     b = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=False, use_graph=False,
-                order=order, waves_per_cu=wpc)
+                order=order, waves_per_cu=wpc, chunk_rays=chunk)
     b.run()
     torch.cuda.synchronize()
     H, HL, st, prm = _host(b)
@@ -66,7 +66,7 @@ def test_batch_equals_pairs_alone(setup, order, wpc):
         assert st[i]["first_arrival_bin"] == a["stats"][0]["first_arrival_bin"]
     info = b.info()
     assert info["n_pairs"] == len(pairs) and info["total_rays"] == sum(p["n_rays"] for p in pairs)
-    assert info["order"] == order and info["graph"] == 0
+    assert info["order"] == order and info["graph"] == 0 and info["chunk_rays"] == (chunk or 1024)
     b.close()
 
 
@@ -79,7 +79,8 @@ def test_graph_replays_match_eager(setup):
     He, HLe, ste, pre = _host(eager)
     g = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=True, use_graph=True)
     info = g.info()
-    assert info["graph"] == 1 and info["n_candidates"] >= 2 and info["best_ms"] <= info["worst_ms"]
+    assert info["graph"] == 1
+    assert info["from_cache"] == 1 or (info["n_candidates"] >= 2 and info["best_ms"] <= info["worst_ms"])
     for rep in range(3):
         g.run()
         torch.cuda.synchronize()
@@ -112,3 +113,53 @@ def test_batch_rejects_bad_pairs(setup):
     bad = [dict(pairs[0], n_rays=0)]
     with pytest.raises(P.RprError):
         P.Batch(scenes, bad, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=False, use_graph=False)
+
+
+_CACHED_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1]); sys.path.insert(0, sys.argv[1] + "/tests")
+import torch
+import paper_1803_00430_amd as P
+import test_gpu_batch as TB
+scenes, pairs = TB._tune_case()
+b = P.Batch(scenes, pairs, n_bins=TB.T, sh_order=TB.NSH, bin_width_s=TB.DT, autotune=True, use_graph=False)
+print(json.dumps(b.info()))
+"""
+
+
+def _tune_case():
+    """A small batch over the tiny room, with a tuning key no other test uses."""
+    tiny = R.tiny_config()
+    scenes = [P.Scene.from_dict(tiny)]
+    pairs = [dict(scene=0, source=tiny["sources"][0], listener=tiny["listener"], radius=0.5, n_rays=700 + 300 * k,
+                  max_bounces=20, seed=77 + k, pair_id=k) for k in range(3)]
+    return scenes, pairs
+
+
+def test_autotune_cache_file(setup, tmp_path, monkeypatch):
+    """With RPR_AUTOTUNE_CACHE set, a tuned shape is written to the file
+    (one line per key) and a new process takes it from there without timing
+    any candidate."""
+    import json
+    import os
+    import subprocess
+    import sys
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("RPR_AUTOTUNE_CACHE", str(path))
+    scenes, pairs = _tune_case()
+    b = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=True, use_graph=False)
+    info = b.info()
+    b.close()
+    assert info["from_cache"] == 1 or info["n_candidates"] >= 8  # 4 widths x (1 + 1 + 3 chunk sizes)
+    lines = [l.split() for l in path.read_text().splitlines()]
+    assert lines and all(len(l) == 4 for l in lines)
+    mine = [l for l in lines if l[1:] == [str(info["waves_per_cu"]), str(info["order"]), str(info["chunk_rays"])]]
+    assert mine, (lines, info)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", _CACHED_CHILD, root], capture_output=True, text=True, timeout=300,
+                         env=dict(os.environ, RPR_AUTOTUNE_CACHE=str(path)))
+    assert out.returncode == 0, out.stderr[-2000:]
+    child = json.loads(out.stdout.strip().splitlines()[-1])
+    assert child["from_cache"] == 1 and child["n_candidates"] == 0
+    assert (child["waves_per_cu"], child["order"], child["chunk_rays"]) == \
+        (info["waves_per_cu"], info["order"], info["chunk_rays"])

@@ -90,10 +90,10 @@ def reference(setup):
     return out
 
 
-def _run_batch(scenes, pairs, method, order, wpc, use_graph=False):
+def _run_batch(scenes, pairs, method, order, wpc, chunk=0, use_graph=False):
     import torch
     b = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=False, use_graph=use_graph,
-                order=order, waves_per_cu=wpc, method=method)
+                order=order, waves_per_cu=wpc, method=method, chunk_rays=chunk)
     b.run()
     torch.cuda.synchronize()
     res = (b.hist.double().cpu().numpy(), b.hist_late.double().cpu().numpy(), P.stats_host(b.stats),
@@ -102,11 +102,11 @@ def _run_batch(scenes, pairs, method, order, wpc, use_graph=False):
     return res
 
 
-@pytest.mark.parametrize("method,order,wpc", [("source", 0, 0), ("source", 1, 2), ("source", 2, 0),
-                                              ("listener", 0, 0), ("listener", 2, 3)])
-def test_batch_pairs_match_oracle(setup, reference, method, order, wpc):
+@pytest.mark.parametrize("method,order,wpc,chunk", [("source", 0, 0, 0), ("source", 1, 2, 0), ("source", 2, 0, 256),
+                                                    ("listener", 0, 0, 0), ("listener", 2, 3, 4096)])
+def test_batch_pairs_match_oracle(setup, reference, method, order, wpc, chunk):
     dicts, scenes, pairs = setup
-    H, HL, st, prm = _run_batch(scenes, pairs, method, order, wpc)
+    H, HL, st, prm = _run_batch(scenes, pairs, method, order, wpc, chunk)
     refs = reference[method]
     # the source-origin trace follows the oracle's paths (FP64 ray state); the
     # listener-origin trace keeps an FP32 ray state and splits more often
