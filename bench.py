@@ -666,11 +666,13 @@ def run_paths(a):
 def run_city_frames(a):
     """City frames with moving sources: the 8 sources walk through the streets
     (3 m per 0.1 s frame, turning away from buildings), the listener stays.
-    Each frame is traced and estimated twice over the same walk: with the
-    workload's fixed 32,768 rays per source, and under a segment budget per
-    frame (Section 5), where the frame's ray count follows the previous
-    frame's segments per ray (`budget_ray_count`).  Reports the spread of the
-    per-frame segment counts and frame times of both."""
+    Each frame is traced and estimated three times over the same walk: with
+    the workload's fixed 32,768 rays per source; under a segment budget per
+    frame (Section 5) whose ray count follows the previous frame's segments
+    per ray (`budget_ray_count`, "predicted"); and under the same budget
+    applied within the frame by trace_ir (first pass of 16,384 rays per
+    source, then the rays that fill each source's share, "in_frame").
+    Reports the spread of the per-frame segment counts and frame times."""
     import torch
 
     import paper_1803_00430_amd as P
@@ -688,15 +690,19 @@ def run_city_frames(a):
     hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
     params = P.alloc_params(S, device=dev)
     res = {}
-    for mode in ("fixed", "budget"):
+    for mode in ("fixed", "predicted", "in_frame"):
         segs_l, rays_l, times = [], [], []
         prev_s = prev_r = 0
         for f in range(a.warmup + n_frames):
-            # budget_ray_count sees the frame's totals over the sources; every source gets an equal share
-            N = N0 if mode == "fixed" else P.budget_ray_count(a.segment_budget, prev_s, prev_r, S * 1024,
-                                                                S * 4 * N0, S * N0) // S
-            prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt,
-                                 seed=cfg["seed"] + f)
+            if mode == "in_frame":
+                prm = P.trace_params(n_rays_total=N0 // 2, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt,
+                                     seed=cfg["seed"] + f, segment_budget=a.segment_budget // S, max_rays=4 * N0)
+            else:
+                # budget_ray_count sees the frame's totals over the sources; every source gets an equal share
+                N = N0 if mode == "fixed" else P.budget_ray_count(a.segment_budget, prev_s, prev_r, S * 1024,
+                                                                    S * 4 * N0, S * N0) // S
+                prm = P.trace_params(n_rays_total=N, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt,
+                                     seed=cfg["seed"] + f)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             P.trace_ir(scene, walk[f], cfg["listener"], cfg["radius"], prm, hist, late, stats)
@@ -716,7 +722,7 @@ def run_city_frames(a):
                      "ms_mean": float(times_a.mean()), "ms_p99": float(np.percentile(times_a, 99)),
                      "ms_cv": float(times_a.std() / times_a.mean())}
         log(f"{mode}: {res[mode]}", q)
-    bud = res["budget"]
+    bud = res["in_frame"]
     out = {
         "metric": "city frames with moving sources: per-frame segments under a segment budget",
         "value": 1e3 / bud["ms_mean"], "unit": "frames/s", "n_gpus": 1, "steps": n_frames, "warmup": a.warmup,
@@ -726,7 +732,7 @@ def run_city_frames(a):
                                f"through the streets, {K} bounces, SH order {n}, {T} x 1 ms bins; fixed "
                                f"{N0} rays per source vs a budget of {a.segment_budget} segments per frame",
                    "segment_budget": a.segment_budget, "frames": n_frames},
-        "fixed": res["fixed"], "budget": bud,
+        "fixed": res["fixed"], "predicted": res["predicted"], "in_frame": bud,
     }
     scene.close()
     print(json.dumps(out), flush=True)

@@ -91,7 +91,21 @@ typedef struct {
     int32_t flags;        /* RPR_TRACE_* bits */
     int32_t waves_per_cu; /* launch width of the persistent trace: resident waves per compute unit
                              (0 = the library's default); results do not depend on it */
+    int64_t segment_budget; /* > 0: trace_ir chooses each source's ray count in the call (below) */
+    int64_t max_rays;       /* with segment_budget: most rays per source, >= ray_end */
 } RprTraceParams;
+
+/* Segment budget (Section 5: every frame traces the same number of ray path
+ * segments; rays that escape early leave budget for more primary rays).  With
+ * segment_budget = B > 0 (ray_begin = 0, n_rays_total = ray_end = N0), trace_ir
+ * traces rays [0, N0) of every source, then per source, from its own segment
+ * count S0 of those rays,
+ *     N' = clamp(N0 + floor((B - S0) * N0 / S0), N0, max_rays),
+ * traces rays [N0, N') as well (one more launch on the stream, no host
+ * round trip), and weights every ray of the source by 1/N' (the outputs are
+ * rescaled by N0 / N').  stats.n_rays = N'.  ray_hash, when given, holds
+ * max_rays entries per source (the first N' written).  B * max_rays must stay
+ * below 2^63.  Only trace_ir takes a budget. */
 
 /* RprTraceParams.flags: count BVH nodes visited and triangles tested into
  * RprIrStats.n_node_visits / n_tri_tests (a separate, slower kernel variant;

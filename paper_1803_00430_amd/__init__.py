@@ -48,7 +48,8 @@ class TraceParams(C.Structure):
     _fields_ = [("n_rays_total", C.c_int64), ("ray_begin", C.c_int64), ("ray_end", C.c_int64),
                 ("max_bounces", C.c_int32), ("sh_order", C.c_int32), ("n_bins", C.c_int32),
                 ("pair_base", C.c_int32), ("bin_width_s", C.c_float), ("speed_of_sound", C.c_float),
-                ("seed", C.c_uint64), ("flags", C.c_int32), ("waves_per_cu", C.c_int32)]
+                ("seed", C.c_uint64), ("flags", C.c_int32), ("waves_per_cu", C.c_int32),
+                ("segment_budget", C.c_int64), ("max_rays", C.c_int64)]
 
 
 TRACE_COUNT_VISITS = 1
@@ -312,10 +313,12 @@ class Scene:
 
 
 def trace_params(*, n_rays_total, max_bounces, sh_order, n_bins, bin_width_s, seed, ray_begin=0, ray_end=None,
-                 pair_base=0, speed_of_sound=343.0, flags=0, waves_per_cu=0) -> TraceParams:
+                 pair_base=0, speed_of_sound=343.0, flags=0, waves_per_cu=0, segment_budget=0,
+                 max_rays=0) -> TraceParams:
     return TraceParams(int(n_rays_total), int(ray_begin), int(n_rays_total if ray_end is None else ray_end),
                        int(max_bounces), int(sh_order), int(n_bins), int(pair_base), float(bin_width_s),
-                       float(speed_of_sound), int(seed), int(flags), int(waves_per_cu))
+                       float(speed_of_sound), int(seed), int(flags), int(waves_per_cu), int(segment_budget),
+                       int(max_rays))
 
 
 def alloc_trace_outputs(n_src, n_bins, n_bands, sh_order, n_rays=0, device="cuda", late=True, want_hash=False):

@@ -121,7 +121,8 @@ void workspace_free(Workspace& ws);
 // Launch the persistent trace over `n_pairs` descriptors already in device memory.
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
                  int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
-                 float* rec = nullptr, unsigned* rec_count = nullptr, int rec_cap = 0);
+                 float* rec = nullptr, unsigned* rec_count = nullptr, int rec_cap = 0,
+                 const long long* total_dev = nullptr);
 
 // Early-reflection path records (trace_ir_paths, path_cache_*): 32 words each,
 // words 0-1 the key (source << 48 | order << 46 | tri1 << 23 | tri2, 23-bit

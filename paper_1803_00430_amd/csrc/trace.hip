@@ -28,12 +28,15 @@ constexpr int kSetupChunk = 64;
 
 // REC: every deposit of an order-1 or order-2 segment also writes one early-reflection
 // path record of kRecWords words (see trace_ir_paths) at rec[slot], slot from *rec_count.
+// total_dev: when not null, the number of queue slots is read from it (a
+// count that an earlier kernel on the stream computed), else it is `total`.
 template <int NB, int STACK, bool COUNT, bool REC>
 __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pairs, int n_pairs,
                                                  unsigned long long* __restrict__ queue, long long total,
                                                  float* __restrict__ rec, unsigned* __restrict__ rec_count,
-                                                 int rec_cap)
+                                                 int rec_cap, const long long* __restrict__ total_dev)
 {
+    if (total_dev) total = *total_dev;
     __shared__ int32_t stk[STACK * kWave];
     const int lane = threadIdx.x;
     const uint64_t lt = lanemask_lt(lane);
@@ -366,6 +369,7 @@ struct SetupArgs {
     PairDesc base;
     int s0, ns;
     long long rays_per_src;
+    long long hash_stride;  // ray_hash entries per source
     long long hist_stride, late_stride;
     float src[kSetupChunk][3];
     unsigned long long* queue;
@@ -386,9 +390,65 @@ __global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
     d.hist = a.base.hist + (size_t)s * a.hist_stride;
     d.hist_late = a.base.hist_late ? a.base.hist_late + (size_t)s * a.late_stride : nullptr;
     d.stats = a.base.stats + s;
-    d.ray_hash = a.base.ray_hash ? a.base.ray_hash + (size_t)s * a.rays_per_src : nullptr;
+    d.ray_hash = a.base.ray_hash ? a.base.ray_hash + (size_t)s * a.hash_stride : nullptr;
     out[s] = d;
     stats_init(d.stats);
+}
+
+// Segment budget, second pass: from each source's segment count of the
+// first N0 rays, its ray count N' = clamp(N0 + floor((B - S0) N0 / S0), N0,
+// max_rays); the pair table is rewritten in place to describe rays [N0, N')
+// of every source (queue slots in source order), the queue counter cleared
+// and the slot total stored for the second launch.  One thread.
+__global__ void k_budget_plan(PairDesc* __restrict__ pairs, int n_src, long long budget, long long n0,
+                              long long max_rays, unsigned long long* __restrict__ queue,
+                              long long* __restrict__ total_dev)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    long long run = 0;
+    for (int s = 0; s < n_src; ++s) {
+        PairDesc& d = pairs[s];
+        const long long s0 = (long long)d.stats->n_segments;
+        // floor((B - S0) N0 / S0); none when the first pass already reached the budget
+        long long dn = (s0 > 0 && budget > s0) ? (budget - s0) * n0 / s0 : 0;
+        dn = dn > max_rays - n0 ? max_rays - n0 : dn;
+        d.ray_begin = n0;
+        d.n_rays = dn;
+        d.queue_begin = run;
+        if (d.ray_hash) d.ray_hash += n0;
+        run += dn;
+    }
+    *queue = 0ull;
+    *total_dev = run;
+}
+
+// Segment budget, last step: every ray was emitted with 1/N0 of the energy;
+// source s traced N' = N0 + n_rays (pass 2) rays, so its histograms and
+// energy statistics are scaled by N0 / N'.  Grid (chunks, sources).
+__global__ void k_budget_scale(const PairDesc* __restrict__ pairs, long long n0, long long hist_n, long long late_n,
+                               int nb)
+{
+    const PairDesc& d = pairs[blockIdx.y];
+    const double scale = (double)n0 / (double)(n0 + d.n_rays);
+    const float fs = (float)scale;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < hist_n; i += stride) d.hist[i] *= fs;
+    if (d.hist_late)
+        for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < late_n; i += stride)
+            d.hist_late[i] *= fs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        RprIrStats* S = d.stats;
+        S->e_emitted *= scale;
+        for (int b = 0; b < nb; ++b) {
+            S->e_class[0][b] *= scale;
+            S->e_class[1][b] *= scale;
+            S->e_class[2][b] *= scale;
+            S->e_escaped[b] *= scale;
+            S->e_alive_at_stop[b] *= scale;
+            S->e_alive_at_bounce_cap[b] *= scale;
+            S->e_absorbed[b] *= scale;
+        }
+    }
 }
 
 __global__ void k_stats_reset(RprIrStats* __restrict__ stats, int n, unsigned long long* __restrict__ queue)
@@ -442,7 +502,8 @@ __global__ void k_debug_sh(const float* __restrict__ dirs, long long n, int orde
 }
 
 // ---------------------------------------------------------------- launch helpers
-using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long, float*, unsigned*, int);
+using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long, float*, unsigned*, int,
+                         const long long*);
 
 template <int NB, int STACK, bool COUNT, bool REC = false>
 TraceFn trace_fn()
@@ -547,8 +608,9 @@ int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hip
 
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,
                  int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
-                 float* rec, unsigned* rec_count, int rec_cap)
+                 float* rec, unsigned* rec_count, int rec_cap, const long long* total_dev)
 {
+    // with total_dev, total_rays is the most slots the launch may find there (it sizes the grid)
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
     int rc = ensure_variants();
     if (rc != RPR_OK) return rc;
@@ -559,7 +621,7 @@ int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_que
     const long long need = (total_rays + kWave - 1) / kWave;
     grid = std::max(1ll, std::min(grid, need));
     hipLaunchKernelGGL(v.fn, dim3((unsigned)grid), dim3(kWave), 0, stream, d_pairs, n_pairs, d_queue,
-                       (long long)total_rays, rec, rec_count, rec_cap);
+                       (long long)total_rays, rec, rec_count, rec_cap, total_dev);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }
@@ -621,6 +683,18 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     if (p->max_bounces < 0) return set_error(RPR_EINVAL, "trace_ir: max_bounces < 0");
     if (p->waves_per_cu < 0) return set_error(RPR_EINVAL, "trace_ir: waves_per_cu < 0");
     if (p->n_rays_total < 1) return set_error(RPR_EINVAL, "trace_ir: n_rays_total < 1");
+    const bool budget = p->segment_budget > 0;
+    if (p->segment_budget < 0) return set_error(RPR_EINVAL, "trace_ir: segment_budget < 0");
+    if (budget) {
+        if (rec || ws) return set_error(RPR_EINVAL, "trace_ir: a segment budget is taken by trace_ir only");
+        if (p->ray_begin != 0 || p->ray_end != p->n_rays_total)
+            return set_error(RPR_EINVAL, "trace_ir: with a segment budget, ray_begin = 0 and ray_end = n_rays_total");
+        if (p->max_rays < p->ray_end || p->max_rays > ((int64_t)1 << 32))
+            return set_error(RPR_EINVAL, "trace_ir: max_rays must be in [ray_end, 2^32]");
+        if (p->segment_budget > INT64_MAX / p->max_rays)
+            return set_error(RPR_EINVAL, "trace_ir: segment_budget x max_rays overflows 64 bits");
+        if (n_src > 65535) return set_error(RPR_EINVAL, "trace_ir: a segment budget takes at most 65535 sources");
+    }
     if (p->ray_begin < 0 || p->ray_end < p->ray_begin || p->ray_end > ((int64_t)1 << 32))
         return set_error(RPR_EINVAL, "trace_ir: bad ray range [%lld, %lld)", (long long)p->ray_begin,
                          (long long)p->ray_end);
@@ -684,6 +758,7 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     d.stats = stats;
     d.ray_hash = ray_hash;
     a.rays_per_src = R;
+    a.hash_stride = budget ? p->max_rays : R;
     a.hist_stride = (long long)hist_stride;
     a.late_stride = (long long)late_stride;
     a.queue = d_queue;
@@ -703,9 +778,23 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
                            hist_late, nl, 0.0f);
     }
     RPR_HIP_TRY(hipGetLastError());
-    return launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need,
-                        (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec, p->waves_per_cu, 0, st, rec, rec_count,
-                        rec_cap);
+    const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;
+    int rc = launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need, count, p->waves_per_cu, 0, st,
+                          rec, rec_count, rec_cap);
+    if (rc != RPR_OK || !budget) return rc;
+    // segment budget: plan the second pass on the device from the first pass's
+    // segment counts, trace it, and rescale every source to 1/N' per ray
+    long long* d_total = (long long*)((char*)ws + 64);
+    hipLaunchKernelGGL(k_budget_plan, dim3(1), dim3(kWave), 0, st, d_pairs, n_src, (long long)p->segment_budget,
+                       (long long)R, (long long)p->max_rays, d_queue, d_total);
+    RPR_HIP_TRY(hipGetLastError());
+    rc = launch_trace(d_pairs, n_src, d_queue, (p->max_rays - R) * n_src, nb, scene->stack_need, count,
+                      p->waves_per_cu, 0, st, nullptr, nullptr, 0, d_total);
+    if (rc != RPR_OK) return rc;
+    hipLaunchKernelGGL(k_budget_scale, dim3(64, (unsigned)n_src), dim3(256), 0, st, d_pairs, (long long)R,
+                       (long long)hist_stride, hist_late ? (long long)late_stride : 0ll, nb);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
 }
 
 }  // namespace
