@@ -7,10 +7,12 @@ size one ray can carry most of a row (a reflection close to a source ball),
 and its FP32 arrival time drifts from the FP64 one by about 6e-6 relative
 (0.7 mm over 124 m and 8 segments, measured) without any change of its hit
 sequence; there cells also get the timing allowance of
-`assert_hist_close(time_rel=1e-5)`, while row sums keep the 1e-4 bar.  Rays whose
-discrete path differs between FP32 and FP64 (hit triangles, bounce kinds,
-and here also the outcome of every occlusion query) are traced again alone
-on both sides and removed; each test states the fraction it allows."""
+`assert_hist_close(time_rel=1e-5)`, while row sums keep the 1e-4 bar.  These
+kernels keep an FP32 ray state; the closest hit of each segment is still
+decided by the FP64 triangle test.  Rays whose discrete path differs between
+the two sides (hit triangles, bounce kinds, and here also the outcome of
+every occlusion query) are traced again alone on both sides and removed;
+each test allows 0.5% and states what was measured."""
 import math
 
 import numpy as np
@@ -48,7 +50,7 @@ def test_listener_tiny_parity(torch_cuda):
     kw = _tiny_kw(c)
     g, o, div = traced_listener_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
     print(f"divergent rays: {len(div)} of {c['n_rays']}")
-    assert len(div) <= 0.02 * c["n_rays"], len(div)
+    assert len(div) <= 0.005 * c["n_rays"], len(div)  # measured 4 of 4096
     assert_hist_close(g["hist"][0], o["hist"][0])
     assert_hist_close(g["hist_late"][0], o["hist_late"][0], what="hist_late")
     assert_stats_close(g["cmp_stats"][0], o["cmp_stats"][0])
@@ -74,7 +76,7 @@ def test_listener_ragged_multisource_parity(torch_cuda):
               pair_base=9)
     g, o, div = traced_listener_pair(sc, sd, srcs, lst, 0.6, **kw)
     print(f"divergent rays: {len(div)} of 1000")
-    assert len(div) <= 0.15 * 1000, len(div)
+    assert len(div) <= 0.005 * 1000, len(div)  # measured 0 of 1000
     for s in range(3):
         assert_hist_close(g["hist"][s], o["hist"][s], what=f"hist[{s}]")
         assert_hist_close(g["hist_late"][s], o["hist_late"][s], what=f"hist_late[{s}]")
@@ -162,7 +164,7 @@ def test_listener_batch_matches_single_pairs(torch_cuda):
     kw = dict(n_rays_total=p["n_rays"], max_bounces=p["max_bounces"], sh_order=n, n_bins=T, bin_width_s=dt,
               seed=p["seed"], pair_base=p["pair_id"])
     g, o, div = traced_listener_pair(scenes[0], rooms[0], p["source"][None], p["listener"], p["radius"], **kw)
-    assert len(div) <= 0.02 * p["n_rays"]
+    assert len(div) <= 0.005 * p["n_rays"]  # measured 0 of 333
     assert_hist_close(g["hist"][0], o["hist"][0])
     b.close()
 
@@ -179,7 +181,7 @@ def test_listener_city_full_size_ray_subset(torch_cuda):
               sh_order=c["sh_order"], n_bins=c["n_bins"], bin_width_s=c["bin_width_s"], seed=c["seed"])
     g, o, div = traced_listener_pair(sc, c, c["sources"], c["listener"], c["radius"], **kw)
     print(f"divergent rays: {len(div)} of 2048")
-    assert len(div) <= 0.05 * 2048, len(div)
+    assert len(div) <= 0.005 * 2048, len(div)  # measured 0 of 2048
     for s in range(8):
         Hg, Ho = g["hist"][s], o["hist"][s]
         row = np.abs(Ho).sum(0)
