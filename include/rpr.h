@@ -111,6 +111,14 @@ typedef struct {
  * RprIrStats.n_node_visits / n_tri_tests (a separate, slower kernel variant;
  * the counts size the traversal's memory traffic). */
 #define RPR_TRACE_COUNT_VISITS 1
+/* RprTraceParams.flags: accumulate the histograms in 64-bit fixed point
+ * (every deposit rounded to a multiple of 2^-61 x the largest sum a cell can
+ * reach, 4 x n_bands x bin_width / sphere volume), so that the histograms do
+ * not depend on the order in which the deposits land: repeated calls, any
+ * launch width and graph replays give bit-identical histograms and RT60.
+ * Source-origin trace only (trace_ir without paths); the library holds the
+ * 8-byte cells in the scene's workspace. */
+#define RPR_TRACE_DETERMINISTIC 2
 
 /* Per-IR trace statistics (device, written by trace_ir). */
 typedef struct {
@@ -349,6 +357,8 @@ typedef struct {
                              a ball of the pair's radius (trace_listener, one source per pair) */
     int32_t chunk_rays;   /* rays per chunk of the interleaved order and of the listener method's
                              chunk table when autotune = 0: 256, 1024 or 4096 (0 = 1024) */
+    int32_t deterministic; /* 1: histograms accumulated as RPR_TRACE_DETERMINISTIC (method 0 only;
+                              the batch holds the fixed-point cells) */
 } RprBatchParams;
 
 typedef struct {

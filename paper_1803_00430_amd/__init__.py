@@ -53,6 +53,7 @@ class TraceParams(C.Structure):
 
 
 TRACE_COUNT_VISITS = 1
+TRACE_DETERMINISTIC = 2
 
 
 class EstimateParams(C.Structure):
@@ -75,7 +76,8 @@ class BatchParams(C.Structure):
     _fields_ = [("n_bins", C.c_int32), ("sh_order", C.c_int32), ("bin_width_s", C.c_float),
                 ("speed_of_sound", C.c_float), ("rt60_source", C.c_int32), ("tail_iters", C.c_int32),
                 ("autotune", C.c_int32), ("use_graph", C.c_int32), ("waves_per_cu", C.c_int32),
-                ("order", C.c_int32), ("method", C.c_int32), ("chunk_rays", C.c_int32)]
+                ("order", C.c_int32), ("method", C.c_int32), ("chunk_rays", C.c_int32),
+                ("deterministic", C.c_int32)]
 
 
 METHODS = {"source": 0, "listener": 1}
@@ -472,7 +474,7 @@ class Batch:
 
     def __init__(self, scenes, pairs, *, n_bins, sh_order, bin_width_s, speed_of_sound=343.0, rt60_source=None,
                  tail_iters=3, autotune=True, use_graph=True, waves_per_cu=0, order=0, late=True, device="cuda",
-                 stream=None, method="source", chunk_rays=0):
+                 stream=None, method="source", chunk_rays=0, deterministic=False):
         import torch
         if rt60_source is None:
             rt60_source = 1 if late else 0
@@ -495,7 +497,7 @@ class Batch:
         self.params = alloc_params(n, device=device)
         bp = BatchParams(int(n_bins), int(sh_order), float(bin_width_s), float(speed_of_sound), int(rt60_source),
                          int(tail_iters), int(bool(autotune)), int(bool(use_graph)), int(waves_per_cu), int(order),
-                         METHODS[method], int(chunk_rays))
+                         METHODS[method], int(chunk_rays), int(bool(deterministic)))
         handles = (C.c_void_p * len(self.scenes))(*[sc.handle.value for sc in self.scenes])
         h = C.c_void_p()
         _check(lib().batch_create(handles, len(self.scenes), arr, n, C.byref(bp), _ptr(self.hist),

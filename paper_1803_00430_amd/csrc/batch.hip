@@ -50,6 +50,8 @@ struct RprBatch {
     float* hist_late = nullptr;
     RprIrStats* stats = nullptr;
     RprReverbParams* params = nullptr;
+    long long* fx = nullptr;       // fixed-point cells [n_pairs][T][B][NC] then [n_pairs][T][B] (deterministic)
+    double* fx_scales = nullptr;   // device [n_pairs]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     RprBatchInfo info{};
@@ -194,6 +196,11 @@ int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t
     if (rc != RPR_OK) return rc;
     rc = enqueue_fill_zero(b.hist, (size_t)b.n_pairs * b.T * b.nb * b.nc, st);
     if (rc != RPR_OK) return rc;
+    const size_t hn = (size_t)b.n_pairs * b.T * b.nb * b.nc, ln = b.hist_late ? (size_t)b.n_pairs * b.T * b.nb : 0;
+    if (b.fx) {
+        rc = enqueue_fill_zero((float*)b.fx, 2 * (hn + ln), st);  // zero bits, as floats
+        if (rc != RPR_OK) return rc;
+    }
     if (b.hist_late) {
         rc = enqueue_fill_zero(b.hist_late, (size_t)b.n_pairs * b.T * b.nb, st);
         if (rc != RPR_OK) return rc;
@@ -205,6 +212,12 @@ int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t
              : launch_trace(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_need, false, b.waves_per_cu, 0,
                             st);
     if (rc != RPR_OK) return rc;
+    if (b.fx) {
+        rc = enqueue_fx_convert(b.fx, b.hist, (long long)b.T * b.nb * b.nc, b.n_pairs, b.fx_scales, 0.0, st);
+        if (rc == RPR_OK && b.hist_late)
+            rc = enqueue_fx_convert(b.fx + hn, b.hist_late, (long long)b.T * b.nb, b.n_pairs, b.fx_scales, 0.0, st);
+        if (rc != RPR_OK) return rc;
+    }
     if (t1) RPR_HIP_TRY(hipEventRecord(t1, st));
     return estimate_reverb(b.hist, b.hist_late, b.stats, b.n_pairs, b.T, b.nb, b.sh_order, b.dt, &b.ep, b.params,
                            st);
@@ -242,6 +255,8 @@ void batch_free(RprBatch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_pairs) (void)hipFree(b->d_pairs);
     if (b->d_queue) (void)hipFree(b->d_queue);
+    if (b->fx) (void)hipFree(b->fx);
+    if (b->fx_scales) (void)hipFree(b->fx_scales);
     delete b;
 }
 
@@ -262,7 +277,8 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         !(bp->speed_of_sound > 0.f) || bp->waves_per_cu < 0 || bp->order < 0 || bp->order > 2 ||
         bp->tail_iters < 0 || bp->tail_iters > 100 || (bp->rt60_source != 0 && bp->rt60_source != 1) ||
         (bp->rt60_source == 1 && !hist_late) || (bp->method != 0 && bp->method != 1) ||
-        (bp->chunk_rays != 0 && bp->chunk_rays != 256 && bp->chunk_rays != 1024 && bp->chunk_rays != 4096))
+        (bp->chunk_rays != 0 && bp->chunk_rays != 256 && bp->chunk_rays != 1024 && bp->chunk_rays != 4096) ||
+        (bp->deterministic != 0 && bp->deterministic != 1) || (bp->deterministic && bp->method != 0))
         return set_error(RPR_EINVAL, "batch_create: bad batch parameters");
     const int nb = scenes[0] ? scenes[0]->n_bands : 0;
     int stack_need = 1;
@@ -339,6 +355,24 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         batch_free(b);
         return code;
     };
+    if (bp->deterministic) {
+        // fixed-point cells and each pair's scale: 2^61 x sphere volume / (4 x bands x bin width)
+        const size_t cells = (size_t)n_pairs * hstride + (hist_late ? (size_t)n_pairs * lstride : 0);
+        if (hipMalloc(&b->fx, sizeof(long long) * cells) != hipSuccess ||
+            hipMalloc(&b->fx_scales, sizeof(double) * n_pairs) != hipSuccess)
+            return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
+        std::vector<double> scales(n_pairs);
+        for (int i = 0; i < n_pairs; ++i) {
+            const double r = pairs[i].radius;
+            scales[i] = 0x1p61 * (4.0 / 3.0 * M_PI * r * r * r) / (4.0 * nb * (double)bp->bin_width_s);
+            PairDesc& d = b->pairs[i];
+            d.hist_fx = b->fx + (size_t)i * hstride;
+            d.late_fx = hist_late ? b->fx + (size_t)n_pairs * hstride + (size_t)i * lstride : nullptr;
+            d.fx_scale = scales[i];
+        }
+        if (hipMemcpy(b->fx_scales, scales.data(), sizeof(double) * n_pairs, hipMemcpyHostToDevice) != hipSuccess)
+            return fail(set_error(RPR_EDEVICE, "batch_create: copy failed"));
+    }
     if (hipMalloc(&b->d_queue, 256) != hipSuccess)
         return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
     if (device_cu_count() <= 0) return fail(set_error(RPR_EDEVICE, "batch_create: no device"));

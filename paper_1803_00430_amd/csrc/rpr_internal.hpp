@@ -86,6 +86,12 @@ struct PairDesc {
     float* hist_late;   // [T][B] or null
     RprIrStats* stats;
     uint32_t* ray_hash; // [n_rays] or null
+    // deterministic accumulation (RPR_TRACE_DETERMINISTIC): deposits are
+    // added as round(value x fx_scale) to 64-bit integer cells, whose sums do
+    // not depend on the order of the atomics, then converted to hist/hist_late
+    long long* hist_fx; // [T][B][NC] or null (float accumulation)
+    long long* late_fx; // [T][B] or null
+    double fx_scale;
 };
 
 struct Workspace {
@@ -115,8 +121,11 @@ struct RprScene {
 };
 
 namespace rpr {
-// Ensure the workspace holds `pairs` pair descriptors; returns RPR_OK or an error.
-int workspace_reserve(Workspace& ws, size_t pairs);
+// Ensure the workspace holds `pairs` pair descriptors, and fx_bytes of
+// fixed-point histogram cells from workspace_fx_offset(pairs) on; returns
+// RPR_OK or an error.
+int workspace_reserve(Workspace& ws, size_t pairs, size_t fx_bytes = 0);
+size_t workspace_fx_offset(size_t pairs);
 void workspace_free(Workspace& ws);
 // Launch the persistent trace over `n_pairs` descriptors already in device memory.
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
@@ -141,6 +150,10 @@ int device_cu_count();
 int trace_max_waves_per_cu(int nb, int stack_need);
 // Zero n floats (a kernel, so that it can be captured into a graph).
 int enqueue_fill_zero(float* p, size_t n, hipStream_t stream);
+// Fixed-point histogram cells to FP32: out[i] = fx[i] / scale of its pair
+// (scales[j] for pair j = i / per_pair, or `scale` when scales is null).
+int enqueue_fx_convert(const long long* fx, float* out, long long per_pair, int n_pairs, const double* scales,
+                       double scale, hipStream_t stream);
 // Initialise n statistics records and zero the ray queue counter.
 int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hipStream_t stream);
 }  // namespace rpr

@@ -193,8 +193,18 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                     const double dtau = hi - lo;
                     if (dtau > 0.0) {
                         const float fd = (float)dtau;
-                        if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * fd);
-                        if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * fd * inv_vs);
+                        if (P.hist_fx) {  // fixed point: the sum does not depend on the order of the adds
+                            const double fx = P.fx_scale;
+                            if (act)
+                                atomicAdd((unsigned long long*)(P.hist_fx + ((size_t)m * nb + b) * nc + ci),
+                                          (unsigned long long)__double2ll_rn((double)(val * fd) * fx));
+                            if (late)
+                                atomicAdd((unsigned long long*)(P.late_fx + (size_t)m * nb + b),
+                                          (unsigned long long)__double2ll_rn((double)(eb * fd * inv_vs) * fx));
+                        } else {
+                            if (act) unsafeAtomicAdd(hist + ((size_t)m * nb + b) * nc + ci, val * fd);
+                            if (late) unsafeAtomicAdd(hlate + (size_t)m * nb + b, eb * fd * inv_vs);
+                        }
                         if (base == 0) {
                             sum_dtau += dtau;
                             first_m = min(first_m, m);
@@ -391,6 +401,8 @@ __global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
     d.hist_late = a.base.hist_late ? a.base.hist_late + (size_t)s * a.late_stride : nullptr;
     d.stats = a.base.stats + s;
     d.ray_hash = a.base.ray_hash ? a.base.ray_hash + (size_t)s * a.hash_stride : nullptr;
+    d.hist_fx = a.base.hist_fx ? a.base.hist_fx + (size_t)s * a.hist_stride : nullptr;
+    d.late_fx = a.base.late_fx ? a.base.late_fx + (size_t)s * a.late_stride : nullptr;
     out[s] = d;
     stats_init(d.stats);
 }
@@ -448,6 +460,19 @@ __global__ void k_budget_scale(const PairDesc* __restrict__ pairs, long long n0,
             S->e_alive_at_bounce_cap[b] *= scale;
             S->e_absorbed[b] *= scale;
         }
+    }
+}
+
+// Fixed-point histograms to FP32 (RPR_TRACE_DETERMINISTIC): out = fx / scale,
+// per_pair cells per pair, the scale of pair j scales[j] (or `scale` for all).
+__global__ void k_fx_convert(const long long* __restrict__ fx, float* __restrict__ out, long long per_pair,
+                             int n_pairs, const double* __restrict__ scales, double scale)
+{
+    const long long n = per_pair * n_pairs;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double sc = scales ? scales[i / per_pair] : scale;
+        out[i] = (float)((double)fx[i] / sc);
     }
 }
 
@@ -561,9 +586,11 @@ int device_cu_count()
     return g_cus;
 }
 
-int workspace_reserve(Workspace& ws, size_t pairs)
+size_t workspace_fx_offset(size_t pairs) { return (256 + sizeof(PairDesc) * (pairs ? pairs : 1) + 255) & ~(size_t)255; }
+
+int workspace_reserve(Workspace& ws, size_t pairs, size_t fx_bytes)
 {
-    const size_t need = 256 + sizeof(PairDesc) * (pairs ? pairs : 1);
+    const size_t need = fx_bytes ? workspace_fx_offset(pairs) + fx_bytes : 256 + sizeof(PairDesc) * (pairs ? pairs : 1);
     if (ws.bytes >= need) return RPR_OK;
     if (ws.dev) {
         RPR_HIP_TRY(hipDeviceSynchronize());
@@ -595,6 +622,17 @@ int enqueue_fill_zero(float* p, size_t n, hipStream_t stream)
     if (n == 0) return RPR_OK;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((n + 255) / 256, 16384)), dim3(256), 0, stream, p, n,
                        0.0f);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
+int enqueue_fx_convert(const long long* fx, float* out, long long per_pair, int n_pairs, const double* scales,
+                       double scale, hipStream_t stream)
+{
+    const long long n = per_pair * n_pairs;
+    if (n <= 0) return RPR_OK;
+    hipLaunchKernelGGL(k_fx_convert, dim3((unsigned)std::min<long long>((n + 255) / 256, 16384)), dim3(256), 0, stream,
+                       fx, out, per_pair, n_pairs, scales, scale);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }
@@ -684,6 +722,8 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     if (p->waves_per_cu < 0) return set_error(RPR_EINVAL, "trace_ir: waves_per_cu < 0");
     if (p->n_rays_total < 1) return set_error(RPR_EINVAL, "trace_ir: n_rays_total < 1");
     const bool budget = p->segment_budget > 0;
+    const bool det = (p->flags & RPR_TRACE_DETERMINISTIC) != 0;
+    if (det && (rec || ws)) return set_error(RPR_EINVAL, "trace_ir: deterministic accumulation is for trace_ir only");
     if (p->segment_budget < 0) return set_error(RPR_EINVAL, "trace_ir: segment_budget < 0");
     if (budget) {
         if (rec || ws) return set_error(RPR_EINVAL, "trace_ir: a segment budget is taken by trace_ir only");
@@ -715,9 +755,12 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     (void)window;
 
     hipStream_t st = (hipStream_t)hip_stream;
+    const int nb0 = scene->n_bands;
+    const int nc0 = (p->sh_order + 1) * (p->sh_order + 1);
+    const size_t fx_cells = det ? (size_t)n_src * p->n_bins * nb0 * (nc0 + (hist_late ? 1 : 0)) : 0;
     if (!ws) {
         RprScene* sc = const_cast<RprScene*>(scene);
-        const int rc = workspace_reserve(sc->ws, (size_t)n_src);
+        const int rc = workspace_reserve(sc->ws, (size_t)n_src, fx_cells * sizeof(long long));
         if (rc != RPR_OK) return rc;
         ws = sc->ws.dev;
     }
@@ -757,6 +800,17 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     d.hist_late = hist_late;
     d.stats = stats;
     d.ray_hash = ray_hash;
+    // fixed point: one cell can reach at most 4 x bands x bin width / sphere volume
+    // (a ray weighs at most bands x 1/n_rays_total, |Y| < 1, a chord overlaps a bin by at most its
+    // width, and a bin holds at most a few crossings per ray); 2^61 of that fits 64 bits
+    const double vs = 4.0 / 3.0 * M_PI * (double)lst->radius * lst->radius * lst->radius;
+    const double fx_scale = 0x1p61 * vs / (4.0 * nb * (double)p->bin_width_s);
+    if (det) {
+        long long* fx = (long long*)((char*)ws + workspace_fx_offset((size_t)n_src));
+        d.hist_fx = fx;
+        d.late_fx = hist_late ? fx + (size_t)n_src * hist_stride : nullptr;
+        d.fx_scale = fx_scale;
+    }
     a.rays_per_src = R;
     a.hash_stride = budget ? p->max_rays : R;
     a.hist_stride = (long long)hist_stride;
@@ -772,6 +826,12 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     const size_t nh = hist_stride * n_src;
     hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nh + 255) / 256, 16384)), dim3(256), 0, st, hist, nh,
                        0.0f);
+    if (det) {
+        float* fx0 = (float*)((char*)ws + workspace_fx_offset((size_t)n_src));
+        const size_t nf = fx_cells * 2;  // zero bits, as floats
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nf + 255) / 256, 16384)), dim3(256), 0, st, fx0,
+                           nf, 0.0f);
+    }
     if (hist_late) {
         const size_t nl = late_stride * n_src;
         hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nl + 255) / 256, 16384)), dim3(256), 0, st,
@@ -781,7 +841,16 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;
     int rc = launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need, count, p->waves_per_cu, 0, st,
                           rec, rec_count, rec_cap);
-    if (rc != RPR_OK || !budget) return rc;
+    if (rc != RPR_OK) return rc;
+    auto convert = [&]() -> int {
+        if (!det) return RPR_OK;
+        const long long* fx = (const long long*)((char*)ws + workspace_fx_offset((size_t)n_src));
+        int rc2 = enqueue_fx_convert(fx, hist, (long long)hist_stride, n_src, nullptr, fx_scale, st);
+        if (rc2 == RPR_OK && hist_late)
+            rc2 = enqueue_fx_convert(fx + nh, hist_late, (long long)late_stride, n_src, nullptr, fx_scale, st);
+        return rc2;
+    };
+    if (!budget) return convert();
     // segment budget: plan the second pass on the device from the first pass's
     // segment counts, trace it, and rescale every source to 1/N' per ray
     long long* d_total = (long long*)((char*)ws + 64);
@@ -790,6 +859,8 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     RPR_HIP_TRY(hipGetLastError());
     rc = launch_trace(d_pairs, n_src, d_queue, (p->max_rays - R) * n_src, nb, scene->stack_need, count,
                       p->waves_per_cu, 0, st, nullptr, nullptr, 0, d_total);
+    if (rc != RPR_OK) return rc;
+    rc = convert();
     if (rc != RPR_OK) return rc;
     hipLaunchKernelGGL(k_budget_scale, dim3(64, (unsigned)n_src), dim3(256), 0, st, d_pairs, (long long)R,
                        (long long)hist_stride, hist_late ? (long long)late_stride : 0ll, nb);
