@@ -197,8 +197,10 @@ int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const 
 
 /* trace_ir for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
- * arguments, results and errors as trace_ir, but the queue counter and the
- * pair table live in a static device array of the library (256 + 1,024 x 176
+ * arguments, results and errors as trace_ir (except that a segment budget and
+ * RPR_TRACE_DETERMINISTIC, which need more scratch, are refused with
+ * RPR_EINVAL), but the queue counter and the
+ * pair table live in a static device array of the library (256 + 1,024 x 200
  * bytes, one per GPU, held until the process ends) instead of the scene's
  * workspace, so the call allocates nothing on the host or the device.
  * Limit: n_src <= 1024 (RPR_EINVAL above).  Every call on one GPU shares that

@@ -110,7 +110,7 @@ def test_batch_pairs_match_oracle(setup, reference, method, order, wpc, chunk):
     refs = reference[method]
     # the source-origin trace follows the oracle's paths (FP64 ray state); the
     # listener-origin trace keeps an FP32 ray state and splits more often
-    max_div = 1e-3 if method == "source" else 0.05
+    max_div = 1e-3 if method == "source" else 5e-3
     assert sum(len(r["div"]) for r in refs) <= max_div * sum(p["n_rays"] for p in pairs)
     for i, (p, r) in enumerate(zip(pairs, refs)):
         o = r["o"]
