@@ -105,6 +105,10 @@ def parse():
     ap.add_argument("--convergence", action="store_true",
                     help="hospital: also trace frame 0 with two more independent seeds and report their mean "
                          "RT60 disagreement")
+    ap.add_argument("--reference", action="store_true",
+                    help="hospital: RT60 of the plain methods against a listener-origin reference traced twice "
+                         "with independent seeds (--ref-rays)")
+    ap.add_argument("--ref-rays", type=int, default=262144, help="hospital --reference: rays of each reference trace")
     ap.add_argument("--learned", action="store_true",
                     help="hospital: also run the learned estimator inline (trains it first on --learn-train "
                          "rooms), with a ray-trace fallback for uncertain sources")
@@ -738,6 +742,77 @@ def run_city_frames(a):
     print(json.dumps(out), flush=True)
 
 
+def run_hospital_reference(a):
+    """The hospital's accuracy question: is there a reference to judge the
+    plain methods against?  The listener-origin trace (next-event queries
+    toward every source ball, Section 5) is run twice at --ref-rays with
+    independent seeds; its seed-to-seed RT60 disagreement says whether it has
+    converged.  The source-origin trace at the workload's 131,072 rays per
+    source and the listener-origin trace at 65,536 rays are then scored
+    against the first reference: mean over sources x bands of
+    |RT60 - RT60_ref| / RT60_ref where the reference fit is valid, an invalid
+    estimate counting as error 1 (as in the learn workload)."""
+    import torch
+
+    import paper_1803_00430_amd as P
+    import rpr_scenes as R
+
+    q = a.quiet
+    dev = torch.device("cuda:0")
+    cfg = R.hospital_config()
+    scene = P.Scene.from_dict(cfg, device=dev)
+    S, K, T, n, dt = len(cfg["sources"]), cfg["max_bounces"], cfg["n_bins"], cfg["sh_order"], cfg["bin_width_s"]
+    B = cfg["absorption"].shape[1]
+    hist, late, stats, _ = P.alloc_trace_outputs(S, T, B, n, device=dev)
+    params = P.alloc_params(S, device=dev)
+
+    def run(method, rays, seed):
+        prm = P.trace_params(n_rays_total=rays, max_bounces=K, sh_order=n, n_bins=T, bin_width_s=dt, seed=seed)
+        t1 = time.perf_counter()
+        tr = P.trace_listener if method == "listener" else P.trace_ir
+        tr(scene, cfg["sources"], cfg["listener"], cfg["radius"], prm, hist, late, stats)
+        P.estimate_reverb(hist, late, stats, T, B, n, dt, params)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3
+        ph = P.params_host(params)
+        log(f"{method} {rays} rays seed {seed}: {ms:.0f} ms", q)
+        return ph["rt60"][:, :B].astype(np.float64), ph["rt60_range"][:, :B], ms
+
+    def err(rt, ref):
+        ok = ref > 0
+        e = np.where(rt > 0, np.abs(rt - ref) / np.where(ok, ref, 1.0), 1.0)[ok]
+        return {"mean": float(e.mean()), "p90": float(np.quantile(e, 0.9)), "valid_estimates": int((rt > 0).sum()),
+                "scored": int(ok.sum()), "of": int(ok.size)}
+
+    run("listener", 4096, 1)  # warm-up
+    ref_a, rng_a, ms_ref = run("listener", a.ref_rays, (1 << 36) + 1)
+    ref_b, rng_b, _ = run("listener", a.ref_rays, (1 << 36) + 2)
+    both = (ref_a > 0) & (ref_b > 0)
+    dis = np.abs(ref_a - ref_b)[both] / (0.5 * (ref_a + ref_b)[both])
+    same = both & (rng_a == rng_b)
+    dis_same = np.abs(ref_a - ref_b)[same] / (0.5 * (ref_a + ref_b)[same])
+    self_dis = {"mean": float(dis.mean()), "p90": float(np.quantile(dis, 0.9)), "valid_both": int(both.sum()),
+                "of": int(both.size), "same_fit_range": int(same.sum()),
+                "mean_where_same_range": float(dis_same.mean()) if same.any() else None,
+                "ranges_a": {str(k): int((rng_a == k).sum()) for k in range(-1, 4)}}
+    plain_src, _, ms_src = run("source", cfg["n_rays"], cfg["seed"])
+    plain_lst, _, ms_lst = run("listener", 65536, cfg["seed"] + 5)
+    res = {"reference_self_disagreement": self_dis,
+           "source_131072": dict(err(plain_src, ref_a), ms_per_frame=ms_src),
+           "listener_65536": dict(err(plain_lst, ref_a), ms_per_frame=ms_lst),
+           "reference_ms": ms_ref}
+    judged = self_dis["mean"] <= 0.05
+    out = {"metric": "hospital RT60 error against a listener-origin reference", "value": res["source_131072"]["mean"],
+           "unit": "relative RT60 error", "n_gpus": 1, "steps": 1, "warmup": 1, "higher_is_better": False,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"hospital: {len(cfg['tris'])} triangles, {S} sources at their frame-0 positions, "
+                                  f"{K} bounces, SH order {n}, {T} x 1 ms bins, late-only RT60; reference = "
+                                  f"listener-origin trace at {a.ref_rays} rays (two seeds)"},
+           "reference_converged_within_5pct": judged, **res}
+    scene.close()
+    print(json.dumps(out), flush=True)
+
+
 def run_hospital(a):
     """Large interactive scene: a hospital-like interior of ~1M triangles
     (rooms 4-12 m on a grid, corridors, doorways, clutter), 64 sources moving
@@ -984,7 +1059,10 @@ def main():
         run_learn(a)
         return
     if a.workload == "hospital":
-        run_hospital(a)
+        if a.reference:
+            run_hospital_reference(a)
+        else:
+            run_hospital(a)
         return
     if a.workload == "rooms":
         run_rooms(a)
