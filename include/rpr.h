@@ -151,7 +151,7 @@ typedef struct {
     int32_t n_degenerate; /* zero-area triangles (kept; never hit) */
     float bounds_lo[3];
     float bounds_hi[3];
-    int32_t stack_need;   /* traversal stack entries the deepest path can need (<= 64) */
+    int32_t stack_need;   /* traversal stack entries the deepest path can need (< 64) */
     int32_t reserved;
 } RprSceneInfo;
 
@@ -168,7 +168,7 @@ typedef struct {
  * Synchronises hip_stream (the build reads back validation flags and the tree
  * depth).  Errors: RPR_EINVAL for out-of-range indices or materials,
  * non-finite vertices, coefficients outside [0, 1]; RPR_EUNSUPPORTED if a
- * path of the tree could need more than the traversal stack (64 entries). */
+ * path of the tree could need 64 or more stack entries (the traversal takes 63). */
 int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                  const int32_t* tri_material, const float* absorption, const float* scattering,
                  int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out);

@@ -996,10 +996,11 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
             sc->lo[a] = unordered(hf.blo[a]);
             sc->hi[a] = unordered(hf.bhi[a]);
         }
-        if (sc->stack_need > kMaxStack)
+        // the traversal writes one slot past the deepest entry (a push without a branch)
+        if (sc->stack_need >= kMaxStack)
             return fail(set_error(RPR_EUNSUPPORTED,
-                                  "scene_create: BVH depth %d needs %d stack entries, more than the traversal's %d",
-                                  sc->max_depth, sc->stack_need, kMaxStack));
+                                  "scene_create: BVH depth %d needs %d stack entries, the traversal takes at most %d",
+                                  sc->max_depth, sc->stack_need, kMaxStack - 1));
     } else {
         BuildFlags hf;
         TRY(read_flags(arena, flags.p, st, &hf));

@@ -1098,7 +1098,7 @@ int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned
     if (total_rays <= 0 || n_chunks <= 0) return RPR_OK;
     int rc = ensure_lstp_variants();
     if (rc != RPR_OK) return rc;
-    const int bi = nb <= 4 ? 0 : 1, si = stack_need <= 32 ? 0 : 1;
+    const int bi = nb <= 4 ? 0 : 1, si = stack_need < 32 ? 0 : 1;
     const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, g_pper[bi][si]) : g_pper[bi][si];
     long long grid = (long long)device_cu_count() * per_cu;
     grid = std::max(1ll, std::min(grid, (long long)n_chunks));
@@ -1110,7 +1110,7 @@ int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned
 int trace_listener_max_waves_per_cu(int nb, int stack_need)
 {
     if (ensure_lstp_variants() != RPR_OK) return 1;
-    return g_pper[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1];
+    return g_pper[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1];
 }
 
 }  // namespace rpr
@@ -1212,7 +1212,7 @@ extern "C" int trace_listener(const RprScene* scene, const RprSource* srcs, int3
     }
     RPR_HIP_TRY(hipGetLastError());
     if (R > 0) {
-        const int bi = nb <= 4 ? 0 : 1, si = scene->stack_need <= 32 ? 0 : 1;
+        const int bi = nb <= 4 ? 0 : 1, si = scene->stack_need < 32 ? 0 : 1;
         const LstFn fn = g_lvar[bi][si].fn;
         const int NBv = bi == 0 ? 4 : 8;
         const size_t dyn = sizeof(double) * (size_t)n_src * 3 * NBv + sizeof(int) * 2 * (size_t)n_src;

@@ -170,9 +170,9 @@ __device__ __forceinline__ float4 gld(const float4* p)
 
 // ---------------------------------------------------------------- intersection
 // Slab test of one box against [0, tmax], with the plane distances formed as
-// lo * (1/d) - o * (1/d) (one fused multiply-add per plane; oi = o * (1/d));
-// tmax is widened by a few ulps so that flat boxes (axis-aligned walls) are
-// not lost to rounding.
+// lo * (1/d) - o * (1/d) (one fused multiply-add per plane; oi = o * (1/d)).
+// No box is flat: every leaf box is padded on all sides (see the build), so
+// a ray through an axis-aligned wall's box has tn < tf by the pad's width.
 __device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix, float hiy, float hiz,
                                      float oix, float oiy, float oiz, float ix, float iy, float iz, float tmax,
                                      float& tnear)
@@ -183,7 +183,7 @@ __device__ __forceinline__ bool slab(float lox, float loy, float loz, float hix,
     const float tn = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), 0.0f));
     const float tf = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
     tnear = tn;
-    return tn <= tf * 1.00000048f;
+    return tn <= tf;
 }
 
 // Moller-Trumbore in FP32 against a triangle record (v0, v1, v2), with the
@@ -321,12 +321,15 @@ __device__ __forceinline__ int closest_hit(const SceneView& sc, double ox, doubl
             cswap(t[1], l[1], t[3], l[3]);
             cswap(t[1], l[1], t[2], l[2]);
             if (t[0] < inf) {
-                // The stack holds what the deepest path can push (checked when
-                // the scene is built); a full stack would drop an entry rather
-                // than write out of bounds.
+                // Every slot is written and the pointer advances over the hit
+                // ones only (no branch per child): a write lands at most at
+                // the deepest entry a path can reach, which the build checks
+                // is below STACK (stack_need < STACK).
 #pragma unroll
-                for (int j = 3; j >= 1; --j)
-                    if (t[j] < inf && sp < STACK) stack[sp++ * kWave + lane] = l[j];
+                for (int j = 3; j >= 1; --j) {
+                    stack[sp * kWave + lane] = l[j];
+                    sp += t[j] < inf ? 1 : 0;
+                }
                 node = l[0];
             } else if (sp > 0) {
                 node = stack[--sp * kWave + lane];

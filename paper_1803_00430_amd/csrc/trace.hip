@@ -73,6 +73,11 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     bool first = true;
 
     for (;;) {
+        // A lane that takes a ray of another pair than the one its statistics
+        // hold needs them flushed; they change only at a bounce, so the flush
+        // waits until the refill is done (one call site keeps the kernel's
+        // register count down).
+        bool flush_req = false;
         // ------------------------------------------------ refill dead lanes
         if (!exhausted) {
             const uint64_t dead = __ballot(!alive);
@@ -96,7 +101,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                     r = (long long)(base + (unsigned long long)__popcll(dead & lt));
                     if (r < total) np = find_pair(pairs, n_pairs, r);
                 }
-                if (__ballot(np >= 0 && acc.p >= 0 && acc.p != np)) lane_acc_flush<NB, COUNT>(acc, pairs, lane);
+                flush_req = np >= 0 && acc.p >= 0 && acc.p != np;
                 if (np >= 0) {
                     const PairDesc& P = pairs[np];
                     p = np;
@@ -119,6 +124,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 }
             }
         }
+        if (__ballot(flush_req)) lane_acc_flush<NB, COUNT>(acc, pairs, lane);
         if (__ballot(alive) == 0) break;
 
         // ------------------------------------------------ closest hit
@@ -614,7 +620,7 @@ void workspace_free(Workspace& ws)
 int trace_max_waves_per_cu(int nb, int stack_need)
 {
     if (ensure_variants() != RPR_OK) return 1;
-    return g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][0].blocks_per_cu;
+    return g_var[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1][0].blocks_per_cu;
 }
 
 int enqueue_fill_zero(float* p, size_t n, hipStream_t stream)
@@ -652,8 +658,8 @@ int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_que
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
     int rc = ensure_variants();
     if (rc != RPR_OK) return rc;
-    const Variant& v = rec ? g_rec[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1]
-                           : g_var[nb <= 4 ? 0 : 1][stack_need <= 32 ? 0 : 1][count_visits ? 1 : 0];
+    const Variant& v = rec ? g_rec[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1]
+                           : g_var[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1][count_visits ? 1 : 0];
     const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, v.blocks_per_cu) : v.blocks_per_cu;
     long long grid = grid_override > 0 ? grid_override : (long long)g_cus * per_cu;
     const long long need = (total_rays + kWave - 1) / kWave;

@@ -93,7 +93,7 @@ def test_bvh_closest_hit_equals_brute_force(torch_cuda, kind):
     sd = _cluttered_room(3) if kind == "room" else _soup(4, 6000)
     sc = P.Scene.from_dict(sd)
     info = sc.info()
-    assert info["n_tris"] == len(sd["tris"]) and 0 < info["max_depth"] and 0 < info["stack_need"] <= 64
+    assert info["n_tris"] == len(sd["tris"]) and 0 < info["max_depth"] and 0 < info["stack_need"] < 64
     lo, hi = (np.zeros(3), sd["dims"]) if kind == "room" else (np.full(3, -25.0), np.full(3, 25.0))
     o, d = R.random_rays(5, 20000, lo + 0.01, hi - 0.01)
     t, tri = sc.closest_hit(o, d)
@@ -442,7 +442,7 @@ def test_bvh_at_one_million_triangles(torch_cuda):
     h = R.hospital_config()
     sc = P.Scene.from_dict(h)
     info = sc.info()
-    assert info["n_tris"] == len(h["tris"]) > 900_000 and info["stack_need"] <= 64
+    assert info["n_tris"] == len(h["tris"]) > 900_000 and info["stack_need"] < 64
     lo, hi = h["verts"].min(0), h["verts"].max(0)
     o, d = R.random_rays(9, 256, lo + 0.05, hi - 0.05)
     t, tri = sc.closest_hit(o, d)
