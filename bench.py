@@ -1220,7 +1220,10 @@ def main():
         # neighbouring steps, so they do not add up to ms_per_step)
         "breakdown_ms": {"build": float(np.mean(t_build)), "trace": trace_ms, "estimate": float(np.mean(t_est))},
         "trace_ray_bounces_per_s": segs / (trace_ms * 1e-3),
+        # every source's IR is traced and estimated each step; `valid_irs_per_s` counts only the IRs
+        # whose every band came back with a fit (see `estimates`)
         "irs_per_s": S / (ms_step * 1e-3),
+        "valid_irs_per_s": int(sum(((pg["status"][i][:B] & 7) == 0).all() for i in range(S))) / (ms_step * 1e-3),
         "segments_per_step": segs,
         # the fit needs a decay range: in the open city most listener spheres catch only a few
         # bins of energy from 32,768 source rays, and those estimates come back invalid (RT60 0)

@@ -156,8 +156,9 @@ typedef struct {
 } RprSceneInfo;
 
 /* Build a scene and its BVH (linear BVH: Morton codes of triangle centroids,
- * radix sort, hierarchy from longest common key prefixes, bottom-up bounds,
- * collapsed into 4-wide nodes for traversal).
+ * 30-bit, or 63-bit from 2^19 triangles on, radix sort, hierarchy from
+ * longest common key prefixes, bottom-up bounds, collapsed into 4-wide nodes
+ * for traversal).
  *   verts        device [n_verts][3] f32, metres
  *   tris         device [n_tris][3] i32 vertex indices
  *   tri_material device [n_tris] i32 in [0, n_materials), or NULL = material 0

@@ -1,6 +1,6 @@
 // Scene creation: material table, triangle records and a linear BVH.
 //
-// Linear BVH (Karras, HPG 2012): 30-bit Morton codes of the triangle
+// Linear BVH (Karras, HPG 2012): Morton codes (30-bit; 63-bit for large scenes) of the triangle
 // centroids in the scene's centroid bounds, a stable least-significant-digit
 // radix sort of (code, triangle) pairs, internal nodes from the longest common
 // prefixes of neighbouring codes (ties broken by the sorted index), and
@@ -23,6 +23,8 @@ constexpr int kBuildBlock = 256;
 constexpr int kPrepBlocks = 128;  // k_prep's grid cap (it strides over the triangles)
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kBuildBlock * kSortItems;
+// Scenes of at least this many triangles get 64-bit Morton keys (21 bits per axis).
+constexpr int64_t kWideKeyTris = (int64_t)1 << 19;
 
 // Validation flags, set by the prep kernel and read back by scene_create.
 enum : uint32_t {
@@ -199,21 +201,39 @@ __device__ __forceinline__ uint32_t spread3(uint32_t v)
     return v;
 }
 
-__global__ void k_morton(const float4* __restrict__ cent, int64_t nt, const BuildFlags* f,
-                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+// Spread the low 21 bits of v to every third bit.
+__device__ __forceinline__ uint64_t spread3_64(uint64_t v)
 {
+    v &= 0x1FFFFFull;
+    v = (v | (v << 32)) & 0x001F00000000FFFFull;
+    v = (v | (v << 16)) & 0x001F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Morton key of each centroid in the centroid bounds: 10 bits per axis in a
+// 32-bit key, or 21 bits per axis in a 64-bit key (large scenes, where 10
+// bits per axis leave triangles sharing a key).
+template <class K>
+__global__ void k_morton(const float4* __restrict__ cent, int64_t nt, const BuildFlags* f, K* __restrict__ keys,
+                         uint32_t* __restrict__ vals)
+{
+    constexpr int kBits = sizeof(K) == 4 ? 10 : 21;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
     const float4 c = cent[t];
     const float cc[3] = {c.x, c.y, c.z};
-    uint32_t code = 0;
+    K code = 0;
     for (int a = 0; a < 3; ++a) {
         const float lo = unordered(f->clo[a]), hi = unordered(f->chi[a]);
         const float ext = hi - lo;
         float u = ext > 0.0f ? (cc[a] - lo) / ext : 0.5f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
-        const uint32_t q = min((uint32_t)(u * 1024.0f), 1023u);
-        code |= spread3(q) << (2 - a);
+        const uint32_t q = min((uint32_t)(u * (float)(1u << kBits)), (1u << kBits) - 1u);
+        if constexpr (sizeof(K) == 4) code |= spread3(q) << (2 - a);
+        else code |= spread3_64(q) << (2 - a);
     }
     keys[t] = code;
     vals[t] = (uint32_t)t;
@@ -221,7 +241,8 @@ __global__ void k_morton(const float4* __restrict__ cent, int64_t nt, const Buil
 
 // ---------------------------------------------------------------- radix sort
 // Per-tile digit counts, stored digit-major: counts[d * n_tiles + tile].
-__global__ void __launch_bounds__(kBuildBlock) k_radix_count(const uint32_t* __restrict__ keys, int64_t n, int shift,
+template <class K>
+__global__ void __launch_bounds__(kBuildBlock) k_radix_count(const K* __restrict__ keys, int64_t n, int shift,
                                                              uint32_t* __restrict__ counts, int n_tiles)
 {
     __shared__ uint32_t h[256];
@@ -230,7 +251,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_radix_count(const uint32_t* __r
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t i = base + r * kBuildBlock + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
@@ -318,10 +339,11 @@ __global__ void __launch_bounds__(kBuildBlock) k_scan_apply(uint32_t* __restrict
 // Stable scatter: each tile is processed in rounds of 256 keys; within a
 // round, lanes of a wave with equal digits are matched by eight ballots and
 // ranked by position, and waves are ordered through per-digit counters.
-__global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
+template <class K>
+__global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const K* __restrict__ keys_in,
                                                                const uint32_t* __restrict__ vals_in, int64_t n,
                                                                int shift, const uint32_t* __restrict__ offsets,
-                                                               int n_tiles, uint32_t* __restrict__ keys_out,
+                                                               int n_tiles, K* __restrict__ keys_out,
                                                                uint32_t* __restrict__ vals_out, BuildFlags* bad)
 {
     constexpr int W = kBuildBlock / kWave;
@@ -338,9 +360,9 @@ __global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const uint32_t* _
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t i = base + r * kBuildBlock + tid;
         const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
+        const K key = valid ? keys_in[i] : (K)0;
         const uint32_t val = valid ? vals_in[i] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t d = (uint32_t)(key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
         for (int bit = 0; bit < 8; ++bit) {
             const uint64_t b = __ballot((d >> bit) & 1u);
@@ -373,19 +395,27 @@ __global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const uint32_t* _
 }
 
 // ---------------------------------------------------------------- hierarchy
-__device__ __forceinline__ int delta(const uint32_t* __restrict__ k, int n, int i, int j)
+// Length of the common prefix of keys i and j, extended by the indices' own
+// common prefix when the keys are equal (so every key is distinct); -1 out of range.
+template <class K>
+__device__ __forceinline__ int delta(const K* __restrict__ k, int n, int i, int j)
 {
     if (j < 0 || j >= n) return -1;
-    const uint32_t a = k[i], b = k[j];
-    if (a != b) return __clz(a ^ b);
-    return 32 + __clz((uint32_t)(i ^ j));
+    const K a = k[i], b = k[j];
+    constexpr int kKeyBits = 8 * (int)sizeof(K);
+    if (a != b) {
+        if constexpr (sizeof(K) == 4) return __clz(a ^ b);
+        else return __clzll((long long)(a ^ b));
+    }
+    return kKeyBits + __clz((uint32_t)(i ^ j));
 }
 
 // Internal node i covers a key range [min(i,j), max(i,j)] grown from i in the
 // direction of the neighbour with the longer common prefix; it splits where
 // the common prefix of the range ends.  parent[] indexes internal nodes
 // 0..n-2 then leaves n-1..2n-2.
-__global__ void k_karras(const uint32_t* __restrict__ keys, int n, int2* __restrict__ child,
+template <class K>
+__global__ void k_karras(const K* __restrict__ keys, int n, int2* __restrict__ child,
                          int32_t* __restrict__ parent, int2* __restrict__ range, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -837,6 +867,25 @@ void scan_exclusive(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st)
     hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBuildBlock), 0, st, data, len, nb > 1 ? sums : nullptr);
 }
 
+// Morton keys of the centroids and a stable LSD radix sort of (key, triangle)
+// pairs, eight bits per pass; the sorted pairs end in (k0, v0).
+template <class K>
+void morton_sort(const float4* cent, int64_t n, BuildFlags* flags, K* k0, K* k1, uint32_t* v0, uint32_t* v1,
+                 uint32_t* counts, uint32_t* sums, int n_tiles, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_morton<K>, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent, n, flags, k0, v0);
+    K *ki = k0, *ko = k1;
+    uint32_t *vi = v0, *vo = v1;
+    for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8) {
+        hipLaunchKernelGGL(k_radix_count<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n, shift, counts, n_tiles);
+        scan_exclusive(counts, (int64_t)256 * n_tiles, sums, st);
+        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, vi, n, shift, counts,
+                           n_tiles, ko, vo, flags);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+    }
+}
+
 }  // namespace
 }  // namespace rpr
 
@@ -894,7 +943,8 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
     TRY(hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * (size_t)(n > 1 ? n - 1 : 1)));
     DevBuf<float4> cent, box;
-    DevBuf<uint32_t> k0, v0, k1, v1, counts, seen, refs, even, idx4, scan_sums;
+    DevBuf<uint64_t> k0, k1;  // Morton keys: 32 or 64 bits each
+    DevBuf<uint32_t> v0, v1, counts, seen, refs, even, idx4, scan_sums;
     DevBuf<int32_t> ibox, parent;
     DevBuf<int2> child, range;
     DevBuf<float4> pyr;
@@ -930,26 +980,24 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         hipLaunchKernelGGL(k_prep, dim3(std::min(blocks(n, kBuildBlock), (unsigned)kPrepBlocks)), dim3(kBuildBlock), 0, st,
                            verts, n_verts, tris,
                            n_tris, tri_material, n_materials, cent.p, seen.p, refs.p, flags.p);
-        hipLaunchKernelGGL(k_morton, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent.p, n_tris,
-                           flags.p, k0.p, v0.p);
-        uint32_t *ki = k0.p, *vi = v0.p, *ko = k1.p, *vo = v1.p;
-        for (int shift = 0; shift < 32; shift += 8) {
-            hipLaunchKernelGGL(k_radix_count, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n_tris, shift, counts.p,
-                               n_tiles);
-            scan_exclusive(counts.p, (int64_t)256 * n_tiles, scan_sums.p, st);
-            hipLaunchKernelGGL(k_radix_scatter, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, vi, n_tris, shift,
-                               counts.p, n_tiles, ko, vo, flags.p);
-            std::swap(ki, ko);
-            std::swap(vi, vo);
-        }
-        // after four passes the sorted keys/ids are back in (k0, v0)
+        const bool wide = n >= kWideKeyTris;
+        if (wide) morton_sort<uint64_t>(cent.p, n_tris, flags.p, (uint64_t*)k0.p, (uint64_t*)k1.p, v0.p, v1.p, counts.p,
+                                        scan_sums.p, n_tiles, st);
+        else morton_sort<uint32_t>(cent.p, n_tris, flags.p, (uint32_t*)k0.p, (uint32_t*)k1.p, v0.p, v1.p, counts.p,
+                                   scan_sums.p, n_tiles, st);
+        uint32_t* vi = v0.p;
+        // after an even number of passes the sorted keys/ids are back in (k0, v0)
         TRY(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), st));
 
         hipLaunchKernelGGL(k_tri_records, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts,
                            n_verts, tris, tri_material, vi, n, sc->tris, box.p, seen.p, flags.p);
         if (n > 1) {
-            hipLaunchKernelGGL(k_karras, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, ki, n,
-                               child.p, parent.p, range.p, flags.p);
+            if (wide)
+                hipLaunchKernelGGL(k_karras<uint64_t>, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st,
+                                   (const uint64_t*)k0.p, n, child.p, parent.p, range.p, flags.p);
+            else
+                hipLaunchKernelGGL(k_karras<uint32_t>, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st,
+                                   (const uint32_t*)k0.p, n, child.p, parent.p, range.p, flags.p);
             hipLaunchKernelGGL(k_check_links, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
                                child.p, refs.p, flags.p);
             hipLaunchKernelGGL(k_check_refs, dim3(blocks(2 * (int64_t)n - 1, kBuildBlock)), dim3(kBuildBlock), 0,
