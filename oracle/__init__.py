@@ -96,6 +96,8 @@ def lib():
         L.orc_cone_batch.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, dp, C.c_double,
                                      C.c_int64, dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_surface_offset.argtypes = [C.c_double]
+        L.orc_get_surface_offset.restype = C.c_double
         L.orc_trace_path.argtypes = [dp, C.c_int64, C.POINTER(C.c_int32), C.POINTER(C.c_int32), dp, dp,
                                      C.c_int32, dp, C.c_uint64, C.c_uint32, C.c_uint32, C.c_int32, C.c_double,
                                      C.c_int32, dp, dp, dp, C.POINTER(C.c_int64)]
@@ -193,6 +195,24 @@ def stats_to_dict(st: IrStats, nb: int) -> dict:
         e_alive_at_bounce_cap=np.array(st.e_alive_at_bounce_cap[:nb]),
         e_absorbed=np.array(st.e_absorbed[:nb]), n_next_event=int(st.n_next_event),
     )
+
+
+class surface_offset:
+    """Context manager: trace with the reflected segment's start `metres` off
+    the surface instead of the 1 mm reading, then restore it.  For the tests
+    that follow the oracle to the limit of a vanishing offset."""
+
+    def __init__(self, metres: float):
+        self.metres = float(metres)
+
+    def __enter__(self):
+        self.prev = lib().orc_get_surface_offset()
+        lib().orc_set_surface_offset(self.metres)
+        return self
+
+    def __exit__(self, *exc):
+        lib().orc_set_surface_offset(self.prev)
+        return False
 
 
 def trace_ir(scene, sources, listener, radius, *, n_rays_total, ray_begin=0, ray_end=None,

@@ -40,8 +40,13 @@
 #define ORC_HASH_ESCAPE 0xFFFFFFFFu
 /* Reading (self-intersection; the paper does not discuss it): a reflected
  * segment starts 1 mm off the surface along the normal that faces the
- * incoming ray, and the triangle just hit is excluded from the next query. */
-#define ORC_SURFACE_OFFSET 1e-3
+ * incoming ray, and the triangle just hit is excluded from the next query.
+ * The offset is a variable only so that a test can trace the limit of a
+ * vanishing offset (orc_set_surface_offset); every other caller keeps 1 mm. */
+static double orc_surface_offset = 1e-3;
+
+void orc_set_surface_offset(double metres) { orc_surface_offset = metres; }
+double orc_get_surface_offset(void) { return orc_surface_offset; }
 /* early-reflection path record: [valid, order, tri1, tri2, e[8], t, d[16]] */
 #define ORC_REC_W 29
 #define ORC_REC_E 4
@@ -574,7 +579,7 @@ static int trace_core(const double *verts, int64_t n_verts, const int32_t *tris,
                     for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
                     h = fnv(h, 0u);
                 }
-                for (int i = 0; i < 3; ++i) o[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
+                for (int i = 0; i < 3; ++i) o[i] = x[i] + orc_surface_offset * nf[i];
                 last = tri;
             }
 #pragma omp atomic
@@ -854,7 +859,7 @@ int orc_trace_listener(const double *verts, int64_t n_verts, const int32_t *tris
             const double *al = absorption + (int64_t)mat * nb;
             const double *sc = scattering + (int64_t)mat * nb;
             double xo[3];
-            for (int i = 0; i < 3; ++i) xo[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
+            for (int i = 0; i < 3; ++i) xo[i] = x[i] + orc_surface_offset * nf[i];
             for (int b = 0; b < nb; ++b) f[b] = E[b] * (1.0 - al[b]) * sc[b];
             next_event(&X, ray, xo, nf, L, k, f, tri, Y0, &h, &nq);
             draw(p->seed, ray, X.pair, (uint32_t)k, u);
@@ -985,7 +990,7 @@ int orc_trace_path(const double *verts, int64_t n_tris, const int32_t *tris, con
             double dn = dot3(d, nf);
             for (int i = 0; i < 3; ++i) d[i] -= 2.0 * dn * nf[i];
         }
-        for (int i = 0; i < 3; ++i) o[i] = x[i] + ORC_SURFACE_OFFSET * nf[i];
+        for (int i = 0; i < 3; ++i) o[i] = x[i] + orc_surface_offset * nf[i];
         last = tri;
     }
     return n;
