@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
     ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
+    ap.add_argument("--learn-arch", choices=("dense", "tower"), default="tower",
+                    help="learn: one dense 12,864 -> 512 first layer, or the histogram through a 64-unit tower "
+                         "beside the statistics (reverb_model_set_tower)")
     ap.add_argument("--learn-views", type=int, default=4, help="1k-ray input traces per training room")
     ap.add_argument("--learn-target-rays", type=int, default=65536, help="rays of each training target trace")
     ap.add_argument("--learn-fallback", choices=("source", "listener"), default="listener",
@@ -302,7 +305,11 @@ def run_learn(a):
     sweep_l, n_star_l = plain_sweep("listener", (4096, 8192, 16384, 32768, 65536))
     fbm = a.learn_fallback
     n_fb = n_star_l if fbm == "listener" else n_star
-    model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    if a.learn_arch == "tower":
+        model = P.Model(P.LEARN_DIMS_TOWER, max_batch=256, seed=1)
+        model.set_tower(P.LEARN_DIMS_TOWER[0] - P.STAT_FEATURES, P.LEARN_TOWER)
+    else:
+        model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
     t0 = time.perf_counter()
     losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
     torch.cuda.synchronize()
@@ -344,7 +351,7 @@ def run_learn(a):
                                f"{a.learn_train} training rooms x {a.learn_views} inputs (100k rooms named for this "
                                f"workload), {a.learn_target_rays}-ray targets, 262,144-ray references",
                    "train_rooms": a.learn_train, "eval_rooms": n_ev, "views": a.learn_views,
-                   "target_rays": a.learn_target_rays},
+                   "target_rays": a.learn_target_rays, "arch": a.learn_arch, "dims": list(model.dims)},
         "plain": {"n_star": n_star, "irs_per_s": ips_plain, "sweep": {str(k): v for k, v in sweep.items()}},
         "plain_listener": {"n_star": n_star_l, "irs_per_s": ips_plain_l,
                            "sweep": {str(k): v for k, v in sweep_l.items()}},

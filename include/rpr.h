@@ -510,6 +510,17 @@ int reverb_model_forward(RprModel* model, const uint16_t* features, int64_t n, f
 int reverb_model_backward(RprModel* model, const uint16_t* features, int64_t n_rows, const int32_t* rows,
                           int32_t m, const float* t, const float* w, double* loss, void* hip_stream);
 int reverb_model_grads(const RprModel* model, float* grads, int64_t n, void* hip_stream);
+/* Two-tower layer 0: the first n_hist inputs (the histogram features) feed
+ * a tower of tower_width units, and the remaining S = dims[0] - n_hist inputs
+ * (the trace statistics) pass through unchanged as +s and -s, so that after
+ * the ReLU layer 1 sees [tower(histogram) | max(s, 0) | max(-s, 0)]; requires
+ * dims[1] = tower_width + 2 S and at least two layers.  The fixed entries of
+ * W_0 and b_0 (zeros, +-1) are written now, after every Adam step and after
+ * reverb_model_load.  n_hist = tower_width = 0 restores a dense layer 0 (the
+ * weights keep their current values).  A narrow tower keeps the network from
+ * fitting the 1k-ray histogram's noise, which swamps the statistics when all
+ * inputs share one wide layer.  Errors: RPR_EINVAL for shapes that do not fit. */
+int reverb_model_set_tower(RprModel* model, int32_t n_hist, int32_t tower_width, void* hip_stream);
 /* One Adam step with the gradients of the last backward (host `ap`). */
 int reverb_model_adam(RprModel* model, const RprAdamParams* ap, void* hip_stream);
 /* backward followed by adam. */

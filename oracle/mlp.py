@@ -197,6 +197,25 @@ def backward(params, X, T, Wm, rnd=None):
     return loss, grads
 
 
+def tower_structure(params, n_hist, tower_width):
+    """Layer 0 as a two-tower layer: rows r < tower_width keep their weights
+    on the first n_hist inputs (the histogram) and get zeros on the S
+    statistics inputs; row tower_width + j (j < S) passes statistic j through
+    with weight +1, row tower_width + S + j with weight -1; those rows' biases
+    are 0.  Returns the parameter list with layer 0 rewritten (FP64)."""
+    W, b = (np.array(p, np.float64) for p in params[0])
+    d1, d0 = W.shape
+    S = d0 - n_hist
+    assert d1 == tower_width + 2 * S
+    W[:tower_width, n_hist:] = 0.0
+    W[tower_width:, :] = 0.0
+    for j in range(S):
+        W[tower_width + j, n_hist + j] = 1.0
+        W[tower_width + S + j, n_hist + j] = -1.0
+    b[tower_width:] = 0.0
+    return [(W, b)] + list(params[1:])
+
+
 def adam_step(params, grads, state, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
     """One Adam step in place.  state: dict(t, m, v) with m, v lists shaped
     like params (created on the first call).  Decoupled weight decay scales

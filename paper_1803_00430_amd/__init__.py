@@ -198,6 +198,7 @@ SIGNATURES = {
     "reverb_model_backward": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, _vp, _vp]),
     "reverb_model_grads": (C.c_int, [_vp, _vp, _i64, _vp]),
     "reverb_model_adam": (C.c_int, [_vp, C.POINTER(AdamParams), _vp]),
+    "reverb_model_set_tower": (C.c_int, [_vp, _i32, _i32, _vp]),
     "reverb_model_train_step": (C.c_int, [_vp, _vp, _i64, _vp, _i32, _vp, _vp, C.POINTER(AdamParams), _vp, _vp]),
     "reverb_model_decode": (C.c_int, [_vp, _vp, _i64, _i32, C.c_float, _vp, _vp, _vp, _vp]),
     "reverb_params_scatter": (C.c_int, [_vp, _vp, _i64, _vp, _vp]),
@@ -529,6 +530,10 @@ class Batch:
 STAT_FEATURES = 64
 # input: 200 bins x 4 bands x 16 SH coefficients + 64 trace statistics -> 16 means + 16 log-variances
 LEARN_DIMS = (12800 + STAT_FEATURES, 512, 512, 512, 32)
+# two-tower variant: the 12,800 histogram features through a 64-unit tower, the 64 statistics
+# passed through as +s and -s (reverb_model_set_tower), then 512 -> 512 -> 32
+LEARN_TOWER = 64
+LEARN_DIMS_TOWER = (12800 + STAT_FEATURES, LEARN_TOWER + 2 * STAT_FEATURES, 512, 512, 32)
 
 
 class Model:
@@ -544,6 +549,7 @@ class Model:
         self.dims = tuple(int(d) for d in dims)
         self.max_batch = int(max_batch)
         self.input_norm = None  # (shift, scale) device tensors, set when the model is trained
+        self.tower = None  # (n_hist, tower_width) when layer 0 is a two-tower layer
 
     def info(self) -> dict:
         mi = ModelInfo()
@@ -590,6 +596,11 @@ class Model:
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0, stream=None):
         ap = AdamParams(lr, beta1, beta2, eps, weight_decay, 0.0)
         _check(lib().reverb_model_adam(self._h, C.byref(ap), _stream(stream)))
+
+    def set_tower(self, n_hist, tower_width, stream=None):
+        """Two-tower layer 0 (see reverb_model_set_tower); (0, 0) restores a dense one."""
+        _check(lib().reverb_model_set_tower(self._h, int(n_hist), int(tower_width), _stream(stream)))
+        self.tower = (int(n_hist), int(tower_width)) if tower_width else None
 
     def train_step(self, features, t, w, rows, loss, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
                    m=None, stream=None):

@@ -272,6 +272,37 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
     }
 }
 
+// Two-tower structure of layer 0 (reverb_model_set_tower).  Rows r < tw
+// read the first n_hist inputs only; with S = d0 - n_hist statistics inputs,
+// row tw + j (j < S) passes input n_hist + j through with weight +1 and row
+// tw + S + j with weight -1, bias 0, so that after the ReLU layer 1 sees
+// [tower(histogram) | max(s, 0) | max(-s, 0)].  The fixed entries are
+// written into the FP32 weights, their BF16 copy and the bias.
+__global__ void k_tower_structure(float* __restrict__ W, float* __restrict__ b, uint16_t* __restrict__ wbf, int d0,
+                                  int d1, int n_hist, int tw)
+{
+    const int S = d0 - n_hist;
+    const long long n = (long long)d1 * d0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(i / d0), c = (int)(i % d0);
+        if (r < tw) {
+            if (c >= n_hist) {
+                W[i] = 0.f;
+                wbf[i] = 0;
+            }
+        } else {
+            const int j = r - tw;
+            const float v = c == n_hist + (j % S) ? (j < S ? 1.f : -1.f) : 0.f;
+            W[i] = v;
+            wbf[i] = f2bf(v);
+        }
+    }
+    for (long long r = (long long)blockIdx.x * blockDim.x + threadIdx.x + tw; r < d1;
+         r += (long long)gridDim.x * blockDim.x)
+        b[r] = 0.f;
+}
+
 __global__ void k_to_bf16(const float* __restrict__ src, long long n, uint16_t* __restrict__ dst)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -537,6 +568,8 @@ struct RprModel {
     uint16_t* gbf[2] = {};      // [max_batch][maxd]
     uint16_t* gt[2] = {};       // [maxd][mpad]
     float* partial = nullptr;   // split-K partial sums
+    int tower_hist = 0;         // two-tower layer 0 (reverb_model_set_tower): histogram inputs, or 0
+    int tower_w = 0;            // tower width
 };
 
 namespace {
@@ -693,6 +726,13 @@ int backward_impl(RprModel& md, const uint16_t* features, int64_t n_rows, const 
     return RPR_OK;
 }
 
+void apply_tower(RprModel& md, hipStream_t st)
+{
+    const long long n = (long long)md.dims[1] * md.dims[0];
+    hipLaunchKernelGGL(k_tower_structure, dim3(grid_for(n)), dim3(256), 0, st, md.params + md.woff[0],
+                       md.params + md.boff[0], md.wbf[0], md.dims[0], md.dims[1], md.tower_hist, md.tower_w);
+}
+
 int adam_impl(RprModel& md, const RprAdamParams* ap, hipStream_t st)
 {
     if (!ap) return set_error(RPR_EINVAL, "adam parameters are NULL");
@@ -711,6 +751,7 @@ int adam_impl(RprModel& md, const RprAdamParams* ap, hipStream_t st)
         hipLaunchKernelGGL(k_adam, dim3(grid_for(nb)), dim3(256), 0, st, md.params + md.boff[l],
                            md.grads + md.boff[l], md.m1 + md.boff[l], md.m2 + md.boff[l], nb, ap->lr, ap->beta1,
                            ap->beta2, ap->eps, 0.f, (float)ic1, (float)ic2, (uint16_t*)nullptr);
+        if (l == 0 && md.tower_w > 0) apply_tower(md, st);
         if (l > 0) {
             hipLaunchKernelGGL(k_transpose_bf16, dim3((md.dims[l] + 31) / 32, (md.dims[l + 1] + 31) / 32),
                                dim3(256), 0, st, md.wbf[l], md.dims[l], nullptr, (long long)md.dims[l + 1],
@@ -818,6 +859,27 @@ extern "C" int reverb_model_create(const int32_t* dims, int32_t n_layers, int32_
     return RPR_OK;
 }
 
+extern "C" int reverb_model_set_tower(RprModel* model, int32_t n_hist, int32_t tower_width, void* hip_stream)
+{
+    if (!model) return set_error(RPR_EINVAL, "model is NULL");
+    RprModel& md = *model;
+    if (n_hist == 0 && tower_width == 0) {
+        md.tower_hist = md.tower_w = 0;
+        return RPR_OK;
+    }
+    if (md.L < 2) return set_error(RPR_EINVAL, "a two-tower layer 0 needs at least two layers");
+    if (n_hist < 1 || n_hist >= md.dims[0])
+        return set_error(RPR_EINVAL, "n_hist = %d must be in 1..%d", n_hist, md.dims[0] - 1);
+    const int S = md.dims[0] - n_hist;
+    if (tower_width < 1 || md.dims[1] != tower_width + 2 * S)
+        return set_error(RPR_EINVAL, "dims[1] = %d must equal tower_width + 2 x %d statistics inputs", md.dims[1], S);
+    md.tower_hist = n_hist;
+    md.tower_w = tower_width;
+    apply_tower(md, (hipStream_t)hip_stream);
+    RPR_HIP_TRY(hipGetLastError());
+    return RPR_OK;
+}
+
 extern "C" int reverb_model_destroy(RprModel* model)
 {
     if (!model) return RPR_OK;
@@ -853,6 +915,7 @@ extern "C" int reverb_model_load(RprModel* model, const float* params, int64_t n
     RPR_HIP_TRY(hipMemcpyAsync(model->params, params, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
     rc = refresh_bf16(*model, st);
     if (rc != RPR_OK) return rc;
+    if (model->tower_w > 0) apply_tower(*model, st);
     return zero_moments(*model, st);
 }
 

@@ -323,3 +323,46 @@ def test_training_fits_a_smooth_function(torch):
     assert float(loss.cpu()[0]) < first - 1.0, (first, float(loss.cpu()[0]))
     assert np.median(o[:, 16:]) < math.log(0.5 * np.var(T)), np.median(o[:, 16:])
     model.close()
+
+
+@pytest.mark.parametrize("dims,n_hist,tw,m", [((160, 96, 64, 96, 32), 128, 32, 45),
+                                              (P.LEARN_DIMS_TOWER, 12800, P.LEARN_TOWER, 64)])
+def test_two_tower_layer_matches_oracle(torch, dims, n_hist, tw, m):
+    """reverb_model_set_tower: the forward pass is the oracle's over the
+    structured parameters (oracle.mlp.tower_structure), and one backward +
+    Adam step equals the oracle's Adam step followed by the structure, whose
+    fixed entries come out exact."""
+    model, vec, Xb, T, W = _setup(torch, dims, m, 21)
+    model.set_tower(n_hist, tw)
+    rel_emu = 1e-3 if dims[0] < 1000 else 1e-2
+    st = M.tower_structure(split_params(vec.astype(np.float64), dims), n_hist, tw)
+    params = [(M.bf16_round(Wl), bl) for Wl, bl in st]
+    out = model.forward(torch.as_tensor(Xb[:m], device="cuda"))
+    torch.cuda.synchronize()
+    ze, _ = M.forward(params, bf16_bits_to_f64(Xb[:m]), rnd=M.bf16_round)
+    rel, cos = rel_cos(out.cpu().numpy(), ze[-1])
+    assert rel <= rel_emu and cos >= COS_EXACT, (rel, cos)
+    rows = np.arange(m, dtype=np.int32)
+    dev = dict(X=torch.as_tensor(Xb, device="cuda"), T=torch.as_tensor(T, device="cuda"),
+               W=torch.as_tensor(W, device="cuda"), rows=torch.as_tensor(rows, device="cuda"))
+    model.backward(dev["X"], dev["T"], dev["W"], rows=dev["rows"])
+    gr = model.grads()
+    s0 = model.save()
+    torch.cuda.synchronize()
+    gg = split_params(gr.cpu().numpy().astype(np.float64), dims)
+    # the structure was written into the model's own parameters
+    have = split_params(s0.cpu().numpy().astype(np.float64), dims)
+    assert np.array_equal(have[0][0], st[0][0].astype(np.float32).astype(np.float64))
+    model.adam(1e-3, weight_decay=0.01)
+    new = model.save()
+    torch.cuda.synchronize()
+    want = M.tower_structure(M.adam_step(st, gg, {}, 1e-3, weight_decay=0.01), n_hist, tw)
+    got = split_params(new.cpu().numpy().astype(np.float64), dims)
+    for (a, b), (c, d) in zip(got, want):
+        assert np.allclose(a, c, rtol=1e-5, atol=1e-7) and np.allclose(b, d, rtol=1e-5, atol=1e-7)
+    S = dims[0] - n_hist
+    W0 = got[0][0]
+    assert np.all(W0[:tw, n_hist:] == 0.0) and np.all(W0[tw:tw + S, n_hist:] == np.eye(S))
+    assert np.all(W0[tw + S:, n_hist:] == -np.eye(S)) and np.all(W0[tw:, :n_hist] == 0.0)
+    assert np.all(got[0][1][tw:] == 0.0)
+    model.close()

@@ -211,3 +211,26 @@ def test_targets_and_decode_by_hand():
     assert d["uncertain"]  # sigma of band 0 is 1 > 0.5
     assert not M.decode(out, 2.0, 2, kappa=1.5)["uncertain"]
     assert M.decode(out, 0.0, 2, kappa=1e9)["uncertain"]
+
+
+def test_tower_structure_is_the_two_tower_network():
+    """A layer 0 rewritten by tower_structure computes, written out by hand:
+    the histogram inputs through the tower's own rows (ReLU), then each
+    statistic as max(s, 0) and max(-s, 0); the rest of the network as given."""
+    g = np.random.default_rng(3)
+    n_hist, S, tw = 40, 6, 8
+    dims = (n_hist + S, tw + 2 * S, 16, 4)
+    params = [(g.normal(0, 0.5, (b, a)), g.normal(0, 0.1, b)) for a, b in zip(dims[:-1], dims[1:])]
+    st = M.tower_structure(params, n_hist, tw)
+    X = g.normal(0, 1, (9, dims[0]))
+    z, _ = M.forward(st, X)
+    W0, b0 = params[0]
+    tower = np.maximum(X[:, :n_hist] @ W0[:tw, :n_hist].T + b0[:tw], 0.0)
+    s = X[:, n_hist:]
+    h1 = np.concatenate([tower, np.maximum(s, 0.0), np.maximum(-s, 0.0)], axis=1)
+    h2 = np.maximum(h1 @ params[1][0].T + params[1][1], 0.0)
+    out = h2 @ params[2][0].T + params[2][1]
+    assert np.allclose(z[-1], out, rtol=1e-12, atol=1e-12)
+    # the other layers and the tower's own weights are untouched
+    assert np.array_equal(st[0][0][:tw, :n_hist], W0[:tw, :n_hist]) and np.array_equal(st[0][1][:tw], b0[:tw])
+    assert all(np.array_equal(a[0], b[0]) for a, b in zip(st[1:], params[1:]))
