@@ -311,9 +311,11 @@ def run_learn(a):
     else:
         model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
     t0 = time.perf_counter()
-    losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
+    losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128,
+                     log=lambda m: log(m, q))
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
+    log(f"trained in {t_train:.1f} s", q)
     fb = L.trace_rooms(scenes["cal"], rooms["cal"], n_rays=n_fb, seed_offset=L.SEED_SWEEP + n_fb, chunk=1024,
                        method=fbm, order=2 if fbm == "listener" else 0, **L.CONVERGED)
     prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
@@ -321,6 +323,7 @@ def run_learn(a):
                                                  L.rt60_error(prm, refs["cal"], 4),
                                                  L.rt60_error(fb["params"], refs["cal"], 4),
                                                  target=a.learn_target_err)
+    log(f"kappa {kappa:.4f}: calibration fallback {fb_frac_cal:.3f}, error {err_cal:.4f}", q)
     # held-out: ungated network error, then the gated path, timed
     cheap_data = L.trace_rooms(scenes["eval"], rooms["eval"], n_rays=1024, seed_offset=L.SEED_INPUT,
                                want_features=True, chunk=1024, **L.INPUT)
@@ -329,6 +332,7 @@ def run_learn(a):
     prm, unc, cheap = L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, fallback=fbm)
     err_learned = L.rt60_error_summary(L.rt60_error(prm, refs["eval"], 4))
     fb_frac = float(unc.float().mean())
+    log(f"held-out: network {err_net}, learned {err_learned}, fallback {fb_frac:.3f}", q)
     for _ in range(a.warmup):
         L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, cheap=cheap, fallback=fbm)
     torch.cuda.synchronize()
@@ -337,9 +341,12 @@ def run_learn(a):
         L.learned_estimate(model, scenes["eval"], rooms["eval"], kappa, n_fb, cheap=cheap, fallback=fbm)
     torch.cuda.synchronize()
     t_learned = (time.perf_counter() - t0) / a.steps
+    log(f"learned: {len(rooms['eval']) / t_learned:.1f} IRs/s", q)
     ips_plain, _ = L.timed_plain(scenes["eval"], rooms["eval"], n_star, steps=a.steps)
+    log(f"plain source: {ips_plain:.1f} IRs/s", q)
     ips_plain_l, _ = L.timed_plain(scenes["eval"], rooms["eval"], n_star_l, steps=a.steps, method="listener",
                                    order=2)
+    log(f"plain listener: {ips_plain_l:.1f} IRs/s", q)
     n_ev = len(rooms["eval"])
     out = {
         "metric": "IRs/s at <=5% RT60 error, learned vs plain ray trace", "value": n_ev / t_learned,
