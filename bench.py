@@ -75,8 +75,8 @@ def parse():
                          "with next-event estimation; reverb: audio-rate rendering of the SH reverberator for "
                          "many sources; paths: early-reflection paths per frame (records, path cache, "
                          "prioritization) on the city")
-    ap.add_argument("--learn-train", type=int, default=32768, help="training rooms of the learn workload")
-    ap.add_argument("--learn-eval", type=int, default=1024, help="calibration and held-out rooms (each)")
+    ap.add_argument("--learn-train", type=int, default=100000, help="training rooms of the learn workload")
+    ap.add_argument("--learn-eval", type=int, default=2048, help="calibration and held-out rooms (each)")
     ap.add_argument("--learn-epochs", type=int, default=16)
     ap.add_argument("--learn-arch", choices=("dense", "tower"), default="tower",
                     help="learn: one dense 12,864 -> 512 first layer, or the histogram through a 64-unit tower "
