@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # and WRITE_SIZE passes scaled by a copy kernel of known size
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
 # was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35562516.5,
-                 "sources_sha256": "829abc1799f05caff4035248d9df4eb5aafbb91b8adcec4fb1b259ef8be88a94"}
+TRACE_TRAFFIC = {"bytes": 35608608.0,
+                 "sources_sha256": "8bcafdce7375a89d285f43db52191f76123fea587eadff1061b860ad144407c8"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
 
@@ -258,6 +258,15 @@ def run_batch(a):
     print(json.dumps(out), flush=True)
 
 
+def learned_model(a, P):
+    """The estimator's network per --learn-arch: two towers (default) or a dense first layer."""
+    if a.learn_arch == "tower":
+        model = P.Model(P.LEARN_DIMS_TOWER, max_batch=256, seed=1)
+        model.set_tower(P.LEARN_DIMS_TOWER[0] - P.STAT_FEATURES, P.LEARN_TOWER)
+        return model
+    return P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+
+
 def run_learn(a):
     """The learned reverb estimator against the plain method (see
     paper_1803_00430_amd/learn.py).  Rooms: shoeboxes and L-rooms (dims
@@ -305,11 +314,7 @@ def run_learn(a):
     sweep_l, n_star_l = plain_sweep("listener", (4096, 8192, 16384, 32768, 65536))
     fbm = a.learn_fallback
     n_fb = n_star_l if fbm == "listener" else n_star
-    if a.learn_arch == "tower":
-        model = P.Model(P.LEARN_DIMS_TOWER, max_batch=256, seed=1)
-        model.set_tower(P.LEARN_DIMS_TOWER[0] - P.STAT_FEATURES, P.LEARN_TOWER)
-    else:
-        model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    model = learned_model(a, P)
     t0 = time.perf_counter()
     losses = L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128,
                      log=lambda m: log(m, q))
@@ -981,7 +986,9 @@ def run_hospital_learned(a, P, scene, cfg, sources_at, params_plain, plain_frame
 
     q = a.quiet
     t0 = time.perf_counter()
-    tr = [R.learn_room(10000 + i) for i in range(a.learn_train)]
+    # the hospital is out of the training rooms' distribution and falls back on every source (§6),
+    # so its inline model trains on at most 32,768 rooms
+    tr = [R.learn_room(10000 + i) for i in range(min(a.learn_train, 32768))]
     ca = [R.learn_room(150000 + i) for i in range(512)]
     tr_sc, ca_sc = L.make_scenes(tr), L.make_scenes(ca)
     data = L.make_dataset(tr_sc, tr, n_target=a.learn_target_rays, inputs_per_room=a.learn_views, chunk=1024)
@@ -989,7 +996,7 @@ def run_hospital_learned(a, P, scene, cfg, sources_at, params_plain, plain_frame
     ref = L.trace_rooms(ca_sc, ca, n_rays=262144, seed_offset=L.SEED_REFERENCE, chunk=1024, **L.CONVERGED)
     fb = L.trace_rooms(ca_sc, ca, n_rays=cfg["n_rays"], seed_offset=L.SEED_SWEEP + cfg["n_rays"], chunk=1024,
                        **L.CONVERGED)
-    model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    model = learned_model(a, P)
     L.train(model, data, epochs=a.learn_epochs, lr=3e-4, weight_decay=1e-2, batch=128)
     prm, sig, _ = L.predict(model, cal["features"], cal["e_in"], 4, 1e9)
     kappa, _, _ = L.choose_kappa(sig.max(dim=1).values.cpu().numpy(), L.rt60_error(prm, ref["params"], 4),

@@ -61,36 +61,75 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint
 // ------------------------------------------------------------------ products
 // C (partial) = A[M][kb:ke] * B[N][kb:ke]^T for one 64 x 64 tile per
 // workgroup; each wave owns a 32 x 32 sub-tile held in one accumulator of
-// v_mfma_f32_32x32x16_bf16.  Lane l supplies row (l & 31) of the A and B
-// fragments with the 8 consecutive K entries starting at 8 (l >> 5); entry e
-// of the accumulator is row 8 (e >> 2) + 4 (l >> 5) + (e & 3), column
-// (l & 31) of the sub-tile.  A row past M (B row past N) is read from the
-// last valid row instead: it only feeds outputs that are never stored.
-// Requires K % 32 == 0, kchunk % 32 == 0 and 16-byte aligned rows (lda, ldb
-// multiples of 8).
+// v_mfma_f32_32x32x16_bf16.  Per K-step of 32 the workgroup stages the tile's
+// 64 rows of A and of B in LDS once (four threads per row, 64 contiguous
+// bytes each), so no operand row is fetched twice and every fetch is a whole
+// 64-byte segment; the next step's rows are loaded into registers while the
+// current step's products run, and LDS is double-buffered (one barrier per
+// step).  Rows are padded to 80 bytes in LDS, which puts the eight rows read
+// together by a 128-bit fragment load on distinct banks.  Lane l supplies row
+// (l & 31) of the A and B fragments with the 8 consecutive K entries starting
+// at 8 (l >> 5); entry e of the accumulator is row 8 (e >> 2) + 4 (l >> 5) +
+// (e & 3), column (l & 31) of the sub-tile.  A row past M (B row past N) is
+// read from the last valid row instead: it only feeds outputs that are never
+// stored.  Requires K % 32 == 0, kchunk % 32 == 0 and 16-byte aligned rows
+// (lda, ldb multiples of 8).
+constexpr int kLdsRow = kKStep + 8;  // BF16 per staged row (80 bytes)
+
 __global__ void __launch_bounds__(256) k_gemm_nt(const uint16_t* __restrict__ A, int lda,
                                                  const uint16_t* __restrict__ B, int ldb, float* __restrict__ P,
                                                  int ldp, size_t split_stride, int M, int N, int K, int kchunk)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ __attribute__((aligned(16))) uint16_t sa[2][kTile * kLdsRow];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[2][kTile * kLdsRow];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
     const int r = lane & 31, q = lane >> 5;
-    const int m0 = blockIdx.y * kTile + (wave >> 1) * 32;
-    const int n0 = blockIdx.x * kTile + (wave & 1) * 32;
+    const int M0 = blockIdx.y * kTile, N0 = blockIdx.x * kTile;
     const int kb = blockIdx.z * kchunk;
     const int ke = min(K, kb + kchunk);
-    const uint16_t* ap = A + (size_t)min(m0 + r, M - 1) * lda + q * 8;
-    const uint16_t* bp = B + (size_t)min(n0 + r, N - 1) * ldb + q * 8;
+    const int nsteps = (ke - kb) / kKStep;
+    // staging: thread t copies row t / 4, K entries 8 (t % 4) .. +8 of the step
+    const int srow = tid >> 2, sseg = (tid & 3) * 8;
+    const uint16_t* ga = A + (size_t)min(M0 + srow, M - 1) * lda + kb + sseg;
+    const uint16_t* gb = B + (size_t)min(N0 + srow, N - 1) * ldb + kb + sseg;
+    const int soff = srow * kLdsRow + sseg;
+    // fragments: this wave's rows of the staged tiles
+    const int fa = ((wave >> 1) * 32 + r) * kLdsRow + q * 8;
+    const int fb = ((wave & 1) * 32 + r) * kLdsRow + q * 8;
     f32x16_t c = {};
-    for (int k = kb; k < ke; k += 2 * 16) {
-        const uint4 a0 = *reinterpret_cast<const uint4*>(ap + k);
-        const uint4 a1 = *reinterpret_cast<const uint4*>(ap + k + 16);
-        const uint4 b0 = *reinterpret_cast<const uint4*>(bp + k);
-        const uint4 b1 = *reinterpret_cast<const uint4*>(bp + k + 16);
+    uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = ra;
+    if (nsteps > 0) {
+        ra = *reinterpret_cast<const uint4*>(ga);
+        rb = *reinterpret_cast<const uint4*>(gb);
+        *reinterpret_cast<uint4*>(&sa[0][soff]) = ra;
+        *reinterpret_cast<uint4*>(&sb[0][soff]) = rb;
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const int cur = s & 1;
+        const bool more = s + 1 < nsteps;
+        if (more) {
+            ra = *reinterpret_cast<const uint4*>(ga + (size_t)(s + 1) * kKStep);
+            rb = *reinterpret_cast<const uint4*>(gb + (size_t)(s + 1) * kKStep);
+        }
+        const uint4 a0 = *reinterpret_cast<const uint4*>(&sa[cur][fa]);
+        const uint4 a1 = *reinterpret_cast<const uint4*>(&sa[cur][fa + 16]);
+        const uint4 b0 = *reinterpret_cast<const uint4*>(&sb[cur][fb]);
+        const uint4 b1 = *reinterpret_cast<const uint4*>(&sb[cur][fb + 16]);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a0), __builtin_bit_cast(bf16x8_t, b0),
                                                     c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a1), __builtin_bit_cast(bf16x8_t, b1),
                                                     c, 0, 0, 0);
+        if (more) {
+            // the other buffer was last read in step s - 1, before that step's barrier
+            *reinterpret_cast<uint4*>(&sa[cur ^ 1][soff]) = ra;
+            *reinterpret_cast<uint4*>(&sb[cur ^ 1][soff]) = rb;
+        }
+        __syncthreads();
     }
+    const int m0 = M0 + (wave >> 1) * 32;
+    const int n0 = N0 + (wave & 1) * 32;
     float* out = P + blockIdx.z * split_stride;
     const int col = n0 + r;
     if (col >= N) return;

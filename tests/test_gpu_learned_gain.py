@@ -31,7 +31,8 @@ def test_learned_estimator_beats_plain_at_1k_rays():
                                **L.INPUT)["params"]
     e_plain = min(L.rt60_error_summary(L.rt60_error(plain_1ms, ref, 4))["mean"],
                   L.rt60_error_summary(L.rt60_error(plain_10ms, ref, 4))["mean"])
-    model = P.Model(P.LEARN_DIMS, max_batch=256, seed=1)
+    model = P.Model(P.LEARN_DIMS_TOWER, max_batch=256, seed=1)  # the default two-tower network
+    model.set_tower(P.LEARN_DIMS_TOWER[0] - P.STAT_FEATURES, P.LEARN_TOWER)
     losses = L.train(model, data, epochs=12, lr=3e-4, weight_decay=1e-2, batch=128)
     assert losses[-1] < losses[0]
     prm, sig, unc = L.predict(model, ev["features"], ev["e_in"], 4, 1e9)
