@@ -53,13 +53,13 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     uint32_t tri1 = kRecNoTri, tri2 = kRecNoTri;  // triangles of the first two reflections (REC)
     uint32_t h = 0;
     // E(b): band energy; Q(b): the path's probability under band b's choice
-    // rule relative to the mean over the bands (see the bounce below).  With
-    // up to four bands and the 32-entry stack they live in LDS, where the
-    // 2 KB per wave still fit 16 waves per CU beside the stacks (in registers
-    // they would cost a wave per SIMD); otherwise in registers.
-    using Bands = BandState<NB, (NB <= 4 && STACK <= 32)>;
-    __shared__ float eq_lds[Bands::kLdsWords];
-    Bands eq(eq_lds, lane);
+    // rule relative to the mean over the bands (see the bounce below).  They
+    // live in registers (with four bands the kernel still fits 4 waves per
+    // SIMD): in LDS they would take 2 KB per wave, and with 16 waves per CU
+    // the stacks and they would fill the CU's LDS, so that the next scene's
+    // build kernels could start on a CU only as this launch's waves leave it.
+    using Bands = BandState<NB, false>;
+    Bands eq(nullptr, lane);
 #pragma unroll
     for (int b = 0; b < NB; ++b) eq.E(b) = eq.Q(b) = 0.f;
     LaneAcc<NB> acc;
