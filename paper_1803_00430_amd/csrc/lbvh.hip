@@ -3,8 +3,16 @@
 // Linear BVH (Karras, HPG 2012): Morton codes (30-bit; 63-bit for large scenes) of the triangle
 // centroids in the scene's centroid bounds, a stable least-significant-digit
 // radix sort of (code, triangle) pairs, internal nodes from the longest common
-// prefixes of neighbouring codes (ties broken by the sorted index), and
-// bottom-up bounds where the second child to finish builds its parent.
+// prefixes of neighbouring codes (ties broken by the sorted index), node
+// boxes as unions over each node's range of sorted leaves, and a collapse of
+// the binary tree into 4-wide nodes.
+//
+// A rebuild is a chain of dependent launches on one stream, and each launch
+// costs a few microseconds before its first wave runs (more while another
+// stream's trace holds the compute units), so the chain is kept short: the
+// material table and the validation share the first kernel, the Morton keys
+// share the first digit count, the scatter scans the digit counts itself, and
+// the leaf records, the hierarchy and its structure checks share launches.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -20,11 +28,20 @@ namespace rpr {
 namespace {
 
 constexpr int kBuildBlock = 256;
-constexpr int kPrepBlocks = 128;  // k_prep's grid cap (it strides over the triangles)
+constexpr int kPrepBlock = 64;     // k_prep's workgroup: one wave, so it can start in any free wave slot
+constexpr int kPrepBlocks = 512;   // k_prep's grid cap (it strides over the triangles)
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kBuildBlock * kSortItems;
 // Scenes of at least this many triangles get 64-bit Morton keys (21 bits per axis).
 constexpr int64_t kWideKeyTris = (int64_t)1 << 19;
+// Up to this many sort tiles the scatter forms its digit offsets from the
+// per-tile counts itself (two launches per pass instead of five); beyond it a
+// device-wide scan runs between count and scatter.
+constexpr int kFusedScanTiles = 128;
+// Up to this many blocks of internal nodes the collapse forms the 4-wide node
+// indices itself (from the even-depth bit masks and per-block counts, scanned
+// in LDS); beyond it a device-wide scan runs before the collapse.
+constexpr int kFusedIndexBlocks = 1024;
 
 // Validation flags, set by the prep kernel and read back by scene_create.
 enum : uint32_t {
@@ -60,68 +77,119 @@ __host__ __device__ inline float unordered(int32_t i)
     return f;
 }
 
-__global__ void k_init_flags(BuildFlags* f)
+// What each k_prep block found: validation flags, degenerate triangles, and
+// the bounds of its centroids and of its triangles (as order-preserving keys).
+// The next kernel reduces them, so that no launch has to clear shared counters
+// before k_prep's blocks could update them.
+struct PrepPartial {
+    uint32_t flags;
+    uint32_t n_degenerate;
+    int32_t clo[3], chi[3];
+    int32_t blo[3], bhi[3];
+};
+
+// Reduce k_prep's per-block results within one wave; every lane returns the total.
+__device__ PrepPartial reduce_prep(const PrepPartial* __restrict__ part, int n_part)
 {
-    if (threadIdx.x == 0) {
-        f->flags = 0;
-        f->max_depth = 0;
-        f->max_stack = 0;
-        f->n_nodes4 = 0;
-        f->n_degenerate = 0;
+    const int lane = threadIdx.x % kWave;
+    PrepPartial r;
+    r.flags = 0;
+    r.n_degenerate = 0;
+    for (int a = 0; a < 3; ++a) {
+        r.clo[a] = r.blo[a] = ordered(__builtin_inff());
+        r.chi[a] = r.bhi[a] = ordered(-__builtin_inff());
+    }
+    for (int j = lane; j < n_part; j += kWave) {
+        const PrepPartial q = part[j];
+        r.flags |= q.flags;
+        r.n_degenerate += q.n_degenerate;
         for (int a = 0; a < 3; ++a) {
-            f->clo[a] = ordered(__builtin_inff());
-            f->chi[a] = ordered(-__builtin_inff());
-            f->blo[a] = ordered(__builtin_inff());
-            f->bhi[a] = ordered(-__builtin_inff());
+            r.clo[a] = min(r.clo[a], q.clo[a]);
+            r.chi[a] = max(r.chi[a], q.chi[a]);
+            r.blo[a] = min(r.blo[a], q.blo[a]);
+            r.bhi[a] = max(r.bhi[a], q.bhi[a]);
         }
     }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        r.flags |= __shfl_xor(r.flags, o, kWave);
+        r.n_degenerate += __shfl_xor(r.n_degenerate, o, kWave);
+        for (int a = 0; a < 3; ++a) {
+            r.clo[a] = min(r.clo[a], __shfl_xor(r.clo[a], o, kWave));
+            r.chi[a] = max(r.chi[a], __shfl_xor(r.chi[a], o, kWave));
+            r.blo[a] = min(r.blo[a], __shfl_xor(r.blo[a], o, kWave));
+            r.bhi[a] = max(r.bhi[a], __shfl_xor(r.bhi[a], o, kWave));
+        }
+    }
+    return r;
 }
 
-// Material record per material (see kMat* offsets): per band the absorption
-// alpha_b, the scattering coefficient s_b (the hero band's s_b is the diffuse
-// probability of a bounce; every band's s_b or 1 - s_b enters the band
-// weights) and 1 - alpha_b, formed in FP64 and rounded to FP32.
-__global__ void k_materials(const float* __restrict__ absorption, const float* __restrict__ scattering, int nm,
-                            int nb, float* __restrict__ mats, BuildFlags* f)
+// The build's flag record, started from k_prep's totals (written by one lane,
+// before any kernel that updates it).
+__device__ void write_flags(const PrepPartial& r, BuildFlags* f)
 {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= nm) return;
-    bool bad = false;
-    for (int b = 0; b < nb; ++b) {
-        const float a = absorption[m * nb + b], s = scattering[m * nb + b];
-        if (!(a >= 0.0f && a <= 1.0f) || !(s >= 0.0f && s <= 1.0f)) bad = true;
-    }
-    if (bad) atomicOr(&f->flags, (uint32_t)kBadCoeff);
-    float* r = mats + (int64_t)m * kMatStride;
-    for (int i = 0; i < kMatStride; ++i) r[i] = 0.0f;
-    for (int b = 0; b < nb; ++b) {
-        const float a = absorption[m * nb + b];
-        r[kMatAlpha + b] = a;
-        r[kMatS + b] = scattering[m * nb + b];
-        r[kMatKeep + b] = (float)(1.0 - (double)a);
+    f->flags = r.flags;
+    f->max_depth = 0;
+    f->max_stack = 0;
+    f->n_nodes4 = 0;
+    f->n_degenerate = r.n_degenerate;
+    f->pad = 0;
+    for (int a = 0; a < 3; ++a) {
+        f->clo[a] = r.clo[a];
+        f->chi[a] = r.chi[a];
+        f->blo[a] = r.blo[a];
+        f->bhi[a] = r.bhi[a];
     }
 }
 
-// Triangle bounds, centroids and validation; reduces the centroid bounds.
-__global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
-                       const int32_t* __restrict__ tri_mat, int nm, float4* __restrict__ cent,
-                       uint32_t* __restrict__ seen, uint32_t* __restrict__ refs, BuildFlags* f)
+// A scene without triangles: the flag record from the material check alone.
+__global__ void k_flags_only(const PrepPartial* __restrict__ part, int n_part, BuildFlags* f)
 {
-    __shared__ int32_t s_lo[3][kBuildBlock / kWave], s_hi[3][kBuildBlock / kWave];
-    __shared__ int32_t s_blo[3][kBuildBlock / kWave], s_bhi[3][kBuildBlock / kWave];
+    const PrepPartial r = reduce_prep(part, n_part);
+    if (threadIdx.x == 0) write_flags(r, f);
+}
+
+// Material records, then triangle bounds, centroids and validation, with the
+// per-block results in part[blockIdx.x].  Material record per material (see
+// kMat* offsets): per band the absorption alpha_b, the scattering coefficient
+// s_b (the hero band's s_b is the diffuse probability of a bounce; every
+// band's s_b or 1 - s_b enters the band weights) and 1 - alpha_b, formed in
+// FP64 and rounded to FP32.  Also clears the counters of later kernels (seen
+// [nt], refs [2 nt - 1]) and sets every parent link to -1.
+__global__ void __launch_bounds__(kPrepBlock)
+k_prep(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris, int64_t nt,
+       const int32_t* __restrict__ tri_mat, const float* __restrict__ absorption,
+       const float* __restrict__ scattering, int nm, int nb, float* __restrict__ mats, float4* __restrict__ cent,
+       uint32_t* __restrict__ seen, uint32_t* __restrict__ refs, int32_t* __restrict__ parent,
+       PrepPartial* __restrict__ part)
+{
     float c[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float cm[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    // grid-stride over the triangles: fewer blocks, so fewer of the atomics
-    // below, which all land on the same flag words
+    uint32_t flags = 0, ndeg = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += stride) {
-        // clear the counters of later kernels: seen [nt], refs [2 nt - 1]
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t m = g; m < nm; m += stride) {
+        for (int b = 0; b < nb; ++b) {
+            const float a = absorption[m * nb + b], s = scattering[m * nb + b];
+            if (!(a >= 0.0f && a <= 1.0f) || !(s >= 0.0f && s <= 1.0f)) flags |= kBadCoeff;
+        }
+        float* r = mats + m * kMatStride;
+        for (int i = 0; i < kMatStride; ++i) r[i] = 0.0f;
+        for (int b = 0; b < nb; ++b) {
+            const float a = absorption[m * nb + b];
+            r[kMatAlpha + b] = a;
+            r[kMatS + b] = scattering[m * nb + b];
+            r[kMatKeep + b] = (float)(1.0 - (double)a);
+        }
+    }
+    // grid-stride over the triangles
+    for (int64_t t = g; t < nt; t += stride) {
         seen[t] = 0u;
         refs[t] = 0u;
         if (t > 0) refs[nt - 1 + t] = 0u;
-        uint32_t flags = 0;
+        parent[t] = -1;
+        if (t + 1 < nt) parent[nt + t] = -1;
         int32_t idx[3];
         for (int k = 0; k < 3; ++k) {
             idx[k] = tris[3 * t + k];
@@ -143,8 +211,7 @@ __global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_
         const float e1x = v[1][0] - v[0][0], e1y = v[1][1] - v[0][1], e1z = v[1][2] - v[0][2];
         const float e2x = v[2][0] - v[0][0], e2y = v[2][1] - v[0][1], e2z = v[2][2] - v[0][2];
         const float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-        if (nx == 0.0f && ny == 0.0f && nz == 0.0f) atomicAdd(&f->n_degenerate, 1u);
-        if (flags) atomicOr(&f->flags, flags);
+        if (nx == 0.0f && ny == 0.0f && nz == 0.0f) ++ndeg;
         float cen[3];
         for (int a = 0; a < 3; ++a) {
             const float l = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
@@ -157,36 +224,28 @@ __global__ void k_prep(const float* __restrict__ verts, int64_t nv, const int32_
         }
         cent[t] = make_float4(cen[0], cen[1], cen[2], 0.0f);
     }
-    // wave then block reduction of the bounds
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    for (int a = 0; a < 3; ++a) {
-        for (int o = 32; o > 0; o >>= 1) {
-            c[a] = fminf(c[a], __shfl_xor(c[a], o));
-            cm[a] = fmaxf(cm[a], __shfl_xor(cm[a], o));
-            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
-            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
-        }
-        if (lane == 0) {
-            s_lo[a][w] = ordered(c[a]);
-            s_hi[a][w] = ordered(cm[a]);
-            s_blo[a][w] = ordered(lo[a]);
-            s_bhi[a][w] = ordered(hi[a]);
+    // reduction over the block (one wave)
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        flags |= __shfl_xor(flags, o, kWave);
+        ndeg += __shfl_xor(ndeg, o, kWave);
+        for (int a = 0; a < 3; ++a) {
+            c[a] = fminf(c[a], __shfl_xor(c[a], o, kWave));
+            cm[a] = fmaxf(cm[a], __shfl_xor(cm[a], o, kWave));
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o, kWave));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o, kWave));
         }
     }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        const int a = threadIdx.x;
-        int32_t l = s_lo[a][0], h = s_hi[a][0], bl = s_blo[a][0], bh = s_bhi[a][0];
-        for (int i = 1; i < kBuildBlock / kWave; ++i) {
-            l = min(l, s_lo[a][i]);
-            h = max(h, s_hi[a][i]);
-            bl = min(bl, s_blo[a][i]);
-            bh = max(bh, s_bhi[a][i]);
+    if (threadIdx.x == 0) {
+        PrepPartial r;
+        r.flags = flags;
+        r.n_degenerate = ndeg;
+        for (int a = 0; a < 3; ++a) {
+            r.clo[a] = ordered(c[a]);
+            r.chi[a] = ordered(cm[a]);
+            r.blo[a] = ordered(lo[a]);
+            r.bhi[a] = ordered(hi[a]);
         }
-        atomicMin(&f->clo[a], l);
-        atomicMax(&f->chi[a], h);
-        atomicMin(&f->blo[a], bl);
-        atomicMax(&f->bhi[a], bh);
+        part[blockIdx.x] = r;
     }
 }
 
@@ -213,34 +272,71 @@ __device__ __forceinline__ uint64_t spread3_64(uint64_t v)
     return v;
 }
 
-// Morton key of each centroid in the centroid bounds: 10 bits per axis in a
-// 32-bit key, or 21 bits per axis in a 64-bit key (large scenes, where 10
-// bits per axis leave triangles sharing a key).
+// Morton key of a centroid in the centroid bounds [lo, lo + ext]: 10 bits per
+// axis in a 32-bit key, or 21 bits per axis in a 64-bit key (large scenes,
+// where 10 bits per axis leave triangles sharing a key).
 template <class K>
-__global__ void k_morton(const float4* __restrict__ cent, int64_t nt, const BuildFlags* f, K* __restrict__ keys,
-                         uint32_t* __restrict__ vals)
+__device__ __forceinline__ K morton_key(const float4 c, const float lo[3], const float hi[3])
 {
     constexpr int kBits = sizeof(K) == 4 ? 10 : 21;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    const float4 c = cent[t];
     const float cc[3] = {c.x, c.y, c.z};
     K code = 0;
     for (int a = 0; a < 3; ++a) {
-        const float lo = unordered(f->clo[a]), hi = unordered(f->chi[a]);
-        const float ext = hi - lo;
-        float u = ext > 0.0f ? (cc[a] - lo) / ext : 0.5f;
+        const float ext = hi[a] - lo[a];
+        float u = ext > 0.0f ? (cc[a] - lo[a]) / ext : 0.5f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
         const uint32_t q = min((uint32_t)(u * (float)(1u << kBits)), (1u << kBits) - 1u);
         if constexpr (sizeof(K) == 4) code |= spread3(q) << (2 - a);
         else code |= spread3_64(q) << (2 - a);
     }
-    keys[t] = code;
-    vals[t] = (uint32_t)t;
+    return code;
 }
 
 // ---------------------------------------------------------------- radix sort
 // Per-tile digit counts, stored digit-major: counts[d * n_tiles + tile].
+__device__ __forceinline__ void store_tile_counts(uint32_t* h, uint32_t* __restrict__ counts, int n_tiles)
+{
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// The first pass's count with the keys made on the way: k_prep's results are
+// reduced (block 0 writes them to the flag record), each centroid's Morton key
+// and its triangle index are stored, and the low digit is counted.
+template <class K>
+__global__ void __launch_bounds__(kBuildBlock)
+k_morton_count(const float4* __restrict__ cent, int64_t n, const PrepPartial* __restrict__ part, int n_part,
+               BuildFlags* f, K* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ counts,
+               int n_tiles)
+{
+    __shared__ uint32_t h[256];
+    __shared__ float s_lo[3], s_hi[3];
+    h[threadIdx.x] = 0;
+    if (threadIdx.x < kWave) {
+        const PrepPartial r = reduce_prep(part, n_part);
+        if (threadIdx.x == 0) {
+            for (int a = 0; a < 3; ++a) {
+                s_lo[a] = unordered(r.clo[a]);
+                s_hi[a] = unordered(r.chi[a]);
+            }
+            if (blockIdx.x == 0) write_flags(r, f);
+        }
+    }
+    __syncthreads();
+    const float lo[3] = {s_lo[0], s_lo[1], s_lo[2]}, hi[3] = {s_hi[0], s_hi[1], s_hi[2]};
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; ++r) {
+        const int64_t i = base + r * kBuildBlock + threadIdx.x;
+        if (i < n) {
+            const K key = morton_key<K>(cent[i], lo, hi);
+            keys[i] = key;
+            vals[i] = (uint32_t)i;
+            atomicAdd(&h[(uint32_t)key & 255u], 1u);
+        }
+    }
+    store_tile_counts(h, counts, n_tiles);
+}
+
 template <class K>
 __global__ void __launch_bounds__(kBuildBlock) k_radix_count(const K* __restrict__ keys, int64_t n, int shift,
                                                              uint32_t* __restrict__ counts, int n_tiles)
@@ -253,8 +349,7 @@ __global__ void __launch_bounds__(kBuildBlock) k_radix_count(const K* __restrict
         const int64_t i = base + r * kBuildBlock + threadIdx.x;
         if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
     }
-    __syncthreads();
-    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+    store_tile_counts(h, counts, n_tiles);
 }
 
 // Exclusive scan of the digit-major counts in one workgroup of 1024 threads.
@@ -339,11 +434,14 @@ __global__ void __launch_bounds__(kBuildBlock) k_scan_apply(uint32_t* __restrict
 // Stable scatter: each tile is processed in rounds of 256 keys; within a
 // round, lanes of a wave with equal digits are matched by eight ballots and
 // ranked by position, and waves are ordered through per-digit counters.
+// `counts` holds the digit-major per-tile counts (fused: the tile forms its
+// offsets from them, the keys of all smaller digits plus those of its digit
+// in earlier tiles) or their exclusive scan (the offsets themselves).
 template <class K>
 __global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const K* __restrict__ keys_in,
                                                                const uint32_t* __restrict__ vals_in, int64_t n,
-                                                               int shift, const uint32_t* __restrict__ offsets,
-                                                               int n_tiles, K* __restrict__ keys_out,
+                                                               int shift, const uint32_t* __restrict__ counts,
+                                                               int n_tiles, bool fused, K* __restrict__ keys_out,
                                                                uint32_t* __restrict__ vals_out, BuildFlags* bad)
 {
     constexpr int W = kBuildBlock / kWave;
@@ -352,7 +450,20 @@ __global__ void __launch_bounds__(kBuildBlock) k_radix_scatter(const K* __restri
     __shared__ uint32_t wcnt[W][256];
     __shared__ uint32_t woff[W][256];
     const int tid = threadIdx.x, lane = tid % kWave, w = tid / kWave;
-    g_off[tid] = offsets[(int64_t)tid * n_tiles + blockIdx.x];
+    if (fused) {
+        const uint32_t* row = counts + (int64_t)tid * n_tiles;
+        uint32_t before = 0, total = 0;
+#pragma unroll 8
+        for (int t = 0; t < n_tiles; ++t) {
+            const uint32_t c = row[t];
+            total += c;
+            before += t < (int)blockIdx.x ? c : 0u;
+        }
+        __shared__ uint32_t s_wave[W];
+        g_off[tid] = block_exclusive(total, s_wave) + before;
+    } else {
+        g_off[tid] = counts[(int64_t)tid * n_tiles + blockIdx.x];
+    }
     run[tid] = 0;
     for (int i = 0; i < W; ++i) wcnt[i][tid] = 0;
     __syncthreads();
@@ -413,13 +524,13 @@ __device__ __forceinline__ int delta(const K* __restrict__ k, int n, int i, int 
 // Internal node i covers a key range [min(i,j), max(i,j)] grown from i in the
 // direction of the neighbour with the longer common prefix; it splits where
 // the common prefix of the range ends.  parent[] indexes internal nodes
-// 0..n-2 then leaves n-1..2n-2.
+// 0..n-2 then leaves n-1..2n-2.  Structure check, first half: each child link
+// is counted in refs (same indexing), and a link out of range is flagged.
 template <class K>
-__global__ void k_karras(const K* __restrict__ keys, int n, int2* __restrict__ child,
-                         int32_t* __restrict__ parent, int2* __restrict__ range, BuildFlags* f)
+__device__ __forceinline__ void karras_node(int i, const K* __restrict__ keys, int n, int2* __restrict__ child,
+                                            int32_t* __restrict__ parent, int2* __restrict__ range,
+                                            uint32_t* __restrict__ refs, BuildFlags* f)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
     const int d = (delta(keys, n, i, i + 1) - delta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
     const int dmin = delta(keys, n, i, i - d);
     int lmax = 2;
@@ -448,18 +559,26 @@ __global__ void k_karras(const K* __restrict__ keys, int n, int2* __restrict__ c
     const int c0 = (lo == g) ? leaf_link(g) : g;
     const int c1 = (hi == g + 1) ? leaf_link(g + 1) : g + 1;
     child[i] = make_int2(c0, c1);
-    parent[is_leaf(c0) ? (n - 1) + leaf_index(c0) : c0] = i;
-    parent[is_leaf(c1) ? (n - 1) + leaf_index(c1) : c1] = i;
+    const int32_t links[2] = {c0, c1};
+    for (int k = 0; k < 2; ++k) {
+        const int32_t c = links[k];
+        const int64_t idx = is_leaf(c) ? (int64_t)(n - 1) + leaf_index(c) : c;
+        const bool ok = is_leaf(c) ? (leaf_index(c) < n) : (c > 0 && c < n - 1);
+        if (!ok) {
+            atomicOr(&f->flags, (uint32_t)kBadTree);
+        } else {
+            parent[idx] = i;
+            atomicAdd(&refs[idx], 1u);
+        }
+    }
 }
 
 // Sorted triangle records and leaf bounds (box[n-1+i]).
-__global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris,
-                              const int32_t* __restrict__ tri_mat, const uint32_t* __restrict__ order, int n,
-                              float4* __restrict__ recs, float4* __restrict__ box, uint32_t* __restrict__ seen,
-                              BuildFlags* f)
+__device__ __forceinline__ void tri_record(int i, const float* __restrict__ verts, int64_t nv,
+                                           const int32_t* __restrict__ tris, const int32_t* __restrict__ tri_mat,
+                                           const uint32_t* __restrict__ order, int n, float4* __restrict__ recs,
+                                           float4* __restrict__ box, uint32_t* __restrict__ seen, BuildFlags* f)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     uint32_t t = order[i];
     if (t >= (uint32_t)n) {
         atomicOr(&f->flags, (uint32_t)kBadTree);
@@ -504,8 +623,23 @@ __global__ void k_tri_records(const float* __restrict__ verts, int64_t nv, const
     box[2 * b + 1] = make_float4(hi[0], hi[1], hi[2], 0.0f);
 }
 
+// After the sort: thread i writes leaf i's record and box (i < n) and internal
+// node i's split, children and parent links (i < n - 1).
+template <class K>
+__global__ void __launch_bounds__(kBuildBlock)
+k_leaves_nodes(const float* __restrict__ verts, int64_t nv, const int32_t* __restrict__ tris,
+               const int32_t* __restrict__ tri_mat, const K* __restrict__ keys, const uint32_t* __restrict__ order,
+               int n, float4* __restrict__ recs, float4* __restrict__ box, uint32_t* __restrict__ seen,
+               int2* __restrict__ child, int32_t* __restrict__ parent, int2* __restrict__ range,
+               uint32_t* __restrict__ refs, BuildFlags* f)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n - 1) karras_node<K>(i, keys, n, child, parent, range, refs, f);
+    if (i < n) tri_record(i, verts, nv, tris, tri_mat, order, n, recs, box, seen, f);
+}
+
 // Internal boxes from leaf ranges.  Every internal node of the LBVH covers a
-// contiguous range [lo, hi] of the Morton-sorted leaves (known to k_karras),
+// contiguous range [lo, hi] of the Morton-sorted leaves (known from its split),
 // so its box is the union of the leaf boxes over that range.  A pyramid of
 // unions over aligned blocks (level L, entry m covers leaves
 // [m 2^L, (m + 1) 2^L)) answers each range with at most two blocks per level,
@@ -524,12 +658,20 @@ __device__ __forceinline__ void box_union(float4& lo, float4& hi, const float4 l
 }
 
 // Levels 1..8 of the pyramid: each workgroup reduces its 256 leaves in LDS.
+// Structure check, second half: every node but the root (internal node 0)
+// has exactly one parent link (thread j checks internal node j and leaf j).
 __global__ void __launch_bounds__(kBuildBlock) k_pyr_low(int n, const float4* __restrict__ box, PyrLevels pl,
-                                                         float4* __restrict__ pyr)
+                                                         float4* __restrict__ pyr, const uint32_t* __restrict__ refs,
+                                                         BuildFlags* f)
 {
     __shared__ float4 s_lo[kBuildBlock], s_hi[kBuildBlock];
     const int t = threadIdx.x;
     const int64_t leaf = (int64_t)blockIdx.x * kBuildBlock + t;
+    if (leaf < n) {
+        bool bad = refs[(n - 1) + leaf] != 1u;
+        if (leaf < n - 1) bad = bad || refs[leaf] != (leaf == 0 ? 0u : 1u);
+        if (bad) atomicOr(&f->flags, (uint32_t)kBadTree);
+    }
     const float inf = __builtin_inff();
     float4 lo = make_float4(inf, inf, inf, 0.0f), hi = make_float4(-inf, -inf, -inf, 0.0f);
     if (leaf < n) {
@@ -575,11 +717,34 @@ __global__ void __launch_bounds__(1024) k_pyr_high(PyrLevels pl, float4* __restr
     }
 }
 
-__global__ void k_refit(int n, const int2* __restrict__ range, const float4* __restrict__ box,
-                        const float4* __restrict__ pyr, PyrLevels pl, int32_t* __restrict__ ibox)
+// Push count of binary node i in the 4-wide traversal: its slot count
+// (a leaf child fills one slot, an internal child two) minus the one taken.
+__device__ __forceinline__ int push_weight(int2 c) { return (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1; }
+
+// One record per internal node for the upward walk of k_node_depth: parent,
+// grandparent (-1 past the root, which is node 0), and the push counts of the
+// node and of its parent, so that the walk climbs two levels per load.
+__device__ __forceinline__ void node_up(int i, const int32_t* __restrict__ parent, const int2* __restrict__ child,
+                                        int4* __restrict__ up)
+{
+    const int p = i == 0 ? -1 : parent[i];
+    int gp = -1, wp = 0;
+    if (p >= 0) {
+        gp = p == 0 ? -1 : parent[p];
+        wp = push_weight(child[p]);
+    }
+    up[i] = make_int4(p, gp, push_weight(child[i]), wp);
+}
+
+// Internal node i's box (as order-preserving keys in ibox) from the pyramid,
+// and its record for the upward walk of k_node_depth.
+__global__ void k_refit_up(int n, const int2* __restrict__ range, const float4* __restrict__ box,
+                           const float4* __restrict__ pyr, PyrLevels pl, int32_t* __restrict__ ibox,
+                           const int32_t* __restrict__ parent, const int2* __restrict__ child, int4* __restrict__ up)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
+    node_up(i, parent, child, up);
     const int2 r = range[i];
     const float inf = __builtin_inff();
     float4 lo = make_float4(inf, inf, inf, 0.0f), hi = make_float4(-inf, -inf, -inf, 0.0f);
@@ -607,30 +772,6 @@ __global__ void k_refit(int n, const int2* __restrict__ range, const float4* __r
     q[5] = ordered(hi.z);
 }
 
-// Structure check: every link in range, and every node except the root
-// referenced by exactly one parent (refs indexes internal nodes then leaves).
-__global__ void k_check_links(int n, const int2* __restrict__ child, uint32_t* __restrict__ refs, BuildFlags* f)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    const int2 c = child[i];
-    const int32_t l[2] = {c.x, c.y};
-    for (int k = 0; k < 2; ++k) {
-        const int64_t idx = is_leaf(l[k]) ? (int64_t)(n - 1) + leaf_index(l[k]) : l[k];
-        const bool ok = is_leaf(l[k]) ? (leaf_index(l[k]) < n) : (l[k] > 0 && l[k] < n - 1);
-        if (!ok) atomicOr(&f->flags, (uint32_t)kBadTree);
-        else atomicAdd(&refs[idx], 1u);
-    }
-}
-
-__global__ void k_check_refs(int n, const uint32_t* __restrict__ refs, BuildFlags* f)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 2 * n - 1) return;
-    const uint32_t want = i == 0 ? 0u : 1u;
-    if (refs[i] != want) atomicOr(&f->flags, (uint32_t)kBadTree);
-}
-
 __device__ __forceinline__ void node_box(int n, int32_t link, const float4* __restrict__ box,
                                          const int32_t* __restrict__ ibox, float4& lo, float4& hi)
 {
@@ -645,30 +786,10 @@ __device__ __forceinline__ void node_box(int n, int32_t link, const float4* __re
     }
 }
 
-// Push count of binary node i in the 4-wide traversal: its slot count
-// (a leaf child fills one slot, an internal child two) minus the one taken.
-__device__ __forceinline__ int push_weight(int2 c) { return (is_leaf(c.x) ? 1 : 2) + (is_leaf(c.y) ? 1 : 2) - 1; }
-
-// One record per internal node for the upward walk of k_node_depth: parent,
-// grandparent (-1 past the root, which is node 0), and the push counts of the
-// node and of its parent, so that the walk climbs two levels per load.
-__global__ void k_node_up(int n, const int32_t* __restrict__ parent, const int2* __restrict__ child,
-                          int4* __restrict__ up)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1) return;
-    const int p = i == 0 ? -1 : parent[i];
-    int gp = -1, wp = 0;
-    if (p >= 0) {
-        gp = p == 0 ? -1 : parent[p];
-        wp = push_weight(child[p]);
-    }
-    up[i] = make_int4(p, gp, push_weight(child[i]), wp);
-}
-
 // Depth of every internal node of the binary tree (the root has depth 0), its
-// parity for the 4-wide collapse (written to even and idx4, the scan's input),
-// and the sizes of the 4-wide traversal.  On the path from the root to a
+// parity for the 4-wide collapse (as bits, 64 nodes to a mask word, and the
+// count per block of kBuildBlock nodes; or as flags in even and idx4, the
+// input of a device-wide scan), and the sizes of the 4-wide traversal.  On the path from the root to a
 // leaf, every binary node at even depth becomes a 4-wide node that pushes at
 // most its slot count minus one entries.  Walking up from node i, the push
 // counts of the ancestors at even and at odd distance from i are summed
@@ -676,10 +797,11 @@ __global__ void k_node_up(int n, const int32_t* __restrict__ parent, const int2*
 // those whose distance has the parity of d.  A node with a leaf child ends
 // that leaf's path: its depth + 1 and its sum give the tree depth and the
 // stack bound (maxima over such nodes, reduced over the wave first).  The
-// walk reads one k_node_up record per two levels; it stops past 4 kMaxStack
+// walk reads one node_up record per two levels; it stops past 4 kMaxStack
 // levels (such a tree is rejected by its stack bound).
-__global__ void k_node_depth(int n, const int4* __restrict__ up, const int2* __restrict__ child,
-                             uint32_t* __restrict__ even, uint32_t* __restrict__ idx4, BuildFlags* f)
+__global__ void __launch_bounds__(kBuildBlock)
+k_node_depth(int n, const int4* __restrict__ up, const int2* __restrict__ child, uint64_t* __restrict__ mask,
+             uint32_t* __restrict__ blk_cnt, uint32_t* __restrict__ even, uint32_t* __restrict__ idx4, BuildFlags* f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int depth_leaf = 0, need = 0;
@@ -698,8 +820,10 @@ __global__ void k_node_depth(int n, const int4* __restrict__ up, const int2* __r
             ++d;
         }
         is_even = (d % 2 == 0) ? 1u : 0u;
-        even[i] = is_even;
-        idx4[i] = is_even;
+        if (even) {
+            even[i] = is_even;
+            idx4[i] = is_even;
+        }
         const int2 c = child[i];
         if (is_leaf(c.x) || is_leaf(c.y)) {
             depth_leaf = d + 1;
@@ -708,6 +832,8 @@ __global__ void k_node_depth(int n, const int4* __restrict__ up, const int2* __r
     }
     // maxima and count over the wave, then over the block: one set of
     // atomics per block (every block updates the same three words)
+    const uint64_t bits = __ballot(is_even);
+    if (mask && (threadIdx.x & (kWave - 1)) == 0 && i < n - 1) mask[i / kWave] = bits;
     uint32_t cnt = is_even;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -730,23 +856,61 @@ __global__ void k_node_depth(int n, const int4* __restrict__ up, const int2* __r
             need = max(need, s_need[j]);
             cnt += s_cnt[j];
         }
+        if (blk_cnt) blk_cnt[blockIdx.x] = cnt;
         if (depth_leaf > 0) atomicMax(&f->max_depth, depth_leaf);
         if (need > 0) atomicMax(&f->max_stack, need);
         if (cnt) atomicAdd(&f->n_nodes4, cnt);
     }
 }
 
+// 4-wide index of an even-depth internal node j: the number of even-depth
+// nodes before it.  Either read from the device-wide scan (idx4), or formed
+// from the per-block prefix (pref, in LDS) and the bit masks of j's block.
+struct Index4 {
+    const uint32_t* idx4;
+    const uint64_t* mask;
+    const uint32_t* pref;
+    __device__ __forceinline__ bool even(int j) const { return ((mask[j / kWave] >> (j % kWave)) & 1u) != 0; }
+    __device__ __forceinline__ uint32_t operator()(int j) const
+    {
+        if (idx4) return idx4[j];
+        uint32_t r = pref[j / kBuildBlock];
+        for (int w = (j / kBuildBlock) * (kBuildBlock / kWave); w < j / kWave; ++w) r += __popcll(mask[w]);
+        return r + (uint32_t)__popcll(mask[j / kWave] & lanemask_lt(j % kWave));
+    }
+};
+
 // Collapse of the binary tree into 4-wide nodes: every internal node at an
 // even depth becomes a 4-wide node whose slots are its children, with each
 // internal child replaced by that child's own two children (which sit at the
-// next even depth).  idx4 = exclusive prefix sum of the even-depth flags, so
-// the root becomes node 0 and nodes keep the Morton order of the binary tree.
-__global__ void k_collapse4(int n, const int2* __restrict__ child, const float4* __restrict__ box,
-                            const int32_t* __restrict__ ibox, const uint32_t* __restrict__ even,
-                            const uint32_t* __restrict__ idx4, float4* __restrict__ nodes)
+// next even depth).  Node indices are the exclusive prefix sum of the
+// even-depth flags, so the root becomes node 0 and nodes keep the Morton order
+// of the binary tree.  With the bit masks (mask non-null), the block first
+// scans the n_blk per-block counts into the dynamic LDS array pref.
+__global__ void __launch_bounds__(kBuildBlock)
+k_collapse4(int n, const int2* __restrict__ child, const float4* __restrict__ box, const int32_t* __restrict__ ibox,
+            const uint32_t* __restrict__ even, const uint32_t* __restrict__ idx4, const uint64_t* __restrict__ mask,
+            const uint32_t* __restrict__ blk_cnt, int n_blk, float4* __restrict__ nodes)
 {
+    extern __shared__ uint32_t pref[];
+    if (mask) {
+        __shared__ uint32_t s_wave[kBuildBlock / kWave];
+        const int per = (n_blk + kBuildBlock - 1) / kBuildBlock;
+        const int b0 = threadIdx.x * per;
+        uint32_t v = 0;
+        for (int k = 0; k < per; ++k)
+            if (b0 + k < n_blk) v += blk_cnt[b0 + k];
+        uint32_t run = block_exclusive(v, s_wave);
+        for (int k = 0; k < per; ++k)
+            if (b0 + k < n_blk) {
+                pref[b0 + k] = run;
+                run += blk_cnt[b0 + k];
+            }
+        __syncthreads();
+    }
+    const Index4 ix{mask ? nullptr : idx4, mask, pref};
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n - 1 || !even[i]) return;
+    if (i >= n - 1 || !(mask ? ix.even(i) : even[i] != 0u)) return;
     int32_t links[4];
     float4 lo[4], hi[4];
     int k = 0;
@@ -761,7 +925,7 @@ __global__ void k_collapse4(int n, const int2* __restrict__ child, const float4*
             const int32_t gs[2] = {g.x, g.y};
             for (int b = 0; b < 2; ++b) {
                 node_box(n, gs[b], box, ibox, lo[k], hi[k]);
-                links[k++] = is_leaf(gs[b]) ? gs[b] : (int32_t)idx4[gs[b]];
+                links[k++] = is_leaf(gs[b]) ? gs[b] : (int32_t)ix(gs[b]);
             }
         }
     }
@@ -773,7 +937,7 @@ __global__ void k_collapse4(int n, const int2* __restrict__ child, const float4*
         hi[k] = lo[k];
         links[k] = leaf_link(0);
     }
-    float4* o = nodes + (int64_t)kNode4 * idx4[i];
+    float4* o = nodes + (int64_t)kNode4 * ix(i);
     for (int j = 0; j < 4; ++j) {
         o[2 * j] = make_float4(lo[j].x, lo[j].y, lo[j].z, __int_as_float(links[j]));
         o[2 * j + 1] = make_float4(hi[j].x, hi[j].y, hi[j].z, 0.0f);
@@ -868,19 +1032,26 @@ void scan_exclusive(uint32_t* data, int64_t len, uint32_t* sums, hipStream_t st)
 }
 
 // Morton keys of the centroids and a stable LSD radix sort of (key, triangle)
-// pairs, eight bits per pass; the sorted pairs end in (k0, v0).
+// pairs, eight bits per pass (an even number of passes, so the sorted pairs
+// end in (k0, v0)).  The first count also reduces k_prep's per-block results
+// into the flag record.
 template <class K>
-void morton_sort(const float4* cent, int64_t n, BuildFlags* flags, K* k0, K* k1, uint32_t* v0, uint32_t* v1,
-                 uint32_t* counts, uint32_t* sums, int n_tiles, hipStream_t st)
+void morton_sort(const float4* cent, int64_t n, const PrepPartial* part, int n_part, BuildFlags* flags, K* k0,
+                 K* k1, uint32_t* v0, uint32_t* v1, uint32_t* counts, uint32_t* sums, int n_tiles, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_morton<K>, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, cent, n, flags, k0, v0);
+    const bool fused = n_tiles <= kFusedScanTiles;
     K *ki = k0, *ko = k1;
     uint32_t *vi = v0, *vo = v1;
     for (int shift = 0; shift < 8 * (int)sizeof(K); shift += 8) {
-        hipLaunchKernelGGL(k_radix_count<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n, shift, counts, n_tiles);
-        scan_exclusive(counts, (int64_t)256 * n_tiles, sums, st);
+        if (shift == 0)
+            hipLaunchKernelGGL(k_morton_count<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, cent, n, part, n_part,
+                               flags, k0, v0, counts, n_tiles);
+        else
+            hipLaunchKernelGGL(k_radix_count<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, n, shift, counts,
+                               n_tiles);
+        if (!fused) scan_exclusive(counts, (int64_t)256 * n_tiles, sums, st);
         hipLaunchKernelGGL(k_radix_scatter<K>, dim3(n_tiles), dim3(kBuildBlock), 0, st, ki, vi, n, shift, counts,
-                           n_tiles, ko, vo, flags);
+                           n_tiles, fused, ko, vo, flags);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
@@ -942,13 +1113,20 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     TRY(hipMalloc(&sc->mats, sizeof(float) * kMatStride * n_materials));
     TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
     TRY(hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * (size_t)(n > 1 ? n - 1 : 1)));
+    DevBuf<PrepPartial> part;
     DevBuf<float4> cent, box;
     DevBuf<uint64_t> k0, k1;  // Morton keys: 32 or 64 bits each
-    DevBuf<uint32_t> v0, v1, counts, seen, refs, even, idx4, scan_sums;
+    DevBuf<uint32_t> v0, v1, counts, seen, refs, even, idx4, blk_cnt, scan_sums;
+    DevBuf<uint64_t> mask;
     DevBuf<int32_t> ibox, parent;
     DevBuf<int2> child, range;
     DevBuf<float4> pyr;
     const int n_tiles = (int)blocks(n > 0 ? n : 1, kSortTile);
+    const int n_blk = (int)blocks(n > 1 ? n - 1 : 1, kBuildBlock);
+    const bool fused_index = n_blk <= kFusedIndexBlocks;
+    const int n_part = (int)std::min<unsigned>(
+        std::max({blocks(n, kPrepBlock), blocks(n_materials, kPrepBlock), 1u}), (unsigned)kPrepBlocks);
+    TRY(part.alloc(n_part));
     if (n > 0) {
         TRY(cent.alloc(n));
         TRY(k0.alloc(n));
@@ -964,44 +1142,39 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(parent.alloc(2 * (size_t)n - 1));
         TRY(ibox.alloc(6 * (size_t)(n > 1 ? n - 1 : 1)));
         TRY(seen.alloc(n));
-        TRY(even.alloc(n > 1 ? n - 1 : 1));
-        TRY(idx4.alloc(n > 1 ? n - 1 : 1));
+        if (fused_index) {
+            TRY(mask.alloc(blocks(n > 1 ? n - 1 : 1, kWave)));
+            TRY(blk_cnt.alloc(n_blk));
+        } else {
+            TRY(even.alloc(n - 1));
+            TRY(idx4.alloc(n - 1));
+        }
         TRY(refs.alloc(2 * (size_t)n - 1));
         TRY(scan_sums.alloc(std::max<size_t>(blocks((int64_t)256 * n_tiles, kSortTile), blocks(n, kSortTile))));
     }
-    TRY(arena_place(arena, flags, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, ibox, parent, child,
-                    range, pyr, scan_sums));
-    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(64), 0, st, flags.p);
-    hipLaunchKernelGGL(k_materials, dim3(blocks(n_materials, 64)), dim3(64), 0, st, absorption, scattering,
-                       n_materials, n_bands, sc->mats, flags.p);
+    TRY(arena_place(arena, flags, part, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, blk_cnt, mask,
+                    ibox, parent, child, range, pyr, scan_sums));
+    hipLaunchKernelGGL(k_prep, dim3(n_part), dim3(kPrepBlock), 0, st, verts, n_verts, tris, n_tris, tri_material,
+                       absorption, scattering, n_materials, n_bands, sc->mats, cent.p, seen.p, refs.p, parent.p,
+                       part.p);
     TRY(hipGetLastError());
 
     if (n > 0) {
-        hipLaunchKernelGGL(k_prep, dim3(std::min(blocks(n, kBuildBlock), (unsigned)kPrepBlocks)), dim3(kBuildBlock), 0, st,
-                           verts, n_verts, tris,
-                           n_tris, tri_material, n_materials, cent.p, seen.p, refs.p, flags.p);
         const bool wide = n >= kWideKeyTris;
-        if (wide) morton_sort<uint64_t>(cent.p, n_tris, flags.p, (uint64_t*)k0.p, (uint64_t*)k1.p, v0.p, v1.p, counts.p,
-                                        scan_sums.p, n_tiles, st);
-        else morton_sort<uint32_t>(cent.p, n_tris, flags.p, (uint32_t*)k0.p, (uint32_t*)k1.p, v0.p, v1.p, counts.p,
-                                   scan_sums.p, n_tiles, st);
-        uint32_t* vi = v0.p;
-        // after an even number of passes the sorted keys/ids are back in (k0, v0)
-        TRY(hipMemsetAsync(parent.p, 0xFF, sizeof(int32_t) * (2 * (size_t)n - 1), st));
-
-        hipLaunchKernelGGL(k_tri_records, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, verts,
-                           n_verts, tris, tri_material, vi, n, sc->tris, box.p, seen.p, flags.p);
+        if (wide) {
+            morton_sort<uint64_t>(cent.p, n_tris, part.p, n_part, flags.p, (uint64_t*)k0.p, (uint64_t*)k1.p, v0.p,
+                                  v1.p, counts.p, scan_sums.p, n_tiles, st);
+            hipLaunchKernelGGL(k_leaves_nodes<uint64_t>, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st,
+                               verts, n_verts, tris, tri_material, (const uint64_t*)k0.p, v0.p, n, sc->tris, box.p,
+                               seen.p, child.p, parent.p, range.p, refs.p, flags.p);
+        } else {
+            morton_sort<uint32_t>(cent.p, n_tris, part.p, n_part, flags.p, (uint32_t*)k0.p, (uint32_t*)k1.p, v0.p,
+                                  v1.p, counts.p, scan_sums.p, n_tiles, st);
+            hipLaunchKernelGGL(k_leaves_nodes<uint32_t>, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st,
+                               verts, n_verts, tris, tri_material, (const uint32_t*)k0.p, v0.p, n, sc->tris, box.p,
+                               seen.p, child.p, parent.p, range.p, refs.p, flags.p);
+        }
         if (n > 1) {
-            if (wide)
-                hipLaunchKernelGGL(k_karras<uint64_t>, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st,
-                                   (const uint64_t*)k0.p, n, child.p, parent.p, range.p, flags.p);
-            else
-                hipLaunchKernelGGL(k_karras<uint32_t>, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st,
-                                   (const uint32_t*)k0.p, n, child.p, parent.p, range.p, flags.p);
-            hipLaunchKernelGGL(k_check_links, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n,
-                               child.p, refs.p, flags.p);
-            hipLaunchKernelGGL(k_check_refs, dim3(blocks(2 * (int64_t)n - 1, kBuildBlock)), dim3(kBuildBlock), 0,
-                               st, n, refs.p, flags.p);
             PyrLevels pl;
             std::memset(&pl, 0, sizeof(pl));
             int64_t off = 0, len = n;
@@ -1013,19 +1186,21 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                 pl.len[pl.top] = len;
                 off += len;
             }
-            hipLaunchKernelGGL(k_pyr_low, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, box.p, pl, pyr.p);
+            hipLaunchKernelGGL(k_pyr_low, dim3(blocks(n, kBuildBlock)), dim3(kBuildBlock), 0, st, n, box.p, pl, pyr.p,
+                               refs.p, flags.p);
             if (pl.top > 8) hipLaunchKernelGGL(k_pyr_high, dim3(1), dim3(1024), 0, st, pl, pyr.p);
-            hipLaunchKernelGGL(k_refit, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, range.p, box.p,
-                               pyr.p, pl, ibox.p);
             // the centroids are dead after the Morton codes: their n float4 hold the n - 1 walk records
             int4* up = reinterpret_cast<int4*>(cent.p);
-            hipLaunchKernelGGL(k_node_up, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, parent.p,
-                               child.p, up);
-            hipLaunchKernelGGL(k_node_depth, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, up,
-                               child.p, even.p, idx4.p, flags.p);
-            scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
-            hipLaunchKernelGGL(k_collapse4, dim3(blocks(n - 1, kBuildBlock)), dim3(kBuildBlock), 0, st, n, child.p,
-                               box.p, ibox.p, even.p, idx4.p, sc->nodes);
+            hipLaunchKernelGGL(k_refit_up, dim3(n_blk), dim3(kBuildBlock), 0, st, n, range.p, box.p, pyr.p, pl,
+                               ibox.p, parent.p, child.p, up);
+            hipLaunchKernelGGL(k_node_depth, dim3(n_blk), dim3(kBuildBlock), 0, st, n, up, child.p,
+                               fused_index ? mask.p : nullptr, fused_index ? blk_cnt.p : nullptr,
+                               fused_index ? nullptr : even.p, fused_index ? nullptr : idx4.p, flags.p);
+            if (!fused_index) scan_exclusive(idx4.p, (int64_t)(n - 1), scan_sums.p, st);
+            hipLaunchKernelGGL(k_collapse4, dim3(n_blk), dim3(kBuildBlock),
+                               fused_index ? sizeof(uint32_t) * n_blk : 0, st, n, child.p, box.p, ibox.p,
+                               fused_index ? nullptr : even.p, fused_index ? nullptr : idx4.p,
+                               fused_index ? mask.p : nullptr, fused_index ? blk_cnt.p : nullptr, n_blk, sc->nodes);
         }
         TRY(hipGetLastError());
         BuildFlags hf;
@@ -1050,6 +1225,8 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
                                   "scene_create: BVH depth %d needs %d stack entries, the traversal takes at most %d",
                                   sc->max_depth, sc->stack_need, kMaxStack - 1));
     } else {
+        hipLaunchKernelGGL(k_flags_only, dim3(1), dim3(kWave), 0, st, part.p, n_part, flags.p);
+        TRY(hipGetLastError());
         BuildFlags hf;
         TRY(read_flags(arena, flags.p, st, &hf));
         if (hf.flags & kBadCoeff)
