@@ -1136,22 +1136,26 @@ def main():
         a.quiet)
 
     # Steps are independent (same scene, same rays), so consecutive steps are
-    # pipelined on several streams (--streams) with their own outputs: step i+1's BVH build
-    # (scene_create waits for its own stream only) and trace start while the
+    # pipelined on several streams (--streams) with their own outputs and their
+    # own scene, which each step rebuilds in place from the triangles
+    # (scene_rebuild: the whole BVH build, into the scene's own arrays, waiting
+    # for its own stream only): step i+1's build and trace start while the
     # longest rays of step i are still bouncing.  Every step does all of its
     # own work; --serial runs them one after another on one stream.
     n_pipe = 1 if a.serial else max(1, a.streams)
     streams = [stream] if a.serial else [torch.cuda.Stream(device=dev) for _ in range(n_pipe)]
     outs = [(hist, late, stats, params)] + [(*P.alloc_trace_outputs(S, T, B, n, device=dev)[:3],
                                              P.alloc_params(S, device=dev)) for _ in range(n_pipe - 1)]
+    pipe_scenes = [P.Scene(verts, tris, tmat, absb, scat, device=dev) for _ in range(n_pipe)]
     rec = []  # per timed step: (build ms, trace events, estimate events)
 
     def step(i, record):
         st_, (h_, l_, s_, p_) = streams[i % n_pipe], outs[i % n_pipe]
+        sc = pipe_scenes[i % n_pipe]
         with torch.cuda.stream(st_):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             ev[3].record(st_)
-            sc = P.Scene(verts, tris, tmat, absb, scat, device=dev)  # waits for this stream only
+            sc.rebuild(verts, tris, tmat, absb, scat)
             ev[0].record(st_)
             P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, h_, l_, s_)
             ev[1].record(st_)
@@ -1159,23 +1163,17 @@ def main():
             ev[2].record(st_)
         if record:
             rec.append(ev)
-        return sc
 
-    keep = []
     for i in range(a.warmup):
-        keep.append(step(i, False))
-    torch.cuda.synchronize()
-    for s_ in keep:
-        s_.close()
+        step(i, False)
     # timed region: exactly `steps` steps, synchronised on both sides
-    scenes = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(a.steps):
-        scenes.append(step(i, True))
+        step(i, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    for s_ in scenes:
+    for s_ in pipe_scenes:
         s_.close()
     t_build = [ev[3].elapsed_time(ev[0]) for ev in rec]
     t_trace = [ev[0].elapsed_time(ev[1]) for ev in rec]

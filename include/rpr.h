@@ -157,8 +157,8 @@ typedef struct {
 
 /* Build a scene and its BVH (linear BVH: Morton codes of triangle centroids,
  * 30-bit, or 63-bit from 2^19 triangles on, radix sort, hierarchy from
- * longest common key prefixes, bottom-up bounds, collapsed into 4-wide nodes
- * for traversal).
+ * longest common key prefixes, node boxes over each node's range of leaves,
+ * collapsed into 4-wide nodes for traversal).
  *   verts        device [n_verts][3] f32, metres
  *   tris         device [n_tris][3] i32 vertex indices
  *   tri_material device [n_tris] i32 in [0, n_materials), or NULL = material 0
@@ -173,6 +173,20 @@ typedef struct {
 int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                  const int32_t* tri_material, const float* absorption, const float* scattering,
                  int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out);
+/* Rebuild a scene in place from new geometry and materials (the same
+ * arguments and build as scene_create), for scenes that change from frame to
+ * frame (Section 5: the propagation update runs every frame).  The build
+ * writes into the scene's own arrays when the new triangles and materials fit
+ * what it holds (no allocation); otherwise the arrays grow first (hipFree and
+ * hipMalloc, which wait for the device's pending work).  The rebuild is
+ * stream-ordered on hip_stream: work that reads the scene on other streams
+ * must be complete before the call.  Synchronises hip_stream, as scene_create.
+ * Errors: those of scene_create, and RPR_EINVAL if the current device is not
+ * the scene's; after an error the scene holds no triangles (every ray
+ * escapes) until a rebuild succeeds. */
+int scene_rebuild(RprScene* scene, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                  const int32_t* tri_material, const float* absorption, const float* scattering,
+                  int32_t n_materials, int32_t n_bands, void* hip_stream);
 int scene_destroy(RprScene* scene);
 int scene_info(const RprScene* scene, RprSceneInfo* out /* host */);
 

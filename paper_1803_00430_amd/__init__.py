@@ -153,6 +153,7 @@ _i32 = C.c_int32
 # name -> (restype, argtypes); every entry point of include/rpr.h
 SIGNATURES = {
     "scene_create": (C.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
+    "scene_rebuild": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
     "scene_destroy": (C.c_int, [_vp]),
     "scene_info": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
     "trace_ir": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp, _vp,
@@ -279,6 +280,23 @@ class Scene:
     @classmethod
     def from_dict(cls, d, **kw):
         return cls(d["verts"], d["tris"], d.get("tri_mat"), d["absorption"], d["scattering"], **kw)
+
+    def rebuild(self, verts, tris, tri_mat, absorption, scattering, stream=None):
+        """Rebuild this scene in place from new geometry and materials
+        (scene_rebuild: no allocation when they fit what the scene holds)."""
+        v = _dev_f32(verts, self.device).reshape(-1, 3)
+        t = _dev_i32(tris, self.device).reshape(-1, 3)
+        m = None if tri_mat is None else _dev_i32(tri_mat, self.device).reshape(-1)
+        a = _dev_f32(absorption, self.device)
+        s = _dev_f32(scattering, self.device)
+        if a.dim() != 2 or a.shape != s.shape:
+            raise ValueError("absorption and scattering must both be [materials, bands]")
+        nm, nb = int(a.shape[0]), int(a.shape[1])
+        rc = lib().scene_rebuild(self.handle, _ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(m), _ptr(a), _ptr(s),
+                                 nm, nb, _stream(stream))
+        # the scene's band count follows the call even when the build fails
+        self.n_materials, self.n_bands = nm, nb
+        _check(rc)
 
     @property
     def handle(self):

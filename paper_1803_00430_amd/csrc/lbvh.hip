@@ -1062,57 +1062,101 @@ void morton_sort(const float4* cent, int64_t n, const PrepPartial* part, int n_p
 
 using namespace rpr;
 
-extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
-                            const int32_t* tri_material, const float* absorption, const float* scattering,
-                            int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out)
-{
-    if (!out) return set_error(RPR_EINVAL, "scene_create: out is null");
-    *out = nullptr;
-    if (n_bands < 1 || n_bands > RPR_MAX_BANDS)
-        return set_error(RPR_EINVAL, "scene_create: n_bands=%d not in 1..%d", n_bands, RPR_MAX_BANDS);
-    if (n_materials < 1) return set_error(RPR_EINVAL, "scene_create: n_materials=%d < 1", n_materials);
-    if (n_tris < 0 || n_verts < 0) return set_error(RPR_EINVAL, "scene_create: negative size");
-    if (n_tris > (int64_t)1 << 30) return set_error(RPR_EUNSUPPORTED, "scene_create: n_tris=%lld too large", (long long)n_tris);
-    if (n_tris > 0 && (!verts || !tris || n_verts < 1))
-        return set_error(RPR_EINVAL, "scene_create: null geometry with n_tris=%lld", (long long)n_tris);
-    if (!absorption || !scattering) return set_error(RPR_EINVAL, "scene_create: null material arrays");
-    hipStream_t st = (hipStream_t)hip_stream;
-    const int n = (int)n_tris;
+namespace {
 
-    RprScene* sc = new RprScene();
-    auto fail = [&](int code) {
-        if (sc->nodes) (void)hipFree(sc->nodes);
-        if (sc->tris) (void)hipFree(sc->tris);
-        if (sc->mats) (void)hipFree(sc->mats);
-        workspace_free(sc->ws);
-        delete sc;
-        return code;
-    };
-    {
-        hipError_t e = hipGetDevice(&sc->device);
-        if (e != hipSuccess) return fail(set_error(RPR_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)));
+// Arguments shared by scene_create and scene_rebuild; `who` names the call in errors.
+int check_args(const char* who, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+               const float* absorption, const float* scattering, int32_t n_materials, int32_t n_bands)
+{
+    if (n_bands < 1 || n_bands > RPR_MAX_BANDS)
+        return set_error(RPR_EINVAL, "%s: n_bands=%d not in 1..%d", who, n_bands, RPR_MAX_BANDS);
+    if (n_materials < 1) return set_error(RPR_EINVAL, "%s: n_materials=%d < 1", who, n_materials);
+    if (n_tris < 0 || n_verts < 0) return set_error(RPR_EINVAL, "%s: negative size", who);
+    if (n_tris > (int64_t)1 << 30)
+        return set_error(RPR_EUNSUPPORTED, "%s: n_tris=%lld too large", who, (long long)n_tris);
+    if (n_tris > 0 && (!verts || !tris || n_verts < 1))
+        return set_error(RPR_EINVAL, "%s: null geometry with n_tris=%lld", who, (long long)n_tris);
+    if (!absorption || !scattering) return set_error(RPR_EINVAL, "%s: null material arrays", who);
+    return RPR_OK;
+}
+
+void free_scene_memory(RprScene* sc)
+{
+    if (sc->nodes) (void)hipFree(sc->nodes);
+    if (sc->tris) (void)hipFree(sc->tris);
+    if (sc->mats) (void)hipFree(sc->mats);
+    sc->nodes = sc->tris = nullptr;
+    sc->mats = nullptr;
+    sc->cap_tris = 0;
+    sc->cap_materials = 0;
+}
+
+// The scene's own arrays: material records, triangle records and 4-wide nodes
+// for up to cap_tris triangles and cap_materials materials.
+int alloc_scene(RprScene* sc, const char* who, int64_t cap_tris, int32_t cap_materials)
+{
+    const size_t nt = (size_t)(cap_tris > 0 ? cap_tris : 1);
+    const size_t nn = (size_t)(cap_tris > 1 ? cap_tris - 1 : 1);
+    hipError_t e = hipMalloc(&sc->mats, sizeof(float) * kMatStride * cap_materials);
+    if (e == hipSuccess) e = hipMalloc(&sc->tris, sizeof(float4) * 3 * nt);
+    if (e == hipSuccess) e = hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * nn);
+    if (e != hipSuccess) {
+        free_scene_memory(sc);
+        return set_error(e == hipErrorOutOfMemory ? RPR_ENOMEM : RPR_EDEVICE, "%s: hipMalloc: %s", who,
+                         hipGetErrorString(e));
     }
-    sc->n_tris = n_tris;
+    sc->cap_tris = cap_tris;
+    sc->cap_materials = cap_materials;
+    return RPR_OK;
+}
+
+// An empty scene: every ray escapes.  A failed build leaves the scene so.
+void set_empty(RprScene* sc)
+{
+    sc->n_tris = 0;
+    sc->max_depth = 0;
+    sc->stack_need = 0;
+    sc->n_nodes4 = 0;
+    sc->n_degenerate = 0;
+    for (int a = 0; a < 3; ++a) sc->lo[a] = sc->hi[a] = 0.0f;
+    sc->view.nodes = sc->nodes;
+    sc->view.tris = sc->tris;
+    sc->view.mats = sc->mats;
+    sc->view.root = 0;
+    sc->view.n_tris = 0;
+    sc->view.n_bands = sc->n_bands;
+}
+
+// Build the material table, triangle records and BVH into the scene's arrays
+// (which hold at least n_tris triangles and n_materials materials), on
+// hip_stream, and read the build's flags back.
+int build_scene(RprScene* sc, const char* who, const float* verts, int64_t n_verts, const int32_t* tris,
+                int64_t n_tris, const int32_t* tri_material, const float* absorption, const float* scattering,
+                int32_t n_materials, int32_t n_bands, hipStream_t st)
+{
+    const int n = (int)n_tris;
     sc->n_bands = n_bands;
     sc->n_materials = n_materials;
+    set_empty(sc);
+    auto fail = [&](int code) {
+        set_empty(sc);
+        return code;
+    };
 
 #define TRY(expr)                                                                                 \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
         if (e_ != hipSuccess)                                                                     \
             return fail(set_error(e_ == hipErrorOutOfMemory ? RPR_ENOMEM : RPR_EDEVICE,           \
-                                  "scene_create: %s: %s", #expr, hipGetErrorString(e_)));         \
+                                  "%s: %s: %s", who, #expr, hipGetErrorString(e_)));              \
     } while (0)
 
     int dev = sc->device;
-    if (dev < 0 || dev >= 16) return fail(set_error(RPR_EUNSUPPORTED, "scene_create: device %d", dev));
+    if (dev < 0 || dev >= 16) return fail(set_error(RPR_EUNSUPPORTED, "%s: device %d", who, dev));
     Arena& arena = g_arena[dev];
     std::lock_guard<std::mutex> arena_lock(arena.mu);
     DevBuf<BuildFlags> flags;
     TRY(flags.alloc(1));
-    TRY(hipMalloc(&sc->mats, sizeof(float) * kMatStride * n_materials));
-    TRY(hipMalloc(&sc->tris, sizeof(float4) * 3 * (size_t)(n > 0 ? n : 1)));
-    TRY(hipMalloc(&sc->nodes, sizeof(float4) * kNode4 * (size_t)(n > 1 ? n - 1 : 1)));
     DevBuf<PrepPartial> part;
     DevBuf<float4> cent, box;
     DevBuf<uint64_t> k0, k1;  // Morton keys: 32 or 64 bits each
@@ -1205,12 +1249,12 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         TRY(hipGetLastError());
         BuildFlags hf;
         TRY(read_flags(arena, flags.p, st, &hf));
-        if (hf.flags & kBadIndex) return fail(set_error(RPR_EINVAL, "scene_create: vertex index out of range"));
-        if (hf.flags & kBadVertex) return fail(set_error(RPR_EINVAL, "scene_create: non-finite vertex"));
-        if (hf.flags & kBadMaterial) return fail(set_error(RPR_EINVAL, "scene_create: material index out of range"));
+        if (hf.flags & kBadIndex) return fail(set_error(RPR_EINVAL, "%s: vertex index out of range", who));
+        if (hf.flags & kBadVertex) return fail(set_error(RPR_EINVAL, "%s: non-finite vertex", who));
+        if (hf.flags & kBadMaterial) return fail(set_error(RPR_EINVAL, "%s: material index out of range", who));
         if (hf.flags & kBadCoeff)
-            return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
-        if (hf.flags & kBadTree) return fail(set_error(RPR_EDEVICE, "scene_create: BVH consistency check failed"));
+            return fail(set_error(RPR_EINVAL, "%s: absorption/scattering outside [0, 1]", who));
+        if (hf.flags & kBadTree) return fail(set_error(RPR_EDEVICE, "%s: BVH consistency check failed", who));
         sc->max_depth = hf.max_depth;
         sc->stack_need = hf.max_stack;
         sc->n_nodes4 = hf.n_nodes4;
@@ -1222,25 +1266,81 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
         // the traversal writes one slot past the deepest entry (a push without a branch)
         if (sc->stack_need >= kMaxStack)
             return fail(set_error(RPR_EUNSUPPORTED,
-                                  "scene_create: BVH depth %d needs %d stack entries, the traversal takes at most %d",
-                                  sc->max_depth, sc->stack_need, kMaxStack - 1));
+                                  "%s: BVH depth %d needs %d stack entries, the traversal takes at most %d",
+                                  who, sc->max_depth, sc->stack_need, kMaxStack - 1));
     } else {
         hipLaunchKernelGGL(k_flags_only, dim3(1), dim3(kWave), 0, st, part.p, n_part, flags.p);
         TRY(hipGetLastError());
         BuildFlags hf;
         TRY(read_flags(arena, flags.p, st, &hf));
         if (hf.flags & kBadCoeff)
-            return fail(set_error(RPR_EINVAL, "scene_create: absorption/scattering outside [0, 1]"));
+            return fail(set_error(RPR_EINVAL, "%s: absorption/scattering outside [0, 1]", who));
     }
 #undef TRY
+    sc->n_tris = n_tris;
     sc->view.nodes = sc->nodes;
     sc->view.tris = sc->tris;
     sc->view.mats = sc->mats;
     sc->view.root = n == 1 ? leaf_link(0) : 0;
     sc->view.n_tris = n;
     sc->view.n_bands = n_bands;
+    return RPR_OK;
+}
+
+}  // namespace
+
+extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                            const int32_t* tri_material, const float* absorption, const float* scattering,
+                            int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out)
+{
+    if (!out) return set_error(RPR_EINVAL, "scene_create: out is null");
+    *out = nullptr;
+    int rc = check_args("scene_create", verts, n_verts, tris, n_tris, absorption, scattering, n_materials, n_bands);
+    if (rc != RPR_OK) return rc;
+    RprScene* sc = new RprScene();
+    hipError_t e = hipGetDevice(&sc->device);
+    rc = e != hipSuccess ? set_error(RPR_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)) : RPR_OK;
+    if (rc == RPR_OK) rc = alloc_scene(sc, "scene_create", n_tris, n_materials);
+    if (rc == RPR_OK)
+        rc = build_scene(sc, "scene_create", verts, n_verts, tris, n_tris, tri_material, absorption, scattering,
+                         n_materials, n_bands, (hipStream_t)hip_stream);
+    if (rc != RPR_OK) {
+        free_scene_memory(sc);
+        workspace_free(sc->ws);
+        delete sc;
+        return rc;
+    }
     *out = sc;
     return RPR_OK;
+}
+
+extern "C" int scene_rebuild(RprScene* scene, const float* verts, int64_t n_verts, const int32_t* tris,
+                             int64_t n_tris, const int32_t* tri_material, const float* absorption,
+                             const float* scattering, int32_t n_materials, int32_t n_bands, void* hip_stream)
+{
+    if (!scene) return set_error(RPR_EINVAL, "scene_rebuild: scene is null");
+    int rc = check_args("scene_rebuild", verts, n_verts, tris, n_tris, absorption, scattering, n_materials, n_bands);
+    if (rc != RPR_OK) return rc;
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return set_error(RPR_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev != scene->device)
+        return set_error(RPR_EINVAL, "scene_rebuild: the scene is on device %d, the current device is %d",
+                         scene->device, dev);
+    if (n_tris > scene->cap_tris || n_materials > scene->cap_materials) {
+        // grow (never shrink) the arrays; hipFree waits for the device's pending work
+        const int64_t cap_tris = std::max(n_tris, scene->cap_tris);
+        const int32_t cap_materials = std::max(n_materials, scene->cap_materials);
+        free_scene_memory(scene);
+        set_empty(scene);
+        rc = alloc_scene(scene, "scene_rebuild", cap_tris, cap_materials);
+        if (rc != RPR_OK) {
+            set_empty(scene);
+            return rc;
+        }
+    }
+    return build_scene(scene, "scene_rebuild", verts, n_verts, tris, n_tris, tri_material, absorption, scattering,
+                       n_materials, n_bands, (hipStream_t)hip_stream);
 }
 
 extern "C" int scene_destroy(RprScene* scene)

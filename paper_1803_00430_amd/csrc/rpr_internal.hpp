@@ -112,6 +112,8 @@ struct RprScene {
     int32_t stack_need = 0;    // traversal stack entries the 4-wide tree can need
     int64_t n_nodes4 = 0;
     int32_t n_degenerate = 0;
+    int64_t cap_tris = 0;        // triangles and materials the arrays below hold
+    int32_t cap_materials = 0;
     float lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
     float4* nodes = nullptr;
     float4* tris = nullptr;

@@ -391,9 +391,8 @@ struct SetupArgs {
     unsigned long long* queue;
 };
 
-__global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
+__device__ __forceinline__ void setup_pair(const SetupArgs& a, PairDesc* __restrict__ out, int i)
 {
-    const int i = threadIdx.x;
     if (i == 0 && a.s0 == 0) *a.queue = 0ull;
     if (i >= a.ns) return;
     const int s = a.s0 + i;
@@ -411,6 +410,26 @@ __global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out)
     d.late_fx = a.base.late_fx ? a.base.late_fx + (size_t)s * a.late_stride : nullptr;
     out[s] = d;
     stats_init(d.stats);
+}
+
+__global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out) { setup_pair(a, out, threadIdx.x); }
+
+// The last (usually the only) chunk of pair descriptors, in the same launch
+// as the clearing of the outputs the trace accumulates into: block 0 writes
+// the descriptors, and every block clears its grid-stride share of up to
+// three ranges (null when absent).
+__global__ void __launch_bounds__(256) k_setup_fill(SetupArgs a, PairDesc* __restrict__ out, float* __restrict__ z0,
+                                                    size_t n0, float* __restrict__ z1, size_t n1,
+                                                    float* __restrict__ z2, size_t n2)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kSetupChunk) setup_pair(a, out, threadIdx.x);
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t i0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (size_t i = i0; i < n0; i += stride) z0[i] = 0.0f;
+    if (z1)
+        for (size_t i = i0; i < n1; i += stride) z1[i] = 0.0f;
+    if (z2)
+        for (size_t i = i0; i < n2; i += stride) z2[i] = 0.0f;
 }
 
 // Segment budget, second pass: from each source's segment count of the
@@ -822,26 +841,24 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     a.hist_stride = (long long)hist_stride;
     a.late_stride = (long long)late_stride;
     a.queue = d_queue;
+    // outputs cleared before the trace accumulates into them (the fixed-point
+    // cells as zero bits, written as floats)
+    const size_t nh = hist_stride * n_src;
+    float* fx0 = det ? (float*)((char*)ws + workspace_fx_offset((size_t)n_src)) : nullptr;
+    const size_t nf = det ? fx_cells * 2 : 0;
+    const size_t nl = hist_late ? late_stride * n_src : 0;
+    const size_t fill_blocks = std::min<size_t>(std::max({(nh + 255) / 256, (nf + 255) / 256, (nl + 255) / 256,
+                                                          (size_t)1}), 16384);
     for (int s0 = 0; s0 < n_src; s0 += kSetupChunk) {
         a.s0 = s0;
         a.ns = std::min(kSetupChunk, n_src - s0);
         for (int i = 0; i < a.ns; ++i)
             for (int c = 0; c < 3; ++c) a.src[i][c] = srcs[s0 + i].pos[c];
-        hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupChunk), 0, st, a, d_pairs);
-    }
-    const size_t nh = hist_stride * n_src;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nh + 255) / 256, 16384)), dim3(256), 0, st, hist, nh,
-                       0.0f);
-    if (det) {
-        float* fx0 = (float*)((char*)ws + workspace_fx_offset((size_t)n_src));
-        const size_t nf = fx_cells * 2;  // zero bits, as floats
-        hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nf + 255) / 256, 16384)), dim3(256), 0, st, fx0,
-                           nf, 0.0f);
-    }
-    if (hist_late) {
-        const size_t nl = late_stride * n_src;
-        hipLaunchKernelGGL(k_fill, dim3((unsigned)std::min<size_t>((nl + 255) / 256, 16384)), dim3(256), 0, st,
-                           hist_late, nl, 0.0f);
+        if (s0 + kSetupChunk < n_src)
+            hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupChunk), 0, st, a, d_pairs);
+        else
+            hipLaunchKernelGGL(k_setup_fill, dim3((unsigned)fill_blocks), dim3(256), 0, st, a, d_pairs, hist, nh, fx0,
+                               nf, hist_late, nl);
     }
     RPR_HIP_TRY(hipGetLastError());
     const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;

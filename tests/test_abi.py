@@ -30,6 +30,8 @@ def test_invalid_arguments_fail_before_any_launch():
     rc = L.scene_create(None, 0, None, 0, None, None, None, 1, 9, None, C.byref(out))
     assert rc == -1 and out.value is None
     assert b"n_bands" in L.last_error()
+    assert L.scene_rebuild(None, None, 0, None, 0, None, None, None, 1, 4, None) == -1
+    assert b"scene is null" in L.last_error()
     assert L.trace_ir(None, None, 0, None, None, None, None, None, None, None) == -1
     ep = P.EstimateParams(0, 3)
     assert L.estimate_reverb(None, None, None, 1, 10, 4, 4, 1e-3, C.byref(ep), None, None) == -1
