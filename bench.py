@@ -1138,10 +1138,12 @@ def main():
     # Steps are independent (same scene, same rays), so consecutive steps are
     # pipelined on several streams (--streams) with their own outputs and their
     # own scene, which each step rebuilds in place from the triangles
-    # (scene_rebuild: the whole BVH build, into the scene's own arrays, waiting
-    # for its own stream only): step i+1's build and trace start while the
-    # longest rays of step i are still bouncing.  Every step does all of its
-    # own work; --serial runs them one after another on one stream.
+    # (scene_rebuild: the whole BVH build, into the scene's own arrays,
+    # enqueued on the step's stream without waiting; the step's trace waits for
+    # it).  Step i+1's rebuild is enqueued before step i's trace, so builds and
+    # traces of neighbouring steps run side by side and the host never waits
+    # for a build it has just enqueued.  Every step does all of its own work;
+    # --serial runs them one after another on one stream.
     n_pipe = 1 if a.serial else max(1, a.streams)
     streams = [stream] if a.serial else [torch.cuda.Stream(device=dev) for _ in range(n_pipe)]
     outs = [(hist, late, stats, params)] + [(*P.alloc_trace_outputs(S, T, B, n, device=dev)[:3],
@@ -1149,28 +1151,40 @@ def main():
     pipe_scenes = [P.Scene(verts, tris, tmat, absb, scat, device=dev) for _ in range(n_pipe)]
     rec = []  # per timed step: (build ms, trace events, estimate events)
 
-    def step(i, record):
-        st_, (h_, l_, s_, p_) = streams[i % n_pipe], outs[i % n_pipe]
-        sc = pipe_scenes[i % n_pipe]
+    def build(i):
+        st_ = streams[i % n_pipe]
         with torch.cuda.stream(st_):
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             ev[3].record(st_)
-            sc.rebuild(verts, tris, tmat, absb, scat)
+            pipe_scenes[i % n_pipe].rebuild(verts, tris, tmat, absb, scat)
             ev[0].record(st_)
-            P.trace_ir(sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, h_, l_, s_)
+        return ev
+
+    def trace_estimate(i, ev):
+        st_, (h_, l_, s_, p_) = streams[i % n_pipe], outs[i % n_pipe]
+        with torch.cuda.stream(st_):
+            P.trace_ir(pipe_scenes[i % n_pipe], cfg["sources"], cfg["listener"], cfg["radius"], prm, h_, l_, s_)
             ev[1].record(st_)
             P.estimate_reverb(h_, l_, s_, T, B, n, dt, p_)
             ev[2].record(st_)
-        if record:
-            rec.append(ev)
 
-    for i in range(a.warmup):
-        step(i, False)
-    # timed region: exactly `steps` steps, synchronised on both sides
+    def run_steps(k, record):
+        if k == 0:
+            return
+        ahead = n_pipe > 1  # one scene per stream: step i+1's rebuild does not touch step i's scene
+        ev = build(0)
+        for i in range(k):
+            nxt = build(i + 1) if ahead and i + 1 < k else None
+            trace_estimate(i, ev)
+            if record:
+                rec.append(ev)
+            ev = nxt if ahead else (build(i + 1) if i + 1 < k else None)
+
+    run_steps(a.warmup, False)
+    # timed region: exactly `steps` steps (each: rebuild, trace, estimate), synchronised on both sides
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(a.steps):
-        step(i, True)
+    run_steps(a.steps, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     for s_ in pipe_scenes:

@@ -175,18 +175,30 @@ int scene_create(const float* verts, int64_t n_verts, const int32_t* tris, int64
                  int32_t n_materials, int32_t n_bands, void* hip_stream, RprScene** out);
 /* Rebuild a scene in place from new geometry and materials (the same
  * arguments and build as scene_create), for scenes that change from frame to
- * frame (Section 5: the propagation update runs every frame).  The build
- * writes into the scene's own arrays when the new triangles and materials fit
- * what it holds (no allocation); otherwise the arrays grow first (hipFree and
- * hipMalloc, which wait for the device's pending work).  The rebuild is
- * stream-ordered on hip_stream: work that reads the scene on other streams
- * must be complete before the call.  Synchronises hip_stream, as scene_create.
- * Errors: those of scene_create, and RPR_EINVAL if the current device is not
- * the scene's; after an error the scene holds no triangles (every ray
- * escapes) until a rebuild succeeds. */
+ * frame (Section 5: the propagation update runs every frame).  Asynchronous:
+ * the build is enqueued on hip_stream into the scene's own arrays and its own
+ * temporaries, and the call returns without waiting (the inputs must stay
+ * valid until the build has run on hip_stream).  The first call that reads
+ * the scene afterwards (trace_ir, trace_ir_noalloc, trace_ir_paths,
+ * trace_listener, scene_closest_hit, scene_info, batch_create, scene_wait)
+ * waits for the build and reports what the device found (scene_create's
+ * errors: out-of-range indices or materials, non-finite vertices,
+ * coefficients outside [0, 1], a tree too deep); after such an error the
+ * scene holds no triangles (every ray escapes) until a rebuild succeeds.
+ * Work that reads the scene on other streams must be complete before the
+ * call.  No allocation when the new triangles and materials fit what the
+ * scene holds and its temporaries were sized by an earlier rebuild; otherwise
+ * the arrays grow first (hipFree and hipMalloc, which wait for the device's
+ * pending work).  A batch holds its scenes' state at batch_create: create it
+ * again after rebuilding one of them.
+ * Errors at the call: RPR_EINVAL for bad sizes or null arrays, or when the
+ * current device is not the scene's; RPR_ENOMEM. */
 int scene_rebuild(RprScene* scene, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                   const int32_t* tri_material, const float* absorption, const float* scattering,
                   int32_t n_materials, int32_t n_bands, void* hip_stream);
+/* Wait for the scene's last scene_rebuild and return its result (RPR_OK, or
+ * the error the build found, reported once; the scene is then empty). */
+int scene_wait(RprScene* scene);
 int scene_destroy(RprScene* scene);
 int scene_info(const RprScene* scene, RprSceneInfo* out /* host */);
 

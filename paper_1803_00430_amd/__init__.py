@@ -154,6 +154,7 @@ _i32 = C.c_int32
 SIGNATURES = {
     "scene_create": (C.c_int, [_vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp, C.POINTER(_vp)]),
     "scene_rebuild": (C.c_int, [_vp, _vp, _i64, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
+    "scene_wait": (C.c_int, [_vp]),
     "scene_destroy": (C.c_int, [_vp]),
     "scene_info": (C.c_int, [_vp, C.POINTER(SceneInfo)]),
     "trace_ir": (C.c_int, [_vp, C.POINTER(Source), _i32, C.POINTER(Listener), C.POINTER(TraceParams), _vp, _vp,
@@ -283,7 +284,9 @@ class Scene:
 
     def rebuild(self, verts, tris, tri_mat, absorption, scattering, stream=None):
         """Rebuild this scene in place from new geometry and materials
-        (scene_rebuild: no allocation when they fit what the scene holds)."""
+        (scene_rebuild: enqueued on the stream without waiting; no allocation
+        when they fit what the scene holds).  What the device finds wrong with
+        the inputs is raised by the next call that uses the scene, or wait()."""
         v = _dev_f32(verts, self.device).reshape(-1, 3)
         t = _dev_i32(tris, self.device).reshape(-1, 3)
         m = None if tri_mat is None else _dev_i32(tri_mat, self.device).reshape(-1)
@@ -292,10 +295,17 @@ class Scene:
         if a.dim() != 2 or a.shape != s.shape:
             raise ValueError("absorption and scattering must both be [materials, bands]")
         nm, nb = int(a.shape[0]), int(a.shape[1])
+        import torch
+        if stream is not None and stream != torch.cuda.current_stream(self.device):
+            for x in (v, t, m, a, s):
+                if x is not None:
+                    x.record_stream(stream)
         rc = lib().scene_rebuild(self.handle, _ptr(v), v.shape[0], _ptr(t), t.shape[0], _ptr(m), _ptr(a), _ptr(s),
                                  nm, nb, _stream(stream))
         # the scene's band count follows the call even when the build fails
         self.n_materials, self.n_bands = nm, nb
+        # the inputs stay referenced until the build has run (the next rebuild waits for it)
+        self._inputs = (v, t, m, a, s)
         _check(rc)
 
     @property
@@ -310,6 +320,10 @@ class Scene:
         return dict(n_tris=si.n_tris, n_nodes=si.n_nodes, max_depth=si.max_depth, n_bands=si.n_bands,
                     n_materials=si.n_materials, n_degenerate=si.n_degenerate,
                     bounds_lo=list(si.bounds_lo), bounds_hi=list(si.bounds_hi), stack_need=si.stack_need)
+
+    def wait(self):
+        """Wait for the last rebuild and raise what it found wrong, if anything."""
+        _check(lib().scene_wait(self.handle))
 
     def closest_hit(self, orig, dirs, stream=None):
         import torch

@@ -280,6 +280,9 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         (bp->chunk_rays != 0 && bp->chunk_rays != 256 && bp->chunk_rays != 1024 && bp->chunk_rays != 4096) ||
         (bp->deterministic != 0 && bp->deterministic != 1) || (bp->deterministic && bp->method != 0))
         return set_error(RPR_EINVAL, "batch_create: bad batch parameters");
+    for (int i = 0; i < n_scenes; ++i)
+        if (scenes[i])
+            if (const int rc = scene_settle(scenes[i]); rc != RPR_OK) return rc;
     const int nb = scenes[0] ? scenes[0]->n_bands : 0;
     int stack_need = 1;
     int64_t max_tris = 0;

@@ -949,8 +949,7 @@ k_collapse4(int n, const int2* __restrict__ child, const float4* __restrict__ bo
 // stream before returning), so a rebuild does not allocate.
 struct Arena {
     std::mutex mu;
-    char* base = nullptr;
-    size_t cap = 0, used = 0;
+    BuildMem mem;
     BuildFlags* host = nullptr;   // pinned host copy of the build's flags
     hipEvent_t done = nullptr;    // marks the copy's completion on the build's stream
 };
@@ -991,30 +990,30 @@ struct DevBuf {
     }
 };
 
-// Lay out `bufs` in the arena (growing it when needed).
+// Lay out `bufs` in the build memory (growing it when needed; hipFree waits
+// for the device's pending work).
 template <class... B>
-hipError_t arena_place(Arena& a, B&... bufs)
+hipError_t mem_place(BuildMem& m, B&... bufs)
 {
     size_t need = 0;
     ((need += bufs.bytes), ...);
-    if (need > a.cap) {
-        if (a.base) {
-            hipError_t e = hipFree(a.base);
+    if (need > m.cap) {
+        if (m.base) {
+            hipError_t e = hipFree(m.base);
             if (e != hipSuccess) return e;
-            a.base = nullptr;
-            a.cap = 0;
+            m.base = nullptr;
+            m.cap = 0;
         }
-        hipError_t e = hipMalloc(&a.base, need + need / 4);
+        hipError_t e = hipMalloc(&m.base, need + need / 4);
         if (e != hipSuccess) return e;
-        a.cap = need + need / 4;
+        m.cap = need + need / 4;
     }
     size_t off = 0;
     auto put = [&](auto& b) {
-        b.p = reinterpret_cast<std::remove_reference_t<decltype(b.p)>>(a.base + off);
+        b.p = reinterpret_cast<std::remove_reference_t<decltype(b.p)>>(m.base + off);
         off += b.bytes;
     };
     (put(bufs), ...);
-    a.used = off;
     return hipSuccess;
 }
 
@@ -1127,12 +1126,15 @@ void set_empty(RprScene* sc)
     sc->view.n_bands = sc->n_bands;
 }
 
-// Build the material table, triangle records and BVH into the scene's arrays
-// (which hold at least n_tris triangles and n_materials materials), on
-// hip_stream, and read the build's flags back.
-int build_scene(RprScene* sc, const char* who, const float* verts, int64_t n_verts, const int32_t* tris,
-                int64_t n_tris, const int32_t* tri_material, const float* absorption, const float* scattering,
-                int32_t n_materials, int32_t n_bands, hipStream_t st)
+// Enqueue the build of the material table, triangle records and BVH into the
+// scene's arrays (which hold at least n_tris triangles and n_materials
+// materials) on hip_stream, with its temporaries in `mem`; *flags_dev is the
+// device record of the build's flags, which finish_build checks once the
+// build has run.  The scene is empty until then.
+int enqueue_build(RprScene* sc, const char* who, BuildMem& mem, const float* verts, int64_t n_verts,
+                  const int32_t* tris, int64_t n_tris, const int32_t* tri_material, const float* absorption,
+                  const float* scattering, int32_t n_materials, int32_t n_bands, hipStream_t st,
+                  BuildFlags** flags_dev)
 {
     const int n = (int)n_tris;
     sc->n_bands = n_bands;
@@ -1151,10 +1153,6 @@ int build_scene(RprScene* sc, const char* who, const float* verts, int64_t n_ver
                                   "%s: %s: %s", who, #expr, hipGetErrorString(e_)));              \
     } while (0)
 
-    int dev = sc->device;
-    if (dev < 0 || dev >= 16) return fail(set_error(RPR_EUNSUPPORTED, "%s: device %d", who, dev));
-    Arena& arena = g_arena[dev];
-    std::lock_guard<std::mutex> arena_lock(arena.mu);
     DevBuf<BuildFlags> flags;
     TRY(flags.alloc(1));
     DevBuf<PrepPartial> part;
@@ -1196,7 +1194,7 @@ int build_scene(RprScene* sc, const char* who, const float* verts, int64_t n_ver
         TRY(refs.alloc(2 * (size_t)n - 1));
         TRY(scan_sums.alloc(std::max<size_t>(blocks((int64_t)256 * n_tiles, kSortTile), blocks(n, kSortTile))));
     }
-    TRY(arena_place(arena, flags, part, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, blk_cnt, mask,
+    TRY(mem_place(mem, flags, part, cent, box, k0, v0, k1, v1, counts, seen, refs, even, idx4, blk_cnt, mask,
                     ibox, parent, child, range, pyr, scan_sums));
     hipLaunchKernelGGL(k_prep, dim3(n_part), dim3(kPrepBlock), 0, st, verts, n_verts, tris, n_tris, tri_material,
                        absorption, scattering, n_materials, n_bands, sc->mats, cent.p, seen.p, refs.p, parent.p,
@@ -1247,44 +1245,50 @@ int build_scene(RprScene* sc, const char* who, const float* verts, int64_t n_ver
                                fused_index ? mask.p : nullptr, fused_index ? blk_cnt.p : nullptr, n_blk, sc->nodes);
         }
         TRY(hipGetLastError());
-        BuildFlags hf;
-        TRY(read_flags(arena, flags.p, st, &hf));
-        if (hf.flags & kBadIndex) return fail(set_error(RPR_EINVAL, "%s: vertex index out of range", who));
-        if (hf.flags & kBadVertex) return fail(set_error(RPR_EINVAL, "%s: non-finite vertex", who));
-        if (hf.flags & kBadMaterial) return fail(set_error(RPR_EINVAL, "%s: material index out of range", who));
-        if (hf.flags & kBadCoeff)
-            return fail(set_error(RPR_EINVAL, "%s: absorption/scattering outside [0, 1]", who));
-        if (hf.flags & kBadTree) return fail(set_error(RPR_EDEVICE, "%s: BVH consistency check failed", who));
-        sc->max_depth = hf.max_depth;
-        sc->stack_need = hf.max_stack;
-        sc->n_nodes4 = hf.n_nodes4;
-        sc->n_degenerate = (int32_t)hf.n_degenerate;
-        for (int a = 0; a < 3; ++a) {
-            sc->lo[a] = unordered(hf.blo[a]);
-            sc->hi[a] = unordered(hf.bhi[a]);
-        }
-        // the traversal writes one slot past the deepest entry (a push without a branch)
-        if (sc->stack_need >= kMaxStack)
-            return fail(set_error(RPR_EUNSUPPORTED,
-                                  "%s: BVH depth %d needs %d stack entries, the traversal takes at most %d",
-                                  who, sc->max_depth, sc->stack_need, kMaxStack - 1));
     } else {
         hipLaunchKernelGGL(k_flags_only, dim3(1), dim3(kWave), 0, st, part.p, n_part, flags.p);
         TRY(hipGetLastError());
-        BuildFlags hf;
-        TRY(read_flags(arena, flags.p, st, &hf));
-        if (hf.flags & kBadCoeff)
-            return fail(set_error(RPR_EINVAL, "%s: absorption/scattering outside [0, 1]", who));
     }
+    *flags_dev = flags.p;
+    return RPR_OK;
 #undef TRY
+}
+
+// Check a finished build's flags and apply its sizes; on failure the scene
+// stays empty.
+int finish_build(RprScene* sc, const char* who, int64_t n_tris, const BuildFlags& hf)
+{
+    const int n = (int)n_tris;
+    if (hf.flags & kBadIndex) return set_error(RPR_EINVAL, "%s: vertex index out of range", who);
+    if (hf.flags & kBadVertex) return set_error(RPR_EINVAL, "%s: non-finite vertex", who);
+    if (hf.flags & kBadMaterial) return set_error(RPR_EINVAL, "%s: material index out of range", who);
+    if (hf.flags & kBadCoeff) return set_error(RPR_EINVAL, "%s: absorption/scattering outside [0, 1]", who);
+    if (hf.flags & kBadTree) return set_error(RPR_EDEVICE, "%s: BVH consistency check failed", who);
+    if (n == 0) return RPR_OK;
+    // the traversal writes one slot past the deepest entry (a push without a branch)
+    if (hf.max_stack >= kMaxStack)
+        return set_error(RPR_EUNSUPPORTED, "%s: BVH depth %d needs %d stack entries, the traversal takes at most %d",
+                         who, hf.max_depth, hf.max_stack, kMaxStack - 1);
+    sc->max_depth = hf.max_depth;
+    sc->stack_need = hf.max_stack;
+    sc->n_nodes4 = hf.n_nodes4;
+    sc->n_degenerate = (int32_t)hf.n_degenerate;
+    for (int a = 0; a < 3; ++a) {
+        sc->lo[a] = unordered(hf.blo[a]);
+        sc->hi[a] = unordered(hf.bhi[a]);
+    }
     sc->n_tris = n_tris;
-    sc->view.nodes = sc->nodes;
-    sc->view.tris = sc->tris;
-    sc->view.mats = sc->mats;
     sc->view.root = n == 1 ? leaf_link(0) : 0;
     sc->view.n_tris = n;
-    sc->view.n_bands = n_bands;
     return RPR_OK;
+}
+
+// Wait (polling, as read_flags) for the event after a rebuild's flag copy.
+hipError_t wait_event(hipEvent_t ev)
+{
+    hipError_t e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) __builtin_ia32_pause();
+    return e;
 }
 
 }  // namespace
@@ -1300,10 +1304,24 @@ extern "C" int scene_create(const float* verts, int64_t n_verts, const int32_t* 
     RprScene* sc = new RprScene();
     hipError_t e = hipGetDevice(&sc->device);
     rc = e != hipSuccess ? set_error(RPR_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)) : RPR_OK;
+    if (rc == RPR_OK && (sc->device < 0 || sc->device >= 16))
+        rc = set_error(RPR_EUNSUPPORTED, "scene_create: device %d", sc->device);
     if (rc == RPR_OK) rc = alloc_scene(sc, "scene_create", n_tris, n_materials);
-    if (rc == RPR_OK)
-        rc = build_scene(sc, "scene_create", verts, n_verts, tris, n_tris, tri_material, absorption, scattering,
-                         n_materials, n_bands, (hipStream_t)hip_stream);
+    if (rc == RPR_OK) {
+        // temporaries from the device's shared arena, held until the flags are back
+        Arena& arena = g_arena[sc->device];
+        std::lock_guard<std::mutex> arena_lock(arena.mu);
+        BuildFlags* fd = nullptr;
+        rc = enqueue_build(sc, "scene_create", arena.mem, verts, n_verts, tris, n_tris, tri_material, absorption,
+                           scattering, n_materials, n_bands, (hipStream_t)hip_stream, &fd);
+        BuildFlags hf;
+        if (rc == RPR_OK) {
+            hipError_t e2 = read_flags(arena, fd, (hipStream_t)hip_stream, &hf);
+            if (e2 != hipSuccess) rc = set_error(RPR_EDEVICE, "scene_create: reading the build's flags: %s",
+                                                 hipGetErrorString(e2));
+        }
+        if (rc == RPR_OK) rc = finish_build(sc, "scene_create", n_tris, hf);
+    }
     if (rc != RPR_OK) {
         free_scene_memory(sc);
         workspace_free(sc->ws);
@@ -1327,6 +1345,13 @@ extern "C" int scene_rebuild(RprScene* scene, const float* verts, int64_t n_vert
     if (dev != scene->device)
         return set_error(RPR_EINVAL, "scene_rebuild: the scene is on device %d, the current device is %d",
                          scene->device, dev);
+    hipStream_t st = (hipStream_t)hip_stream;
+    std::lock_guard<std::mutex> lk(scene->mu);
+    if (scene->pending) {
+        // an earlier rebuild not yet applied: this one replaces it
+        (void)wait_event(scene->built);
+        scene->pending = false;
+    }
     if (n_tris > scene->cap_tris || n_materials > scene->cap_materials) {
         // grow (never shrink) the arrays; hipFree waits for the device's pending work
         const int64_t cap_tris = std::max(n_tris, scene->cap_tris);
@@ -1339,8 +1364,47 @@ extern "C" int scene_rebuild(RprScene* scene, const float* verts, int64_t n_vert
             return rc;
         }
     }
-    return build_scene(scene, "scene_rebuild", verts, n_verts, tris, n_tris, tri_material, absorption, scattering,
-                       n_materials, n_bands, (hipStream_t)hip_stream);
+    if (!scene->flags_host) {
+        e = hipHostMalloc(&scene->flags_host, sizeof(BuildFlags), hipHostMallocDefault);
+        if (e != hipSuccess) return set_error(RPR_ENOMEM, "scene_rebuild: hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    if (!scene->built) {
+        e = hipEventCreateWithFlags(&scene->built, hipEventDisableTiming);
+        if (e != hipSuccess) return set_error(RPR_EDEVICE, "scene_rebuild: hipEventCreate: %s", hipGetErrorString(e));
+    }
+    BuildFlags* fd = nullptr;
+    rc = enqueue_build(scene, "scene_rebuild", scene->build_mem, verts, n_verts, tris, n_tris, tri_material,
+                       absorption, scattering, n_materials, n_bands, st, &fd);
+    if (rc != RPR_OK) return rc;
+    e = hipMemcpyAsync(scene->flags_host, fd, sizeof(BuildFlags), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(scene->built, st);
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(st);
+        set_empty(scene);
+        return set_error(RPR_EDEVICE, "scene_rebuild: flag copy: %s", hipGetErrorString(e));
+    }
+    scene->pending = true;
+    scene->pending_tris = n_tris;
+    return RPR_OK;
+}
+
+extern "C" int scene_wait(RprScene* scene)
+{
+    if (!scene) return set_error(RPR_EINVAL, "scene_wait: scene is null");
+    return scene_settle(scene);
+}
+
+int rpr::scene_settle(const RprScene* scene_c)
+{
+    RprScene* sc = const_cast<RprScene*>(scene_c);
+    std::lock_guard<std::mutex> lk(sc->mu);
+    if (!sc->pending) return RPR_OK;
+    sc->pending = false;
+    const hipError_t e = wait_event(sc->built);
+    if (e != hipSuccess) return set_error(RPR_EDEVICE, "scene_rebuild: %s", hipGetErrorString(e));
+    BuildFlags hf;
+    std::memcpy(&hf, sc->flags_host, sizeof(hf));
+    return finish_build(sc, "scene_rebuild", sc->pending_tris, hf);
 }
 
 extern "C" int scene_destroy(RprScene* scene)
@@ -1349,9 +1413,11 @@ extern "C" int scene_destroy(RprScene* scene)
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (dev != scene->device) (void)hipSetDevice(scene->device);
-    (void)hipFree(scene->nodes);
-    (void)hipFree(scene->tris);
-    (void)hipFree(scene->mats);
+    if (scene->pending) (void)wait_event(scene->built);
+    free_scene_memory(scene);
+    if (scene->build_mem.base) (void)hipFree(scene->build_mem.base);
+    if (scene->flags_host) (void)hipHostFree(scene->flags_host);
+    if (scene->built) (void)hipEventDestroy(scene->built);
     workspace_free(scene->ws);
     if (dev >= 0 && dev != scene->device) (void)hipSetDevice(dev);
     delete scene;
@@ -1362,6 +1428,7 @@ extern "C" int scene_info(const RprScene* scene, RprSceneInfo* out)
 {
     if (!scene || !out) return set_error(RPR_EINVAL, "scene_info: null argument");
     std::memset(out, 0, sizeof(*out));
+    const int rc = scene_settle(scene);
     out->n_tris = scene->n_tris;
     out->n_nodes = scene->n_nodes4;
     out->max_depth = scene->max_depth;
@@ -1373,5 +1440,5 @@ extern "C" int scene_info(const RprScene* scene, RprSceneInfo* out)
         out->bounds_lo[a] = scene->lo[a];
         out->bounds_hi[a] = scene->hi[a];
     }
-    return RPR_OK;
+    return rc;
 }

@@ -1123,6 +1123,7 @@ extern "C" int trace_listener(const RprScene* scene, const RprSource* srcs, int3
 {
     if (!scene || !p || !lst || (n_src > 0 && (!srcs || !hist || !stats)))
         return set_error(RPR_EINVAL, "trace_listener: null argument");
+    if (const int rc = scene_settle(scene); rc != RPR_OK) return rc;
     if (n_src < 0 || n_src > kMaxListenerSources)
         return set_error(RPR_EINVAL, "trace_listener: n_src=%d not in 0..%d", n_src, kMaxListenerSources);
     if (p->sh_order < 0 || p->sh_order > RPR_MAX_SH_ORDER)

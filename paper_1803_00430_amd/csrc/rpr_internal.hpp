@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -94,6 +96,12 @@ struct PairDesc {
     double fx_scale;
 };
 
+// Device memory for a build's temporaries (grow-only).
+struct BuildMem {
+    char* base = nullptr;
+    size_t cap = 0;
+};
+
 struct Workspace {
     void* dev = nullptr;      // queue counter (+ padding) followed by the pair table
     size_t bytes = 0;
@@ -104,6 +112,7 @@ struct Workspace {
 }  // namespace rpr
 
 struct RprScene {
+    std::mutex mu;  // guards the pending-rebuild state below
     int device = 0;
     int64_t n_tris = 0;
     int32_t n_bands = 0;
@@ -120,9 +129,21 @@ struct RprScene {
     float* mats = nullptr;
     rpr::SceneView view{};
     rpr::Workspace ws;
+    // scene_rebuild: its own build temporaries (grow-only), the pinned host
+    // copy of the build's flags and the event after that copy; `pending` until
+    // the result is applied (rpr::scene_settle)
+    rpr::BuildMem build_mem;
+    void* flags_host = nullptr;
+    hipEvent_t built = nullptr;
+    bool pending = false;
+    int64_t pending_tris = 0;
 };
 
 namespace rpr {
+// Wait for the scene's pending rebuild, if any, and apply its result: the
+// scene's sizes on success; an empty scene and the build's error otherwise
+// (reported once).  Every call that reads a scene calls this first.
+int scene_settle(const RprScene* scene);
 // Ensure the workspace holds `pairs` pair descriptors, and fx_bytes of
 // fixed-point histogram cells from workspace_fx_offset(pairs) on; returns
 // RPR_OK or an error.

@@ -736,6 +736,7 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     if (!scene || !p || !lst || (n_src > 0 && (!srcs || !hist || !stats)))
         return set_error(RPR_EINVAL, "trace_ir: null argument");
     if (n_src < 0) return set_error(RPR_EINVAL, "trace_ir: n_src=%d < 0", n_src);
+    if (const int rc = scene_settle(scene); rc != RPR_OK) return rc;
     if (p->sh_order < 0 || p->sh_order > RPR_MAX_SH_ORDER)
         return set_error(RPR_EINVAL, "trace_ir: sh_order=%d not in 0..3", p->sh_order);
     if (p->n_bins < 1) return set_error(RPR_EINVAL, "trace_ir: n_bins=%d < 1", p->n_bins);
@@ -935,6 +936,7 @@ extern "C" int scene_closest_hit(const RprScene* scene, const float* orig, const
 {
     if (!scene || n < 0 || (n > 0 && (!orig || !dir || !t_out || !tri_out)))
         return set_error(RPR_EINVAL, "scene_closest_hit: bad argument");
+    if (const int rc = scene_settle(scene); rc != RPR_OK) return rc;
     if (n == 0) return RPR_OK;
     hipLaunchKernelGGL(k_closest, dim3((unsigned)((n + kWave - 1) / kWave)), dim3(kWave), 0,
                        (hipStream_t)hip_stream, scene->view, orig, dir, (long long)n, t_out, tri_out);

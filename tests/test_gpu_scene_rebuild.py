@@ -1,10 +1,12 @@
 """scene_rebuild against scene_create: a scene rebuilt in place from new
 geometry must be the scene that scene_create makes from it.  Checked through
-the scene information, every closest hit of 20,000 random rays (distance and
-triangle, exactly), and a deterministic trace (histograms bit for bit, every
+every closest hit of 20,000 random rays (distance and triangle, exactly), the
+scene information and a deterministic trace (histograms bit for bit, every
 ray's path hash), over a sequence of rebuilds that grows the scene, shrinks
-it within its arrays, empties it, fails on a bad vertex index (the scene is
-then empty) and fills it again."""
+it within its arrays, empties it, fails on a bad vertex index (reported by the
+next call that uses the scene; the scene is then empty) and fills it again.
+The rebuild is asynchronous: the first call after it (a closest-hit query, a
+trace, scene_wait) waits for it."""
 import numpy as np
 import pytest
 
@@ -48,8 +50,8 @@ def _trace(scene, src, lst):
 def _same_scene(rebuilt, d, rays, src, lst):
     fresh = P.Scene(*_args(d))
     try:
-        assert rebuilt.info() == fresh.info()
         (t0, i0), (t1, i1) = _hits(rebuilt, rays), _hits(fresh, rays)
+        assert rebuilt.info() == fresh.info()
         assert np.array_equal(i0, i1)
         assert np.array_equal(t0.view(np.uint32), t1.view(np.uint32))
         if len(d["tris"]):
@@ -74,6 +76,14 @@ def test_rebuild_in_place_equals_a_fresh_scene():
         _same_scene(sc, big, rays, src, lst)
         sc.rebuild(*_args(tiny))                # fits: no allocation
         _same_scene(sc, tiny, rays, src, lst)
+        sc.rebuild(*_args(big))                 # a trace is the first call after the rebuild
+        fresh = P.Scene(*_args(big))
+        for a, b in zip(_trace(sc, src, lst), _trace(fresh, src, lst)):
+            assert np.array_equal(a, b)
+        fresh.close()
+        sc.rebuild(*_args(small))               # two rebuilds in a row: the second replaces the first
+        sc.rebuild(*_args(tiny))
+        _same_scene(sc, tiny, rays, src, lst)
         empty = dict(big, tris=np.zeros((0, 3), np.int32), tri_mat=np.zeros(0, np.int32))
         sc.rebuild(*_args(empty))
         info = sc.info()
@@ -81,10 +91,15 @@ def test_rebuild_in_place_equals_a_fresh_scene():
         assert (_hits(sc, rays)[1] == -1).all()
         bad = dict(big, tris=big["tris"].copy())
         bad["tris"][123, 2] = 10 ** 7
+        sc.rebuild(*_args(bad))                 # enqueued: the device finds the bad index
         with pytest.raises(RuntimeError, match="scene_rebuild: vertex index out of range"):
-            sc.rebuild(*_args(bad))
+            sc.wait()
+        sc.wait()                               # reported once
         assert sc.info()["n_tris"] == 0
         assert (_hits(sc, rays)[1] == -1).all()
+        sc.rebuild(*_args(bad))
+        with pytest.raises(RuntimeError, match="scene_rebuild: vertex index out of range"):
+            _hits(sc, rays)                     # or by the next call that uses the scene
         sc.rebuild(*_args(big))                 # fits again
         _same_scene(sc, big, rays, src, lst)
     finally:
