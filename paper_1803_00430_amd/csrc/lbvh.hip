@@ -1,7 +1,7 @@
 // Scene creation: material table, triangle records and a linear BVH.
 //
 // Linear BVH (Karras, HPG 2012): Morton codes (30-bit; 63-bit for large scenes) of the triangle
-// centroids in the scene's centroid bounds, a stable least-significant-digit
+// centroids in the scene's centroid bounds (cells of bounded aspect), a stable least-significant-digit
 // radix sort of (code, triangle) pairs, internal nodes from the longest common
 // prefixes of neighbouring codes (ties broken by the sorted index), node
 // boxes as unions over each node's range of sorted leaves, and a collapse of
@@ -34,6 +34,8 @@ constexpr int kSortItems = 8;
 constexpr int kSortTile = kBuildBlock * kSortItems;
 // Scenes of at least this many triangles get 64-bit Morton keys (21 bits per axis).
 constexpr int64_t kWideKeyTris = (int64_t)1 << 19;
+// Largest ratio of the Morton cells' sides (see k_morton_count).
+constexpr float kMaxCellAspect = 8.0f;
 // Up to this many sort tiles the scatter forms its digit offsets from the
 // per-tile counts itself (two launches per pass instead of five); beyond it a
 // device-wide scan runs between count and scatter.
@@ -272,18 +274,17 @@ __device__ __forceinline__ uint64_t spread3_64(uint64_t v)
     return v;
 }
 
-// Morton key of a centroid in the centroid bounds [lo, lo + ext]: 10 bits per
-// axis in a 32-bit key, or 21 bits per axis in a 64-bit key (large scenes,
-// where 10 bits per axis leave triangles sharing a key).
+// Morton key of a centroid in the box [lo, lo + ext] on the centroid bounds:
+// 10 bits per axis in a 32-bit key, or 21 bits per axis in a 64-bit key
+// (large scenes, where 10 bits per axis leave triangles sharing a key).
 template <class K>
-__device__ __forceinline__ K morton_key(const float4 c, const float lo[3], const float hi[3])
+__device__ __forceinline__ K morton_key(const float4 c, const float lo[3], const float ext[3])
 {
     constexpr int kBits = sizeof(K) == 4 ? 10 : 21;
     const float cc[3] = {c.x, c.y, c.z};
     K code = 0;
     for (int a = 0; a < 3; ++a) {
-        const float ext = hi[a] - lo[a];
-        float u = ext > 0.0f ? (cc[a] - lo[a]) / ext : 0.5f;
+        float u = ext[a] > 0.0f ? (cc[a] - lo[a]) / ext[a] : 0.5f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
         const uint32_t q = min((uint32_t)(u * (float)(1u << kBits)), (1u << kBits) - 1u);
         if constexpr (sizeof(K) == 4) code |= spread3(q) << (2 - a);
@@ -323,12 +324,21 @@ k_morton_count(const float4* __restrict__ cent, int64_t n, const PrepPartial* __
         }
     }
     __syncthreads();
-    const float lo[3] = {s_lo[0], s_lo[1], s_lo[2]}, hi[3] = {s_hi[0], s_hi[1], s_hi[2]};
+    // Each axis spans its centroid extent, raised to at least 1/kMaxCellAspect
+    // of the longest: the key's cells are then at most that many times longer
+    // on one axis than on another, so a flat scene (a storey 3 m high and
+    // 90 m wide) is not cut along its short axis as often as along the long
+    // ones, while a scene of moderate aspect keeps its own extents.
+    const float lo[3] = {s_lo[0], s_lo[1], s_lo[2]};
+    const float emax = fmaxf(fmaxf(s_hi[0] - s_lo[0], s_hi[1] - s_lo[1]), s_hi[2] - s_lo[2]);
+    const float ext[3] = {fmaxf(s_hi[0] - s_lo[0], emax / kMaxCellAspect),
+                          fmaxf(s_hi[1] - s_lo[1], emax / kMaxCellAspect),
+                          fmaxf(s_hi[2] - s_lo[2], emax / kMaxCellAspect)};
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; ++r) {
         const int64_t i = base + r * kBuildBlock + threadIdx.x;
         if (i < n) {
-            const K key = morton_key<K>(cent[i], lo, hi);
+            const K key = morton_key<K>(cent[i], lo, ext);
             keys[i] = key;
             vals[i] = (uint32_t)i;
             atomicAdd(&h[(uint32_t)key & 255u], 1u);
