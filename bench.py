@@ -27,12 +27,14 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per k_trace launch on the city workload, from rocprofv3 FETCH_SIZE
 # and WRITE_SIZE passes scaled by a copy kernel of known size
-# (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace sources it
-# was measured on: reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35608608.0,
-                 "sources_sha256": "8bcafdce7375a89d285f43db52191f76123fea587eadff1061b860ad144407c8"}
+# (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace and build
+# sources it was measured on (the build makes the tree the trace reads):
+# reported as null once they change.
+TRACE_TRAFFIC = {"bytes": 35762400.0,
+                 "sources_sha256": "46092d99de6aca22465407e22b219e7da5a406cff7684e9012105eac978cc0aa"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
-                 "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp")
+                 "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp",
+                 "paper_1803_00430_amd/csrc/lbvh.hip")
 
 
 # HBM bytes per k_reverb_render launch on the default reverb workload (4096 sources x
