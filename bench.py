@@ -58,7 +58,8 @@ def trace_sources_sha256(sources=TRACE_SOURCES):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=60)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 60 for the city workload, 20 for the others)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serial", action="store_true",
@@ -123,7 +124,10 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device-to-device three times "
                          "(a known-size reference for the HBM byte counters)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.steps is None:
+        a.steps = 60 if a.workload == "city" else 20
+    return a
 
 
 def probe_rate(P, torch, nbytes, pattern, *, grid, block, iters, reps=5):
