@@ -58,8 +58,7 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
     // SIMD): in LDS they would take 2 KB per wave, and with 16 waves per CU
     // the stacks and they would fill the CU's LDS, so that the next scene's
     // build kernels could start on a CU only as this launch's waves leave it.
-    using Bands = BandState<NB, false>;
-    Bands eq(nullptr, lane);
+    BandState<NB> eq;
 #pragma unroll
     for (int b = 0; b < NB; ++b) eq.E(b) = eq.Q(b) = 0.f;
     LaneAcc<NB> acc;

@@ -14,25 +14,10 @@ namespace rpr {
 namespace {
 
 // Per-lane band state of a ray (energy E and choice weight Q per band), in
-// LDS (band b of lane l at word b * 64 + l: no bank conflicts) or in
 // registers.
-template <int NB, bool LDS>
-struct BandState;
-
 template <int NB>
-struct BandState<NB, true> {
-    static constexpr int kLdsWords = 2 * NB * kWave;
-    float* p;
-    __device__ BandState(float* lds, int lane) : p(lds + lane) {}
-    __device__ float& E(int b) { return p[b * kWave]; }
-    __device__ float& Q(int b) { return p[(NB + b) * kWave]; }
-};
-
-template <int NB>
-struct BandState<NB, false> {
-    static constexpr int kLdsWords = 1;
+struct BandState {
     float e[NB], q[NB];
-    __device__ BandState(float*, int) {}
     __device__ float& E(int b) { return e[b]; }
     __device__ float& Q(int b) { return q[b]; }
 };
