@@ -104,3 +104,60 @@ def test_rebuild_in_place_equals_a_fresh_scene():
         _same_scene(sc, big, rays, src, lst)
     finally:
         sc.close()
+
+
+def test_pipelined_rebuilds_match_serial():
+    """The benchmark's step pattern: three streams, one scene per stream
+    rebuilt in place each step, step i+1's rebuild enqueued before step i's
+    trace.  In deterministic accumulation every step's histograms and path
+    hashes equal those of a scene built and traced alone, bit for bit, and its
+    counts are equal."""
+    import torch
+    cfg = R.city_config()
+    n_rays, S = 4096, len(cfg["sources"])
+    T, n, B = cfg["n_bins"], cfg["sh_order"], cfg["absorption"].shape[1]
+    prm = P.trace_params(n_rays_total=n_rays, max_bounces=cfg["max_bounces"], sh_order=n, n_bins=T,
+                         bin_width_s=cfg["bin_width_s"], seed=cfg["seed"], flags=P.TRACE_DETERMINISTIC)
+    dev = torch.device("cuda:0")
+    inputs = [torch.as_tensor(np.asarray(cfg[k]), device=dev)
+              for k in ("verts", "tris", "tri_mat", "absorption", "scattering")]
+
+    def outputs():
+        h, l_, s, rh = P.alloc_trace_outputs(S, T, B, n, n_rays, want_hash=True)
+        return h, l_, s, rh
+
+    ref_sc = P.Scene(*inputs)
+    ref = outputs()
+    P.trace_ir(ref_sc, cfg["sources"], cfg["listener"], cfg["radius"], prm, *ref)
+    torch.cuda.synchronize()
+    ref_np = [x.cpu().numpy() for x in (ref[0], ref[1], ref[3])]
+    ref_st = P.stats_host(ref[2])
+    ref_sc.close()
+
+    n_pipe, steps = 3, 7
+    streams = [torch.cuda.Stream() for _ in range(n_pipe)]
+    scenes = [P.Scene(*inputs) for _ in range(n_pipe)]
+    outs = [outputs() for _ in range(steps)]
+    torch.cuda.synchronize()  # inputs and outputs made on the default stream, used on the others
+
+    def rebuild(i):
+        with torch.cuda.stream(streams[i % n_pipe]):
+            scenes[i % n_pipe].rebuild(*inputs)
+
+    rebuild(0)
+    for i in range(steps):
+        if i + 1 < steps:
+            rebuild(i + 1)
+        with torch.cuda.stream(streams[i % n_pipe]):
+            P.trace_ir(scenes[i % n_pipe], cfg["sources"], cfg["listener"], cfg["radius"], prm, *outs[i])
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        got = [x.cpu().numpy() for x in (o[0], o[1], o[3])]
+        for a, b in zip(got, ref_np):
+            assert np.array_equal(a, b), i
+        st = P.stats_host(o[2])
+        for s in range(S):
+            for key in ("n_segments", "n_finite_segments", "n_escaped", "n_rays", "first_arrival_bin"):
+                assert st[s][key] == ref_st[s][key], (i, s, key)
+    for sc in scenes:
+        sc.close()
