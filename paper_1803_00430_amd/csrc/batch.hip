@@ -84,9 +84,10 @@ std::string tune_key(int device, const RprBatch& b, int64_t max_tris)
     for (const auto& d : b.pairs) bounces += (double)d.n_rays * (d.max_bounces + 1);
     bounces /= (double)std::max<int64_t>(1, b.total);
     char buf[256];
+    const int stack = b.stack_need < 32 ? 32 : (b.stack_need < 48 ? 48 : 64);
     std::snprintf(buf, sizeof(buf), "%s/cu%d/m%d/nb%d/T%d/nc%d/st%d/p%d/r%d/k%d/t%d", arch, device_cu_count(),
-                  b.method, b.nb, b.T, b.nc, b.stack_need < 32 ? 32 : 64, ilog2(b.n_pairs), ilog2((double)b.total),
-                  ilog2(bounces), ilog2((double)max_tris));
+                  b.method, b.nb, b.T, b.nc, stack, ilog2(b.n_pairs), ilog2((double)b.total), ilog2(bounces),
+                  ilog2((double)max_tris));
     std::string k(buf);
     for (char& c : k)
         if (c == ' ') c = '_';

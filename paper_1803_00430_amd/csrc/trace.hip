@@ -566,8 +566,12 @@ struct Variant {
 };
 
 std::mutex g_mu;
-Variant g_var[2][2][2];  // [bands 4/8][stack 32/64][count visits]
-Variant g_rec[2][2];     // [bands 4/8][stack 32/64], with early-path records
+// Stack depths of the variants, 32, 48 and 64 entries: a scene takes the
+// smallest that exceeds its stack bound (LDS per wave 8 / 12 / 16 KB: 16 / 13 /
+// 10 waves per CU).
+inline int stack_bucket(int stack_need) { return stack_need < 32 ? 0 : (stack_need < 48 ? 1 : 2); }
+Variant g_var[2][3][2];  // [bands 4/8][stack 32/48/64][count visits]
+Variant g_rec[2][3];     // [bands 4/8][stack 32/48/64], with early-path records
 bool g_var_init = false;
 int g_cus = 0;
 
@@ -578,22 +582,26 @@ int ensure_variants()
     int dev = 0;
     RPR_HIP_TRY(hipGetDevice(&dev));
     RPR_HIP_TRY(hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev));
-    TraceFn fns[2][2][2] = {{{trace_fn<4, 32, false>(), trace_fn<4, 32, true>()},
+    TraceFn fns[2][3][2] = {{{trace_fn<4, 32, false>(), trace_fn<4, 32, true>()},
+                             {trace_fn<4, 48, false>(), trace_fn<4, 48, true>()},
                              {trace_fn<4, 64, false>(), trace_fn<4, 64, true>()}},
                             {{trace_fn<8, 32, false>(), trace_fn<8, 32, true>()},
+                             {trace_fn<8, 48, false>(), trace_fn<8, 48, true>()},
                              {trace_fn<8, 64, false>(), trace_fn<8, 64, true>()}}};
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < 3; ++b)
             for (int c = 0; c < 2; ++c) {
                 int nb = 0;
                 RPR_HIP_TRY(
                     hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)fns[a][b][c], kWave, 0));
                 g_var[a][b][c] = Variant{fns[a][b][c], nb > 0 ? nb : 1};
             }
-    TraceFn rfns[2][2] = {{trace_fn<4, 32, false, true>(), trace_fn<4, 64, false, true>()},
-                          {trace_fn<8, 32, false, true>(), trace_fn<8, 64, false, true>()}};
+    TraceFn rfns[2][3] = {{trace_fn<4, 32, false, true>(), trace_fn<4, 48, false, true>(),
+                           trace_fn<4, 64, false, true>()},
+                          {trace_fn<8, 32, false, true>(), trace_fn<8, 48, false, true>(),
+                           trace_fn<8, 64, false, true>()}};
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 3; ++b) {
             int nb = 0;
             RPR_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)rfns[a][b], kWave, 0));
             g_rec[a][b] = Variant{rfns[a][b], nb > 0 ? nb : 1};
@@ -638,7 +646,7 @@ void workspace_free(Workspace& ws)
 int trace_max_waves_per_cu(int nb, int stack_need)
 {
     if (ensure_variants() != RPR_OK) return 1;
-    return g_var[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1][0].blocks_per_cu;
+    return g_var[nb <= 4 ? 0 : 1][stack_bucket(stack_need)][0].blocks_per_cu;
 }
 
 int enqueue_fill_zero(float* p, size_t n, hipStream_t stream)
@@ -676,8 +684,8 @@ int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_que
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
     int rc = ensure_variants();
     if (rc != RPR_OK) return rc;
-    const Variant& v = rec ? g_rec[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1]
-                           : g_var[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1][count_visits ? 1 : 0];
+    const Variant& v = rec ? g_rec[nb <= 4 ? 0 : 1][stack_bucket(stack_need)]
+                           : g_var[nb <= 4 ? 0 : 1][stack_bucket(stack_need)][count_visits ? 1 : 0];
     const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, v.blocks_per_cu) : v.blocks_per_cu;
     long long grid = grid_override > 0 ? grid_override : (long long)g_cus * per_cu;
     const long long need = (total_rays + kWave - 1) / kWave;
