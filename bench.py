@@ -258,8 +258,8 @@ def run_batch(a):
                    "pairs": len(pairs), "total_rays": int(info["total_rays"]),
                    "tris": [int(len(sd["tris"])) for sd in cfg["scenes"]]},
         "irs_per_s": len(pairs) / (ms * 1e-3), "segments_per_step": segs, "plan_s": plan_s,
-        "launch_shape": {k: info[k] for k in ("waves_per_cu", "order", "chunk_rays", "n_candidates", "best_ms",
-                                             "worst_ms", "stack_need", "from_cache")},
+        "launch_shape": {k: info[k] for k in ("waves_per_cu", "order", "chunk_rays", "stack_entries", "fixed_point",
+                                             "n_candidates", "best_ms", "worst_ms", "stack_need", "from_cache")},
     }
     print(json.dumps(out), flush=True)
 

@@ -403,6 +403,10 @@ typedef struct {
     float worst_ms;        /* autotuner's worst trace time */
     int32_t chunk_rays;    /* chosen chunk size (interleaved order, listener method) */
     int32_t from_cache;    /* 1 if the shape came from the tuning cache (in memory or file) */
+    int32_t stack_entries; /* traversal stack depth of the chosen kernel variant: 32, 48 or 64 (the
+                              autotuner may pick one deeper than stack_need asks for) */
+    int32_t fixed_point;   /* 1 if the histograms are accumulated in 64-bit fixed point: asked for
+                              (deterministic), or picked by the autotuner as the faster deposit */
 } RprBatchInfo;
 
 /* Plan a batch.

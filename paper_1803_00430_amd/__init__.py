@@ -87,7 +87,8 @@ class BatchInfo(C.Structure):
     _fields_ = [("total_rays", C.c_int64), ("n_pairs", C.c_int32), ("waves_per_cu", C.c_int32),
                 ("order", C.c_int32), ("stack_need", C.c_int32), ("graph", C.c_int32),
                 ("n_candidates", C.c_int32), ("best_ms", C.c_float), ("worst_ms", C.c_float),
-                ("chunk_rays", C.c_int32), ("from_cache", C.c_int32)]
+                ("chunk_rays", C.c_int32), ("from_cache", C.c_int32), ("stack_entries", C.c_int32),
+                ("fixed_point", C.c_int32)]
 
 
 # Host views of the device structs (same layout as include/rpr.h).

@@ -37,6 +37,7 @@ struct RprBatch {
     float dt = 0.f;
     int64_t total = 0;
     int stack_need = 0;
+    int stack_launch = 0;  // stack bound the launches take (at least stack_need: a deeper variant)
     int waves_per_cu = 0, order = 0;
     int64_t chunk = 1024;  // rays per chunk (interleaved order, listener chunk table)
     int method = 0;        // 0 source-origin, 1 listener-origin
@@ -50,7 +51,8 @@ struct RprBatch {
     float* hist_late = nullptr;
     RprIrStats* stats = nullptr;
     RprReverbParams* params = nullptr;
-    long long* fx = nullptr;       // fixed-point cells [n_pairs][T][B][NC] then [n_pairs][T][B] (deterministic)
+    long long* fx = nullptr;       // the fixed-point cells while deposits are in fixed point, else null
+    long long* fx_mem = nullptr;   // fixed-point cells [n_pairs][T][B][NC] then [n_pairs][T][B], once allocated
     double* fx_scales = nullptr;   // device [n_pairs]
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -60,9 +62,10 @@ struct RprBatch {
 namespace rpr {
 namespace {
 
-// The tuning cache: key -> (waves per CU, queue order, chunk rays).
+// The tuning cache: key -> (waves per CU, queue order, chunk rays, stack
+// bound the launches take, fixed-point deposits).
 struct TuneChoice {
-    int waves_per_cu, order, chunk;
+    int waves_per_cu, order, chunk, stack, fixed;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneChoice> g_tune_cache;
@@ -94,7 +97,8 @@ std::string tune_key(int device, const RprBatch& b, int64_t max_tris)
     return k;
 }
 
-// Read the file cache once (lines: key waves order chunk); called with g_tune_mu held.
+// Read the file cache once (lines: key waves order chunk stack fixed); called
+// with g_tune_mu held.
 void tune_file_read()
 {
     if (g_tune_file_read) return;
@@ -104,9 +108,11 @@ void tune_file_read()
     FILE* f = std::fopen(path, "r");
     if (!f) return;
     char key[256];
-    int w, o, c;
-    while (std::fscanf(f, "%255s %d %d %d", key, &w, &o, &c) == 4)
-        if (w >= 1 && o >= 0 && o <= 2 && (c == 256 || c == 1024 || c == 4096)) g_tune_cache[key] = TuneChoice{w, o, c};
+    int w, o, c, s, x;
+    while (std::fscanf(f, "%255s %d %d %d %d %d", key, &w, &o, &c, &s, &x) == 6)
+        if (w >= 1 && o >= 0 && o <= 2 && (c == 256 || c == 1024 || c == 4096) && s >= 0 && s < kMaxStack &&
+            (x == 0 || x == 1))
+            g_tune_cache[key] = TuneChoice{w, o, c, s, x};
     std::fclose(f);
 }
 
@@ -119,7 +125,8 @@ void tune_file_write()
     FILE* f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
     for (const auto& kv : g_tune_cache)
-        std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.waves_per_cu, kv.second.order, kv.second.chunk);
+        std::fprintf(f, "%s %d %d %d %d %d\n", kv.first.c_str(), kv.second.waves_per_cu, kv.second.order,
+                     kv.second.chunk, kv.second.stack, kv.second.fixed);
     const bool ok = std::fclose(f) == 0;
     if (ok) std::rename(tmp.c_str(), path);
 }
@@ -191,6 +198,39 @@ int upload_order(RprBatch& b, int ord, hipStream_t st)
     return RPR_OK;
 }
 
+// Deposits in 64-bit fixed point (RPR_TRACE_DETERMINISTIC's cells, allocated
+// on first use, released when FP32 deposits are chosen again) or in FP32
+// atomics: points the pair descriptors at the cells or not; upload_order then
+// carries the change to the device table.
+int set_deposit(RprBatch& b, bool fixed)
+{
+    const size_t hstride = (size_t)b.T * b.nb * b.nc, lstride = (size_t)b.T * b.nb;
+    if (!fixed && b.fx_mem) {
+        RPR_HIP_TRY(hipFree(b.fx_mem));
+        RPR_HIP_TRY(hipFree(b.fx_scales));
+        b.fx_mem = nullptr;
+        b.fx_scales = nullptr;
+    }
+    if (fixed && !b.fx_mem) {
+        const size_t cells = (size_t)b.n_pairs * hstride + (b.hist_late ? (size_t)b.n_pairs * lstride : 0);
+        RPR_HIP_TRY(hipMalloc(&b.fx_mem, sizeof(long long) * cells));
+        RPR_HIP_TRY(hipMalloc(&b.fx_scales, sizeof(double) * b.n_pairs));
+    }
+    std::vector<double> scales(b.n_pairs);
+    for (int i = 0; i < b.n_pairs; ++i) {
+        // 2^61 x sphere volume / (4 x bands x bin width)
+        const double r = b.pairs[i].radius;
+        scales[i] = 0x1p61 * (4.0 / 3.0 * M_PI * r * r * r) / (4.0 * b.nb * (double)b.dt);
+        PairDesc& d = b.pairs[i];
+        d.hist_fx = fixed ? b.fx_mem + (size_t)i * hstride : nullptr;
+        d.late_fx = fixed && b.hist_late ? b.fx_mem + (size_t)b.n_pairs * hstride + (size_t)i * lstride : nullptr;
+        d.fx_scale = fixed ? scales[i] : 0.0;
+    }
+    if (fixed) RPR_HIP_TRY(hipMemcpy(b.fx_scales, scales.data(), sizeof(double) * b.n_pairs, hipMemcpyHostToDevice));
+    b.fx = fixed ? b.fx_mem : nullptr;
+    return RPR_OK;
+}
+
 int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr)
 {
     int rc = enqueue_stats_reset(b.stats, b.n_pairs, b.d_queue, st);
@@ -208,10 +248,10 @@ int enqueue_run(RprBatch& b, hipStream_t st, hipEvent_t t0 = nullptr, hipEvent_t
     }
     if (t0) RPR_HIP_TRY(hipEventRecord(t0, st));
     rc = b.method == 1
-             ? launch_trace_listener_pairs(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_need,
+             ? launch_trace_listener_pairs(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_launch,
                                            b.waves_per_cu, st)
-             : launch_trace(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_need, false, b.waves_per_cu, 0,
-                            st);
+             : launch_trace(b.d_pairs, b.n_table, b.d_queue, b.total, b.nb, b.stack_launch, false, b.waves_per_cu,
+                            0, st);
     if (rc != RPR_OK) return rc;
     if (b.fx) {
         rc = enqueue_fx_convert(b.fx, b.hist, (long long)b.T * b.nb * b.nc, b.n_pairs, b.fx_scales, 0.0, st);
@@ -256,7 +296,7 @@ void batch_free(RprBatch* b)
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_pairs) (void)hipFree(b->d_pairs);
     if (b->d_queue) (void)hipFree(b->d_queue);
-    if (b->fx) (void)hipFree(b->fx);
+    if (b->fx_mem) (void)hipFree(b->fx_mem);
     if (b->fx_scales) (void)hipFree(b->fx_scales);
     delete b;
 }
@@ -360,28 +400,26 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         return code;
     };
     if (bp->deterministic) {
-        // fixed-point cells and each pair's scale: 2^61 x sphere volume / (4 x bands x bin width)
-        const size_t cells = (size_t)n_pairs * hstride + (hist_late ? (size_t)n_pairs * lstride : 0);
-        if (hipMalloc(&b->fx, sizeof(long long) * cells) != hipSuccess ||
-            hipMalloc(&b->fx_scales, sizeof(double) * n_pairs) != hipSuccess)
-            return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
-        std::vector<double> scales(n_pairs);
-        for (int i = 0; i < n_pairs; ++i) {
-            const double r = pairs[i].radius;
-            scales[i] = 0x1p61 * (4.0 / 3.0 * M_PI * r * r * r) / (4.0 * nb * (double)bp->bin_width_s);
-            PairDesc& d = b->pairs[i];
-            d.hist_fx = b->fx + (size_t)i * hstride;
-            d.late_fx = hist_late ? b->fx + (size_t)n_pairs * hstride + (size_t)i * lstride : nullptr;
-            d.fx_scale = scales[i];
-        }
-        if (hipMemcpy(b->fx_scales, scales.data(), sizeof(double) * n_pairs, hipMemcpyHostToDevice) != hipSuccess)
-            return fail(set_error(RPR_EDEVICE, "batch_create: copy failed"));
+        const int rc0 = set_deposit(*b, true);
+        if (rc0 != RPR_OK) return fail(rc0);
     }
     if (hipMalloc(&b->d_queue, 256) != hipSuccess)
         return fail(set_error(RPR_ENOMEM, "batch_create: device allocation failed"));
     if (device_cu_count() <= 0) return fail(set_error(RPR_EDEVICE, "batch_create: no device"));
-    const int max_wpc = bp->method == 1 ? trace_listener_max_waves_per_cu(nb, stack_need)
-                                        : trace_max_waves_per_cu(nb, stack_need);
+    // stack bounds the launches may take: the scene's own, or one that selects a
+    // deeper stack variant (more LDS per wave, fewer waves per CU)
+    auto max_wpc_for = [&](int stack) {
+        return bp->method == 1 ? trace_listener_max_waves_per_cu(nb, stack) : trace_max_waves_per_cu(nb, stack);
+    };
+    std::vector<int> stacks = {stack_need};
+    if (bp->method == 0) {
+        if (stack_need < 32) stacks.push_back(47);
+        if (stack_need < 48) stacks.push_back(63);
+    } else if (stack_need < 32) {
+        stacks.push_back(63);
+    }
+    b->stack_launch = stack_need;
+    const int max_wpc = max_wpc_for(stack_need);
 
     // launch shape: cached, autotuned or as requested
     int rc = RPR_OK;
@@ -390,27 +428,37 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     if (bp->autotune) {
         const std::string key = tune_key(b->device, *b, max_tris);
         bool cached = false;
+        TuneChoice pick{max_wpc, 0, 1024, stack_need, bp->deterministic ? 1 : 0};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             tune_file_read();
             auto it = g_tune_cache.find(key);
             if (it != g_tune_cache.end()) {
-                b->waves_per_cu = std::min(it->second.waves_per_cu, max_wpc);
-                b->order = it->second.order;
-                b->chunk = it->second.chunk;
+                pick = it->second;
                 cached = true;
             }
         }
         if (cached) {
             b->info.from_cache = 1;
-            rc = upload_order(*b, b->order, st);
-            if (rc != RPR_OK) return fail(rc);
+            if (std::find(stacks.begin(), stacks.end(), pick.stack) == stacks.end()) pick.stack = stack_need;
+            pick.fixed = bp->deterministic || (pick.fixed && bp->method == 0) ? 1 : 0;
         } else {
-            std::vector<int> widths;
-            for (int w : {max_wpc / 4, max_wpc / 2, (3 * max_wpc) / 4, max_wpc})
-                if (w >= 1 && std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+            auto widths_for = [](int mw) {
+                std::vector<int> widths;
+                for (int w : {mw / 4, mw / 2, (3 * mw) / 4, mw})
+                    if (w >= 1 && std::find(widths.begin(), widths.end(), w) == widths.end()) widths.push_back(w);
+                return widths;
+            };
             float best = 1e30f, worst = 0.f;
-            TuneChoice pick{max_wpc, 0, 1024};
+            auto time_width = [&](int w, float& ms) {
+                b->waves_per_cu = w;
+                const int rc1 = time_shape(*b, st, 3, ms);
+                if (rc1 != RPR_OK) return rc1;
+                ++b->info.n_candidates;
+                worst = std::max(worst, ms);
+                return RPR_OK;
+            };
+            // stage 1: widths x queue orders x chunk sizes, on the scene's own stack bound
             for (int o = 0; o < 3; ++o) {
                 // the chunk size matters to the interleaved order and to the listener method's chunk table
                 const bool chunked = o == 2 || b->method == 1;
@@ -418,30 +466,59 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
                     b->chunk = chunked ? kChunkChoices[ci] : 1024;
                     rc = upload_order(*b, o, st);
                     if (rc != RPR_OK) return fail(rc);
-                    for (int w : widths) {
-                        b->waves_per_cu = w;
+                    for (int w : widths_for(max_wpc)) {
                         float ms = 0.f;
-                        rc = time_shape(*b, st, 3, ms);
+                        rc = time_width(w, ms);
                         if (rc != RPR_OK) return fail(rc);
-                        ++b->info.n_candidates;
-                        worst = std::max(worst, ms);
                         if (ms < best) {
                             best = ms;
-                            pick = TuneChoice{w, o, (int)b->chunk};
+                            pick = TuneChoice{w, o, (int)b->chunk, stack_need, pick.fixed};
                         }
                     }
                 }
             }
-            b->info.best_ms = best;
-            b->info.worst_ms = worst;
-            b->waves_per_cu = pick.waves_per_cu;
+            // stage 2: the deeper stack variants, at the best order and chunk size
             b->chunk = pick.chunk;
             rc = upload_order(*b, pick.order, st);
             if (rc != RPR_OK) return fail(rc);
+            for (size_t si = 1; si < stacks.size(); ++si) {
+                b->stack_launch = stacks[si];
+                for (int w : widths_for(max_wpc_for(stacks[si]))) {
+                    float ms = 0.f;
+                    rc = time_width(w, ms);
+                    if (rc != RPR_OK) return fail(rc);
+                    if (ms < best) {
+                        best = ms;
+                        pick.waves_per_cu = w;
+                        pick.stack = stacks[si];
+                    }
+                }
+            }
+            // stage 3: 64-bit fixed-point deposits at the best shape (unless already asked for)
+            if (bp->method == 0 && !bp->deterministic) {
+                b->stack_launch = pick.stack;
+                rc = set_deposit(*b, true);
+                if (rc == RPR_OK) rc = upload_order(*b, pick.order, st);
+                float ms = 0.f;
+                if (rc == RPR_OK) rc = time_width(pick.waves_per_cu, ms);
+                if (rc != RPR_OK) return fail(rc);
+                if (ms < best) {
+                    best = ms;
+                    pick.fixed = 1;
+                }
+            }
+            b->info.best_ms = best;
+            b->info.worst_ms = worst;
             std::lock_guard<std::mutex> lk(g_tune_mu);
             g_tune_cache[key] = pick;
             tune_file_write();
         }
+        b->stack_launch = pick.stack;
+        b->waves_per_cu = std::min(pick.waves_per_cu, max_wpc_for(pick.stack));
+        b->chunk = pick.chunk;
+        rc = set_deposit(*b, pick.fixed != 0);
+        if (rc == RPR_OK) rc = upload_order(*b, pick.order, st);
+        if (rc != RPR_OK) return fail(rc);
     } else {
         b->waves_per_cu = bp->waves_per_cu > 0 ? std::min(bp->waves_per_cu, max_wpc) : max_wpc;
         b->chunk = bp->chunk_rays > 0 ? bp->chunk_rays : 1024;
@@ -475,6 +552,8 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     b->info.stack_need = stack_need;
     b->info.graph = b->exec ? 1 : 0;
     b->info.chunk_rays = (int32_t)b->chunk;
+    b->info.stack_entries = b->stack_launch < 32 ? 32 : (b->stack_launch < 48 && b->method == 0 ? 48 : 64);
+    b->info.fixed_point = b->fx ? 1 : 0;
     *out = b;
     return RPR_OK;
 }

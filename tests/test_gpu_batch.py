@@ -137,9 +137,9 @@ def _tune_case():
 
 
 def test_autotune_cache_file(setup, tmp_path, monkeypatch):
-    """With RPR_AUTOTUNE_CACHE set, a tuned shape is written to the file
-    (one line per key) and a new process takes it from there without timing
-    any candidate."""
+    """With RPR_AUTOTUNE_CACHE set, a tuned shape (width, queue order, chunk
+    size, stack variant, deposit mode) is written to the file (one line per
+    key) and a new process takes it from there without timing any candidate."""
     import json
     import os
     import subprocess
@@ -150,10 +150,14 @@ def test_autotune_cache_file(setup, tmp_path, monkeypatch):
     b = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=True, use_graph=False)
     info = b.info()
     b.close()
-    assert info["from_cache"] == 1 or info["n_candidates"] >= 8  # 4 widths x (1 + 1 + 3 chunk sizes)
+    # 4 widths x (1 + 1 + 3 chunk sizes), then the deeper stack variants and fixed-point deposits
+    assert info["from_cache"] == 1 or info["n_candidates"] >= 8
+    assert info["stack_entries"] in (32, 48, 64) and info["stack_need"] < info["stack_entries"]
+    assert info["fixed_point"] in (0, 1)
     lines = [l.split() for l in path.read_text().splitlines()]
-    assert lines and all(len(l) == 4 for l in lines)
-    mine = [l for l in lines if l[1:] == [str(info["waves_per_cu"]), str(info["order"]), str(info["chunk_rays"])]]
+    assert lines and all(len(l) == 6 for l in lines)
+    mine = [l for l in lines if l[1:4] == [str(info["waves_per_cu"]), str(info["order"]), str(info["chunk_rays"])]
+            and l[5] == str(info["fixed_point"])]
     assert mine, (lines, info)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out = subprocess.run([sys.executable, "-c", _CACHED_CHILD, root], capture_output=True, text=True, timeout=300,
@@ -161,8 +165,8 @@ def test_autotune_cache_file(setup, tmp_path, monkeypatch):
     assert out.returncode == 0, out.stderr[-2000:]
     child = json.loads(out.stdout.strip().splitlines()[-1])
     assert child["from_cache"] == 1 and child["n_candidates"] == 0
-    assert (child["waves_per_cu"], child["order"], child["chunk_rays"]) == \
-        (info["waves_per_cu"], info["order"], info["chunk_rays"])
+    keys = ("waves_per_cu", "order", "chunk_rays", "stack_entries", "fixed_point")
+    assert tuple(child[k] for k in keys) == tuple(info[k] for k in keys)
 
 
 def test_deterministic_graph_replays_equal_eager(setup):
@@ -178,6 +182,7 @@ def test_deterministic_graph_replays_equal_eager(setup):
     He, HLe, ste, pre = _host(eager)
     g = P.Batch(scenes, pairs, n_bins=T, sh_order=NSH, bin_width_s=DT, autotune=True, use_graph=True,
                 deterministic=True)
+    assert eager.info()["fixed_point"] == 1 and g.info()["fixed_point"] == 1
     for rep in range(3):
         g.run()
         torch.cuda.synchronize()
