@@ -412,12 +412,8 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
         return bp->method == 1 ? trace_listener_max_waves_per_cu(nb, stack) : trace_max_waves_per_cu(nb, stack);
     };
     std::vector<int> stacks = {stack_need};
-    if (bp->method == 0) {
-        if (stack_need < 32) stacks.push_back(47);
-        if (stack_need < 48) stacks.push_back(63);
-    } else if (stack_need < 32) {
-        stacks.push_back(63);
-    }
+    if (stack_need < 32) stacks.push_back(47);
+    if (stack_need < 48) stacks.push_back(63);
     b->stack_launch = stack_need;
     const int max_wpc = max_wpc_for(stack_need);
 
@@ -552,7 +548,7 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
     b->info.stack_need = stack_need;
     b->info.graph = b->exec ? 1 : 0;
     b->info.chunk_rays = (int32_t)b->chunk;
-    b->info.stack_entries = b->stack_launch < 32 ? 32 : (b->stack_launch < 48 && b->method == 0 ? 48 : 64);
+    b->info.stack_entries = b->stack_launch < 32 ? 32 : (b->stack_launch < 48 ? 48 : 64);
     b->info.fixed_point = b->fx ? 1 : 0;
     *out = b;
     return RPR_OK;

@@ -240,7 +240,10 @@ __device__ __forceinline__ float occlusion_query(const SceneView& sc, float ox, 
 }
 
 template <int NB, int STACK>
-__global__ void __launch_bounds__(kWave) k_trace_lst(const LstDesc D, unsigned long long* __restrict__ queue)
+// With four bands and up to 48 stack entries the kernel is held to 168 VGPRs
+// (a few bytes of spills) so that 3 waves fit per SIMD instead of 2.
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(NB <= 4 && STACK <= 48 ? 3 : 1)))
+k_trace_lst(const LstDesc D, unsigned long long* __restrict__ queue)
 {
     __shared__ int32_t stk[STACK * kWave];
     __shared__ float shrow[kWave * RPR_MAX_COEFFS];  // SH of each lane's arrival direction
@@ -670,8 +673,8 @@ __device__ __forceinline__ void pair_deposit(const PairDesc* __restrict__ pairs,
 // over many pairs.  Each pair's rays leave its listener point and query its
 // source's ball.
 template <int NB, int STACK>
-__global__ void __launch_bounds__(kWave) k_trace_lstp(const PairDesc* __restrict__ pairs, int n_table,
-                                                      unsigned long long* __restrict__ queue)
+__global__ void __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(NB <= 4 && STACK <= 48 ? 3 : 1)))
+k_trace_lstp(const PairDesc* __restrict__ pairs, int n_table, unsigned long long* __restrict__ queue)
 {
     __shared__ int32_t stk[STACK * kWave];
     __shared__ float shrow[kWave * RPR_MAX_COEFFS];  // SH of each lane's arrival direction
@@ -1046,7 +1049,10 @@ struct LstVariant {
 };
 
 std::mutex g_lmu;
-LstVariant g_lvar[2][2];  // [bands 4/8][stack 32/64]
+// Stack depths of the variants, 32, 48 and 64 entries: a scene takes the
+// smallest that exceeds its stack bound.
+inline int lst_stack_bucket(int stack_need) { return stack_need < 32 ? 0 : (stack_need < 48 ? 1 : 2); }
+LstVariant g_lvar[2][3];  // [bands 4/8][stack 32/48/64]
 bool g_lvar_init = false;
 int g_lcus = 0;
 
@@ -1058,9 +1064,11 @@ int ensure_lst_variants()
     RPR_HIP_TRY(hipGetDevice(&dev));
     RPR_HIP_TRY(hipDeviceGetAttribute(&g_lcus, hipDeviceAttributeMultiprocessorCount, dev));
     g_lvar[0][0].fn = k_trace_lst<4, 32>;
-    g_lvar[0][1].fn = k_trace_lst<4, 64>;
+    g_lvar[0][1].fn = k_trace_lst<4, 48>;
+    g_lvar[0][2].fn = k_trace_lst<4, 64>;
     g_lvar[1][0].fn = k_trace_lst<8, 32>;
-    g_lvar[1][1].fn = k_trace_lst<8, 64>;
+    g_lvar[1][1].fn = k_trace_lst<8, 48>;
+    g_lvar[1][2].fn = k_trace_lst<8, 64>;
     g_lvar_init = true;
     return RPR_OK;
 }
@@ -1068,8 +1076,8 @@ int ensure_lst_variants()
 using LstpFn = void (*)(const PairDesc*, int, unsigned long long*);
 
 std::mutex g_pmu;
-LstpFn g_pfn[2][2];
-int g_pper[2][2];
+LstpFn g_pfn[2][3];
+int g_pper[2][3];
 bool g_p_init = false;
 
 int ensure_lstp_variants()
@@ -1077,11 +1085,13 @@ int ensure_lstp_variants()
     std::lock_guard<std::mutex> lk(g_pmu);
     if (g_p_init) return RPR_OK;
     g_pfn[0][0] = k_trace_lstp<4, 32>;
-    g_pfn[0][1] = k_trace_lstp<4, 64>;
+    g_pfn[0][1] = k_trace_lstp<4, 48>;
+    g_pfn[0][2] = k_trace_lstp<4, 64>;
     g_pfn[1][0] = k_trace_lstp<8, 32>;
-    g_pfn[1][1] = k_trace_lstp<8, 64>;
+    g_pfn[1][1] = k_trace_lstp<8, 48>;
+    g_pfn[1][2] = k_trace_lstp<8, 64>;
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 3; ++b) {
             int nb = 0;
             RPR_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)g_pfn[a][b], kWave, 0));
             g_pper[a][b] = nb > 0 ? nb : 1;
@@ -1098,7 +1108,7 @@ int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned
     if (total_rays <= 0 || n_chunks <= 0) return RPR_OK;
     int rc = ensure_lstp_variants();
     if (rc != RPR_OK) return rc;
-    const int bi = nb <= 4 ? 0 : 1, si = stack_need < 32 ? 0 : 1;
+    const int bi = nb <= 4 ? 0 : 1, si = lst_stack_bucket(stack_need);
     const int per_cu = waves_per_cu > 0 ? std::min(waves_per_cu, g_pper[bi][si]) : g_pper[bi][si];
     long long grid = (long long)device_cu_count() * per_cu;
     grid = std::max(1ll, std::min(grid, (long long)n_chunks));
@@ -1110,7 +1120,7 @@ int launch_trace_listener_pairs(const PairDesc* d_chunks, int n_chunks, unsigned
 int trace_listener_max_waves_per_cu(int nb, int stack_need)
 {
     if (ensure_lstp_variants() != RPR_OK) return 1;
-    return g_pper[nb <= 4 ? 0 : 1][stack_need < 32 ? 0 : 1];
+    return g_pper[nb <= 4 ? 0 : 1][lst_stack_bucket(stack_need)];
 }
 
 }  // namespace rpr
@@ -1213,7 +1223,7 @@ extern "C" int trace_listener(const RprScene* scene, const RprSource* srcs, int3
     }
     RPR_HIP_TRY(hipGetLastError());
     if (R > 0) {
-        const int bi = nb <= 4 ? 0 : 1, si = scene->stack_need < 32 ? 0 : 1;
+        const int bi = nb <= 4 ? 0 : 1, si = lst_stack_bucket(scene->stack_need);
         const LstFn fn = g_lvar[bi][si].fn;
         const int NBv = bi == 0 ? 4 : 8;
         const size_t dyn = sizeof(double) * (size_t)n_src * 3 * NBv + sizeof(int) * 2 * (size_t)n_src;
