@@ -490,17 +490,22 @@ extern "C" int batch_create(const RprScene* const* scenes, int32_t n_scenes, con
                     }
                 }
             }
-            // stage 3: 64-bit fixed-point deposits at the best shape (unless already asked for)
+            // stage 3: 64-bit fixed-point deposits at the best shape (unless already asked
+            // for); skipped when the cells do not fit in device memory
             if (bp->method == 0 && !bp->deterministic) {
                 b->stack_launch = pick.stack;
-                rc = set_deposit(*b, true);
-                if (rc == RPR_OK) rc = upload_order(*b, pick.order, st);
-                float ms = 0.f;
-                if (rc == RPR_OK) rc = time_width(pick.waves_per_cu, ms);
-                if (rc != RPR_OK) return fail(rc);
-                if (ms < best) {
-                    best = ms;
-                    pick.fixed = 1;
+                if (set_deposit(*b, true) == RPR_OK) {
+                    rc = upload_order(*b, pick.order, st);
+                    float ms = 0.f;
+                    if (rc == RPR_OK) rc = time_width(pick.waves_per_cu, ms);
+                    if (rc != RPR_OK) return fail(rc);
+                    if (ms < best) {
+                        best = ms;
+                        pick.fixed = 1;
+                    }
+                } else {
+                    (void)hipGetLastError();
+                    rc = RPR_OK;
                 }
             }
             b->info.best_ms = best;
