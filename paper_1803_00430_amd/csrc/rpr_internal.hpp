@@ -144,9 +144,9 @@ namespace rpr {
 // scene's sizes on success; an empty scene and the build's error otherwise
 // (reported once).  Every call that reads a scene calls this first.
 int scene_settle(const RprScene* scene);
-// Ensure the workspace holds `pairs` pair descriptors, and fx_bytes of
-// fixed-point histogram cells from workspace_fx_offset(pairs) on; returns
-// RPR_OK or an error.
+// Ensure the workspace holds `pairs` pair descriptors, and fx_bytes more from
+// workspace_fx_offset(pairs) on (fixed-point histogram cells, then the slot
+// order of the trace); returns RPR_OK or an error.
 int workspace_reserve(Workspace& ws, size_t pairs, size_t fx_bytes = 0);
 size_t workspace_fx_offset(size_t pairs);
 void workspace_free(Workspace& ws);
@@ -154,7 +154,7 @@ void workspace_free(Workspace& ws);
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays,
                  int nb, int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
                  float* rec = nullptr, unsigned* rec_count = nullptr, int rec_cap = 0,
-                 const long long* total_dev = nullptr);
+                 const long long* total_dev = nullptr, const uint32_t* order = nullptr);
 
 // Early-reflection path records (trace_ir_paths, path_cache_*): 32 words each,
 // words 0-1 the key (source << 48 | order << 46 | tri1 << 23 | tri2, 23-bit

@@ -34,7 +34,8 @@ template <int NB, int STACK, bool COUNT, bool REC>
 __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pairs, int n_pairs,
                                                  unsigned long long* __restrict__ queue, long long total,
                                                  float* __restrict__ rec, unsigned* __restrict__ rec_count,
-                                                 int rec_cap, const long long* __restrict__ total_dev)
+                                                 int rec_cap, const long long* __restrict__ total_dev,
+                                                 const uint32_t* __restrict__ order)
 {
     if (total_dev) total = *total_dev;
     __shared__ int32_t stk[STACK * kWave];
@@ -98,7 +99,10 @@ __global__ void __launch_bounds__(kWave) k_trace(const PairDesc* __restrict__ pa
                 long long r = -1;
                 if (!alive) {
                     r = (long long)(base + (unsigned long long)__popcll(dead & lt));
-                    if (r < total) np = find_pair(pairs, n_pairs, r);
+                    if (r < total) {
+                        if (order) r = (long long)order[r];  // the slot's ray (see k_dir_scatter)
+                        np = find_pair(pairs, n_pairs, r);
+                    }
                 }
                 flush_req = np >= 0 && acc.p >= 0 && acc.p != np;
                 if (np >= 0) {
@@ -419,7 +423,8 @@ __global__ void k_setup(SetupArgs a, PairDesc* __restrict__ out) { setup_pair(a,
 // three ranges (null when absent).
 __global__ void __launch_bounds__(256) k_setup_fill(SetupArgs a, PairDesc* __restrict__ out, float* __restrict__ z0,
                                                     size_t n0, float* __restrict__ z1, size_t n1,
-                                                    float* __restrict__ z2, size_t n2)
+                                                    float* __restrict__ z2, size_t n2, uint32_t* __restrict__ z3,
+                                                    size_t n3)
 {
     if (blockIdx.x == 0 && threadIdx.x < kSetupChunk) setup_pair(a, out, threadIdx.x);
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -429,6 +434,86 @@ __global__ void __launch_bounds__(256) k_setup_fill(SetupArgs a, PairDesc* __res
         for (size_t i = i0; i < n1; i += stride) z1[i] = 0.0f;
     if (z2)
         for (size_t i = i0; i < n2; i += stride) z2[i] = 0.0f;
+    if (z3)
+        for (size_t i = i0; i < n3; i += stride) z3[i] = 0u;
+}
+
+// Lanes of a wave that trace rays of similar first direction visit the same
+// nodes for that segment, and wait less for each other: which queue slot
+// traces which ray does not change any ray's path (every random number is
+// drawn from the ray id), so the slots of each source are given its rays
+// sorted into 64 x 64 cells of the two uniforms that set the first direction
+// (height and azimuth on the sphere, an equal-area map), in Morton order of the
+// cells.  A counting sort: cell counts, one exclusive scan over (source, cell),
+// then each ray takes the next position of its cell.  The order inside a cell
+// is that of the atomics.
+constexpr int kDirCellBits = 6;
+constexpr int kDirCells = 1 << (2 * kDirCellBits);
+constexpr int kDirMaxSources = 1024;  // 16 KB of cell counts each
+
+__device__ __forceinline__ uint32_t dir_cell(const PairDesc& P, uint32_t ray)
+{
+    const uint4 x = philox4x32_10(make_uint4(ray, P.pair_id, 0u, 0u), P.key0, P.key1);
+    uint32_t a = x.x >> (32 - kDirCellBits), b = x.y >> (32 - kDirCellBits), c = 0;
+#pragma unroll
+    for (int k = 0; k < kDirCellBits; ++k) c |= (((a >> k) & 1u) << (2 * k + 1)) | (((b >> k) & 1u) << (2 * k));
+    return c;
+}
+
+__global__ void k_dir_count(const PairDesc* __restrict__ pairs, long long R, long long total,
+                            uint32_t* __restrict__ counts)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int s = (int)(q / R);
+    const PairDesc& P = pairs[s];
+    atomicAdd(&counts[(size_t)s * kDirCells + dir_cell(P, (uint32_t)(P.ray_begin + (q - (long long)s * R)))], 1u);
+}
+
+// Each source's cell counts become the first queue slot of each cell: an
+// exclusive scan of its kDirCells counts, from the source's first slot s * R.
+// One workgroup per source, four cells per thread.
+static_assert(kDirCells == 4 * 1024, "k_dir_scan takes four cells per thread");
+__global__ void __launch_bounds__(1024) k_dir_scan(uint32_t* __restrict__ v, long long R)
+{
+    __shared__ uint32_t wsum[1024 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    uint4* row = reinterpret_cast<uint4*>(v + (size_t)blockIdx.x * kDirCells);
+    const uint4 c = row[t];
+    const uint32_t own = c.x + c.y + c.z + c.w;
+    uint32_t inc = own;  // inclusive scan over the wave
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t x = __shfl_up(inc, o);
+        if (lane >= o) inc += x;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    uint32_t run = (uint32_t)((long long)blockIdx.x * R) + before + inc - own;
+    uint4 o;
+    o.x = run;
+    run += c.x;
+    o.y = run;
+    run += c.y;
+    o.z = run;
+    run += c.z;
+    o.w = run;
+    row[t] = o;
+}
+
+// order[slot] = the queue slot of the ray that slot traces.
+__global__ void k_dir_scatter(const PairDesc* __restrict__ pairs, long long R, long long total,
+                              uint32_t* __restrict__ next, uint32_t* __restrict__ order)
+{
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int s = (int)(q / R);
+    const PairDesc& P = pairs[s];
+    const uint32_t c = dir_cell(P, (uint32_t)(P.ray_begin + (q - (long long)s * R)));
+    const uint32_t pos = atomicAdd(&next[(size_t)s * kDirCells + c], 1u);
+    if (pos < (uint64_t)total) order[pos] = (uint32_t)q;
 }
 
 // Segment budget, second pass: from each source's segment count of the
@@ -552,7 +637,7 @@ __global__ void k_debug_sh(const float* __restrict__ dirs, long long n, int orde
 
 // ---------------------------------------------------------------- launch helpers
 using TraceFn = void (*)(const PairDesc*, int, unsigned long long*, long long, float*, unsigned*, int,
-                         const long long*);
+                         const long long*, const uint32_t*);
 
 template <int NB, int STACK, bool COUNT, bool REC = false>
 TraceFn trace_fn()
@@ -678,7 +763,7 @@ int enqueue_stats_reset(RprIrStats* stats, int n, unsigned long long* queue, hip
 
 int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_queue, int64_t total_rays, int nb,
                  int stack_need, bool count_visits, int waves_per_cu, int grid_override, hipStream_t stream,
-                 float* rec, unsigned* rec_count, int rec_cap, const long long* total_dev)
+                 float* rec, unsigned* rec_count, int rec_cap, const long long* total_dev, const uint32_t* order)
 {
     // with total_dev, total_rays is the most slots the launch may find there (it sizes the grid)
     if (total_rays <= 0 || n_pairs <= 0) return RPR_OK;
@@ -691,7 +776,7 @@ int launch_trace(const PairDesc* d_pairs, int n_pairs, unsigned long long* d_que
     const long long need = (total_rays + kWave - 1) / kWave;
     grid = std::max(1ll, std::min(grid, need));
     hipLaunchKernelGGL(v.fn, dim3((unsigned)grid), dim3(kWave), 0, stream, d_pairs, n_pairs, d_queue,
-                       (long long)total_rays, rec, rec_count, rec_cap, total_dev);
+                       (long long)total_rays, rec, rec_count, rec_cap, total_dev, order);
     RPR_HIP_TRY(hipGetLastError());
     return RPR_OK;
 }
@@ -791,12 +876,21 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     const int nb0 = scene->n_bands;
     const int nc0 = (p->sh_order + 1) * (p->sh_order + 1);
     const size_t fx_cells = det ? (size_t)n_src * p->n_bins * nb0 * (nc0 + (hist_late ? 1 : 0)) : 0;
+    // slots ordered by first direction (k_dir_*) in the scene's own workspace
+    const long long rays_all = (p->ray_end - p->ray_begin) * (long long)n_src;
+    const bool by_dir = !ws && !rec && !budget && n_src <= kDirMaxSources && p->ray_end - p->ray_begin >= kWave &&
+                        rays_all < ((long long)1 << 32);
+    const size_t dir_off = (fx_cells * sizeof(long long) + 255) & ~(size_t)255;
+    const size_t dir_counts = by_dir ? (size_t)n_src * kDirCells : 0;
+    const size_t dir_bytes = by_dir ? sizeof(uint32_t) * (dir_counts + (size_t)rays_all) : 0;
     if (!ws) {
         RprScene* sc = const_cast<RprScene*>(scene);
-        const int rc = workspace_reserve(sc->ws, (size_t)n_src, fx_cells * sizeof(long long));
+        const int rc = workspace_reserve(sc->ws, (size_t)n_src, dir_off + dir_bytes);
         if (rc != RPR_OK) return rc;
         ws = sc->ws.dev;
     }
+    uint32_t* dir_next = by_dir ? (uint32_t*)((char*)ws + workspace_fx_offset((size_t)n_src) + dir_off) : nullptr;
+    uint32_t* dir_order = by_dir ? dir_next + dir_counts : nullptr;
     unsigned long long* d_queue = (unsigned long long*)ws;
     PairDesc* d_pairs = (PairDesc*)((char*)ws + 256);
 
@@ -866,12 +960,19 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
             hipLaunchKernelGGL(k_setup, dim3(1), dim3(kSetupChunk), 0, st, a, d_pairs);
         else
             hipLaunchKernelGGL(k_setup_fill, dim3((unsigned)fill_blocks), dim3(256), 0, st, a, d_pairs, hist, nh, fx0,
-                               nf, hist_late, nl);
+                               nf, hist_late, nl, dir_next, dir_counts);
     }
     RPR_HIP_TRY(hipGetLastError());
+    if (by_dir) {
+        const unsigned g = (unsigned)((rays_all + 255) / 256);
+        hipLaunchKernelGGL(k_dir_count, dim3(g), dim3(256), 0, st, d_pairs, R, rays_all, dir_next);
+        hipLaunchKernelGGL(k_dir_scan, dim3((unsigned)n_src), dim3(1024), 0, st, dir_next, R);
+        hipLaunchKernelGGL(k_dir_scatter, dim3(g), dim3(256), 0, st, d_pairs, R, rays_all, dir_next, dir_order);
+        RPR_HIP_TRY(hipGetLastError());
+    }
     const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;
     int rc = launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need, count, p->waves_per_cu, 0, st,
-                          rec, rec_count, rec_cap);
+                          rec, rec_count, rec_cap, nullptr, dir_order);
     if (rc != RPR_OK) return rc;
     auto convert = [&]() -> int {
         if (!det) return RPR_OK;
