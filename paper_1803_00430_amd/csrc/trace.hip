@@ -460,14 +460,30 @@ __device__ __forceinline__ uint32_t dir_cell(const PairDesc& P, uint32_t ray)
     return c;
 }
 
-__global__ void k_dir_count(const PairDesc* __restrict__ pairs, long long R, long long total,
-                            uint32_t* __restrict__ counts)
+// Blocks of kDirChunk rays of one source (grid: chunks x sources) count in
+// LDS first; each block then adds its nonzero cells to the source's counts
+// with atomics over consecutive words, a few cache lines per wave.
+constexpr int kDirThreads = 256;
+constexpr int kDirChunk = 4 * kDirThreads;
+
+__global__ void __launch_bounds__(kDirThreads) k_dir_count(const PairDesc* __restrict__ pairs, long long R,
+                                                           uint32_t* __restrict__ counts)
 {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const int s = (int)(q / R);
+    __shared__ uint32_t h[kDirCells];
+    const int s = blockIdx.y;
     const PairDesc& P = pairs[s];
-    atomicAdd(&counts[(size_t)s * kDirCells + dir_cell(P, (uint32_t)(P.ray_begin + (q - (long long)s * R)))], 1u);
+    for (int i = threadIdx.x; i < kDirCells; i += kDirThreads) h[i] = 0u;
+    __syncthreads();
+    const long long j0 = (long long)blockIdx.x * kDirChunk + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kDirChunk / kDirThreads; ++k) {
+        const long long j = j0 + k * kDirThreads;
+        if (j < R) atomicAdd(&h[dir_cell(P, (uint32_t)(P.ray_begin + j))], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = counts + (size_t)s * kDirCells;
+    for (int i = threadIdx.x; i < kDirCells; i += kDirThreads)
+        if (const uint32_t c = h[i]) atomicAdd(&row[i], c);
 }
 
 // Each source's cell counts become the first queue slot of each cell: an
@@ -503,17 +519,44 @@ __global__ void __launch_bounds__(1024) k_dir_scan(uint32_t* __restrict__ v, lon
     row[t] = o;
 }
 
-// order[slot] = the queue slot of the ray that slot traces.
-__global__ void k_dir_scatter(const PairDesc* __restrict__ pairs, long long R, long long total,
-                              uint32_t* __restrict__ next, uint32_t* __restrict__ order)
+// order[slot] = the queue slot of the ray that slot traces.  Same blocks as
+// k_dir_count: ranks inside the block's cells from LDS atomics, then one
+// atomic per nonzero cell reserves the block's run of that cell's slots.
+__global__ void __launch_bounds__(kDirThreads) k_dir_scatter(const PairDesc* __restrict__ pairs, long long R,
+                                                             uint32_t* __restrict__ next,
+                                                             uint32_t* __restrict__ order)
 {
-    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const int s = (int)(q / R);
+    __shared__ uint32_t h[kDirCells];
+    const int s = blockIdx.y;
     const PairDesc& P = pairs[s];
-    const uint32_t c = dir_cell(P, (uint32_t)(P.ray_begin + (q - (long long)s * R)));
-    const uint32_t pos = atomicAdd(&next[(size_t)s * kDirCells + c], 1u);
-    if (pos < (uint64_t)total) order[pos] = (uint32_t)q;
+    for (int i = threadIdx.x; i < kDirCells; i += kDirThreads) h[i] = 0u;
+    __syncthreads();
+    const long long j0 = (long long)blockIdx.x * kDirChunk + threadIdx.x;
+    uint32_t cell[kDirChunk / kDirThreads], rank[kDirChunk / kDirThreads];
+#pragma unroll
+    for (int k = 0; k < kDirChunk / kDirThreads; ++k) {
+        const long long j = j0 + k * kDirThreads;
+        cell[k] = 0u;
+        rank[k] = 0u;
+        if (j < R) {
+            cell[k] = dir_cell(P, (uint32_t)(P.ray_begin + j));
+            rank[k] = atomicAdd(&h[cell[k]], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* row = next + (size_t)s * kDirCells;
+    for (int i = threadIdx.x; i < kDirCells; i += kDirThreads)
+        if (const uint32_t c = h[i]) h[i] = atomicAdd(&row[i], c);
+    __syncthreads();
+    const long long total = R * (long long)gridDim.y;
+#pragma unroll
+    for (int k = 0; k < kDirChunk / kDirThreads; ++k) {
+        const long long j = j0 + k * kDirThreads;
+        if (j < R) {
+            const uint32_t pos = h[cell[k]] + rank[k];
+            if ((long long)pos < total) order[pos] = (uint32_t)((long long)s * R + j);
+        }
+    }
 }
 
 // Segment budget, second pass: from each source's segment count of the
@@ -964,10 +1007,10 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     }
     RPR_HIP_TRY(hipGetLastError());
     if (by_dir) {
-        const unsigned g = (unsigned)((rays_all + 255) / 256);
-        hipLaunchKernelGGL(k_dir_count, dim3(g), dim3(256), 0, st, d_pairs, R, rays_all, dir_next);
+        const dim3 g((unsigned)((R + kDirChunk - 1) / kDirChunk), (unsigned)n_src);
+        hipLaunchKernelGGL(k_dir_count, g, dim3(kDirThreads), 0, st, d_pairs, R, dir_next);
         hipLaunchKernelGGL(k_dir_scan, dim3((unsigned)n_src), dim3(1024), 0, st, dir_next, R);
-        hipLaunchKernelGGL(k_dir_scatter, dim3(g), dim3(256), 0, st, d_pairs, R, rays_all, dir_next, dir_order);
+        hipLaunchKernelGGL(k_dir_scatter, g, dim3(kDirThreads), 0, st, d_pairs, R, dir_next, dir_order);
         RPR_HIP_TRY(hipGetLastError());
     }
     const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;
