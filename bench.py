@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace and build
 # sources it was measured on (the build makes the tree the trace reads):
 # reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 35816016.0,
-                 "sources_sha256": "7b3bdbe69af4c9dbc589cae8daa5eef28ba8fe8cf2b2b515f8a2a822a132f31f"}
+TRACE_TRAFFIC = {"bytes": 36645591.0,
+                 "sources_sha256": "19f5cd63070ffb973ed994bf6ec832ffe45200f71f85b4e29edc918147473237"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp",
                  "paper_1803_00430_amd/csrc/lbvh.hip")

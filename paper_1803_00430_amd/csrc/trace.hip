@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(1024) k_dir_scan(uint32_t* __restrict__ v, lon
 
 // order[slot] = the queue slot of the ray that slot traces.  Same blocks as
 // k_dir_count: ranks inside the block's cells from LDS atomics, then one
-// atomic per nonzero cell reserves the block's run of that cell's slots.
+// atomic per cell reserves the block's run of that cell's slots.
 __global__ void __launch_bounds__(kDirThreads) k_dir_scatter(const PairDesc* __restrict__ pairs, long long R,
                                                              uint32_t* __restrict__ next,
                                                              uint32_t* __restrict__ order)
@@ -544,9 +544,14 @@ __global__ void __launch_bounds__(kDirThreads) k_dir_scatter(const PairDesc* __r
         }
     }
     __syncthreads();
+    // all of a thread's atomics in flight at once (a cell with no ray adds 0)
     uint32_t* row = next + (size_t)s * kDirCells;
-    for (int i = threadIdx.x; i < kDirCells; i += kDirThreads)
-        if (const uint32_t c = h[i]) h[i] = atomicAdd(&row[i], c);
+    uint32_t first[kDirCells / kDirThreads];
+#pragma unroll
+    for (int k = 0; k < kDirCells / kDirThreads; ++k)
+        first[k] = atomicAdd(&row[threadIdx.x + k * kDirThreads], h[threadIdx.x + k * kDirThreads]);
+#pragma unroll
+    for (int k = 0; k < kDirCells / kDirThreads; ++k) h[threadIdx.x + k * kDirThreads] = first[k];
     __syncthreads();
     const long long total = R * (long long)gridDim.y;
 #pragma unroll
