@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # (profiles/k_trace_city_hbm_counters.md).  Valid only for the trace and build
 # sources it was measured on (the build makes the tree the trace reads):
 # reported as null once they change.
-TRACE_TRAFFIC = {"bytes": 36645591.0,
-                 "sources_sha256": "19f5cd63070ffb973ed994bf6ec832ffe45200f71f85b4e29edc918147473237"}
+TRACE_TRAFFIC = {"bytes": 38906512.0,
+                 "sources_sha256": "2c7218dd55244ae53a3899d8e92264024eeee120ae990eb283e0b57e658dceb3"}
 TRACE_SOURCES = ("paper_1803_00430_amd/csrc/trace.hip", "paper_1803_00430_amd/csrc/rpr_device.hpp",
                  "paper_1803_00430_amd/csrc/rpr_internal.hpp", "paper_1803_00430_amd/csrc/trace_acc.hpp",
                  "paper_1803_00430_amd/csrc/lbvh.hip")

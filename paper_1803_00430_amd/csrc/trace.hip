@@ -1019,8 +1019,19 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
         RPR_HIP_TRY(hipGetLastError());
     }
     const bool count = (p->flags & RPR_TRACE_COUNT_VISITS) != 0 && !rec;
-    int rc = launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need, count, p->waves_per_cu, 0, st,
-                          rec, rec_count, rec_cap, nullptr, dir_order);
+    // Default width of a direction-ordered launch whose rays about fill the
+    // chip's resident lanes (from 3/4 to 5/4 of them): about 4/5 of the rays
+    // resident, so that lanes whose rays end early take the rest from the
+    // queue instead of idling through the longest rays of their wave.
+    int wpc = p->waves_per_cu;
+    if (wpc == 0 && by_dir) {
+        const long long cus = device_cu_count(), full = trace_max_waves_per_cu(nb, scene->stack_need);
+        const long long lanes = cus * full * kWave;
+        if (cus > 0 && 4 * rays_all >= 3 * lanes && 4 * rays_all <= 5 * lanes)
+            wpc = (int)std::max(1ll, std::min(full, (4 * rays_all + 5 * cus * kWave - 1) / (5 * cus * kWave)));
+    }
+    int rc = launch_trace(d_pairs, n_src, d_queue, R * n_src, nb, scene->stack_need, count, wpc, 0, st, rec,
+                          rec_count, rec_cap, nullptr, dir_order);
     if (rc != RPR_OK) return rc;
     auto convert = [&]() -> int {
         if (!det) return RPR_OK;
