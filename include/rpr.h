@@ -218,10 +218,11 @@ int scene_info(const RprScene* scene, RprSceneInfo* out /* host */);
  *             ray's sequence of hit triangle ids and bounce kinds.
  * Rays are traced by persistent workgroups that refill lanes from a global
  * queue; the scene's workspace makes calls on one scene stream-ordered.
- * Without a segment budget, and for up to 1,024 sources of at least 64 rays,
- * each source's queue slots take its rays in the order of their first
- * directions (a counting sort in the workspace, 16 KB per source + 4 bytes
- * per ray), which changes no ray's path or deposits. */
+ * Without a segment budget, and for up to 1,024 sources of at least 64 rays
+ * and at most 2^26 rays in all, each source's queue slots take its rays in
+ * the order of their first directions (a counting sort in the workspace,
+ * 16 KB per source + 4 bytes per ray), which changes no ray's path or
+ * deposits. */
 int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const RprListener* lst,
              const RprTraceParams* p, float* hist, float* hist_late, RprIrStats* stats,
              uint32_t* ray_hash, void* hip_stream);

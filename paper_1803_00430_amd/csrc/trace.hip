@@ -924,10 +924,13 @@ int trace_common(const RprScene* scene, const RprSource* srcs, int32_t n_src, co
     const int nb0 = scene->n_bands;
     const int nc0 = (p->sh_order + 1) * (p->sh_order + 1);
     const size_t fx_cells = det ? (size_t)n_src * p->n_bins * nb0 * (nc0 + (hist_late ? 1 : 0)) : 0;
-    // slots ordered by first direction (k_dir_*) in the scene's own workspace
+    // slots ordered by first direction (k_dir_*) in the scene's own workspace,
+    // for launches of at most 2^26 rays (a 256 MB order): far larger ones
+    // refill every lane many times, and the first segments' coherence is a
+    // small part of their work
     const long long rays_all = (p->ray_end - p->ray_begin) * (long long)n_src;
     const bool by_dir = !ws && !rec && !budget && n_src <= kDirMaxSources && p->ray_end - p->ray_begin >= kWave &&
-                        rays_all < ((long long)1 << 32);
+                        rays_all <= ((long long)1 << 26);
     const size_t dir_off = (fx_cells * sizeof(long long) + 255) & ~(size_t)255;
     const size_t dir_counts = by_dir ? (size_t)n_src * kDirCells : 0;
     const size_t dir_bytes = by_dir ? sizeof(uint32_t) * (dir_counts + (size_t)rays_all) : 0;
