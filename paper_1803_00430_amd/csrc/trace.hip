@@ -444,9 +444,9 @@ __global__ void __launch_bounds__(256) k_setup_fill(SetupArgs a, PairDesc* __res
 // drawn from the ray id), so the slots of each source are given its rays
 // sorted into 64 x 64 cells of the two uniforms that set the first direction
 // (height and azimuth on the sphere, an equal-area map), in Morton order of the
-// cells.  A counting sort: cell counts, one exclusive scan over (source, cell),
-// then each ray takes the next position of its cell.  The order inside a cell
-// is that of the atomics.
+// cells.  A counting sort: cell counts, an exclusive scan over each source's
+// cells, then each ray takes the next position of its cell.  The order inside
+// a cell is that of the atomics.
 constexpr int kDirCellBits = 6;
 constexpr int kDirCells = 1 << (2 * kDirCellBits);
 constexpr int kDirMaxSources = 1024;  // 16 KB of cell counts each
