@@ -473,6 +473,41 @@ def test_lane_refill_matches_one_ray_per_lane(torch_cuda):
     sc.close()
 
 
+def test_city_launch_width_and_slot_order_change_no_ray(torch_cuda):
+    """The city launch (8 x 32,768 rays, about the chip's resident lanes): by
+    default its queue slots are ordered by first direction and a fifth of its
+    rays refill lanes; at 16 waves per CU every ray starts at once; through
+    trace_ir_noalloc the slots stay in ray order.  Every ray makes the same
+    decisions in all three (identical hashes and counts), and the fixed-point
+    histograms of the first two are the same bits."""
+    import torch
+    c = R.city_config()
+    sc = P.Scene.from_dict(c)
+    n_src, n = len(c["sources"]), c["n_rays"]
+    kw = dict(n_rays_total=n, max_bounces=c["max_bounces"], sh_order=c["sh_order"], n_bins=c["n_bins"],
+              bin_width_s=c["bin_width_s"], seed=c["seed"])
+
+    def run(fn, **over):
+        hist, late, stats, rh = P.alloc_trace_outputs(n_src, c["n_bins"], sc.n_bands, c["sh_order"], n,
+                                                      want_hash=True)
+        fn(sc, np.asarray(c["sources"], np.float32), c["listener"], c["radius"], P.trace_params(**kw, **over), hist,
+           late, stats, rh)
+        torch.cuda.synchronize()
+        return (hist.cpu().numpy(), late.cpu().numpy(), P.stats_host(stats), rh.cpu().numpy().view(np.uint32))
+
+    auto = run(P.trace_ir, flags=P.TRACE_DETERMINISTIC)
+    full = run(P.trace_ir, flags=P.TRACE_DETERMINISTIC, waves_per_cu=16)
+    plain = run(P.trace_ir_noalloc)
+    assert np.array_equal(auto[3], full[3]) and np.array_equal(auto[3], plain[3])
+    assert np.array_equal(auto[0].view(np.uint32), full[0].view(np.uint32))
+    assert np.array_equal(auto[1].view(np.uint32), full[1].view(np.uint32))
+    for s in range(n_src):
+        assert_hist_close(plain[0][s], auto[0][s].astype(np.float64), tol=1e-5, what=f"hist[{s}]")
+        for key in ("n_segments", "n_finite_segments", "n_escaped", "first_arrival_bin", "first_late_bin"):
+            assert auto[2][s][key] == full[2][s][key] == plain[2][s][key], (s, key)
+    sc.close()
+
+
 def test_concurrent_streams_match_serial(torch_cuda):
     """Steps of the benchmark rotate over several streams: scenes built and
     traced on three streams at once give each trace the result it has alone
