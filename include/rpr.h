@@ -234,7 +234,10 @@ int trace_ir(const RprScene* scene, const RprSource* srcs, int32_t n_src, const 
  * RPR_EINVAL), but the queue counter and the
  * pair table live in a static device array of the library (256 + 1,024 x 200
  * bytes, one per GPU, held until the process ends) instead of the scene's
- * workspace, so the call allocates nothing on the host or the device.
+ * workspace, so the call allocates nothing on the host or the device.  Its
+ * queue slots take the rays in ray order (no direction sort: per-ray results
+ * are those of trace_ir) at the full launch width unless p->waves_per_cu
+ * says otherwise.
  * Limit: n_src <= 1024 (RPR_EINVAL above).  Every call on one GPU shares that
  * array and leaves its contents behind (each call rewrites what it reads):
  * calls that overlap on one GPU -- on different streams or from different
